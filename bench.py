@@ -1,0 +1,195 @@
+"""Benchmark: shifted pipelined CG on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Workload (one step): a complete shifted p-CG solve (Alg. 3) of the 3-D
+Poisson 7-point problem on a 256^3 grid (16,777,216 unknowns), Jacobi
+preconditioner, sigma = 1 (midpoint of spec(A M^-1)), binary64, x_true ~
+U(-1, 1) from seed 0, b = A x_true, x0 = 0, to ||r||/||b|| <= 1e-10 with the
+explicit-residual check (cap 5000).  A step includes the init passes, every
+fused iteration pass, the explicit residual and any restart; inputs are
+resident in HBM before the timed region.
+
+Printed: one JSON line with the metric (iterations per second over the K
+timed solves), the roofline of the fused iteration pass (algorithmic bytes
+per pass / average pass duration from HIP events on the solver's stream, vs
+8 TB/s), and the oracle's rate on a bounded sample of the same workload on
+the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "shifted p-CG iters/s + HBM GB/s (3D Poisson 256^3); batched solves/s, p99"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pipe_3d7_jacobi_fp64_256.json")
+KERNEL_SOURCES = ["paper_1706_05988_amd/csrc/pcg_kernels.h", "paper_1706_05988_amd/csrc/pcg_device.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def bytes_per_unknown(method: str, jacobi: bool, fp32: bool) -> int:
+    """Algorithmic HBM bytes per unknown per iteration pass: every stored
+    vector read once and written once, w read once (halo counted once) and
+    written once into the other buffer; x and b stay binary64."""
+    es = 4 if fp32 else 8
+    if method == "cg":  # per iteration over both passes: r, p(x2), s + x
+        return 8 * 2 + es * 8
+    if jacobi:  # x rw; r u z q s t p rw; w r, w' w
+        return 8 * 2 + es * (7 * 2 + 2)
+    return 8 * 2 + es * (4 * 2 + 2)  # x rw; r z s t rw; w r, w' w
+
+
+def traffic_entry():
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(p, iters: int) -> dict:
+    """The oracle, as it stands, on a bounded sample of the same workload:
+    `iters` p-CG-sh iterations (plus its init and final explicit residual)."""
+    import oracle
+    threads = oracle.max_threads()
+    t0 = time.perf_counter()
+    r = oracle.solve(p.op, p.b, p.x0, method="pipe_shift", sigma=p.sigma, rtol=1e-30, max_iter=iters,
+                     jacobi=True, record=False, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": r["iterations"] / dt, "unit": "iterations/s", "cores": threads, "kind": "oracle",
+            "sample": f"{r['iterations']} shifted p-CG iterations of the same 256^3 Jacobi problem "
+                      f"(timing includes the oracle's init and final explicit residual), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--N", type=int, default=256, help="grid side (default: the 256^3 workload)")
+    ap.add_argument("--fp32", action="store_true", help="FP32-stream form instead of binary64")
+    ap.add_argument("--method", default="pipe_shift", choices=["cg", "pipe", "pipe_shift"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--K", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs the solver on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import problems
+    from paper_1706_05988_amd import pcg as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    t_gen = time.perf_counter()
+    p = problems.poisson3d(args.N, seed=0, jacobi=True)
+    n = p.op.n
+    print(f"[bench] generated 3-D Poisson {args.N}^3 (n={n}) in {time.perf_counter() - t_gen:.1f} s", flush=True)
+    sigma = p.sigma if args.method == "pipe_shift" else 0.0
+    opt = P.make_options(method=args.method, jacobi=True, fp32=args.fp32, sigma=sigma, rtol=1e-10,
+                         max_iter=5000, true_residual_check=True, replace_max=8, timing=True,
+                         block_size=args.block, grid_blocks=args.grid, iters_per_launch=args.K)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    solver = P.Solver(p.op, opt, stream=stream)
+    b = torch.from_numpy(p.b).to(dev)
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+
+    def step():
+        x.zero_()
+        return solver.solve(b, x)
+
+    for w in range(args.warmup):
+        r = step()
+        print(f"[bench] warmup {w}: {r['status']} in {r['iterations']} iterations, "
+              f"true residual {r['rel_res_true']:.3e}, {r['seconds']:.3f} s", flush=True)
+    torch.cuda.synchronize()
+    results = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        results.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    for k, r in enumerate(results):
+        print(f"[bench] step {k}: {r['status']} {r['iterations']} it, true {r['rel_res_true']:.3e}, "
+              f"{r['seconds']:.3f} s, pass {r['iter_kernel_ms'] / max(1, r['iter_passes']) * 1e3:.1f} us",
+              flush=True)
+    iters = sum(r["iterations"] for r in results)
+    passes = sum(r["iter_passes"] for r in results)
+    kernel_ms = sum(r["iter_kernel_ms"] for r in results)
+    bpu = bytes_per_unknown(args.method, True, args.fp32)
+    per_pass_bytes = bpu * n / (2 if args.method == "cg" else 1)
+    avg_pass_s = kernel_ms / 1e3 / max(1, passes)
+    achieved = per_pass_bytes / avg_pass_s / 1e9
+    traffic = traffic_entry() if (args.N == 256 and args.method == "pipe_shift" and not args.fp32
+                                  and not args.block and not args.grid) else None
+    out = {
+        "metric": METRIC,
+        "value": iters / elapsed,
+        "unit": "iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if args.fp32 else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3-D Poisson 7-point {args.N}^3 (n={n}), Jacobi, {args.method} "
+                        f"sigma={sigma:g}, {'FP32-stream' if args.fp32 else 'FP64'}, full solve to "
+                        f"||r||/||b|| <= 1e-10 (explicit-residual check), x0 = 0",
+            "n": n,
+            "iterations_per_solve": iters / args.steps,
+            "true_residual_max": max(r["rel_res_true"] for r in results),
+            "hbm_gbs_effective": bpu * n * iters / elapsed / 1e9,
+            "algorithmic_bytes_per_iteration": bpu * n,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_pipe (fused p-CG-sh iteration pass)" if args.method != "cg" else "k_cg_a + k_cg_b",
+            "avg_pass_us": avg_pass_s * 1e6,
+            "bytes_per_pass": per_pass_bytes,
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_iters)
+    solver.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,230 @@
+/*
+ * pcg.h -- C ABI of libpcg, a shifted pipelined Conjugate Gradients library
+ * for one AMD Instinct MI355X (gfx950).
+ *
+ * The library solves A x = b for a real symmetric positive definite n-by-n
+ * operator A (Section 2.1 of Cools & Vanroose, "Numerically stable variants
+ * of the communication-hiding pipelined Conjugate Gradients algorithm") with
+ *   - classic preconditioned CG ........................ Alg. 1  (PCG_CG)
+ *   - preconditioned pipelined CG ...................... Alg. 2  (PCG_PIPE)
+ *   - shifted preconditioned pipelined CG .............. Alg. 3  (PCG_PIPE_SHIFT)
+ * Alg. 3 with sigma = 0 is Alg. 2 (end of Section 2.2); both run the same
+ * fused kernel.  Each pipelined iteration is ONE device pass: the
+ * preconditioner apply and SPMV (m_i = M^-1 w_i, n_i = A m_i), the five
+ * beta-recurrences (z, q, s, t, p), the four alpha-recurrences including the
+ * shift terms (x, r, u, w), and the local parts of the next iteration's dot
+ * products gamma = (r, u), delta = (w + sigma r, u) and rho = (r, r).  The
+ * global part of the reduction is summed in a fixed order at the head of the
+ * next pass, overlapping that pass's SPMV loads -- the single-GPU form of the
+ * paper's overlap of the global reduction with the SPMV (Section 1).
+ *
+ * Conventions for every entry point
+ *   - All calls return a pcg_status: PCG_OK (0), PCG_PENDING (1, polling
+ *     only) or a negative error.  No C++ exception crosses the ABI.
+ *   - Device pointers are HIP device addresses (e.g. torch tensors' data_ptr).
+ *     The library never allocates device memory: the caller provides a
+ *     workspace of at least pcg_workspace_size() bytes (256-byte aligned).
+ *   - All device work is issued on the caller's HIP stream (hipStream_t passed
+ *     as void*, NULL = the legacy default stream), stream-ordered with the
+ *     caller's own work.  pcg_solve() returns after the solve has completed.
+ *   - x and b are always binary64 vectors of length n.  In PCG_FP32_STREAM
+ *     form the Krylov vectors (r, u, w, z, q, s, t, p), the CSR values and the
+ *     Jacobi diagonal are stored in binary32; all arithmetic, dot products,
+ *     scalar recurrences, the explicit residual and x stay binary64.
+ *   - Handles are not thread-safe: one thread at a time per pcg_solver.
+ */
+#ifndef PCG_H
+#define PCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status */
+
+typedef int32_t pcg_status;
+
+#define PCG_OK              0
+#define PCG_PENDING         1   /* pcg_poll(): the ticket has not finished       */
+#define PCG_ERR_INVALID   (-1)  /* bad argument (null, size, layout, alignment)  */
+#define PCG_ERR_NONFINITE (-2)  /* b holds NaN or Inf                             */
+#define PCG_ERR_HIP       (-3)  /* a HIP runtime call failed (see pcg_last_error) */
+#define PCG_ERR_BUDGET    (-4)  /* a request can never fit the server's memory    */
+#define PCG_ERR_STATE     (-5)  /* unknown ticket / handle used in a wrong state  */
+
+/* outcome of a solve, in pcg_result.status */
+#define PCG_CONVERGED  0   /* recursive (and, if checked, explicit) residual <= rtol */
+#define PCG_MAX_ITER   1   /* iteration cap reached                                 */
+#define PCG_BREAKDOWN  2   /* gamma <= 0, delta <= 0, (s,p) <= 0 or alpha not > 0     */
+#define PCG_NONFINITE  3   /* a reduction produced NaN / Inf                         */
+
+typedef enum { PCG_CG = 0, PCG_PIPE = 1, PCG_PIPE_SHIFT = 2 } pcg_method;
+typedef enum { PCG_OP_STENCIL2D5 = 0, PCG_OP_STENCIL3D7 = 1, PCG_OP_CSR = 2 } pcg_op_kind;
+typedef enum { PCG_PC_NONE = 0, PCG_PC_JACOBI = 1 } pcg_pc_kind;
+typedef enum { PCG_FP64 = 0, PCG_FP32_STREAM = 1 } pcg_precision;
+
+/* ---------------------------------------------------------------- operator */
+
+/*
+ * The SPD operator A (Section 2.1: a real SPD n-by-n matrix).
+ *
+ * Stencils (matrix-free): the second-order finite-difference Laplacian on the
+ * interior points of an nx-by-ny(-by-nz) grid with homogeneous Dirichlet
+ * boundaries, lexicographic order with x fastest: row k holds (diag + shift)
+ * on the diagonal and `offdiag` for each existing grid neighbour (4 in 2-D,
+ * 6 in 3-D).  The unscaled Laplacian is diag = 4 (2-D) / 6 (3-D),
+ * offdiag = -1; shift adds c I.  n must equal nx*ny (2-D) or nx*ny*nz (3-D).
+ *
+ * CSR: n rows; row_ptr (n + 1 int32, row_ptr[0] = 0, row_ptr[n] = nnz),
+ * col_idx (nnz int32 in [0, n)), vals (nnz values: double in PCG_FP64 form,
+ * float in PCG_FP32_STREAM form); all device memory, borrowed until
+ * pcg_destroy().  Each row must hold its diagonal entry when the Jacobi
+ * preconditioner is used.  n and nnz must be < 2^31.
+ */
+typedef struct {
+    int32_t kind;               /* pcg_op_kind                                    */
+    int32_t nx, ny, nz;         /* stencil grid (nz = 1 for 2-D)                  */
+    int64_t n;                  /* number of unknowns                             */
+    double diag, offdiag, shift;/* stencil coefficients                           */
+    const int32_t *row_ptr;     /* CSR, device                                    */
+    const int32_t *col_idx;     /* CSR, device                                    */
+    const void *vals;           /* CSR, device, double or float per precision     */
+    int64_t nnz;                /* CSR                                            */
+} pcg_operator;
+
+/* ----------------------------------------------------------------- options */
+
+#define PCG_HISTORY_FIELDS 5    /* per iteration: sqrt(rho_i)/||b||, alpha_i, beta_i, gamma_i, delta_i */
+
+typedef struct {
+    int32_t method;             /* pcg_method                                              */
+    int32_t pc;                 /* pcg_pc_kind; Jacobi: M = diag(A), m = (1/a_kk) w         */
+    int32_t prec;               /* pcg_precision                                           */
+    int32_t max_iter;           /* iteration cap (>= 0)                                    */
+    double sigma;               /* shift of Alg. 3 (>= 0); NaN: midpoint of the spectrum
+                                   bounds of A M^-1 (closed form for stencils, Gershgorin
+                                   for CSR); ignored by PCG_CG and PCG_PIPE                 */
+    double rtol;                /* stop at the top of iteration i when
+                                   sqrt((r_i, r_i)) <= rtol ||b||  (> 0)                  */
+    int32_t true_residual_check;/* 1: at a claim of convergence also compute
+                                   ||b - A x|| / ||b|| in binary64 and, if it exceeds rtol,
+                                   restart from x (below)                                   */
+    int32_t replace_max;        /* max restarts from x ("residual replacement": the
+                                   initialisation is re-run with x_0 := x_i while the
+                                   iteration count continues); 0 = none                     */
+    int32_t iters_per_launch;   /* K: iteration passes per HIP graph launch (even, >= 2);
+                                   0 = library default                                       */
+    int32_t history_cap;        /* rows of `history` (0 = no history)                       */
+    double *history;            /* HOST buffer of history_cap * PCG_HISTORY_FIELDS doubles,
+                                   row i = iteration i (NaN for alpha.. when not computed);
+                                   filled when pcg_solve returns                            */
+    int32_t block_size;         /* threads per block (64..1024, multiple of 64); 0 = tuned   */
+    int32_t grid_blocks;        /* blocks of the persistent grid; 0 = tuned                 */
+    int32_t timing;             /* 1: time the iteration graph launches with HIP events     */
+    int32_t use_graph;          /* 1: capture the K passes of a launch in a HIP graph
+                                   (pcg_default_options' choice); 0: launch them one by one  */
+    int32_t reserved[4];
+} pcg_options;
+
+typedef struct {
+    int32_t status;             /* PCG_CONVERGED .. PCG_NONFINITE                         */
+    int32_t iterations;         /* i at exit (x = x_i)                                    */
+    int32_t replacements;       /* restarts from x                                        */
+    int32_t launches;           /* graph (or single-pass) launches issued                 */
+    double rel_res_recursive;   /* sqrt((r_i, r_i)) / ||b||                              */
+    double rel_res_true;        /* ||b - A x_i|| / ||b|| in binary64 (NaN if not computed) */
+    double seconds;             /* host wall time of pcg_solve                            */
+    double iter_kernel_ms;      /* HIP-event time of the iteration launches (timing = 1)  */
+    int32_t iter_passes;        /* iteration passes that did work (iterations of all methods;
+                                   CG counts 2 passes per iteration)                       */
+    int32_t reserved;
+    double sigma;               /* the shift actually used                                */
+} pcg_result;
+
+/* Fill *opt with defaults: PCG_PIPE_SHIFT, no PC, FP64, max_iter 1000,
+ * sigma NaN (midpoint), rtol 1e-10, true-residual check on, 4 restarts,
+ * library-chosen launch shape, HIP graphs on. */
+pcg_status pcg_default_options(pcg_options *opt);
+
+/* -------------------------------------------------------------- one solver */
+
+typedef struct pcg_solver_ *pcg_solver;
+
+/* Bytes of device workspace a solver for (op, opt) needs. */
+pcg_status pcg_workspace_size(const pcg_operator *op, const pcg_options *opt, size_t *bytes);
+
+/*
+ * Create a solver bound to op, opt, a device workspace (>= the size above,
+ * 256-byte aligned, owned by the caller, borrowed until pcg_destroy) and a
+ * HIP stream.  Validates all arguments (PCG_ERR_INVALID), sets up the Jacobi
+ * diagonal for CSR operators on the stream, and captures the iteration graph.
+ */
+pcg_status pcg_create(pcg_solver *solver, const pcg_operator *op, const pcg_options *opt,
+                      void *workspace, size_t bytes, void *hip_stream);
+
+/*
+ * Solve A x = b.  b: device, n binary64 (read only).  x: device, n binary64,
+ * x_0 on entry and the final iterate on return (overwritten in place; it must
+ * not alias b).  Blocks the calling host thread until done.  Returns
+ * PCG_ERR_NONFINITE (x untouched beyond x_0) when ||b|| is not finite.
+ */
+pcg_status pcg_solve(pcg_solver solver, const double *b, double *x, pcg_result *result);
+
+/* ||b - A x|| / ||b|| in binary64 for the solver's operator (Section 3.1's
+ * explicit residual); device b, x; host *rel. */
+pcg_status pcg_true_residual(pcg_solver solver, const double *b, const double *x, double *rel);
+
+pcg_status pcg_destroy(pcg_solver solver);
+
+/* ------------------------------------------------------------ batched solve */
+
+/*
+ * Solve `count` independent systems A_k x_k = b_k in ONE persistent pass per
+ * iteration (every active system advances one phase or iteration per pass).
+ * ops[k], opts[k]: per-system operator and options; all systems must share
+ * method, pc and prec (the shape parameters of opts[0] are used).  b[k], x[k]:
+ * host arrays of device pointers.  Per-system results in results[k].  Each
+ * system's arithmetic -- tiling, reduction order -- depends only on that
+ * system, so its result does not depend on what else is in the batch.
+ */
+pcg_status pcg_batch_workspace_size(int32_t count, const pcg_operator *ops, const pcg_options *opts,
+                                    size_t *bytes);
+pcg_status pcg_batch_solve(int32_t count, const pcg_operator *ops, const pcg_options *opts,
+                           const double *const *b, double *const *x, pcg_result *results,
+                           void *workspace, size_t bytes, void *hip_stream);
+
+/* ---------------------------------------------------------------- serving */
+
+typedef struct pcg_server_ *pcg_server;
+
+/*
+ * A continuously batching solve server.  `arena` (device, `arena_bytes`,
+ * owned by the caller) is the HBM budget from which the server sub-allocates
+ * each admitted request's Krylov vectors; requests wait until their footprint
+ * and a slot (max_slots) are free, and join the running batch at the next
+ * launch boundary.  A scheduler thread owned by the server drives the device.
+ */
+pcg_status pcg_server_create(pcg_server *server, void *arena, size_t arena_bytes, int32_t max_slots,
+                             void *hip_stream);
+/* Enqueue a solve; op, b, x device data stay borrowed until the ticket is
+ * done.  opt->method/pc/prec must match the server's first request's. */
+pcg_status pcg_submit(pcg_server server, const pcg_operator *op, const pcg_options *opt,
+                      const double *b, double *x, uint64_t *ticket);
+pcg_status pcg_poll(pcg_server server, uint64_t ticket, pcg_result *result);   /* PCG_PENDING until done */
+pcg_status pcg_wait(pcg_server server, uint64_t ticket, pcg_result *result);
+pcg_status pcg_server_destroy(pcg_server server);
+
+/* ------------------------------------------------------------------ misc */
+
+const char *pcg_status_str(pcg_status status);
+/* Text of the last HIP error seen by this thread (empty if none). */
+const char *pcg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCG_H */

@@ -1,0 +1,53 @@
+"""Build libpcg.so (the C-ABI library and its gfx950 kernels) in-tree with hipcc.
+
+    python -m paper_1706_05988_amd.build
+
+The shared library lands next to this file; ``paper_1706_05988_amd.pcg``
+loads it from there.  Every call compiles (no staleness shortcut), so a
+build after a source change is never skipped.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(HERE, "libpcg.so")
+ARCH = os.environ.get("PCG_OFFLOAD_ARCH", "gfx950")
+
+SOURCES = ["pcg_solver.hip", "pcg_batch.hip", "pcg_server.hip"]
+
+# -Xclang -target-feature -Xclang -packed-fp32-ops keeps the compiler from
+# emitting packed FP32 VALU instructions on gfx950.
+HIPCC_FLAGS = [
+    "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found")
+
+
+def build(verbose: bool = False) -> str:
+    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    tmp = LIB + ".tmp"
+    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + srcs + ["-lpthread"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,223 @@
+// pcg_device.h -- device-side building blocks of the fused p-CG(-sh) passes.
+//
+// Everything here is gfx950 code written for 64-wide wavefronts:
+//   * FastDiv: division by a runtime constant (grid extents) with one
+//     multiply-high, used to recover stencil coordinates from a flat index.
+//   * wave64 butterfly reductions and a fixed-order block reduction, which
+//     give the same bits in every lane and every block -- the basis of the
+//     deterministic two-stage FP64 grid reduction of the dot products.
+//   * the operator: Dirichlet 5-/7-point stencils (matrix-free, neighbours
+//     summed centre, -x, +x, -y, +y, -z, +z) and CSR rows (storage order).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcg {
+
+// ------------------------------------------------------------------ enums
+
+enum OpKind : int { OP_2D5 = 0, OP_3D7 = 1, OP_CSR = 2 };
+
+// run status kept in the device state (PCG_CONVERGED.. values of pcg.h, or
+// RUNNING while the iteration goes on)
+enum RunStatus : int { RUNNING = -1, ST_CONVERGED = 0, ST_MAX_ITER = 1, ST_BREAKDOWN = 2, ST_NONFINITE = 3 };
+
+constexpr int kFields = 4;      // doubles per block partial (32 bytes)
+constexpr int kMaxWaves = 16;   // up to 1024 threads per block
+
+// ------------------------------------------------------------------ state
+
+// Scalars carried from one pass to the next.  Pass k reads slot k%2 and
+// block 0 writes slot (k+1)%2, so no block ever reads what another block of
+// the same pass writes.
+struct DevState {
+    double bnorm2;      // ||b||^2
+    double alpha_prev;  // alpha_{i-1}
+    double gamma_prev;  // gamma_{i-1}
+    double rho;         // rho_i = (r_i, r_i) of the last head reduction
+    double gamma;       // CG: gamma_i handed from pass A to pass B
+    double true_res2;   // ||b - A x||^2 of the last explicit-residual pass
+    int32_t iter;       // i at the top of the next pass
+    int32_t i_start;    // iteration of the last (re)start: takes the i = 0 branch
+    int32_t status;     // RunStatus
+    int32_t pad;
+    double spare[2];
+};
+static_assert(sizeof(DevState) == 80, "DevState layout");
+
+// ------------------------------------------------------------ fast division
+
+// q = x / d for 0 <= x < 2^31, d >= 1:  q = (umulhi(x, m) + x) >> s with
+// s = ceil(log2 d) and m = floor(2^32 (2^s - d) / d) + 1 (round-up method of
+// Granlund & Montgomery; exact for 31-bit numerators).
+struct FastDiv {
+    uint32_t d, m, s, pad;
+};
+
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    FastDiv f{};
+    f.d = d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    f.s = s;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+    return f;
+}
+
+__host__ __device__ inline uint32_t fdiv(uint32_t x, const FastDiv &f)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    uint32_t hi = __umulhi(x, f.m);
+#else
+    uint32_t hi = (uint32_t)(((uint64_t)x * f.m) >> 32);
+#endif
+    return (hi + x) >> f.s;
+}
+
+// --------------------------------------------------------------- operator
+
+template <typename T>
+struct OpDev {
+    int32_t n;           // unknowns
+    int32_t nx, ny, nz;  // stencil grid
+    FastDiv dx;          // / nx
+    FastDiv dxy;         // / (nx * ny)
+    double centre;       // diag + shift
+    double off;          // off-diagonal coefficient
+    const int32_t *row_ptr;
+    const int32_t *col;
+    const T *val;
+};
+
+template <typename T>
+__device__ __forceinline__ double ld(const T *p, uint32_t i) { return (double)p[i]; }
+
+// Round a value to the storage type and back, so that every later use of a
+// stored quantity sees exactly the stored bits.
+template <typename T>
+__device__ __forceinline__ double rnd(double v) { return (double)(T)v; }
+
+// (A v)_e for the row e; v(k) returns the k-th entry of the operand.
+template <int OP, typename T, typename F>
+__device__ __forceinline__ double apply_row(const OpDev<T> &A, uint32_t e, F v)
+{
+    if constexpr (OP == OP_CSR) {
+        const int32_t k0 = A.row_ptr[e], k1 = A.row_ptr[e + 1];
+        double acc = 0.0;
+        for (int32_t k = k0; k < k1; ++k) acc += (double)A.val[k] * v((uint32_t)A.col[k]);
+        return acc;
+    } else {
+        const uint32_t q = fdiv(e, A.dx);          // e / nx
+        const uint32_t i = e - q * (uint32_t)A.nx;
+        uint32_t j, k = 0;
+        if constexpr (OP == OP_3D7) {
+            k = fdiv(e, A.dxy);
+            j = q - k * (uint32_t)A.ny;
+        } else {
+            j = q;
+        }
+        const uint32_t nx = (uint32_t)A.nx, sxy = (uint32_t)A.nx * (uint32_t)A.ny;
+        double acc = A.centre * v(e);
+        if (i > 0) acc += A.off * v(e - 1);
+        if (i + 1 < nx) acc += A.off * v(e + 1);
+        if (j > 0) acc += A.off * v(e - nx);
+        if (j + 1 < (uint32_t)A.ny) acc += A.off * v(e + nx);
+        if constexpr (OP == OP_3D7) {
+            if (k > 0) acc += A.off * v(e - sxy);
+            if (k + 1 < (uint32_t)A.nz) acc += A.off * v(e + sxy);
+        }
+        return acc;
+    }
+}
+
+// ---------------------------------------------------------------- reductions
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    // xor butterfly: every lane ends with the same bits (each step adds the
+    // same two operands in every lane, and IEEE addition is commutative)
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum NF values over the block in a fixed order; the result is returned in
+// every thread.  lds: kMaxWaves * kFields doubles.  Ends with a barrier so
+// the LDS can be reused.
+template <int NF>
+__device__ __forceinline__ void block_sum(double (&v)[NF], double *lds)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) v[f] = wave_sum(v[f]);
+    if (lane == 0) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) lds[wave * kFields + f] = v[f];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[w * kFields + f];
+        v[f] = s;
+    }
+    __syncthreads();
+}
+
+// Stage 2 of the grid reduction: sum the P block partials (kFields doubles
+// each) in a fixed order -- thread t takes partials t, t + B, t + 2B, ...
+// sequentially, then the fixed block order above.  Every block computes the
+// same bits.
+template <int NF>
+__device__ __forceinline__ void stage2(const double *part, int P, double (&tot)[NF], double *lds)
+{
+#pragma unroll
+    for (int f = 0; f < NF; ++f) tot[f] = 0.0;
+    for (int k = threadIdx.x; k < P; k += blockDim.x) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) tot[f] += part[k * kFields + f];
+    }
+    block_sum<NF>(tot, lds);
+}
+
+// Write the block's NF partial sums (already block-summed, so equal in every
+// thread) to part[blockIdx]; unused fields are written as zero.
+template <int NF>
+__device__ __forceinline__ void store_partial(double *part, const double (&v)[NF])
+{
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int f = 0; f < kFields; ++f) part[blockIdx.x * kFields + f] = f < NF ? v[f] : 0.0;
+    }
+}
+
+// ------------------------------------------------------- persistent tiling
+
+// Tiles are contiguous runs of blockDim * EPT unknowns.  With the XCD map on,
+// the tiles are split into 8 contiguous slabs and the blocks that the
+// hardware places on XCD x (blockIdx % 8 == x) sweep slab x in order, so a
+// stencil's neighbouring rows and planes are fetched through the same L2.
+struct TileRange {
+    int first, step, end;
+};
+
+__device__ __forceinline__ TileRange tile_range(int ntiles, int xcd_map)
+{
+    TileRange t;
+    if (xcd_map) {
+        const int per = (ntiles + 7) >> 3;
+        const int x = blockIdx.x & 7;
+        t.first = x * per + (int)(blockIdx.x >> 3);
+        t.step = (int)(gridDim.x >> 3);
+        t.end = min(ntiles, (x + 1) * per);
+    } else {
+        t.first = blockIdx.x;
+        t.step = gridDim.x;
+        t.end = ntiles;
+    }
+    return t;
+}
+
+}  // namespace pcg

@@ -1,0 +1,51 @@
+// pcg_internal.h -- host-side declarations shared by the library's sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "pcg.h"
+#include "pcg_device.h"
+
+namespace pcg {
+
+constexpr int kNumCU = 256;              // MI355X compute units (8 XCDs x 32)
+constexpr int kDefaultBlocksPerCU = 4;   // persistent grid: 4 blocks of 256 threads per CU
+constexpr int kMaxGrid = 16384;
+constexpr int kGershBlocks = 256;
+
+// vector slots of the workspace
+enum VecSlot { V_R = 0, V_U, V_W0, V_W1, V_Z, V_Q, V_S, V_T, V_P };
+
+struct LaunchShape {
+    int block;    // threads per block
+    int ept;      // unknowns per thread per tile
+    int ntiles;   // tiles of block * ept unknowns
+    int grid;     // persistent blocks
+    int xcd_map;  // XCD-slab tile order on/off
+    int K;        // iterations per graph launch
+};
+
+// byte offsets into the caller's workspace (SIZE_MAX: absent)
+struct Layout {
+    static constexpr int kVecs = 9;
+    size_t state, part[2], gersh, flag, hist, dinv;
+    size_t vec[kVecs];
+    size_t total;
+};
+
+// Type-erased kernel arguments (PassArgs<double> or PassArgs<float>).
+struct PassArgsAny {
+    alignas(16) unsigned char bytes[320];
+};
+
+extern thread_local std::string g_last_error;
+pcg_status hip_fail(hipError_t e, const char *what);
+pcg_status invalid(const char *why);
+pcg_status validate_operator(const pcg_operator *op, int prec);
+pcg_status validate_options(const pcg_options *o);
+
+}  // namespace pcg

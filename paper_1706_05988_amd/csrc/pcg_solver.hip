@@ -1,0 +1,677 @@
+// pcg_solver.hip -- host side of the single-system C ABI (pcg.h): argument
+// validation, workspace layout, kernel dispatch, HIP-graph capture of K
+// iteration passes, and the solve loop (init passes, graph launches with the
+// device status polled one launch behind, explicit residual, restarts).
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "pcg.h"
+#include "pcg_internal.h"
+#include "pcg_kernels.h"
+
+using namespace pcg;
+
+// ----------------------------------------------------------------- errors
+
+namespace pcg {
+thread_local std::string g_last_error;
+
+pcg_status hip_fail(hipError_t e, const char *what)
+{
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return PCG_ERR_HIP;
+}
+
+pcg_status invalid(const char *why)
+{
+    g_last_error = std::string("invalid argument: ") + why;
+    return PCG_ERR_INVALID;
+}
+}  // namespace pcg
+
+#define HIPCHK(call)                                  \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+extern "C" const char *pcg_last_error(void) { return g_last_error.c_str(); }
+
+extern "C" const char *pcg_status_str(pcg_status s)
+{
+    switch (s) {
+    case PCG_OK: return "ok";
+    case PCG_PENDING: return "pending";
+    case PCG_ERR_INVALID: return "invalid argument";
+    case PCG_ERR_NONFINITE: return "right-hand side is not finite";
+    case PCG_ERR_HIP: return "HIP runtime error";
+    case PCG_ERR_BUDGET: return "request can never fit the memory budget";
+    case PCG_ERR_STATE: return "unknown handle or wrong state";
+    default: return "unknown status";
+    }
+}
+
+extern "C" pcg_status pcg_default_options(pcg_options *o)
+{
+    if (!o) return invalid("options is null");
+    std::memset(o, 0, sizeof(*o));
+    o->method = PCG_PIPE_SHIFT;
+    o->pc = PCG_PC_NONE;
+    o->prec = PCG_FP64;
+    o->max_iter = 1000;
+    o->sigma = std::nan("");
+    o->rtol = 1e-10;
+    o->true_residual_check = 1;
+    o->replace_max = 4;
+    o->iters_per_launch = 0;
+    o->use_graph = 1;
+    return PCG_OK;
+}
+
+// ------------------------------------------------------------ validation
+
+namespace pcg {
+
+static bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+pcg_status validate_operator(const pcg_operator *op, int prec)
+{
+    if (!op) return invalid("operator is null");
+    if (op->kind < PCG_OP_STENCIL2D5 || op->kind > PCG_OP_CSR) return invalid("unknown operator kind");
+    if (op->n < 1 || op->n >= (int64_t(1) << 31)) return invalid("n must be in [1, 2^31)");
+    if (op->kind == PCG_OP_CSR) {
+        if (!op->row_ptr || !op->col_idx || !op->vals) return invalid("CSR arrays must be non-null");
+        if (op->nnz < 0 || op->nnz >= (int64_t(1) << 31)) return invalid("nnz must be in [0, 2^31)");
+        if (!aligned(op->row_ptr, 4) || !aligned(op->col_idx, 4)) return invalid("CSR index arrays misaligned");
+        if (!aligned(op->vals, prec == PCG_FP64 ? 8 : 4)) return invalid("CSR values misaligned");
+    } else {
+        if (op->nx < 1 || op->ny < 1 || op->nz < 1) return invalid("grid extents must be >= 1");
+        if (op->kind == PCG_OP_STENCIL2D5 && op->nz != 1) return invalid("2-D stencil needs nz = 1");
+        const int64_t cells = int64_t(op->nx) * op->ny * op->nz;
+        if (cells != op->n) return invalid("n does not match the grid");
+        if (!std::isfinite(op->diag) || !std::isfinite(op->offdiag) || !std::isfinite(op->shift))
+            return invalid("stencil coefficients must be finite");
+        if (!(op->diag + op->shift > 0.0)) return invalid("stencil diagonal must be positive");
+    }
+    return PCG_OK;
+}
+
+pcg_status validate_options(const pcg_options *o)
+{
+    if (!o) return invalid("options is null");
+    if (o->method < PCG_CG || o->method > PCG_PIPE_SHIFT) return invalid("unknown method");
+    if (o->pc < PCG_PC_NONE || o->pc > PCG_PC_JACOBI) return invalid("unknown preconditioner");
+    if (o->prec < PCG_FP64 || o->prec > PCG_FP32_STREAM) return invalid("unknown precision");
+    if (o->max_iter < 0) return invalid("max_iter must be >= 0");
+    if (!(o->rtol > 0.0) || !std::isfinite(o->rtol)) return invalid("rtol must be finite and > 0");
+    if (!std::isnan(o->sigma) && !(o->sigma >= 0.0 && std::isfinite(o->sigma)))
+        return invalid("sigma must be >= 0 (or NaN for the default)");
+    if (o->iters_per_launch < 0 || (o->iters_per_launch % 2) != 0)
+        return invalid("iters_per_launch must be 0 or an even number >= 2");
+    if (o->block_size != 0 && (o->block_size < 64 || o->block_size > 1024 || o->block_size % 64 != 0))
+        return invalid("block_size must be a multiple of 64 in [64, 1024]");
+    if (o->grid_blocks < 0 || o->grid_blocks > kMaxGrid) return invalid("grid_blocks out of range");
+    if (o->history_cap < 0) return invalid("history_cap must be >= 0");
+    if (o->history_cap > 0 && !o->history) return invalid("history buffer is null");
+    if (o->replace_max < 0) return invalid("replace_max must be >= 0");
+    return PCG_OK;
+}
+
+// ----------------------------------------------------------------- shape
+
+LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
+{
+    LaunchShape s{};
+    s.block = o->block_size ? o->block_size : 256;
+    s.ept = 2;
+    const int64_t tile = int64_t(s.block) * s.ept;
+    s.ntiles = (int)((op->n + tile - 1) / tile);
+    int g = o->grid_blocks ? o->grid_blocks : kDefaultBlocksPerCU * kNumCU;
+    if (g > s.ntiles) g = s.ntiles;
+    if (g >= 64) g &= ~7;  // a multiple of the XCD count
+    if (g < 1) g = 1;
+    s.grid = g;
+    s.xcd_map = (g >= 64 && (g % 8) == 0) ? 1 : 0;
+    s.K = o->iters_per_launch ? o->iters_per_launch : (op->n >= (1 << 20) ? 16 : 64);
+    return s;
+}
+
+static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &sh, Layout *L)
+{
+    const size_t n = (size_t)op->n;
+    const size_t es = o->prec == PCG_FP64 ? 8 : 4;
+    const bool jac = o->pc == PCG_PC_JACOBI;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += up256(bytes);
+        return at;
+    };
+    Layout l{};
+    l.state = take(2 * sizeof(DevState) + 128);
+    l.part[0] = take(size_t(sh.grid) * kFields * 8);
+    l.part[1] = take(size_t(sh.grid) * kFields * 8);
+    l.gersh = take(size_t(kGershBlocks) * 2 * 8);
+    l.flag = take(64);
+    l.hist = take(size_t(o->history_cap) * PCG_HISTORY_FIELDS * 8);
+    l.dinv = (op->kind == PCG_OP_CSR && jac) ? take(n * es) : SIZE_MAX;
+    const size_t v = n * es;
+    for (int k = 0; k < Layout::kVecs; ++k) l.vec[k] = SIZE_MAX;
+    if (o->method == PCG_CG) {
+        l.vec[V_R] = take(v);
+        l.vec[V_W0] = take(v);  // p ping-pong
+        l.vec[V_W1] = take(v);
+        l.vec[V_S] = take(v);
+    } else {
+        l.vec[V_R] = take(v);
+        l.vec[V_W0] = take(v);
+        l.vec[V_W1] = take(v);
+        l.vec[V_Z] = take(v);
+        l.vec[V_S] = take(v);
+        l.vec[V_T] = take(v);
+        if (jac) {
+            l.vec[V_U] = take(v);
+            l.vec[V_Q] = take(v);
+            l.vec[V_P] = take(v);
+        }
+    }
+    l.total = off;
+    if (L) *L = l;
+    return off;
+}
+
+}  // namespace pcg
+
+// ------------------------------------------------------------- dispatch
+
+static_assert(sizeof(PassArgs<double>) <= sizeof(PassArgsAny), "PassArgsAny too small");
+static_assert(sizeof(PassArgs<float>) <= sizeof(PassArgsAny), "PassArgsAny too small");
+
+namespace {
+
+template <typename T>
+OpDev<T> make_opdev(const pcg_operator *op)
+{
+    OpDev<T> A{};
+    A.n = (int32_t)op->n;
+    A.nx = op->nx;
+    A.ny = op->ny;
+    A.nz = op->kind == PCG_OP_STENCIL3D7 ? op->nz : 1;
+    if (op->kind != PCG_OP_CSR) {
+        A.dx = make_fastdiv((uint32_t)op->nx);
+        A.dxy = make_fastdiv((uint32_t)op->nx * (uint32_t)op->ny);
+    }
+    A.centre = op->diag + op->shift;
+    A.off = op->offdiag;
+    A.row_ptr = op->row_ptr;
+    A.col = op->col_idx;
+    A.val = (const T *)op->vals;
+    return A;
+}
+
+// Kernel table for one (T, OP, JAC) combination.
+struct Kernels {
+    void (*init0_pipe)(PassArgsAny, int, int, hipStream_t);
+    void (*init0_cg)(PassArgsAny, int, int, hipStream_t);
+    void (*init1)(PassArgsAny, int, int, hipStream_t);
+    void (*pipe)(PassArgsAny, int, int, hipStream_t);
+    void (*cg_init1)(PassArgsAny, int, int, hipStream_t);
+    void (*cg_a)(PassArgsAny, int, int, hipStream_t);
+    void (*cg_b)(PassArgsAny, int, int, hipStream_t);
+    void (*resid)(PassArgsAny, int, int, hipStream_t);
+};
+
+template <typename T, int OP, bool JAC, int EPT>
+struct KernelSet {
+    static PassArgs<T> &A(PassArgsAny &a) { return *reinterpret_cast<PassArgs<T> *>(a.bytes); }
+    static void init0_pipe(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_init0<T, OP, JAC, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void init0_cg(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_init0<T, OP, JAC, false, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void init1(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_init1<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void pipe(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void cg_init1(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_cg_init1<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void cg_a(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_cg_a<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void cg_b(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_cg_b<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void resid(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_resid<T, OP, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static Kernels table()
+    { return Kernels{init0_pipe, init0_cg, init1, pipe, cg_init1, cg_a, cg_b, resid}; }
+};
+
+template <typename T, int OP>
+Kernels pick_jac(bool jac)
+{
+    return jac ? KernelSet<T, OP, true, 2>::table() : KernelSet<T, OP, false, 2>::table();
+}
+
+template <typename T>
+Kernels pick_op(int op, bool jac)
+{
+    switch (op) {
+    case PCG_OP_STENCIL2D5: return pick_jac<T, OP_2D5>(jac);
+    case PCG_OP_STENCIL3D7: return pick_jac<T, OP_3D7>(jac);
+    default: return pick_jac<T, OP_CSR>(jac);
+    }
+}
+
+Kernels pick(int prec, int op, bool jac)
+{
+    return prec == PCG_FP64 ? pick_op<double>(op, jac) : pick_op<float>(op, jac);
+}
+
+}  // namespace
+
+// --------------------------------------------------------------- solver
+
+struct pcg_solver_ {
+    pcg_operator op;
+    pcg_options opt;
+    hipStream_t stream;      // the caller's stream: all work goes here
+    hipStream_t cap_stream;  // private stream used only to capture the graph
+    char *ws;
+    size_t ws_bytes;
+    Layout L;
+    LaunchShape sh;
+    Kernels kern;
+    double sigma;            // shift in use (0 for CG / p-CG)
+    double dinv_s;           // stencil Jacobi scalar
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    DevState *pinned = nullptr;  // 2 host slots for polled status
+    hipEvent_t ev_begin[2] = {nullptr, nullptr};
+    hipEvent_t ev_end[2] = {nullptr, nullptr};
+    hipEvent_t ev_copy[2] = {nullptr, nullptr};
+    const double *graph_b = nullptr;  // b and x baked into the captured graph
+    double *graph_x = nullptr;
+
+    DevState *state(int k) { return reinterpret_cast<DevState *>(ws + L.state) + k; }
+    double *part(int k) { return reinterpret_cast<double *>(ws + L.part[k]); }
+    template <typename T> T *vec(int k) { return L.vec[k] == SIZE_MAX ? nullptr : reinterpret_cast<T *>(ws + L.vec[k]); }
+
+    // Arguments of the pass at parity `par` (reads slot par, writes 1 - par).
+    PassArgsAny args(int par, const double *b, double *x, int i0 = 0, int w_par = -1);
+    pcg_status run_init(const double *b, double *x, int i0);
+    pcg_status run_true_residual(const double *b, const double *x, double *res2, double *b2 = nullptr);
+    pcg_status launch_iterations(const double *b, double *x);
+};
+
+PassArgsAny pcg_solver_::args(int par, const double *b, double *x, int i0, int w_par)
+{
+    PassArgsAny any{};
+    auto fill = [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        PassArgs<T> &a = *reinterpret_cast<PassArgs<T> *>(any.bytes);
+        a.A = make_opdev<T>(&op);
+        a.dinv = L.dinv == SIZE_MAX ? nullptr : reinterpret_cast<const T *>(ws + L.dinv);
+        a.dinv_s = dinv_s;
+        a.b = b;
+        a.x = x;
+        a.r = vec<T>(V_R);
+        a.u = vec<T>(V_U);
+        const int wp = w_par < 0 ? par : w_par;
+        a.w_in = vec<T>(wp ? V_W1 : V_W0);
+        a.w_out = vec<T>(wp ? V_W0 : V_W1);
+        a.z = vec<T>(V_Z);
+        a.q = vec<T>(V_Q);
+        a.s = vec<T>(V_S);
+        a.t = vec<T>(V_T);
+        a.p = vec<T>(V_P);
+        a.part_in = part(par);
+        a.part_out = part(1 - par);
+        a.nparts = sh.grid;
+        a.ntiles = sh.ntiles;
+        a.st_in = state(par);
+        a.st_out = state(1 - par);
+        a.hist = opt.history_cap > 0 ? reinterpret_cast<double *>(ws + L.hist) : nullptr;
+        a.hist_cap = opt.history_cap;
+        a.max_iter = opt.max_iter;
+        a.sigma = sigma;
+        a.rtol = opt.rtol;
+        a.i0 = i0;
+        a.xcd_map = sh.xcd_map;
+    };
+    if (opt.prec == PCG_FP64) fill((double *)nullptr);
+    else fill((float *)nullptr);
+    return any;
+}
+
+// K iterations: pipelined = K passes, CG = 2K passes.  Pass k reads slot
+// k % 2.  The w (pipelined) or p (CG) buffers flip once per iteration.
+static void enqueue_iterations(pcg_solver_ *s, hipStream_t st, const double *b, double *x)
+{
+    const int K = s->sh.K;
+    if (s->opt.method == PCG_CG) {
+        for (int it = 0; it < K; ++it) {
+            // pass A: state slot 0 -> 1, p[it%2] -> p[1-it%2]; pass B: slot 1 -> 0
+            s->kern.cg_a(s->args(0, b, x, 0, it & 1), s->sh.grid, s->sh.block, st);
+            s->kern.cg_b(s->args(1, b, x, 0, it & 1), s->sh.grid, s->sh.block, st);
+        }
+    } else {
+        for (int k = 0; k < K; ++k) s->kern.pipe(s->args(k & 1, b, x), s->sh.grid, s->sh.block, st);
+    }
+}
+
+pcg_status pcg_solver_::run_init(const double *b, double *x, int i0)
+{
+    // init0 writes partials to slot 1; init1 reads slot 1 and writes state 0,
+    // partials 0 and w[0] (pipelined).
+    if (opt.method == PCG_CG) {
+        kern.init0_cg(args(0, b, x, i0), sh.grid, sh.block, stream);
+        kern.cg_init1(args(1, b, x, i0), sh.grid, sh.block, stream);
+    } else {
+        kern.init0_pipe(args(0, b, x, i0), sh.grid, sh.block, stream);
+        // w_par = 1 makes w_out = w[0]
+        kern.init1(args(1, b, x, i0, 1), sh.grid, sh.block, stream);
+    }
+    HIPCHK(hipGetLastError());
+    return PCG_OK;
+}
+
+// ||b - A x||^2 and ||b||^2 (binary64): partials into slot 1 (free between
+// iteration launches), summed into the true_res2 / spare[0] fields of state 0.
+pcg_status pcg_solver_::run_true_residual(const double *b, const double *x, double *res2, double *b2)
+{
+    kern.resid(args(0, b, const_cast<double *>(x)), sh.grid, sh.block, stream);
+    hipLaunchKernelGGL(k_reduce_true, dim3(1), dim3(1024), 0, stream, part(1), sh.grid, state(0));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&pinned[0], state(0), sizeof(DevState), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    *res2 = pinned[0].true_res2;
+    if (b2) *b2 = pinned[0].spare[0];
+    return PCG_OK;
+}
+
+// ------------------------------------------------------------- C ABI
+
+extern "C" pcg_status pcg_workspace_size(const pcg_operator *op, const pcg_options *opt, size_t *bytes)
+{
+    if (!bytes) return invalid("bytes is null");
+    pcg_status st = validate_options(opt);
+    if (st) return st;
+    if ((st = validate_operator(op, opt->prec))) return st;
+    *bytes = layout(op, opt, choose_shape(op, opt), nullptr);
+    return PCG_OK;
+}
+
+static double default_sigma(const pcg_operator *op, const pcg_options *opt, const double *gersh_host)
+{
+    if (opt->method != PCG_PIPE_SHIFT) return 0.0;
+    if (!std::isnan(opt->sigma)) return opt->sigma;
+    if (op->kind != PCG_OP_CSR) {
+        // Dirichlet grid Laplacian: lambda_min + lambda_max = 2 (diag + shift)
+        // (cos(j pi/(N+1)) runs symmetrically about 0), so the spectrum
+        // midpoint of A is diag + shift and that of A M^-1 with the constant
+        // Jacobi diagonal is 1.
+        return opt->pc == PCG_PC_JACOBI ? 1.0 : op->diag + op->shift;
+    }
+    return 0.5 * (gersh_host[0] + gersh_host[1]);
+}
+
+extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const pcg_options *opt, void *workspace,
+                                 size_t bytes, void *hip_stream)
+{
+    if (!out) return invalid("solver out-pointer is null");
+    *out = nullptr;
+    pcg_status st = validate_options(opt);
+    if (st) return st;
+    if ((st = validate_operator(op, opt->prec))) return st;
+    if (!workspace || !aligned(workspace, 256)) return invalid("workspace must be non-null and 256-byte aligned");
+    const LaunchShape sh = choose_shape(op, opt);
+    Layout L;
+    const size_t need = layout(op, opt, sh, &L);
+    if (bytes < need) return invalid("workspace too small");
+
+    pcg_solver_ *s = new pcg_solver_();
+    s->op = *op;
+    if (s->op.kind != PCG_OP_STENCIL3D7) s->op.nz = 1;
+    s->opt = *opt;
+    s->stream = (hipStream_t)hip_stream;
+    s->ws = (char *)workspace;
+    s->ws_bytes = bytes;
+    s->L = L;
+    s->sh = sh;
+    s->kern = pick(opt->prec, op->kind, opt->pc == PCG_PC_JACOBI);
+    const double centre = op->diag + op->shift;
+    s->dinv_s = 1.0;
+    if (opt->pc == PCG_PC_JACOBI && op->kind != PCG_OP_CSR)
+        s->dinv_s = opt->prec == PCG_FP64 ? 1.0 / centre : (double)(float)(1.0 / centre);
+
+    auto fail = [&](pcg_status e) {
+        pcg_destroy(s);
+        return e;
+    };
+    hipError_t he;
+    if ((he = hipHostMalloc((void **)&s->pinned, 2 * sizeof(DevState), hipHostMallocDefault)) != hipSuccess)
+        return fail(hip_fail(he, "hipHostMalloc"));
+    for (int k = 0; k < 2; ++k) {
+        if ((he = hipEventCreate(&s->ev_begin[k])) != hipSuccess) return fail(hip_fail(he, "hipEventCreate"));
+        if ((he = hipEventCreate(&s->ev_end[k])) != hipSuccess) return fail(hip_fail(he, "hipEventCreate"));
+        if ((he = hipEventCreateWithFlags(&s->ev_copy[k], hipEventDisableTiming)) != hipSuccess)
+            return fail(hip_fail(he, "hipEventCreate"));
+    }
+
+    double gersh[2] = {0.0, 0.0};
+    if (op->kind == PCG_OP_CSR) {
+        // validate the CSR structure on the device before any pass reads it
+        int *flag = reinterpret_cast<int *>(s->ws + L.flag);
+        if ((he = hipMemsetAsync(flag, 0, sizeof(int), s->stream)) != hipSuccess) return fail(hip_fail(he, "memset"));
+        const int need_diag = opt->pc == PCG_PC_JACOBI;
+        if (opt->prec == PCG_FP64)
+            hipLaunchKernelGGL(k_csr_check<double>, dim3(kGershBlocks), dim3(256), 0, s->stream,
+                               make_opdev<double>(op), need_diag, op->nnz, flag);
+        else
+            hipLaunchKernelGGL(k_csr_check<float>, dim3(kGershBlocks), dim3(256), 0, s->stream,
+                               make_opdev<float>(op), need_diag, op->nnz, flag);
+        int bad = 0;
+        if ((he = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
+            return fail(hip_fail(he, "copy"));
+        if ((he = hipStreamSynchronize(s->stream)) != hipSuccess) return fail(hip_fail(he, "sync"));
+        if (bad) return fail(invalid("CSR structure invalid (row_ptr, col_idx or missing diagonal)"));
+        if (opt->pc == PCG_PC_JACOBI) {
+            const int g = (int)((op->n + 255) / 256);
+            if (opt->prec == PCG_FP64)
+                hipLaunchKernelGGL(k_jacobi<double>, dim3(g), dim3(256), 0, s->stream, make_opdev<double>(op),
+                                   reinterpret_cast<double *>(s->ws + L.dinv));
+            else
+                hipLaunchKernelGGL(k_jacobi<float>, dim3(g), dim3(256), 0, s->stream, make_opdev<float>(op),
+                                   reinterpret_cast<float *>(s->ws + L.dinv));
+        }
+        if (opt->method == PCG_PIPE_SHIFT && std::isnan(opt->sigma)) {
+            double *gb = reinterpret_cast<double *>(s->ws + L.gersh);
+            if (opt->prec == PCG_FP64)
+                hipLaunchKernelGGL(k_gershgorin<double>, dim3(kGershBlocks), dim3(256), 0, s->stream,
+                                   make_opdev<double>(op), need_diag, gb);
+            else
+                hipLaunchKernelGGL(k_gershgorin<float>, dim3(kGershBlocks), dim3(256), 0, s->stream,
+                                   make_opdev<float>(op), need_diag, gb);
+            std::vector<double> h(2 * kGershBlocks);
+            if ((he = hipMemcpyAsync(h.data(), gb, h.size() * 8, hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
+                return fail(hip_fail(he, "copy"));
+            if ((he = hipStreamSynchronize(s->stream)) != hipSuccess) return fail(hip_fail(he, "sync"));
+            gersh[0] = INFINITY;
+            gersh[1] = -INFINITY;
+            for (int k = 0; k < kGershBlocks; ++k) {
+                gersh[0] = std::fmin(gersh[0], h[2 * k]);
+                gersh[1] = std::fmax(gersh[1], h[2 * k + 1]);
+            }
+            gersh[0] = std::fmax(gersh[0], 0.0);  // SPD: the spectrum is positive
+        }
+        if ((he = hipGetLastError()) != hipSuccess) return fail(hip_fail(he, "setup kernels"));
+    }
+    s->sigma = default_sigma(op, opt, gersh);
+    *out = s;
+    return PCG_OK;
+}
+
+extern "C" pcg_status pcg_destroy(pcg_solver s)
+{
+    if (!s) return PCG_OK;
+    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    for (int k = 0; k < 2; ++k) {
+        if (s->ev_begin[k]) (void)hipEventDestroy(s->ev_begin[k]);
+        if (s->ev_end[k]) (void)hipEventDestroy(s->ev_end[k]);
+        if (s->ev_copy[k]) (void)hipEventDestroy(s->ev_copy[k]);
+    }
+    if (s->pinned) (void)hipHostFree(s->pinned);
+    delete s;
+    return PCG_OK;
+}
+
+// Build (once per (b, x) pair) the graph of K iteration passes.
+static pcg_status ensure_graph(pcg_solver_ *s, const double *b, double *x)
+{
+    if (s->gexec && s->graph_b == b && s->graph_x == x) return PCG_OK;
+    if (s->gexec) {
+        (void)hipGraphExecDestroy(s->gexec);
+        s->gexec = nullptr;
+    }
+    if (s->graph) {
+        (void)hipGraphDestroy(s->graph);
+        s->graph = nullptr;
+    }
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    enqueue_iterations(s, cs, b, x);
+    e = hipStreamEndCapture(cs, &s->graph);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    HIPCHK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+    s->graph_b = b;
+    s->graph_x = x;
+    return PCG_OK;
+}
+
+pcg_status pcg_solver_::launch_iterations(const double *b, double *x)
+{
+    if (opt.use_graph) {
+        pcg_status st = ensure_graph(this, b, x);
+        if (st) return st;
+        HIPCHK(hipGraphLaunch(gexec, stream));
+    } else {
+        enqueue_iterations(this, stream, b, x);
+        HIPCHK(hipGetLastError());
+    }
+    return PCG_OK;
+}
+
+extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_result *res)
+{
+    if (!s) return PCG_ERR_STATE;
+    if (!b || !x || !res) return invalid("b, x and result must be non-null");
+    if (!aligned(b, 8) || !aligned(x, 8)) return invalid("b and x must be 8-byte aligned");
+    if (b == x) return invalid("x must not alias b");
+    const auto t0 = std::chrono::steady_clock::now();
+    std::memset(res, 0, sizeof(*res));
+    res->sigma = s->sigma;
+    res->rel_res_true = std::nan("");
+    const pcg_options &o = s->opt;
+    if (o.history_cap > 0)
+        HIPCHK(hipMemsetAsync(s->ws + s->L.hist, 0xff, size_t(o.history_cap) * PCG_HISTORY_FIELDS * 8, s->stream));
+
+    pcg_status st = s->run_init(b, x, 0);
+    if (st) return st;
+
+    DevState S{};
+    int launches = 0;
+    double kernel_ms = 0.0;
+    int replacements = 0;
+    auto add_time = [&](int slot) -> pcg_status {
+        if (o.timing) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, s->ev_begin[slot], s->ev_end[slot]));
+            kernel_ms += ms;
+        }
+        return PCG_OK;
+    };
+    for (;;) {
+        // Two launches in flight: issue launch g, then wait for the status
+        // copied after launch g - 1, so the host round trip overlaps work.
+        bool done = false;
+        for (int g = 0; !done; ++g) {
+            const int slot = g & 1;
+            if (o.timing) HIPCHK(hipEventRecord(s->ev_begin[slot], s->stream));
+            if ((st = s->launch_iterations(b, x))) return st;
+            if (o.timing) HIPCHK(hipEventRecord(s->ev_end[slot], s->stream));
+            HIPCHK(hipMemcpyAsync(&s->pinned[slot], s->state(0), sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
+            HIPCHK(hipEventRecord(s->ev_copy[slot], s->stream));
+            ++launches;
+            if (g > 0) {
+                const int prev = slot ^ 1;
+                HIPCHK(hipEventSynchronize(s->ev_copy[prev]));
+                if ((st = add_time(prev))) return st;
+                done = s->pinned[prev].status != RUNNING;
+            }
+            if (done) {
+                HIPCHK(hipEventSynchronize(s->ev_copy[slot]));
+                if ((st = add_time(slot))) return st;
+                S = s->pinned[slot];
+            }
+        }
+        if (S.status == ST_NONFINITE && !(std::isfinite(S.bnorm2))) {
+            res->status = PCG_NONFINITE;
+            res->iterations = 0;
+            return PCG_ERR_NONFINITE;
+        }
+        if (S.status == ST_CONVERGED && o.true_residual_check && replacements < o.replace_max &&
+            S.iter < o.max_iter) {
+            double tr2 = 0.0;
+            if ((st = s->run_true_residual(b, x, &tr2))) return st;
+            // restart from x when the explicit residual misses the tolerance
+            if (std::sqrt(tr2) > o.rtol * std::sqrt(S.bnorm2)) {
+                ++replacements;
+                if ((st = s->run_init(b, x, S.iter))) return st;
+                continue;
+            }
+        }
+        break;
+    }
+    double tr2 = 0.0;
+    if ((st = s->run_true_residual(b, x, &tr2))) return st;
+    const double bn = std::sqrt(S.bnorm2);
+    res->status = S.status;
+    res->iterations = S.iter;
+    res->replacements = replacements;
+    res->launches = launches;
+    res->rel_res_recursive = bn > 0 ? std::sqrt(S.rho) / bn : std::sqrt(S.rho);
+    res->rel_res_true = bn > 0 ? std::sqrt(tr2) / bn : std::sqrt(tr2);
+    res->iter_kernel_ms = kernel_ms;
+    res->iter_passes = (o.method == PCG_CG ? 2 : 1) * S.iter;
+    if (o.history_cap > 0)
+        HIPCHK(hipMemcpyAsync(o.history, s->ws + s->L.hist, size_t(o.history_cap) * PCG_HISTORY_FIELDS * 8,
+                              hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return PCG_OK;
+}
+
+extern "C" pcg_status pcg_true_residual(pcg_solver s, const double *b, const double *x, double *rel)
+{
+    if (!s) return PCG_ERR_STATE;
+    if (!b || !x || !rel) return invalid("b, x and rel must be non-null");
+    double tr2 = 0.0, b2 = 0.0;
+    pcg_status st = s->run_true_residual(b, x, &tr2, &b2);
+    if (st) return st;
+    *rel = b2 > 0 ? std::sqrt(tr2) / std::sqrt(b2) : std::sqrt(tr2);
+    return PCG_OK;
+}

@@ -1,0 +1,319 @@
+"""ctypes binding of libpcg (``include/pcg.h``): argument marshalling only.
+
+Every function named ``pcg_*`` here calls the C entry point of the same name;
+all solver work runs in the library's HIP kernels.  PyTorch supplies device
+memory (workspace, operator arrays) and the HIP stream.  Importing this
+module does not need a GPU; loading the library fails loudly when it has not
+been built (``python -m paper_1706_05988_amd.build``) -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import re
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpcg.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "pcg.h")
+
+PCG_OK, PCG_PENDING = 0, 1
+PCG_ERR_INVALID, PCG_ERR_NONFINITE, PCG_ERR_HIP, PCG_ERR_BUDGET, PCG_ERR_STATE = -1, -2, -3, -4, -5
+PCG_CONVERGED, PCG_MAX_ITER, PCG_BREAKDOWN, PCG_NONFINITE = 0, 1, 2, 3
+PCG_CG, PCG_PIPE, PCG_PIPE_SHIFT = 0, 1, 2
+PCG_OP_STENCIL2D5, PCG_OP_STENCIL3D7, PCG_OP_CSR = 0, 1, 2
+PCG_PC_NONE, PCG_PC_JACOBI = 0, 1
+PCG_FP64, PCG_FP32_STREAM = 0, 1
+PCG_HISTORY_FIELDS = 5
+
+METHOD = {"cg": PCG_CG, "pipe": PCG_PIPE, "pipe_shift": PCG_PIPE_SHIFT}
+OUTCOME = {PCG_CONVERGED: "converged", PCG_MAX_ITER: "max_iter", PCG_BREAKDOWN: "breakdown",
+           PCG_NONFINITE: "nonfinite"}
+OPKIND = {"2d5": PCG_OP_STENCIL2D5, "3d7": PCG_OP_STENCIL3D7, "csr": PCG_OP_CSR}
+
+
+class pcg_operator(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("n", C.c_int64), ("diag", C.c_double), ("offdiag", C.c_double), ("shift", C.c_double),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("vals", C.c_void_p),
+                ("nnz", C.c_int64)]
+
+
+class pcg_options(C.Structure):
+    _fields_ = [("method", C.c_int32), ("pc", C.c_int32), ("prec", C.c_int32), ("max_iter", C.c_int32),
+                ("sigma", C.c_double), ("rtol", C.c_double), ("true_residual_check", C.c_int32),
+                ("replace_max", C.c_int32), ("iters_per_launch", C.c_int32), ("history_cap", C.c_int32),
+                ("history", C.c_void_p), ("block_size", C.c_int32), ("grid_blocks", C.c_int32),
+                ("timing", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 4)]
+
+
+class pcg_result(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("replacements", C.c_int32),
+                ("launches", C.c_int32), ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double),
+                ("seconds", C.c_double), ("iter_kernel_ms", C.c_double), ("iter_passes", C.c_int32),
+                ("reserved", C.c_int32), ("sigma", C.c_double)]
+
+
+class PcgError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {pcg_status_str(status)} ({status}) {pcg_last_error()}")
+        self.status = status
+
+
+_lib = None
+
+_SIGS = {
+    "pcg_default_options": (C.c_int32, [C.POINTER(pcg_options)]),
+    "pcg_workspace_size": (C.c_int32, [C.POINTER(pcg_operator), C.POINTER(pcg_options), C.POINTER(C.c_size_t)]),
+    "pcg_create": (C.c_int32, [C.POINTER(C.c_void_p), C.POINTER(pcg_operator), C.POINTER(pcg_options),
+                               C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pcg_solve": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(pcg_result)]),
+    "pcg_true_residual": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "pcg_destroy": (C.c_int32, [C.c_void_p]),
+    "pcg_batch_workspace_size": (C.c_int32, [C.c_int32, C.POINTER(pcg_operator), C.POINTER(pcg_options),
+                                             C.POINTER(C.c_size_t)]),
+    "pcg_batch_solve": (C.c_int32, [C.c_int32, C.POINTER(pcg_operator), C.POINTER(pcg_options),
+                                    C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(pcg_result),
+                                    C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pcg_server_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]),
+    "pcg_submit": (C.c_int32, [C.c_void_p, C.POINTER(pcg_operator), C.POINTER(pcg_options), C.c_void_p,
+                               C.c_void_p, C.POINTER(C.c_uint64)]),
+    "pcg_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(pcg_result)]),
+    "pcg_wait": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(pcg_result)]),
+    "pcg_server_destroy": (C.c_int32, [C.c_void_p]),
+    "pcg_status_str": (C.c_char_p, [C.c_int32]),
+    "pcg_last_error": (C.c_char_p, []),
+}
+
+
+def lib() -> C.CDLL:
+    """Load libpcg.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built: run python -m paper_1706_05988_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def header_functions() -> list:
+    """Names of the functions include/pcg.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _check(st: int, what: str):
+    if st != PCG_OK:
+        raise PcgError(st, what)
+
+
+def pcg_status_str(st: int) -> str:
+    return lib().pcg_status_str(st).decode()
+
+
+def pcg_last_error() -> str:
+    return lib().pcg_last_error().decode()
+
+
+def pcg_default_options() -> pcg_options:
+    o = pcg_options()
+    _check(lib().pcg_default_options(C.byref(o)), "pcg_default_options")
+    return o
+
+
+def pcg_workspace_size(op: pcg_operator, opt: pcg_options) -> int:
+    n = C.c_size_t()
+    _check(lib().pcg_workspace_size(C.byref(op), C.byref(opt), C.byref(n)), "pcg_workspace_size")
+    return n.value
+
+
+def pcg_create(op: pcg_operator, opt: pcg_options, workspace: int, nbytes: int, stream: int) -> int:
+    h = C.c_void_p()
+    _check(lib().pcg_create(C.byref(h), C.byref(op), C.byref(opt), workspace, nbytes, stream), "pcg_create")
+    return h.value
+
+
+def pcg_solve(handle: int, b: int, x: int) -> pcg_result:
+    r = pcg_result()
+    _check(lib().pcg_solve(handle, b, x, C.byref(r)), "pcg_solve")
+    return r
+
+
+def pcg_true_residual(handle: int, b: int, x: int) -> float:
+    v = C.c_double()
+    _check(lib().pcg_true_residual(handle, b, x, C.byref(v)), "pcg_true_residual")
+    return v.value
+
+
+def pcg_destroy(handle: int) -> None:
+    _check(lib().pcg_destroy(handle), "pcg_destroy")
+
+
+def pcg_batch_workspace_size(ops: Sequence[pcg_operator], opts: Sequence[pcg_options]) -> int:
+    k = len(ops)
+    OA, PA = (pcg_operator * k)(*ops), (pcg_options * k)(*opts)
+    n = C.c_size_t()
+    _check(lib().pcg_batch_workspace_size(k, OA, PA, C.byref(n)), "pcg_batch_workspace_size")
+    return n.value
+
+
+def pcg_batch_solve(ops, opts, b_ptrs, x_ptrs, workspace: int, nbytes: int, stream: int) -> list:
+    k = len(ops)
+    OA, PA = (pcg_operator * k)(*ops), (pcg_options * k)(*opts)
+    BA, XA = (C.c_void_p * k)(*b_ptrs), (C.c_void_p * k)(*x_ptrs)
+    R = (pcg_result * k)()
+    _check(lib().pcg_batch_solve(k, OA, PA, BA, XA, R, workspace, nbytes, stream), "pcg_batch_solve")
+    return list(R)
+
+
+def pcg_server_create(arena: int, nbytes: int, max_slots: int, stream: int) -> int:
+    h = C.c_void_p()
+    _check(lib().pcg_server_create(C.byref(h), arena, nbytes, max_slots, stream), "pcg_server_create")
+    return h.value
+
+
+def pcg_submit(server: int, op: pcg_operator, opt: pcg_options, b: int, x: int) -> int:
+    t = C.c_uint64()
+    _check(lib().pcg_submit(server, C.byref(op), C.byref(opt), b, x, C.byref(t)), "pcg_submit")
+    return t.value
+
+
+def pcg_poll(server: int, ticket: int):
+    r = pcg_result()
+    st = lib().pcg_poll(server, ticket, C.byref(r))
+    if st == PCG_PENDING:
+        return None
+    _check(st, "pcg_poll")
+    return r
+
+
+def pcg_wait(server: int, ticket: int) -> pcg_result:
+    r = pcg_result()
+    _check(lib().pcg_wait(server, ticket, C.byref(r)), "pcg_wait")
+    return r
+
+
+def pcg_server_destroy(server: int) -> None:
+    _check(lib().pcg_server_destroy(server), "pcg_server_destroy")
+
+
+# ------------------------------------------------------------------ helpers
+# (marshalling: operator description -> device arrays, tensors -> pointers)
+
+def _torch():
+    import torch
+    return torch
+
+
+def current_stream_handle(device=None) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class DeviceOperator:
+    """Device copies of an operator description (an object with ``kind``,
+    ``n``, ``nx``, ``ny``, ``nz``, ``diag``, ``off``, ``shift`` and, for CSR,
+    ``row_ptr``, ``col``, ``val``) and its ``pcg_operator`` struct."""
+
+    def __init__(self, op, prec: int = PCG_FP64, device="cuda"):
+        torch = _torch()
+        self.keep = []
+        s = pcg_operator()
+        s.kind = OPKIND[op.kind]
+        s.n = int(op.n)
+        if op.kind == "csr":
+            vdt = torch.float64 if prec == PCG_FP64 else torch.float32
+            rp = torch.as_tensor(op.row_ptr).to(torch.int32).to(device)
+            ci = torch.as_tensor(op.col).to(torch.int32).to(device)
+            va = torch.as_tensor(op.val).to(vdt).to(device)
+            self.keep += [rp, ci, va]
+            s.row_ptr, s.col_idx, s.vals = rp.data_ptr(), ci.data_ptr(), va.data_ptr()
+            s.nnz = int(op.row_ptr[-1])
+            s.nx, s.ny, s.nz = 0, 0, 1
+        else:
+            s.nx, s.ny = int(op.nx), int(op.ny)
+            s.nz = int(op.nz) if op.kind == "3d7" else 1
+            s.diag, s.offdiag, s.shift = float(op.diag), float(op.off), float(op.shift)
+        self.struct = s
+
+
+def make_options(method: str = "pipe_shift", jacobi: bool = False, fp32: bool = False,
+                 sigma: Optional[float] = None, rtol: float = 1e-10, max_iter: int = 1000,
+                 true_residual_check: bool = True, replace_max: int = 4, iters_per_launch: int = 0,
+                 history_cap: int = 0, block_size: int = 0, grid_blocks: int = 0, timing: bool = False,
+                 use_graph: bool = True) -> pcg_options:
+    o = pcg_default_options()
+    o.method = METHOD[method]
+    o.pc = PCG_PC_JACOBI if jacobi else PCG_PC_NONE
+    o.prec = PCG_FP32_STREAM if fp32 else PCG_FP64
+    o.sigma = math.nan if sigma is None else float(sigma)
+    o.rtol = float(rtol)
+    o.max_iter = int(max_iter)
+    o.true_residual_check = int(bool(true_residual_check))
+    o.replace_max = int(replace_max)
+    o.iters_per_launch = int(iters_per_launch)
+    o.history_cap = int(history_cap)
+    o.block_size = int(block_size)
+    o.grid_blocks = int(grid_blocks)
+    o.timing = int(bool(timing))
+    o.use_graph = int(bool(use_graph))
+    return o
+
+
+class Solver:
+    """One solver: device operator, torch-allocated workspace, C handle."""
+
+    def __init__(self, op, options: pcg_options, device="cuda", stream: Optional[int] = None):
+        import numpy as np
+        torch = _torch()
+        self.dev = DeviceOperator(op, options.prec, device)
+        self.opt = options
+        self.hist = None
+        if options.history_cap > 0:
+            self.hist = np.full((options.history_cap, PCG_HISTORY_FIELDS), np.nan)
+            self.opt.history = self.hist.ctypes.data
+        self.nbytes = pcg_workspace_size(self.dev.struct, self.opt)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        self.stream = current_stream_handle() if stream is None else stream
+        self.handle = pcg_create(self.dev.struct, self.opt, self.ws_ptr, self.nbytes, self.stream)
+
+    def solve(self, b, x) -> dict:
+        r = pcg_solve(self.handle, b.data_ptr(), x.data_ptr())
+        return result_dict(r, self.hist)
+
+    def true_residual(self, b, x) -> float:
+        return pcg_true_residual(self.handle, b.data_ptr(), x.data_ptr())
+
+    def close(self):
+        if self.handle:
+            pcg_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def result_dict(r: pcg_result, hist=None) -> dict:
+    d = dict(status=OUTCOME.get(r.status, str(r.status)), iterations=r.iterations,
+             replacements=r.replacements, launches=r.launches, rel_res_recursive=r.rel_res_recursive,
+             rel_res_true=r.rel_res_true, seconds=r.seconds, iter_kernel_ms=r.iter_kernel_ms,
+             iter_passes=r.iter_passes, sigma=r.sigma)
+    if hist is not None:
+        k = r.iterations + 1
+        d.update(res=hist[:k, 0].copy(), alpha=hist[:k, 1].copy(), beta=hist[:k, 2].copy(),
+                 gamma=hist[:k, 3].copy(), delta=hist[:k, 4].copy())
+    return d

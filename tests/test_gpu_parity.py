@@ -1,0 +1,299 @@
+"""Parity of the HIP path (through the C ABI) with the oracle.
+
+Tolerances (FP64 form): the recursive residual history sqrt(rho_i)/||b||
+matches the oracle's to 1e-10 relative over the first 50 iterations, and the
+final explicit residual ||b - A x||/||b|| matches to 1e-12 absolute (p-CG: a
+10x band, its stagnation level being rounding-determined).  The GPU sums
+dot products in a different order and contracts multiply-adds, so iterates
+differ from the oracle's by rounding only.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import problems
+
+pytestmark = pytest.mark.gpu
+
+METHODS = ["cg", "pipe", "pipe_shift"]
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def gpu_solve(torch, p, method, jacobi=None, fp32=False, sigma=None, rtol=None, max_iter=None,
+              hist=True, x0=None, **kw):
+    from paper_1706_05988_amd import pcg as P
+    jac = p.jacobi if jacobi is None else jacobi
+    if sigma is None:
+        sigma = p.sigma if method == "pipe_shift" else 0.0
+    mi = p.max_iter if max_iter is None else max_iter
+    opt = P.make_options(method=method, jacobi=jac, fp32=fp32, sigma=sigma,
+                         rtol=p.rtol if rtol is None else rtol, max_iter=mi,
+                         history_cap=(mi + 2) if hist else 0, **kw)
+    s = P.Solver(p.op, opt)
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.from_numpy(p.x0 if x0 is None else x0).clone().cuda()
+    r = s.solve(b, x)
+    torch.cuda.synchronize()
+    r["x"] = x.cpu().numpy()
+    s.close()
+    return r
+
+
+def oracle_solve(p, method, jacobi=None, fp32=False, sigma=None, rtol=None, max_iter=None, **kw):
+    return oracle.solve(p.op, p.b, p.x0, method=method,
+                        sigma=(p.sigma if method == "pipe_shift" else 0.0) if sigma is None else sigma,
+                        rtol=p.rtol if rtol is None else rtol,
+                        max_iter=p.max_iter if max_iter is None else max_iter,
+                        jacobi=p.jacobi if jacobi is None else jacobi, fp32_storage=fp32, threads=8, **kw)
+
+
+def check_history(g, o, upto=50, rtol=1e-10):
+    k = min(upto, len(o["res"]) - 1, len(g["res"]) - 1)
+    np.testing.assert_allclose(g["res"][: k + 1], o["res"][: k + 1], rtol=rtol)
+    # alpha and beta of the same iterations
+    np.testing.assert_allclose(g["alpha"][:k], o["alpha"][:k], rtol=rtol)
+    np.testing.assert_allclose(g["beta"][1:k], o["beta"][1:k], rtol=rtol)
+
+
+# ---------------------------------------------------------------- config 1
+
+@pytest.mark.parametrize("method", METHODS)
+def test_config1_poisson2d_history_and_final_residual(torch, method):
+    p = problems.poisson2d_manufactured(100)
+    g = gpu_solve(torch, p, method, true_residual_check=False)
+    o = oracle_solve(p, method)
+    assert g["status"] == o["status"] == "converged"
+    assert abs(g["iterations"] - o["iterations"]) <= 1
+    check_history(g, o)
+    if method == "pipe":
+        assert g["rel_res_true"] <= 10 * o["rel_res_true"]
+    else:
+        assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-12
+        assert g["rel_res_true"] <= 1e-12
+    np.testing.assert_allclose(g["x"], p.x_true, rtol=1e-8)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_lapl200_table1_on_gpu(torch, method):
+    """500 iterations of lapl200 (Table 1): CG and p-CG-sh reach ~6.8e-12;
+    p-CG stagnates orders of magnitude higher."""
+    p = problems.lapl200()
+    g = gpu_solve(torch, p, method, true_residual_check=False, rtol=1e-30, max_iter=500)
+    o = oracle_solve(p, method, rtol=1e-30, max_iter=500, ignore_breakdown=True)
+    check_history(g, o)
+    if method == "pipe":
+        # the GPU stops at the first non-positive alpha, as the library must
+        assert g["rel_res_true"] > 1e-10
+    else:
+        assert g["iterations"] == 500
+        assert g["rel_res_true"] <= 3 * 6.8e-12
+        assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-11
+
+
+# ---------------------------------------------------------------- 3-D, Jacobi, ragged
+
+@pytest.mark.parametrize("method", METHODS)
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_3d_ragged_grid(torch, method, jacobi):
+    op = problems.stencil3d(37, 41, 43)  # 65,231 unknowns: many tiles and a ragged tail
+    rng = np.random.default_rng(11)
+    xt = rng.uniform(-1, 1, op.n)
+    b = problems.to_scipy(op) @ xt
+    p = problems.Problem("ragged3d", op, b, np.zeros(op.n), xt, jacobi=jacobi,
+                         sigma=1.0 if jacobi else 6.0, rtol=1e-10, max_iter=2000)
+    g = gpu_solve(torch, p, method, true_residual_check=False)
+    o = oracle_solve(p, method)
+    assert g["status"] == o["status"] == "converged"
+    assert abs(g["iterations"] - o["iterations"]) <= 1
+    check_history(g, o)
+    assert abs(g["rel_res_true"] - o["rel_res_true"]) <= (1e-11 if method == "pipe" else 1e-12)
+
+
+# ---------------------------------------------------------------- CSR
+
+@pytest.mark.parametrize("method", METHODS)
+def test_csr_anisotropic_jacobi(torch, method):
+    p = problems.anisotropic_csr(48, seed=5)
+    p.rtol, p.max_iter = 1e-10, 5000
+    g = gpu_solve(torch, p, method, true_residual_check=False)
+    o = oracle_solve(p, method)
+    assert g["status"] == o["status"]
+    assert abs(g["iterations"] - o["iterations"]) <= 2
+    check_history(g, o, upto=30, rtol=1e-9)
+    assert g["rel_res_true"] <= max(10 * o["rel_res_true"], 1e-9)
+
+
+@pytest.mark.parametrize("method", ["cg", "pipe_shift"])
+def test_csr_banded(torch, method):
+    p = problems.banded_csr(5003, seed=3)
+    p.rtol = 1e-10
+    g = gpu_solve(torch, p, method, true_residual_check=False)
+    o = oracle_solve(p, method)
+    assert g["status"] == o["status"] == "converged"
+    check_history(g, o)
+    assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-12
+
+
+def test_csr_default_sigma_gershgorin(torch):
+    """sigma = NaN picks the Gershgorin midpoint of spec(M^-1 A): 1 for a
+    Jacobi-scaled row-diagonally-dominant matrix (discs centred at 1)."""
+    p = problems.banded_csr(2000, seed=1)
+    g = gpu_solve(torch, p, "pipe_shift", sigma=math.nan)
+    A = problems.to_scipy(p.op)
+    d = A.diagonal()
+    R = np.asarray(abs(A).sum(axis=1)).ravel() - d
+    lo, hi = max(0.0, ((d - R) / d).min()), ((d + R) / d).max()
+    assert g["sigma"] == pytest.approx(0.5 * (lo + hi), rel=1e-12)
+    assert g["status"] == "converged"
+
+
+# ---------------------------------------------------------------- FP32-stream form
+
+@pytest.mark.parametrize("method", ["cg", "pipe_shift"])
+def test_fp32_stream_attainable_accuracy(torch, method):
+    """FP32-stream form lands within 10x of the oracle's attainable accuracy
+    in the same form (binary32 storage emulation, same sigma)."""
+    p = problems.poisson2d_manufactured(64)
+    g = gpu_solve(torch, p, method, fp32=True, rtol=1e-30, max_iter=400, true_residual_check=False)
+    o = oracle_solve(p, method, fp32=True, rtol=1e-30, max_iter=400, ignore_breakdown=True)
+    assert g["rel_res_true"] <= 10 * o["rel_res_true"]
+    # early history agrees to binary32 resolution
+    np.testing.assert_allclose(g["res"][:15], o["res"][:15], rtol=1e-4)
+
+
+@pytest.mark.parametrize("method", ["cg", "pipe_shift"])
+def test_fp32_stream_with_restarts_reaches_fp64_tolerance(torch, method):
+    """x and b stay binary64; restarting from x when the explicit residual
+    misses the tolerance reaches 1e-10 in the FP32-stream form."""
+    p = problems.poisson3d(40, seed=2)
+    g = gpu_solve(torch, p, method, fp32=True, rtol=1e-10, max_iter=4000, replace_max=10, hist=False)
+    assert g["status"] == "converged"
+    assert g["replacements"] >= 1
+    assert g["rel_res_true"] <= 1e-10
+
+
+def test_fp32_stream_csr(torch):
+    p = problems.anisotropic_csr(48, seed=5)
+    g = gpu_solve(torch, p, "pipe_shift", fp32=True, rtol=1e-30, max_iter=600, true_residual_check=False)
+    o = oracle_solve(p, "pipe_shift", fp32=True, rtol=1e-30, max_iter=600, ignore_breakdown=True)
+    assert g["rel_res_true"] <= 10 * o["rel_res_true"]
+
+
+# ---------------------------------------------------------------- identities, determinism
+
+def test_shift_zero_equals_pipe_bitwise_on_gpu(torch):
+    p = problems.poisson3d(30, seed=1)
+    a = gpu_solve(torch, p, "pipe", max_iter=80)
+    b = gpu_solve(torch, p, "pipe_shift", sigma=0.0, max_iter=80)
+    assert np.array_equal(a["x"], b["x"])
+    assert np.array_equal(a["res"], b["res"], equal_nan=True)
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_deterministic_across_runs_graph_and_K(torch, method):
+    p = problems.poisson3d(33, seed=4)
+    base = gpu_solve(torch, p, method, max_iter=120, rtol=1e-30)
+    again = gpu_solve(torch, p, method, max_iter=120, rtol=1e-30)
+    nograph = gpu_solve(torch, p, method, max_iter=120, rtol=1e-30, use_graph=False)
+    k6 = gpu_solve(torch, p, method, max_iter=120, rtol=1e-30, iters_per_launch=6)
+    for other in (again, nograph, k6):
+        assert np.array_equal(base["x"], other["x"])
+        assert np.array_equal(base["res"], other["res"], equal_nan=True)
+
+
+# ---------------------------------------------------------------- edge cases
+
+@pytest.mark.parametrize("shape", [(1, 1), (2, 1), (1, 7), (3, 5)])
+@pytest.mark.parametrize("method", METHODS)
+def test_tiny_grids(torch, method, shape):
+    op = problems.stencil2d(*shape)
+    b = np.arange(1, op.n + 1, dtype=np.float64)
+    p = problems.Problem("tiny", op, b, np.zeros(op.n), None, sigma=4.0, rtol=1e-12, max_iter=50)
+    g = gpu_solve(torch, p, method)
+    o = oracle_solve(p, method)
+    assert g["status"] == "converged"
+    xs = np.linalg.solve(problems.to_scipy(op).toarray(), b)
+    np.testing.assert_allclose(g["x"], xs, rtol=1e-11)
+    assert abs(g["iterations"] - o["iterations"]) <= 1
+
+
+def test_zero_iterations_and_exact_start(torch):
+    p = problems.poisson2d_manufactured(20)
+    g = gpu_solve(torch, p, "pipe_shift", max_iter=0)
+    assert g["status"] == "max_iter" and g["iterations"] == 0
+    assert np.array_equal(g["x"], p.x0)
+    g = gpu_solve(torch, p, "pipe_shift", x0=p.x_true.copy())
+    assert g["status"] == "converged" and g["iterations"] == 0
+
+
+def test_nonfinite_rhs_is_an_error(torch):
+    from paper_1706_05988_amd import pcg as P
+    p = problems.poisson2d_manufactured(20)
+    p.b = p.b.copy()
+    p.b[7] = np.inf
+    with pytest.raises(P.PcgError) as ei:
+        gpu_solve(torch, p, "pipe_shift")
+    assert ei.value.status == P.PCG_ERR_NONFINITE
+
+
+def test_breakdown_on_indefinite_csr(torch):
+    n = 40
+    vals = np.linspace(-1.0, 3.0, n)
+    vals[np.abs(vals) < 1e-3] = 0.5
+    op = problems.csr_operator(np.arange(n + 1), np.arange(n, dtype=np.int32), vals)
+    p = problems.Problem("indef", op, np.ones(n), np.zeros(n), None, sigma=1.0, rtol=1e-12, max_iter=100)
+    for m in METHODS:
+        assert gpu_solve(torch, p, m)["status"] == "breakdown"
+
+
+def test_invalid_csr_rejected_before_any_pass(torch):
+    from paper_1706_05988_amd import pcg as P
+    n = 10
+    op = problems.csr_operator(np.arange(n + 1), np.arange(n, dtype=np.int32), np.ones(n))
+    op.col = op.col.copy()
+    op.col[3] = 99  # out of range
+    opt = P.make_options(method="pipe_shift", sigma=1.0)
+    with pytest.raises(P.PcgError) as ei:
+        P.Solver(op, opt)
+    assert ei.value.status == P.PCG_ERR_INVALID
+
+
+def test_workspace_too_small_rejected(torch):
+    from paper_1706_05988_amd import pcg as P
+    op = problems.stencil2d(30)
+    dev = P.DeviceOperator(op)
+    opt = P.make_options()
+    need = P.pcg_workspace_size(dev.struct, opt)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.PcgError) as ei:
+        P.pcg_create(dev.struct, opt, ws.data_ptr(), need - 256, 0)
+    assert ei.value.status == P.PCG_ERR_INVALID
+
+
+# ---------------------------------------------------------------- full size (configs 2, 3)
+
+def test_config2_full_size_sampled(torch):
+    """3-D Poisson 256^3, Jacobi, sigma = 1, FP64, in the benchmark's launch
+    configuration: the first iterations' residual history matches the oracle
+    on the same input, and the solve reaches a true residual <= 1e-10."""
+    p = problems.poisson3d(256, seed=0)
+    o = oracle_solve(p, "pipe_shift", max_iter=3, rtol=1e-30)
+    g3 = gpu_solve(torch, p, "pipe_shift", max_iter=3, rtol=1e-30, true_residual_check=False)
+    np.testing.assert_allclose(g3["res"][:4], o["res"][:4], rtol=1e-12)
+    np.testing.assert_allclose(g3["alpha"][:3], o["alpha"][:3], rtol=1e-12)
+    # x after 3 iterations at sampled unknowns
+    idx = np.random.default_rng(0).integers(0, p.op.n, 1000)
+    np.testing.assert_allclose(g3["x"][idx], o["x"][idx], rtol=1e-11, atol=1e-14)
+    g = gpu_solve(torch, p, "pipe_shift", hist=False)
+    assert g["status"] == "converged"
+    assert g["rel_res_true"] <= 1e-10
+    err = np.abs(g["x"] - p.x_true).max()
+    assert err < 1e-6
