@@ -32,6 +32,16 @@ sys.path.insert(0, ROOT)
 METRIC = "shifted p-CG iters/s + HBM GB/s (3D Poisson 256^3); batched solves/s, p99"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pipe_3d7_jacobi_fp64_256.json")
+# the rocprofv3 runs whose output --ingest-profile summarises (run from the repo root)
+PROFILE_COMMANDS = [
+    "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- "
+    "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch --output-format csv -- "
+    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --max-iter 24 --calib-copy",
+    "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write -o write --output-format csv -- "
+    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --max-iter 24 --calib-copy",
+    "python3 bench.py --ingest-profile gpurun_out/prof_trace gpurun_out/prof_fetch gpurun_out/prof_write",
+]
 KERNEL_SOURCES = ["paper_1706_05988_amd/csrc/pcg_kernels.h", "paper_1706_05988_amd/csrc/pcg_device.h"]
 
 
@@ -80,6 +90,79 @@ def cpu_baseline(p, iters: int) -> dict:
                       f"(timing includes the oracle's init and final explicit residual), {dt:.1f} s"}
 
 
+def _csv(path_glob):
+    import csv
+    import glob
+    files = sorted(glob.glob(path_glob, recursive=True))
+    if not files:
+        raise FileNotFoundError(path_glob)
+    with open(files[0]) as f:
+        return list(csv.DictReader(f))
+
+
+def ingest_profiles(trace_dir: str, fetch_dir: str, write_dir: str, kernel: str, name: str, commands: list):
+    """Summarise rocprofv3 output of this benchmark into profiles/:
+    the kernel's duration statistics (--kernel-trace --stats) and its HBM
+    traffic per launch from FETCH_SIZE / WRITE_SIZE (KiB per dispatch), each
+    scaled by what the same counter reads for the 1 GiB device copy that the
+    --calib-copy run performs first.  Working passes are the dispatches whose
+    value is above half the maximum (passes after convergence return early)."""
+    GiB_KiB = 2 ** 20
+    stats = _csv(os.path.join(trace_dir, "**", "*kernel_stats.csv"))
+    trace = _csv(os.path.join(trace_dir, "**", "*kernel_trace.csv"))
+    krow = [r for r in stats if kernel in r["Name"]]
+    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace if kernel in r["Kernel_Name"]]
+    work = [d for d in durs if d > 0.5 * max(durs)]
+    out = {"kernel": kernel, "kernel_source_hash": kernel_source_hash(), "commands": commands}
+    out["rocprof_calls"] = int(krow[0]["Calls"]) if krow else len(durs)
+    out["rocprof_average_ns_all"] = float(krow[0]["AverageNs"]) if krow else sum(durs) / len(durs)
+    out["working_passes"] = len(work)
+    out["average_ns_working"] = sum(work) / len(work)
+
+    def counter(dirname, cname):
+        rows = _csv(os.path.join(dirname, "**", "*counter_collection.csv"))
+        copy = [float(r["Counter_Value"]) for r in rows
+                if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == cname]
+        kv = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"] and r["Counter_Name"] == cname]
+        kv = [v for v in kv if v > 0.5 * max(kv)]
+        calib = max(copy)  # the 1 GiB device-to-device copies
+        return sum(kv) / len(kv), calib, GiB_KiB / calib
+
+    f_kib, f_cal, f_scale = counter(fetch_dir, "FETCH_SIZE")
+    w_kib, w_cal, w_scale = counter(write_dir, "WRITE_SIZE")
+    out.update(fetch_kib_per_launch=f_kib, write_kib_per_launch=w_kib,
+               copy_1GiB_fetch_kib=f_cal, copy_1GiB_write_kib=w_cal,
+               fetch_scale=f_scale, write_scale=w_scale,
+               bytes_per_launch=(f_kib * f_scale + w_kib * w_scale) * 1024)
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    with open(os.path.join(ROOT, "profiles", f"traffic_{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]
+    lines = [f"# rocprofv3 summary: {kernel} ({name})", "",
+             "Commands (from the repository root on the GPU box):", ""]
+    lines += [f"    {c}" for c in commands]
+    lines += ["", "## Kernel statistics (--kernel-trace --stats)", "",
+              "| kernel | calls | average ns | % |", "|---|---|---|---|"]
+    lines += [f"| {r['Name'][:70]} | {r['Calls']} | {float(r['AverageNs']):.0f} | {float(r['Percentage']):.2f} |"
+              for r in top]
+    bpp = bytes_per_unknown("pipe_shift", True, False) * 256 ** 3
+    lines += ["", f"Working passes of the fused kernel: {len(work)}, average {out['average_ns_working']:.0f} ns "
+              f"(all {out['rocprof_calls']} dispatches incl. early-returning ones after convergence: "
+              f"{out['rocprof_average_ns_all']:.0f} ns).",
+              f"Algorithmic bytes per pass: {bpp} -> {bpp / out['average_ns_working']:.0f} GB/s "
+              f"({bpp / out['average_ns_working'] / HBM_PEAK_GBS * 100:.1f}% of 8 TB/s).", "",
+              "## HBM traffic (--pmc FETCH_SIZE, --pmc WRITE_SIZE; KiB per dispatch)", "",
+              f"- calibration: a 1 GiB device copy reads as FETCH_SIZE {f_cal:.0f} KiB and WRITE_SIZE {w_cal:.0f} KiB "
+              f"-> scale factors {f_scale:.4f} (fetch), {w_scale:.4f} (write)",
+              f"- fused pass: FETCH_SIZE {f_kib:.0f} KiB, WRITE_SIZE {w_kib:.0f} KiB per working dispatch",
+              f"- scaled traffic per pass: {out['bytes_per_launch']:.4g} B "
+              f"(algorithmic {bpp:.4g} B, ratio {out['bytes_per_launch'] / bpp:.4f})",
+              f"- kernel source hash: {out['kernel_source_hash']}", ""]
+    with open(os.path.join(ROOT, "profiles", f"{name}.md"), "w") as f:
+        f.write("\n".join(lines))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -89,11 +172,26 @@ def main():
     ap.add_argument("--fp32", action="store_true", help="FP32-stream form instead of binary64")
     ap.add_argument("--method", default="pipe_shift", choices=["cg", "pipe", "pipe_shift"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=12)
+    ap.add_argument("--cpu-iters", type=int, default=240)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--K", type=int, default=0)
+    ap.add_argument("--variant", type=int, default=0)
+    ap.add_argument("--max-iter", type=int, default=5000,
+                    help="iteration cap (profiling runs use a short fixed count)")
+    ap.add_argument("--ingest-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="summarise rocprofv3 output of this benchmark into profiles/ and exit")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (torch) 3 times: the reference kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
+
+    if args.ingest_profile:
+        t, fdir, wdir = args.ingest_profile
+        res = ingest_profiles(t, fdir, wdir, "k_pipe<double, 1, true", "pipe_3d7_jacobi_fp64_256",
+                              commands=PROFILE_COMMANDS)
+        print(json.dumps(res, indent=1))
+        return
 
     if args.gpus != 1:
         print(f"bench.py: this build runs the solver on one GPU; --gpus {args.gpus} is not supported "
@@ -108,14 +206,25 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.calib_copy:
+        src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] calibration: 3 copies of 1 GiB (2^27 doubles) done", flush=True)
+        del src, dst
     t_gen = time.perf_counter()
     p = problems.poisson3d(args.N, seed=0, jacobi=True)
     n = p.op.n
     print(f"[bench] generated 3-D Poisson {args.N}^3 (n={n}) in {time.perf_counter() - t_gen:.1f} s", flush=True)
     sigma = p.sigma if args.method == "pipe_shift" else 0.0
-    opt = P.make_options(method=args.method, jacobi=True, fp32=args.fp32, sigma=sigma, rtol=1e-10,
-                         max_iter=5000, true_residual_check=True, replace_max=8, timing=True,
-                         block_size=args.block, grid_blocks=args.grid, iters_per_launch=args.K)
+    fixed = args.max_iter != 5000
+    opt = P.make_options(method=args.method, jacobi=True, fp32=args.fp32, sigma=sigma,
+                         rtol=1e-30 if fixed else 1e-10, max_iter=args.max_iter,
+                         true_residual_check=not fixed, replace_max=8, timing=True,
+                         block_size=args.block, grid_blocks=args.grid, iters_per_launch=args.K,
+                         variant=args.variant)
     stream = torch.cuda.current_stream(dev).cuda_stream
     solver = P.Solver(p.op, opt, stream=stream)
     b = torch.from_numpy(p.b).to(dev)
@@ -148,7 +257,7 @@ def main():
     avg_pass_s = kernel_ms / 1e3 / max(1, passes)
     achieved = per_pass_bytes / avg_pass_s / 1e9
     traffic = traffic_entry() if (args.N == 256 and args.method == "pipe_shift" and not args.fp32
-                                  and not args.block and not args.grid) else None
+                                  and not args.block and not args.grid and not args.variant) else None
     out = {
         "metric": METRIC,
         "value": iters / elapsed,

@@ -121,13 +121,25 @@ typedef struct {
     double *history;            /* HOST buffer of history_cap * PCG_HISTORY_FIELDS doubles,
                                    row i = iteration i (NaN for alpha.. when not computed);
                                    filled when pcg_solve returns                            */
-    int32_t block_size;         /* threads per block (64..1024, multiple of 64); 0 = tuned   */
+    int32_t block_size;         /* threads per block (64..256, multiple of 64); 0 = tuned    */
     int32_t grid_blocks;        /* blocks of the persistent grid; 0 = tuned                 */
     int32_t timing;             /* 1: time the iteration graph launches with HIP events     */
     int32_t use_graph;          /* 1: capture the K passes of a launch in a HIP graph
                                    (pcg_default_options' choice); 0: launch them one by one  */
-    int32_t reserved[4];
+    int32_t variant;            /* 0: the tuned kernel variant; else PCG_VAR_SET | bits below */
+    int32_t reserved[3];
 } pcg_options;
+
+/* Kernel variant bits (pcg_options.variant).  Every variant performs the same
+ * per-unknown arithmetic; they differ in how unknowns map to threads, so the
+ * order in which dot-product partials are accumulated (and hence the last
+ * bits of gamma, delta, rho) may differ between variants.  Each variant is
+ * deterministic run to run. */
+#define PCG_VAR_SET      0x01   /* use the bits below instead of the tuned default      */
+#define PCG_VAR_XCD_MAP  0x02   /* tiles in 8 contiguous slabs, one per XCD             */
+#define PCG_VAR_NT       0x04   /* non-temporal hint on the once-touched streams        */
+#define PCG_VAR_EPT1     0x10   /* 1 unknown per thread per tile (default 2)            */
+#define PCG_VAR_EPT4     0x20   /* 4 unknowns per thread per tile                       */
 
 typedef struct {
     int32_t status;             /* PCG_CONVERGED .. PCG_NONFINITE                         */

@@ -17,8 +17,8 @@ constexpr int kDefaultBlocksPerCU = 4;   // persistent grid: 4 blocks of 256 thr
 constexpr int kMaxGrid = 16384;
 constexpr int kGershBlocks = 256;
 
-// vector slots of the workspace
-enum VecSlot { V_R = 0, V_U, V_W0, V_W1, V_Z, V_Q, V_S, V_T, V_P };
+// vector slots of the blocked workspace region
+enum VecSlot { V_X = 0, V_R, V_U, V_W0, V_W1, V_Z, V_Q, V_S, V_T, V_P, V_COUNT };
 
 struct LaunchShape {
     int block;    // threads per block
@@ -26,14 +26,16 @@ struct LaunchShape {
     int ntiles;   // tiles of block * ept unknowns
     int grid;     // persistent blocks
     int xcd_map;  // XCD-slab tile order on/off
+    int nt;       // non-temporal streams on/off
     int K;        // iterations per graph launch
 };
 
 // byte offsets into the caller's workspace (SIZE_MAX: absent)
 struct Layout {
-    static constexpr int kVecs = 9;
     size_t state, part[2], gersh, flag, hist, dinv;
-    size_t vec[kVecs];
+    size_t blk;                  // blocked vectors: ceil(n / 512) tiles of tile_bytes
+    uint32_t tile_bytes;
+    uint32_t slot_off[V_COUNT];  // byte offset of each slot in a tile (kNoSlot: absent)
     size_t total;
 };
 

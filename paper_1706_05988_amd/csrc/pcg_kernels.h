@@ -6,39 +6,51 @@
 // stored value is rounded once at its store and all later uses see the
 // stored bits).
 //
+// The solver's vectors (an internal copy of x, and r, u, w, w', z, q, s, t,
+// p) are blocked in the workspace (see slot_ptr in pcg_device.h); b and the
+// caller's x are plain vectors.
+//
 // Passes of shifted pipelined CG (Alg. 3; Alg. 2 is sigma = 0):
-//   k_init0    r_0 := b - A x_0, u_0 := M^-1 r_0; block partials of (b, b)
+//   k_copy_x   caller x -> internal x (solve start) and back (solve end)
+//   k_init0    r_0 := b - A x_0, u_0 := M^-1 r_0; clears z, q, s, t, p;
+//              block partials of (b, b)
 //   k_init1    head: ||b||^2 (stage 2);  w_0 := A u_0 - sigma r_0;
 //              partials of gamma_0, delta_0, rho_0
 //   k_pipe     one whole iteration i (see the kernel)
 // Passes of classic CG (Alg. 1, two fused passes per iteration):
-//   k_init0    r_0 := b - A x_0; partials of (b, b)
+//   k_init0    r_0 := b - A x_0; clears p_{-1}; partials of (b, b)
 //   k_cg_init1 head: ||b||^2; partials of gamma_0 = (r_0, u_0), rho_0
 //   k_cg_a     head: gamma_i, rho_i -> stop test, beta_i; p_i := u_i + beta_i p_{i-1}
 //              (recomputed at the stencil neighbours), s_i := A p_i; partial (s_i, p_i)
 //   k_cg_b     head: (s_i, p_i) -> alpha_i; x, r updates, u := M^-1 r;
 //              partials of gamma_{i+1}, rho_{i+1}
 // Support:
-//   k_resid    partials of ||b - A x||^2 (explicit residual, binary64)
-//   k_reduce   one block: stage 2 of a partial array into the state
+//   k_resid    partials of ||b - A x||^2 and ||b||^2 (explicit residual, binary64)
+//   k_reduce_true  one block: stage 2 of the residual partials into the state
 //   k_jacobi   dinv_k := 1 / a_kk for CSR operators
+//   k_gershgorin, k_csr_check   CSR set-up
 #pragma once
 
 #include "pcg_device.h"
 
 namespace pcg {
 
+// init-0 clear mask
+enum ClearBits : uint32_t { CLR_Z = 1, CLR_Q = 2, CLR_S = 4, CLR_T = 8, CLR_P = 16, CLR_WIN = 32 };
+
 template <typename T>
 struct PassArgs {
     OpDev<T> A;
-    const T *dinv;        // CSR Jacobi diagonal inverse (nullptr otherwise)
+    const T *dinv;        // CSR Jacobi diagonal inverse (plain vector, nullptr otherwise)
     double dinv_s;        // stencil Jacobi: 1/(diag + shift); 1.0 without preconditioner
-    const double *b;
-    double *x;
-    T *r, *u;             // u == r without preconditioner
-    const T *w_in;        // w_i (or, in CG, p_{i-1})
-    T *w_out;             // w_{i+1} (or, in CG, p_i)
-    T *z, *q, *s, *t, *p; // q == s and p == t without preconditioner
+    const double *b;      // caller's right-hand side (plain)
+    double *x_user;       // caller's x (plain): copy in / out, or the explicit residual's x
+    char *blk;            // blocked vectors
+    uint32_t tile_bytes;  // bytes of one 512-unknown tile of all slots
+    // byte offsets of the slots within a tile (kNoSlot: absent).  Without a
+    // preconditioner u, q, p are r, s, t (the kernels never touch off_u..).
+    uint32_t off_x, off_r, off_u, off_win, off_wout, off_z, off_q, off_s, off_t, off_p;
+    uint32_t clear;       // init 0: ClearBits of the slots to set to zero
     const double *part_in;
     double *part_out;
     int32_t nparts;       // partials in part_in (= grid size of the previous pass)
@@ -52,7 +64,32 @@ struct PassArgs {
     double rtol;
     int32_t i0;           // init passes: iteration count at which the (re)start happens
     int32_t xcd_map;
+    int32_t copy_out;     // k_copy_x: 0 = caller -> internal, 1 = internal -> caller
+    int32_t x_plain;      // k_resid: read the caller's x instead of the internal one
 };
+
+template <typename V, typename T>
+__device__ __forceinline__ V *vp(const PassArgs<T> &a, uint32_t off, uint32_t e)
+{
+    return slot_ptr<V>(a.blk, a.tile_bytes, off, e);
+}
+
+// Streaming loads / stores.  With NT the accesses carry the non-temporal
+// hint so the once-touched vectors do not evict the stencil operand (w, or p
+// in CG) from the caches.
+template <bool NT, typename V>
+__device__ __forceinline__ double lds(const V *p)
+{
+    if constexpr (NT) return (double)__builtin_nontemporal_load(p);
+    else return (double)*p;
+}
+
+template <bool NT, typename V>
+__device__ __forceinline__ void sts(V *p, double v)
+{
+    if constexpr (NT) __builtin_nontemporal_store((V)v, p);
+    else *p = (V)v;
+}
 
 // M^{-1} applied at index k to the stored value v (binary64 product of the
 // stored diagonal inverse and v).
@@ -81,105 +118,48 @@ __device__ __forceinline__ void write_hist(double *h, int cap, int i, double res
     }
 }
 
-// ----------------------------------------------------------------- init 0
+// The unknowns of one tile handled by this thread: e_j = tile * (B * EPT) +
+// j * B + threadIdx (each access of a wave is one contiguous run).  Lanes
+// past n work on the clamped index n - 1 (loads stay in bounds) and skip
+// their stores and partial sums.
+template <int EPT>
+struct TileIdx {
+    uint32_t e[EPT];
+    bool live[EPT];
+};
 
-// r_0 := b - A x_0 (stored), and for the pipelined methods with a
-// preconditioner u_0 := M^-1 r_0 (stored).  Partials of (b, b).
-template <typename T, int OP, bool JAC, bool STORE_U, int EPT>
-__global__ void __launch_bounds__(1024) k_init0(PassArgs<T> a)
+template <int EPT>
+__device__ __forceinline__ TileIdx<EPT> tile_idx(int tile, uint32_t n)
 {
-    __shared__ double lds[kMaxWaves * kFields];
-    double acc[1] = {0.0};
-    const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    const uint32_t tile_elems = blockDim.x * EPT;
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+    TileIdx<EPT> t;
+    const uint32_t base = (uint32_t)tile * blockDim.x * EPT + threadIdx.x;
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const uint32_t e = (uint32_t)tile * tile_elems + j * blockDim.x + threadIdx.x;
-            if (e < (uint32_t)a.A.n) {
-                const double be = a.b[e];
-                const double ax = apply_row<OP>(a.A, e, [&](uint32_t k) { return a.x[k]; });
-                const double r = rnd<T>(be - ax);
-                a.r[e] = (T)r;
-                if constexpr (STORE_U) a.u[e] = (T)minv<T, JAC, OP>(a, e, r);
-                acc[0] += be * be;
-            }
-        }
+    for (int j = 0; j < EPT; ++j) {
+        const uint32_t e = base + j * blockDim.x;
+        t.live[j] = e < n;
+        t.e[j] = t.live[j] ? e : n - 1;
     }
-    block_sum<1>(acc, lds);
-    store_partial<1>(a.part_out, acc);
+    return t;
 }
 
-// ----------------------------------------------------------------- init 1 (pipelined)
+// Head of an iteration pass of the pipelined methods: stage 2 of the
+// previous pass's partials, the stop test and the scalar recurrences
+// (identical bits in every block), and block 0's state / history record.
+// Returns false when the iteration has ended (or had ended before).
+struct PipeScalars {
+    double alpha, beta;
+};
 
-// head: ||b||^2 from the init-0 partials; w_0 := A u_0 - sigma r_0 into
-// w_out; partials of gamma_0 = (r, u), delta_0 = (w + sigma r, u), rho_0.
-// Block 0 writes the state for iteration i0.
-template <typename T, int OP, bool JAC, int EPT>
-__global__ void __launch_bounds__(1024) k_init1(PassArgs<T> a)
+template <typename T>
+__device__ __forceinline__ bool pipe_head(const PassArgs<T> &a, double *lds_red, PipeScalars &sc)
 {
-    __shared__ double lds[kMaxWaves * kFields];
-    double bb[1];
-    stage2<1>(a.part_in, a.nparts, bb, lds);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        DevState o{};
-        o.bnorm2 = bb[0];
-        o.iter = a.i0;
-        o.i_start = a.i0;
-        o.status = isfinite(bb[0]) ? RUNNING : ST_NONFINITE;
-        o.true_res2 = __builtin_nan("");
-        *a.st_out = o;
-    }
-    const T *u = JAC ? a.u : a.r;
-    double acc[3] = {0.0, 0.0, 0.0};
-    const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    const uint32_t tile_elems = blockDim.x * EPT;
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const uint32_t e = (uint32_t)tile * tile_elems + j * blockDim.x + threadIdx.x;
-            if (e < (uint32_t)a.A.n) {
-                const double au = apply_row<OP>(a.A, e, [&](uint32_t k) { return ld(u, k); });
-                const double r = ld(a.r, e), ue = ld(u, e);
-                const double w = rnd<T>(au - a.sigma * r);
-                a.w_out[e] = (T)w;
-                acc[0] += r * ue;
-                acc[1] += (w + a.sigma * r) * ue;
-                acc[2] += r * r;
-            }
-        }
-    }
-    block_sum<3>(acc, lds);
-    store_partial<3>(a.part_out, acc);
-}
-
-// ----------------------------------------------------------------- p-CG(-sh) iteration
-
-// One iteration i of Alg. 3 as one pass:
-//   head (every block, identical bits): gamma_i, delta_i, rho_i from the
-//     previous pass's partials; stop test sqrt(rho_i) <= rtol ||b||, cap,
-//     breakdown; beta_i = gamma_i / gamma_{i-1},
-//     alpha_i = (delta_i / gamma_i - beta_i / alpha_{i-1})^-1 (i = i_start:
-//     beta = 0, alpha = gamma / delta)
-//   body (per unknown):  m = M^-1 w_i, n = A m (stencil / CSR over m at the
-//     neighbours), then
-//     z := n + beta z   q := m + beta q   s := w + beta s   t := r + beta t
-//     p := u + beta p   x := x + alpha p
-//     r := r - (alpha s + (alpha sigma) t)   u := u - (alpha q + (alpha sigma) p)
-//     w_{i+1} := w - alpha z  (into the other w buffer: neighbours read w_i)
-//   tail: block partials of gamma_{i+1} = (r, u),
-//     delta_{i+1} = (w_{i+1} + sigma r, u), rho_{i+1} = (r, r).
-template <typename T, int OP, bool JAC, int EPT>
-__global__ void __launch_bounds__(1024) k_pipe(PassArgs<T> a)
-{
-    __shared__ double lds[kMaxWaves * kFields];
     const DevState S = *a.st_in;
     if (S.status != RUNNING) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = S;
-        return;
+        return false;
     }
     double tot[3];
-    stage2<3>(a.part_in, a.nparts, tot, lds);
+    stage2<3>(a.part_in, a.nparts, tot, lds_red);
     const double gamma = tot[0], delta = tot[1], rho = tot[2];
     const int i = S.iter;
     int status = RUNNING;
@@ -194,8 +174,8 @@ __global__ void __launch_bounds__(1024) k_pipe(PassArgs<T> a)
         status = ST_BREAKDOWN;
     } else {
         if (i > S.i_start) {
-            beta = gamma / S.gamma_prev;
-            alpha = 1.0 / (delta / gamma - beta / S.alpha_prev);
+            beta = gamma / S.gamma_prev;                             // beta_i
+            alpha = 1.0 / (delta / gamma - beta / S.alpha_prev);     // alpha_i
         } else {
             beta = 0.0;
             alpha = gamma / delta;
@@ -215,76 +195,224 @@ __global__ void __launch_bounds__(1024) k_pipe(PassArgs<T> a)
         write_hist(a.hist, a.hist_cap, i, sqrt(rho / S.bnorm2), alpha, beta, gamma, delta);
         *a.st_out = o;
     }
-    if (status != RUNNING) return;
+    sc.alpha = alpha;
+    sc.beta = beta;
+    return status == RUNNING;
+}
 
-    const bool first = (i == S.i_start);
-    const double sigma = a.sigma, as = alpha * sigma;
-    T *const u = JAC ? a.u : a.r;
-    T *const q = JAC ? a.q : a.s;
-    T *const p = JAC ? a.p : a.t;
-    double acc[3] = {0.0, 0.0, 0.0};
+// ----------------------------------------------------------------- copy x
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kMaxBlock) k_copy_x(PassArgs<T> a)
+{
+    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    const uint32_t tile_elems = blockDim.x * EPT;
     for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            const uint32_t e = (uint32_t)tile * tile_elems + j * blockDim.x + threadIdx.x;
-            if (e >= (uint32_t)a.A.n) continue;
-            // preconditioner and SPMV on the fly: m, n never stored
-            const double we = ld(a.w_in, e);
-            const double me = minv<T, JAC, OP>(a, e, we);
-            const double ne = apply_row<OP>(a.A, e, [&](uint32_t k) { return minv<T, JAC, OP>(a, k, ld(a.w_in, k)); });
-            const double re = ld(a.r, e);
-            const double ue = JAC ? ld(u, e) : re;
-            const double zo = first ? 0.0 : ld(a.z, e);
-            const double so = first ? 0.0 : ld(a.s, e);
-            const double to = first ? 0.0 : ld(a.t, e);
+            if (!ti.live[j]) continue;
+            double *xi = vp<double>(a, a.off_x, ti.e[j]);
+            if (a.copy_out) a.x_user[ti.e[j]] = *xi;
+            else *xi = a.x_user[ti.e[j]];
+        }
+    }
+}
+
+// ----------------------------------------------------------------- init 0
+
+// r_0 := b - A x_0 (stored), and for the pipelined methods with a
+// preconditioner u_0 := M^-1 r_0 (stored).  Clears the slots in a.clear (so
+// the first iteration's beta = 0 terms are exact zeros).  Partials of (b, b).
+template <typename T, int OP, bool JAC, bool STORE_U, int EPT, bool NT>
+__global__ void __launch_bounds__(kMaxBlock) k_init0(PassArgs<T> a)
+{
+    __shared__ double lds_red[kMaxWaves * kFields];
+    double acc[1] = {0.0};
+    const uint32_t n = (uint32_t)a.A.n;
+    const TileRange tr = tile_range(a.ntiles, a.xcd_map);
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
+        double be[EPT], ax[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            be[j] = lds<NT>(a.b + ti.e[j]);
+            ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (!ti.live[j]) continue;
+            const uint32_t e = ti.e[j];
+            const double r = rnd<T>(be[j] - ax[j]);
+            sts<NT>(vp<T>(a, a.off_r, e), r);
+            if constexpr (STORE_U) sts<NT>(vp<T>(a, a.off_u, e), minv<T, JAC, OP>(a, e, r));
+            if (a.clear & CLR_Z) sts<NT>(vp<T>(a, a.off_z, e), 0.0);
+            if (a.clear & CLR_Q) sts<NT>(vp<T>(a, a.off_q, e), 0.0);
+            if (a.clear & CLR_S) sts<NT>(vp<T>(a, a.off_s, e), 0.0);
+            if (a.clear & CLR_T) sts<NT>(vp<T>(a, a.off_t, e), 0.0);
+            if (a.clear & CLR_P) sts<NT>(vp<T>(a, a.off_p, e), 0.0);
+            if (a.clear & CLR_WIN) sts<NT>(vp<T>(a, a.off_win, e), 0.0);
+            acc[0] += be[j] * be[j];
+        }
+    }
+    block_sum<1>(acc, lds_red);
+    store_partial<1>(a.part_out, acc);
+}
+
+// ----------------------------------------------------------------- init 1 (pipelined)
+
+// head: ||b||^2 from the init-0 partials; w_0 := A u_0 - sigma r_0 into
+// w_out; partials of gamma_0 = (r, u), delta_0 = (w + sigma r, u), rho_0.
+// Block 0 writes the state for iteration i0.
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+__global__ void __launch_bounds__(kMaxBlock) k_init1(PassArgs<T> a)
+{
+    __shared__ double lds_red[kMaxWaves * kFields];
+    double bb[1];
+    stage2<1>(a.part_in, a.nparts, bb, lds_red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        DevState o{};
+        o.bnorm2 = bb[0];
+        o.iter = a.i0;
+        o.i_start = a.i0;
+        o.status = isfinite(bb[0]) ? RUNNING : ST_NONFINITE;
+        o.true_res2 = __builtin_nan("");
+        *a.st_out = o;
+    }
+    const uint32_t off_u = JAC ? a.off_u : a.off_r;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const uint32_t n = (uint32_t)a.A.n;
+    const TileRange tr = tile_range(a.ntiles, a.xcd_map);
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
+        double au[EPT], re[EPT], ue[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            au[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return ld(vp<T>(a, off_u, k), 0); });
+            re[j] = lds<NT>(vp<T>(a, a.off_r, ti.e[j]));
+            ue[j] = JAC ? ld(vp<T>(a, off_u, ti.e[j]), 0) : re[j];
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (!ti.live[j]) continue;
+            const double w = rnd<T>(au[j] - a.sigma * re[j]);
+            sts<NT>(vp<T>(a, a.off_wout, ti.e[j]), w);
+            acc[0] += re[j] * ue[j];
+            acc[1] += (w + a.sigma * re[j]) * ue[j];
+            acc[2] += re[j] * re[j];
+        }
+    }
+    block_sum<3>(acc, lds_red);
+    store_partial<3>(a.part_out, acc);
+}
+
+// ----------------------------------------------------------------- p-CG(-sh) iteration
+
+// One iteration i of Alg. 3 as one pass:
+//   head (every block, identical bits): gamma_i, delta_i, rho_i from the
+//     previous pass's partials; stop test sqrt(rho_i) <= rtol ||b||, cap,
+//     breakdown; beta_i = gamma_i / gamma_{i-1},
+//     alpha_i = (delta_i / gamma_i - beta_i / alpha_{i-1})^-1 (i = i_start:
+//     beta = 0, alpha = gamma / delta)
+//   body (per unknown):  m = M^-1 w_i, n = A m (stencil / CSR over m at the
+//     neighbours), then
+//     z := n + beta z   q := m + beta q   s := w + beta s   t := r + beta t
+//     p := u + beta p   x := x + alpha p
+//     r := r - (alpha s + (alpha sigma) t)   u := u - (alpha q + (alpha sigma) p)
+//     w_{i+1} := w - alpha z  (into the other w slot: neighbours read w_i)
+//   tail: block partials of gamma_{i+1} = (r, u),
+//     delta_{i+1} = (w_{i+1} + sigma r, u), rho_{i+1} = (r, r).
+// All loads of a tile are issued before any of its stores.
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+__global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
+{
+    __shared__ double lds_red[kMaxWaves * kFields];
+    PipeScalars sc;
+    if (!pipe_head(a, lds_red, sc)) return;
+    const double alpha = sc.alpha, beta = sc.beta;
+    const double sigma = a.sigma, as = alpha * sigma;
+    const uint32_t off_u = JAC ? a.off_u : a.off_r;
+    const uint32_t off_q = JAC ? a.off_q : a.off_s;
+    const uint32_t off_p = JAC ? a.off_p : a.off_t;
+    double acc[3] = {0.0, 0.0, 0.0};
+    const uint32_t n = (uint32_t)a.A.n;
+    const TileRange tr = tile_range(a.ntiles, a.xcd_map);
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
+        double ne[EPT], we[EPT], re[EPT], ue[EPT], zo[EPT], so[EPT], to[EPT], qo[EPT], po[EPT], xo[EPT];
+        // loads: the stencil / CSR operand w_i (cached), then the streams
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            const uint32_t e = ti.e[j];
+            we[j] = ld(vp<T>(a, a.off_win, e), 0);
+            ne[j] = apply_row<OP>(a.A, e, [&](uint32_t k) {
+                return minv<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_win, k), 0));
+            });
+            re[j] = lds<NT>(vp<T>(a, a.off_r, e));
+            zo[j] = lds<NT>(vp<T>(a, a.off_z, e));
+            so[j] = lds<NT>(vp<T>(a, a.off_s, e));
+            to[j] = lds<NT>(vp<T>(a, a.off_t, e));
+            xo[j] = lds<NT>(vp<double>(a, a.off_x, e));
+            if constexpr (JAC) {
+                ue[j] = lds<NT>(vp<T>(a, off_u, e));
+                qo[j] = lds<NT>(vp<T>(a, off_q, e));
+                po[j] = lds<NT>(vp<T>(a, off_p, e));
+            } else {
+                ue[j] = re[j];
+                qo[j] = so[j];
+                po[j] = to[j];
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (!ti.live[j]) continue;
+            const uint32_t e = ti.e[j];
+            const double me = minv<T, JAC, OP>(a, e, we[j]);
             // beta-recurrences
-            const double z = rnd<T>(ne + beta * zo);
-            const double s = rnd<T>(we + beta * so);
-            const double t = rnd<T>(re + beta * to);
-            a.z[e] = (T)z;
-            a.s[e] = (T)s;
-            a.t[e] = (T)t;
+            const double z = rnd<T>(ne[j] + beta * zo[j]);
+            const double s = rnd<T>(we[j] + beta * so[j]);
+            const double t = rnd<T>(re[j] + beta * to[j]);
             double qv = s, pv = t;
             if constexpr (JAC) {
-                const double qo = first ? 0.0 : ld(q, e);
-                const double po = first ? 0.0 : ld(p, e);
-                qv = rnd<T>(me + beta * qo);
-                pv = rnd<T>(ue + beta * po);
-                q[e] = (T)qv;
-                p[e] = (T)pv;
+                qv = rnd<T>(me + beta * qo[j]);
+                pv = rnd<T>(ue[j] + beta * po[j]);
             }
-            // alpha-recurrences with the shift terms grouped first
-            a.x[e] = a.x[e] + alpha * pv;
-            const double rn = rnd<T>(re - (alpha * s + as * t));
-            a.r[e] = (T)rn;
+            // alpha-recurrences, the shift terms grouped first
+            const double xn = xo[j] + alpha * pv;
+            const double rn = rnd<T>(re[j] - (alpha * s + as * t));
             double un = rn;
+            if constexpr (JAC) un = rnd<T>(ue[j] - (alpha * qv + as * pv));
+            const double wn = rnd<T>(we[j] - alpha * z);
+            sts<NT>(vp<T>(a, a.off_z, e), z);
+            sts<NT>(vp<T>(a, a.off_s, e), s);
+            sts<NT>(vp<T>(a, a.off_t, e), t);
             if constexpr (JAC) {
-                un = rnd<T>(ue - (alpha * qv + as * pv));
-                u[e] = (T)un;
+                sts<NT>(vp<T>(a, off_q, e), qv);
+                sts<NT>(vp<T>(a, off_p, e), pv);
+                sts<NT>(vp<T>(a, off_u, e), un);
             }
-            const double wn = rnd<T>(we - alpha * z);
-            a.w_out[e] = (T)wn;
+            sts<NT>(vp<double>(a, a.off_x, e), xn);
+            sts<NT>(vp<T>(a, a.off_r, e), rn);
+            sts<NT>(vp<T>(a, a.off_wout, e), wn);
             // next iteration's dot products
             acc[0] += rn * un;
             acc[1] += (wn + sigma * rn) * un;
             acc[2] += rn * rn;
         }
     }
-    block_sum<3>(acc, lds);
+    block_sum<3>(acc, lds_red);
     store_partial<3>(a.part_out, acc);
 }
 
 // ----------------------------------------------------------------- classic CG
 
 // head: ||b||^2; partials of gamma_0 = (r_0, M^-1 r_0) and rho_0.
-template <typename T, int OP, bool JAC, int EPT>
-__global__ void __launch_bounds__(1024) k_cg_init1(PassArgs<T> a)
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+__global__ void __launch_bounds__(kMaxBlock) k_cg_init1(PassArgs<T> a)
 {
-    __shared__ double lds[kMaxWaves * kFields];
+    __shared__ double lds_red[kMaxWaves * kFields];
     double bb[1];
-    stage2<1>(a.part_in, a.nparts, bb, lds);
+    stage2<1>(a.part_in, a.nparts, bb, lds_red);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         DevState o{};
         o.bnorm2 = bb[0];
@@ -295,36 +423,37 @@ __global__ void __launch_bounds__(1024) k_cg_init1(PassArgs<T> a)
         *a.st_out = o;
     }
     double acc[2] = {0.0, 0.0};
+    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    const uint32_t tile_elems = blockDim.x * EPT;
     for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
+        double re[EPT];
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) re[j] = lds<NT>(vp<T>(a, a.off_r, ti.e[j]));
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            const uint32_t e = (uint32_t)tile * tile_elems + j * blockDim.x + threadIdx.x;
-            if (e < (uint32_t)a.A.n) {
-                const double r = ld(a.r, e);
-                const double u = rnd<T>(minv<T, JAC, OP>(a, e, r));
-                acc[0] += r * u;
-                acc[1] += r * r;
-            }
+            if (!ti.live[j]) continue;
+            const double u = rnd<T>(minv<T, JAC, OP>(a, ti.e[j], re[j]));
+            acc[0] += re[j] * u;
+            acc[1] += re[j] * re[j];
         }
     }
-    block_sum<2>(acc, lds);
+    block_sum<2>(acc, lds_red);
     store_partial<2>(a.part_out, acc);
 }
 
 // Pass A of CG iteration i.  w_in = p_{i-1}, w_out = p_i.
-template <typename T, int OP, bool JAC, int EPT>
-__global__ void __launch_bounds__(1024) k_cg_a(PassArgs<T> a)
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+__global__ void __launch_bounds__(kMaxBlock) k_cg_a(PassArgs<T> a)
 {
-    __shared__ double lds[kMaxWaves * kFields];
+    __shared__ double lds_red[kMaxWaves * kFields];
     const DevState S = *a.st_in;
     if (S.status != RUNNING) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = S;
         return;
     }
     double tot[2];
-    stage2<2>(a.part_in, a.nparts, tot, lds);
+    stage2<2>(a.part_in, a.nparts, tot, lds_red);
     const double gamma = tot[0], rho = tot[1];
     const int i = S.iter;
     int status = RUNNING;
@@ -351,43 +480,48 @@ __global__ void __launch_bounds__(1024) k_cg_a(PassArgs<T> a)
     }
     if (status != RUNNING) return;
 
-    const bool first = (i == S.i_start);
     // p_i at index k, recomputed identically wherever it is needed
+    // (p_{-1} = 0 after the init, so the first iteration needs no branch)
     auto pnew = [&](uint32_t k) {
-        const double uk = rnd<T>(minv<T, JAC, OP>(a, k, ld(a.r, k)));
-        return rnd<T>(uk + beta * (first ? 0.0 : ld(a.w_in, k)));
+        const double uk = rnd<T>(minv<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_r, k), 0)));
+        return rnd<T>(uk + beta * ld(vp<T>(a, a.off_win, k), 0));
     };
     double acc[1] = {0.0};
+    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    const uint32_t tile_elems = blockDim.x * EPT;
     for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
+        double pe[EPT], se[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            const uint32_t e = (uint32_t)tile * tile_elems + j * blockDim.x + threadIdx.x;
-            if (e >= (uint32_t)a.A.n) continue;
-            const double pe = pnew(e);
-            const double se = rnd<T>(apply_row<OP>(a.A, e, pnew));
-            a.w_out[e] = (T)pe;
-            a.s[e] = (T)se;
-            acc[0] += se * pe;
+            pe[j] = pnew(ti.e[j]);
+            se[j] = apply_row<OP>(a.A, ti.e[j], pnew);
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (!ti.live[j]) continue;
+            const double sv = rnd<T>(se[j]);
+            sts<NT>(vp<T>(a, a.off_wout, ti.e[j]), pe[j]);
+            sts<NT>(vp<T>(a, a.off_s, ti.e[j]), sv);
+            acc[0] += sv * pe[j];
         }
     }
-    block_sum<1>(acc, lds);
+    block_sum<1>(acc, lds_red);
     store_partial<1>(a.part_out, acc);
 }
 
 // Pass B of CG iteration i.  w_out = p_i (written by pass A).
-template <typename T, int OP, bool JAC, int EPT>
-__global__ void __launch_bounds__(1024) k_cg_b(PassArgs<T> a)
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+__global__ void __launch_bounds__(kMaxBlock) k_cg_b(PassArgs<T> a)
 {
-    __shared__ double lds[kMaxWaves * kFields];
+    __shared__ double lds_red[kMaxWaves * kFields];
     const DevState S = *a.st_in;
     if (S.status != RUNNING) {
         if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = S;
         return;
     }
     double tot[1];
-    stage2<1>(a.part_in, a.nparts, tot, lds);
+    stage2<1>(a.part_in, a.nparts, tot, lds_red);
     const double sp = tot[0];
     const int i = S.iter;
     int status = RUNNING;
@@ -418,50 +552,65 @@ __global__ void __launch_bounds__(1024) k_cg_b(PassArgs<T> a)
     if (status != RUNNING) return;
 
     double acc[2] = {0.0, 0.0};
+    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    const uint32_t tile_elems = blockDim.x * EPT;
     for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
+        double pe[EPT], se[EPT], re[EPT], xo[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            const uint32_t e = (uint32_t)tile * tile_elems + j * blockDim.x + threadIdx.x;
-            if (e >= (uint32_t)a.A.n) continue;
-            const double pe = ld(a.w_out, e);
-            const double se = ld(a.s, e);
-            a.x[e] = a.x[e] + alpha * pe;
-            const double rn = rnd<T>(ld(a.r, e) - alpha * se);
-            a.r[e] = (T)rn;
+            pe[j] = lds<NT>(vp<T>(a, a.off_wout, ti.e[j]));
+            se[j] = lds<NT>(vp<T>(a, a.off_s, ti.e[j]));
+            re[j] = lds<NT>(vp<T>(a, a.off_r, ti.e[j]));
+            xo[j] = lds<NT>(vp<double>(a, a.off_x, ti.e[j]));
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (!ti.live[j]) continue;
+            const uint32_t e = ti.e[j];
+            sts<NT>(vp<double>(a, a.off_x, e), xo[j] + alpha * pe[j]);
+            const double rn = rnd<T>(re[j] - alpha * se[j]);
+            sts<NT>(vp<T>(a, a.off_r, e), rn);
             const double un = rnd<T>(minv<T, JAC, OP>(a, e, rn));
             acc[0] += rn * un;
             acc[1] += rn * rn;
         }
     }
-    block_sum<2>(acc, lds);
+    block_sum<2>(acc, lds_red);
     store_partial<2>(a.part_out, acc);
 }
 
 // ----------------------------------------------------------------- support
 
-// partials of ||b - A x||^2 and ||b||^2 in binary64 (A in its storage precision).
+// partials of ||b - A x||^2 and ||b||^2 in binary64 (A in its storage
+// precision); x is the internal copy, or the caller's when x_plain is set.
 template <typename T, int OP, int EPT>
-__global__ void __launch_bounds__(1024) k_resid(PassArgs<T> a)
+__global__ void __launch_bounds__(kMaxBlock) k_resid(PassArgs<T> a)
 {
-    __shared__ double lds[kMaxWaves * kFields];
+    __shared__ double lds_red[kMaxWaves * kFields];
     double acc[2] = {0.0, 0.0};
+    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    const uint32_t tile_elems = blockDim.x * EPT;
     for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
+        double be[EPT], ax[EPT];
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            const uint32_t e = (uint32_t)tile * tile_elems + j * blockDim.x + threadIdx.x;
-            if (e < (uint32_t)a.A.n) {
-                const double be = a.b[e];
-                const double d = be - apply_row<OP>(a.A, e, [&](uint32_t k) { return a.x[k]; });
-                acc[0] += d * d;
-                acc[1] += be * be;
-            }
+            be[j] = a.b[ti.e[j]];
+            if (a.x_plain)
+                ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return a.x_user[k]; });
+            else
+                ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
+        }
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (!ti.live[j]) continue;
+            const double d = be[j] - ax[j];
+            acc[0] += d * d;
+            acc[1] += be[j] * be[j];
         }
     }
-    block_sum<2>(acc, lds);
+    block_sum<2>(acc, lds_red);
     store_partial<2>(a.part_out, acc);
 }
 
@@ -469,9 +618,9 @@ __global__ void __launch_bounds__(1024) k_resid(PassArgs<T> a)
 // out->spare[0] (= ||b||^2).
 __global__ void __launch_bounds__(1024) k_reduce_true(const double *part, int nparts, DevState *out)
 {
-    __shared__ double lds[kMaxWaves * kFields];
+    __shared__ double lds_red[kMaxWaves * kFields];
     double tot[2];
-    stage2<2>(part, nparts, tot, lds);
+    stage2<2>(part, nparts, tot, lds_red);
     if (threadIdx.x == 0) {
         out->true_res2 = tot[0];
         out->spare[0] = tot[1];

@@ -6,6 +6,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -36,9 +37,9 @@ pcg_status invalid(const char *why)
 }
 }  // namespace pcg
 
-#define HIPCHK(call)                                  \
-    do {                                              \
-        hipError_t e_ = (call);                       \
+#define HIPCHK(call)                                      \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
         if (e_ != hipSuccess) return hip_fail(e_, #call); \
     } while (0)
 
@@ -115,8 +116,8 @@ pcg_status validate_options(const pcg_options *o)
         return invalid("sigma must be >= 0 (or NaN for the default)");
     if (o->iters_per_launch < 0 || (o->iters_per_launch % 2) != 0)
         return invalid("iters_per_launch must be 0 or an even number >= 2");
-    if (o->block_size != 0 && (o->block_size < 64 || o->block_size > 1024 || o->block_size % 64 != 0))
-        return invalid("block_size must be a multiple of 64 in [64, 1024]");
+    if (o->block_size != 0 && (o->block_size < 64 || o->block_size > kMaxBlock || o->block_size % 64 != 0))
+        return invalid("block_size must be a multiple of 64 in [64, 256]");
     if (o->grid_blocks < 0 || o->grid_blocks > kMaxGrid) return invalid("grid_blocks out of range");
     if (o->history_cap < 0) return invalid("history_cap must be >= 0");
     if (o->history_cap > 0 && !o->history) return invalid("history buffer is null");
@@ -126,19 +127,46 @@ pcg_status validate_options(const pcg_options *o)
 
 // ----------------------------------------------------------------- shape
 
+// Launch shape.  Without PCG_VAR_SET the measured defaults for MI355X
+// (256-cube sweeps of every method / precision) apply: the fused pipelined
+// pass with Jacobi streams 18 vectors and runs best as ONE block per CU with
+// several unknowns per thread (a compact window of tiles in flight keeps HBM
+// pages open), the lighter passes as more, smaller blocks; the XCD slab map
+// measured slower everywhere and is off unless asked for.
 LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
 {
     LaunchShape s{};
-    s.block = o->block_size ? o->block_size : 256;
-    s.ept = 2;
+    const int var = o->variant;
+    const bool set = var & PCG_VAR_SET;
+    int blocks_per_cu;
+    if (set) {
+        s.ept = (var & PCG_VAR_EPT1) ? 1 : (var & PCG_VAR_EPT4) ? 4 : 2;
+        s.nt = (var & PCG_VAR_NT) ? 1 : 0;
+        s.block = 256;
+        blocks_per_cu = kDefaultBlocksPerCU;
+    } else {
+        s.nt = 1;
+        const bool pipe = o->method != PCG_CG, jac = o->pc == PCG_PC_JACOBI, fp64 = o->prec == PCG_FP64;
+        if (pipe && jac) {
+            s.ept = 2, s.block = 256, blocks_per_cu = 1;
+        } else if (pipe) {
+            s.ept = 1, s.block = 128, blocks_per_cu = 4;
+        } else if (fp64) {
+            s.ept = 1, s.block = 128, blocks_per_cu = 4;
+        } else {
+            s.ept = 4, s.block = 256, blocks_per_cu = 4;
+        }
+    }
+    if (o->block_size) s.block = o->block_size;
     const int64_t tile = int64_t(s.block) * s.ept;
     s.ntiles = (int)((op->n + tile - 1) / tile);
-    int g = o->grid_blocks ? o->grid_blocks : kDefaultBlocksPerCU * kNumCU;
+    int g = o->grid_blocks ? o->grid_blocks : blocks_per_cu * kNumCU;
     if (g > s.ntiles) g = s.ntiles;
     if (g >= 64) g &= ~7;  // a multiple of the XCD count
     if (g < 1) g = 1;
     s.grid = g;
-    s.xcd_map = (g >= 64 && (g % 8) == 0) ? 1 : 0;
+    const bool want_xcd = set && (var & PCG_VAR_XCD_MAP) != 0;
+    s.xcd_map = (want_xcd && g >= 64 && (g % 8) == 0) ? 1 : 0;
     s.K = o->iters_per_launch ? o->iters_per_launch : (op->n >= (1 << 20) ? 16 : 64);
     return s;
 }
@@ -148,7 +176,7 @@ static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &sh, Layout *L)
 {
     const size_t n = (size_t)op->n;
-    const size_t es = o->prec == PCG_FP64 ? 8 : 4;
+    const uint32_t es = o->prec == PCG_FP64 ? 8 : 4;
     const bool jac = o->pc == PCG_PC_JACOBI;
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -164,26 +192,29 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
     l.flag = take(64);
     l.hist = take(size_t(o->history_cap) * PCG_HISTORY_FIELDS * 8);
     l.dinv = (op->kind == PCG_OP_CSR && jac) ? take(n * es) : SIZE_MAX;
-    const size_t v = n * es;
-    for (int k = 0; k < Layout::kVecs; ++k) l.vec[k] = SIZE_MAX;
-    if (o->method == PCG_CG) {
-        l.vec[V_R] = take(v);
-        l.vec[V_W0] = take(v);  // p ping-pong
-        l.vec[V_W1] = take(v);
-        l.vec[V_S] = take(v);
-    } else {
-        l.vec[V_R] = take(v);
-        l.vec[V_W0] = take(v);
-        l.vec[V_W1] = take(v);
-        l.vec[V_Z] = take(v);
-        l.vec[V_S] = take(v);
-        l.vec[V_T] = take(v);
+    // slots of a 512-unknown tile: x (binary64) first, then the stored vectors
+    for (int k = 0; k < V_COUNT; ++k) l.slot_off[k] = kNoSlot;
+    uint32_t tb = 0;
+    auto slot = [&](int k, uint32_t bytes_per) {
+        l.slot_off[k] = tb;
+        tb += kBlk * bytes_per;
+    };
+    slot(V_X, 8);
+    slot(V_R, es);
+    slot(V_W0, es);  // CG: p ping-pong
+    slot(V_W1, es);
+    slot(V_S, es);
+    if (o->method != PCG_CG) {
+        slot(V_Z, es);
+        slot(V_T, es);
         if (jac) {
-            l.vec[V_U] = take(v);
-            l.vec[V_Q] = take(v);
-            l.vec[V_P] = take(v);
+            slot(V_U, es);
+            slot(V_Q, es);
+            slot(V_P, es);
         }
     }
+    l.tile_bytes = tb;
+    l.blk = take(((n + kBlk - 1) / kBlk) * (size_t)tb);
     l.total = off;
     if (L) *L = l;
     return off;
@@ -218,60 +249,72 @@ OpDev<T> make_opdev(const pcg_operator *op)
     return A;
 }
 
-// Kernel table for one (T, OP, JAC) combination.
+using LaunchFn = void (*)(PassArgsAny, int, int, hipStream_t);
+
+// Kernel table for one (T, OP, JAC, EPT, NT) combination.
 struct Kernels {
-    void (*init0_pipe)(PassArgsAny, int, int, hipStream_t);
-    void (*init0_cg)(PassArgsAny, int, int, hipStream_t);
-    void (*init1)(PassArgsAny, int, int, hipStream_t);
-    void (*pipe)(PassArgsAny, int, int, hipStream_t);
-    void (*cg_init1)(PassArgsAny, int, int, hipStream_t);
-    void (*cg_a)(PassArgsAny, int, int, hipStream_t);
-    void (*cg_b)(PassArgsAny, int, int, hipStream_t);
-    void (*resid)(PassArgsAny, int, int, hipStream_t);
+    LaunchFn copy_x, init0_pipe, init0_cg, init1, pipe, cg_init1, cg_a, cg_b, resid;
+};
+
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+struct KernelSet {
+    static PassArgs<T> &A(PassArgsAny &a) { return *reinterpret_cast<PassArgs<T> *>(a.bytes); }
+    static void copy_x(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_copy_x<T, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void init0_pipe(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_init0<T, OP, JAC, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void init0_cg(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_init0<T, OP, JAC, false, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void init1(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_init1<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void pipe(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void cg_init1(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_cg_init1<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void cg_a(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_cg_a<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void cg_b(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_cg_b<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void resid(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_resid<T, OP, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static Kernels table() { return Kernels{copy_x, init0_pipe, init0_cg, init1, pipe, cg_init1, cg_a, cg_b, resid}; }
 };
 
 template <typename T, int OP, bool JAC, int EPT>
-struct KernelSet {
-    static PassArgs<T> &A(PassArgsAny &a) { return *reinterpret_cast<PassArgs<T> *>(a.bytes); }
-    static void init0_pipe(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_init0<T, OP, JAC, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void init0_cg(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_init0<T, OP, JAC, false, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void init1(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_init1<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void pipe(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void cg_init1(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_cg_init1<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void cg_a(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_cg_a<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void cg_b(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_cg_b<T, OP, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void resid(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_resid<T, OP, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static Kernels table()
-    { return Kernels{init0_pipe, init0_cg, init1, pipe, cg_init1, cg_a, cg_b, resid}; }
-};
-
-template <typename T, int OP>
-Kernels pick_jac(bool jac)
+Kernels pick_nt(bool nt)
 {
-    return jac ? KernelSet<T, OP, true, 2>::table() : KernelSet<T, OP, false, 2>::table();
+    return nt ? KernelSet<T, OP, JAC, EPT, true>::table() : KernelSet<T, OP, JAC, EPT, false>::table();
 }
 
-template <typename T>
-Kernels pick_op(int op, bool jac)
+template <typename T, int OP, bool JAC>
+Kernels pick_ept(int ept, bool nt)
 {
-    switch (op) {
-    case PCG_OP_STENCIL2D5: return pick_jac<T, OP_2D5>(jac);
-    case PCG_OP_STENCIL3D7: return pick_jac<T, OP_3D7>(jac);
-    default: return pick_jac<T, OP_CSR>(jac);
+    switch (ept) {
+    case 1: return pick_nt<T, OP, JAC, 1>(nt);
+    case 4: return pick_nt<T, OP, JAC, 4>(nt);
+    default: return pick_nt<T, OP, JAC, 2>(nt);
     }
 }
 
-Kernels pick(int prec, int op, bool jac)
+template <typename T, int OP>
+Kernels pick_jac(bool jac, int ept, bool nt)
 {
-    return prec == PCG_FP64 ? pick_op<double>(op, jac) : pick_op<float>(op, jac);
+    return jac ? pick_ept<T, OP, true>(ept, nt) : pick_ept<T, OP, false>(ept, nt);
+}
+
+template <typename T>
+Kernels pick_op(int op, bool jac, int ept, bool nt)
+{
+    switch (op) {
+    case PCG_OP_STENCIL2D5: return pick_jac<T, OP_2D5>(jac, ept, nt);
+    case PCG_OP_STENCIL3D7: return pick_jac<T, OP_3D7>(jac, ept, nt);
+    default: return pick_jac<T, OP_CSR>(jac, ept, nt);
+    }
+}
+
+Kernels pick(int prec, int op, bool jac, int ept, bool nt)
+{
+    return prec == PCG_FP64 ? pick_op<double>(op, jac, ept, nt) : pick_op<float>(op, jac, ept, nt);
 }
 
 }  // namespace
@@ -282,7 +325,6 @@ struct pcg_solver_ {
     pcg_operator op;
     pcg_options opt;
     hipStream_t stream;      // the caller's stream: all work goes here
-    hipStream_t cap_stream;  // private stream used only to capture the graph
     char *ws;
     size_t ws_bytes;
     Layout L;
@@ -292,25 +334,25 @@ struct pcg_solver_ {
     double dinv_s;           // stencil Jacobi scalar
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    DevState *pinned = nullptr;  // 2 host slots for polled status
+    const double *graph_b = nullptr;  // b baked into the captured graph
+    DevState *pinned = nullptr;       // 2 host slots for polled status
     hipEvent_t ev_begin[2] = {nullptr, nullptr};
     hipEvent_t ev_end[2] = {nullptr, nullptr};
     hipEvent_t ev_copy[2] = {nullptr, nullptr};
-    const double *graph_b = nullptr;  // b and x baked into the captured graph
-    double *graph_x = nullptr;
 
     DevState *state(int k) { return reinterpret_cast<DevState *>(ws + L.state) + k; }
     double *part(int k) { return reinterpret_cast<double *>(ws + L.part[k]); }
-    template <typename T> T *vec(int k) { return L.vec[k] == SIZE_MAX ? nullptr : reinterpret_cast<T *>(ws + L.vec[k]); }
 
-    // Arguments of the pass at parity `par` (reads slot par, writes 1 - par).
-    PassArgsAny args(int par, const double *b, double *x, int i0 = 0, int w_par = -1);
-    pcg_status run_init(const double *b, double *x, int i0);
-    pcg_status run_true_residual(const double *b, const double *x, double *res2, double *b2 = nullptr);
-    pcg_status launch_iterations(const double *b, double *x);
+    // Arguments of the pass at parity `par` (reads state / partial slot par,
+    // writes 1 - par; w / p buffers by w_par, default par).
+    PassArgsAny args(int par, const double *b, double *x_user, int i0 = 0, int w_par = -1);
+    pcg_status run_init(const double *b, int i0);
+    pcg_status run_copy_x(double *x_user, int out);
+    pcg_status run_true_residual(const double *b, const double *x_plain, double *res2, double *b2 = nullptr);
+    pcg_status launch_iterations(const double *b);
 };
 
-PassArgsAny pcg_solver_::args(int par, const double *b, double *x, int i0, int w_par)
+PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, int w_par)
 {
     PassArgsAny any{};
     auto fill = [&](auto *tag) {
@@ -320,17 +362,21 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x, int i0, int w
         a.dinv = L.dinv == SIZE_MAX ? nullptr : reinterpret_cast<const T *>(ws + L.dinv);
         a.dinv_s = dinv_s;
         a.b = b;
-        a.x = x;
-        a.r = vec<T>(V_R);
-        a.u = vec<T>(V_U);
+        a.x_user = x_user;
+        a.blk = ws + L.blk;
+        a.tile_bytes = L.tile_bytes;
         const int wp = w_par < 0 ? par : w_par;
-        a.w_in = vec<T>(wp ? V_W1 : V_W0);
-        a.w_out = vec<T>(wp ? V_W0 : V_W1);
-        a.z = vec<T>(V_Z);
-        a.q = vec<T>(V_Q);
-        a.s = vec<T>(V_S);
-        a.t = vec<T>(V_T);
-        a.p = vec<T>(V_P);
+        a.off_x = L.slot_off[V_X];
+        a.off_r = L.slot_off[V_R];
+        a.off_u = L.slot_off[V_U];
+        a.off_win = L.slot_off[wp ? V_W1 : V_W0];
+        a.off_wout = L.slot_off[wp ? V_W0 : V_W1];
+        a.off_z = L.slot_off[V_Z];
+        a.off_q = L.slot_off[V_Q];
+        a.off_s = L.slot_off[V_S];
+        a.off_t = L.slot_off[V_T];
+        a.off_p = L.slot_off[V_P];
+        a.clear = 0;
         a.part_in = part(par);
         a.part_out = part(1 - par);
         a.nparts = sh.grid;
@@ -344,39 +390,62 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x, int i0, int w
         a.rtol = opt.rtol;
         a.i0 = i0;
         a.xcd_map = sh.xcd_map;
+        a.copy_out = 0;
+        a.x_plain = 0;
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
     else fill((float *)nullptr);
     return any;
 }
 
+// Members of PassArgs set after args(); every T-dependent member is a
+// pointer, so PassArgs<double> and PassArgs<float> share this layout.
+static_assert(offsetof(PassArgs<double>, clear) == offsetof(PassArgs<float>, clear), "PassArgs layout");
+static_assert(offsetof(PassArgs<double>, copy_out) == offsetof(PassArgs<float>, copy_out), "PassArgs layout");
+static_assert(offsetof(PassArgs<double>, x_plain) == offsetof(PassArgs<float>, x_plain), "PassArgs layout");
+static PassArgs<double> &head(PassArgsAny &a) { return *reinterpret_cast<PassArgs<double> *>(a.bytes); }
+
 // K iterations: pipelined = K passes, CG = 2K passes.  Pass k reads slot
 // k % 2.  The w (pipelined) or p (CG) buffers flip once per iteration.
-static void enqueue_iterations(pcg_solver_ *s, hipStream_t st, const double *b, double *x)
+static void enqueue_iterations(pcg_solver_ *s, hipStream_t st, const double *b)
 {
     const int K = s->sh.K;
     if (s->opt.method == PCG_CG) {
         for (int it = 0; it < K; ++it) {
             // pass A: state slot 0 -> 1, p[it%2] -> p[1-it%2]; pass B: slot 1 -> 0
-            s->kern.cg_a(s->args(0, b, x, 0, it & 1), s->sh.grid, s->sh.block, st);
-            s->kern.cg_b(s->args(1, b, x, 0, it & 1), s->sh.grid, s->sh.block, st);
+            s->kern.cg_a(s->args(0, b, nullptr, 0, it & 1), s->sh.grid, s->sh.block, st);
+            s->kern.cg_b(s->args(1, b, nullptr, 0, it & 1), s->sh.grid, s->sh.block, st);
         }
     } else {
-        for (int k = 0; k < K; ++k) s->kern.pipe(s->args(k & 1, b, x), s->sh.grid, s->sh.block, st);
+        for (int k = 0; k < K; ++k) s->kern.pipe(s->args(k & 1, b, nullptr), s->sh.grid, s->sh.block, st);
     }
 }
 
-pcg_status pcg_solver_::run_init(const double *b, double *x, int i0)
+pcg_status pcg_solver_::run_copy_x(double *x_user, int out)
+{
+    PassArgsAny a = args(0, nullptr, x_user);
+    head(a).copy_out = out;
+    kern.copy_x(a, sh.grid, sh.block, stream);
+    HIPCHK(hipGetLastError());
+    return PCG_OK;
+}
+
+pcg_status pcg_solver_::run_init(const double *b, int i0)
 {
     // init0 writes partials to slot 1; init1 reads slot 1 and writes state 0,
-    // partials 0 and w[0] (pipelined).
+    // partials 0 and (pipelined) w[0].
     if (opt.method == PCG_CG) {
-        kern.init0_cg(args(0, b, x, i0), sh.grid, sh.block, stream);
-        kern.cg_init1(args(1, b, x, i0), sh.grid, sh.block, stream);
+        PassArgsAny a0 = args(0, b, nullptr, i0);
+        head(a0).clear = CLR_WIN;  // the first pass A of a launch reads p_{-1} from p[0]
+        kern.init0_cg(a0, sh.grid, sh.block, stream);
+        kern.cg_init1(args(1, b, nullptr, i0), sh.grid, sh.block, stream);
     } else {
-        kern.init0_pipe(args(0, b, x, i0), sh.grid, sh.block, stream);
-        // w_par = 1 makes w_out = w[0]
-        kern.init1(args(1, b, x, i0, 1), sh.grid, sh.block, stream);
+        PassArgsAny a0 = args(0, b, nullptr, i0);
+        uint32_t clr = CLR_Z | CLR_S | CLR_T;
+        if (opt.pc == PCG_PC_JACOBI) clr |= CLR_Q | CLR_P;
+        head(a0).clear = clr;
+        kern.init0_pipe(a0, sh.grid, sh.block, stream);
+        kern.init1(args(1, b, nullptr, i0, 1), sh.grid, sh.block, stream);  // w_par 1: w_out = w[0]
     }
     HIPCHK(hipGetLastError());
     return PCG_OK;
@@ -384,9 +453,12 @@ pcg_status pcg_solver_::run_init(const double *b, double *x, int i0)
 
 // ||b - A x||^2 and ||b||^2 (binary64): partials into slot 1 (free between
 // iteration launches), summed into the true_res2 / spare[0] fields of state 0.
-pcg_status pcg_solver_::run_true_residual(const double *b, const double *x, double *res2, double *b2)
+// x_plain: the caller's x, or nullptr for the internal copy.
+pcg_status pcg_solver_::run_true_residual(const double *b, const double *x_plain, double *res2, double *b2)
 {
-    kern.resid(args(0, b, const_cast<double *>(x)), sh.grid, sh.block, stream);
+    PassArgsAny a = args(0, b, const_cast<double *>(x_plain));
+    head(a).x_plain = x_plain != nullptr;
+    kern.resid(a, sh.grid, sh.block, stream);
     hipLaunchKernelGGL(k_reduce_true, dim3(1), dim3(1024), 0, stream, part(1), sh.grid, state(0));
     HIPCHK(hipGetLastError());
     HIPCHK(hipMemcpyAsync(&pinned[0], state(0), sizeof(DevState), hipMemcpyDeviceToHost, stream));
@@ -445,7 +517,7 @@ extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const 
     s->ws_bytes = bytes;
     s->L = L;
     s->sh = sh;
-    s->kern = pick(opt->prec, op->kind, opt->pc == PCG_PC_JACOBI);
+    s->kern = pick(opt->prec, op->kind, opt->pc == PCG_PC_JACOBI, sh.ept, sh.nt != 0);
     const double centre = op->diag + op->shift;
     s->dinv_s = 1.0;
     if (opt->pc == PCG_PC_JACOBI && op->kind != PCG_OP_CSR)
@@ -533,10 +605,11 @@ extern "C" pcg_status pcg_destroy(pcg_solver s)
     return PCG_OK;
 }
 
-// Build (once per (b, x) pair) the graph of K iteration passes.
-static pcg_status ensure_graph(pcg_solver_ *s, const double *b, double *x)
+// Build (once per b) the graph of K iteration passes.  The passes read only
+// the workspace and b, so the graph is reused by every solve with that b.
+static pcg_status ensure_graph(pcg_solver_ *s, const double *b)
 {
-    if (s->gexec && s->graph_b == b && s->graph_x == x) return PCG_OK;
+    if (s->gexec && s->graph_b == b) return PCG_OK;
     if (s->gexec) {
         (void)hipGraphExecDestroy(s->gexec);
         s->gexec = nullptr;
@@ -552,24 +625,23 @@ static pcg_status ensure_graph(pcg_solver_ *s, const double *b, double *x)
         (void)hipStreamDestroy(cs);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    enqueue_iterations(s, cs, b, x);
+    enqueue_iterations(s, cs, b);
     e = hipStreamEndCapture(cs, &s->graph);
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
     HIPCHK(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
     s->graph_b = b;
-    s->graph_x = x;
     return PCG_OK;
 }
 
-pcg_status pcg_solver_::launch_iterations(const double *b, double *x)
+pcg_status pcg_solver_::launch_iterations(const double *b)
 {
     if (opt.use_graph) {
-        pcg_status st = ensure_graph(this, b, x);
+        pcg_status st = ensure_graph(this, b);
         if (st) return st;
         HIPCHK(hipGraphLaunch(gexec, stream));
     } else {
-        enqueue_iterations(this, stream, b, x);
+        enqueue_iterations(this, stream, b);
         HIPCHK(hipGetLastError());
     }
     return PCG_OK;
@@ -589,8 +661,9 @@ extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_re
     if (o.history_cap > 0)
         HIPCHK(hipMemsetAsync(s->ws + s->L.hist, 0xff, size_t(o.history_cap) * PCG_HISTORY_FIELDS * 8, s->stream));
 
-    pcg_status st = s->run_init(b, x, 0);
+    pcg_status st = s->run_copy_x(x, 0);
     if (st) return st;
+    if ((st = s->run_init(b, 0))) return st;
 
     DevState S{};
     int launches = 0;
@@ -611,7 +684,7 @@ extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_re
         for (int g = 0; !done; ++g) {
             const int slot = g & 1;
             if (o.timing) HIPCHK(hipEventRecord(s->ev_begin[slot], s->stream));
-            if ((st = s->launch_iterations(b, x))) return st;
+            if ((st = s->launch_iterations(b))) return st;
             if (o.timing) HIPCHK(hipEventRecord(s->ev_end[slot], s->stream));
             HIPCHK(hipMemcpyAsync(&s->pinned[slot], s->state(0), sizeof(DevState), hipMemcpyDeviceToHost, s->stream));
             HIPCHK(hipEventRecord(s->ev_copy[slot], s->stream));
@@ -631,23 +704,25 @@ extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_re
         if (S.status == ST_NONFINITE && !(std::isfinite(S.bnorm2))) {
             res->status = PCG_NONFINITE;
             res->iterations = 0;
+            HIPCHK(hipStreamSynchronize(s->stream));
             return PCG_ERR_NONFINITE;
         }
         if (S.status == ST_CONVERGED && o.true_residual_check && replacements < o.replace_max &&
             S.iter < o.max_iter) {
             double tr2 = 0.0;
-            if ((st = s->run_true_residual(b, x, &tr2))) return st;
+            if ((st = s->run_true_residual(b, nullptr, &tr2))) return st;
             // restart from x when the explicit residual misses the tolerance
             if (std::sqrt(tr2) > o.rtol * std::sqrt(S.bnorm2)) {
                 ++replacements;
-                if ((st = s->run_init(b, x, S.iter))) return st;
+                if ((st = s->run_init(b, S.iter))) return st;
                 continue;
             }
         }
         break;
     }
     double tr2 = 0.0;
-    if ((st = s->run_true_residual(b, x, &tr2))) return st;
+    if ((st = s->run_true_residual(b, nullptr, &tr2))) return st;
+    if ((st = s->run_copy_x(x, 1))) return st;
     const double bn = std::sqrt(S.bnorm2);
     res->status = S.status;
     res->iterations = S.iter;

@@ -26,6 +26,7 @@ PCG_OP_STENCIL2D5, PCG_OP_STENCIL3D7, PCG_OP_CSR = 0, 1, 2
 PCG_PC_NONE, PCG_PC_JACOBI = 0, 1
 PCG_FP64, PCG_FP32_STREAM = 0, 1
 PCG_HISTORY_FIELDS = 5
+PCG_VAR_SET, PCG_VAR_XCD_MAP, PCG_VAR_NT, PCG_VAR_EPT1, PCG_VAR_EPT4 = 0x01, 0x02, 0x04, 0x10, 0x20
 
 METHOD = {"cg": PCG_CG, "pipe": PCG_PIPE, "pipe_shift": PCG_PIPE_SHIFT}
 OUTCOME = {PCG_CONVERGED: "converged", PCG_MAX_ITER: "max_iter", PCG_BREAKDOWN: "breakdown",
@@ -45,7 +46,8 @@ class pcg_options(C.Structure):
                 ("sigma", C.c_double), ("rtol", C.c_double), ("true_residual_check", C.c_int32),
                 ("replace_max", C.c_int32), ("iters_per_launch", C.c_int32), ("history_cap", C.c_int32),
                 ("history", C.c_void_p), ("block_size", C.c_int32), ("grid_blocks", C.c_int32),
-                ("timing", C.c_int32), ("use_graph", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("timing", C.c_int32), ("use_graph", C.c_int32), ("variant", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class pcg_result(C.Structure):
@@ -250,7 +252,7 @@ def make_options(method: str = "pipe_shift", jacobi: bool = False, fp32: bool = 
                  sigma: Optional[float] = None, rtol: float = 1e-10, max_iter: int = 1000,
                  true_residual_check: bool = True, replace_max: int = 4, iters_per_launch: int = 0,
                  history_cap: int = 0, block_size: int = 0, grid_blocks: int = 0, timing: bool = False,
-                 use_graph: bool = True) -> pcg_options:
+                 use_graph: bool = True, variant: int = 0) -> pcg_options:
     o = pcg_default_options()
     o.method = METHOD[method]
     o.pc = PCG_PC_JACOBI if jacobi else PCG_PC_NONE
@@ -266,6 +268,7 @@ def make_options(method: str = "pipe_shift", jacobi: bool = False, fp32: bool = 
     o.grid_blocks = int(grid_blocks)
     o.timing = int(bool(timing))
     o.use_graph = int(bool(use_graph))
+    o.variant = int(variant)
     return o
 
 
