@@ -1,0 +1,638 @@
+// pcg_batch.hip -- the batched persistent pass (kernels), the batch engine
+// shared with the server, and pcg_batch_workspace_size / pcg_batch_solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "pcg.h"
+#include "pcg_batch_engine.h"
+
+namespace pcg {
+
+// ----------------------------------------------------------------- kernels
+
+template <typename T>
+__device__ __forceinline__ PassArgs<T> batch_args(const BatchSys &D, const BatchState &S)
+{
+    PassArgs<T> a;
+    a.A.n = D.n;
+    a.A.nx = D.nx;
+    a.A.ny = D.ny;
+    a.A.nz = D.nz;
+    a.A.dx = D.dx;
+    a.A.dxy = D.dxy;
+    a.A.centre = D.centre;
+    a.A.off = D.off;
+    a.A.row_ptr = D.row_ptr;
+    a.A.col = D.col;
+    a.A.val = (const T *)D.val;
+    a.dinv = (const T *)D.dinv;
+    a.dinv_s = D.dinv_s;
+    a.b = D.b;
+    a.x_user = D.x;
+    a.blk = D.blk;
+    a.tile_bytes = D.tile_bytes;
+    a.off_x = D.off_slot[V_X];
+    a.off_r = D.off_slot[V_R];
+    a.off_u = D.off_slot[V_U];
+    // ITER reads w[wcur] and writes w[1 - wcur]; INIT1 writes w_0 into the
+    // slot the first ITER pass reads
+    a.off_win = D.off_slot[S.wcur ? V_W1 : V_W0];
+    a.off_wout = S.phase == PH_INIT1 ? a.off_win : D.off_slot[S.wcur ? V_W0 : V_W1];
+    a.off_z = D.off_slot[V_Z];
+    a.off_q = D.off_slot[V_Q];
+    a.off_s = D.off_slot[V_S];
+    a.off_t = D.off_slot[V_T];
+    a.off_p = D.off_slot[V_P];
+    a.clear = CLR_Z | CLR_S | CLR_T | (D.jac ? (CLR_Q | CLR_P) : 0u);
+    a.sigma = D.sigma;
+    a.copy_out = S.phase == PH_COPYOUT;
+    a.x_plain = 0;
+    return a;
+}
+
+// One tile of one system in its current phase; NF partials into acc.
+template <typename T, int OP, bool JAC>
+__device__ __forceinline__ void batch_tile(const PassArgs<T> &a, const BatchState &S, int tile, double (&acc)[3])
+{
+    constexpr int E = kBatchEPT;
+    switch (S.phase) {
+    case PH_COPYIN:
+    case PH_COPYOUT: tile_copy_x<T, E>(a, tile); break;
+    case PH_INIT0: {
+        double b1[1] = {0.0};
+        tile_init0<T, OP, JAC, JAC, E, true>(a, tile, b1);
+        acc[0] = b1[0];
+        break;
+    }
+    case PH_INIT1: tile_init1<T, OP, JAC, E, true>(a, tile, acc); break;
+    case PH_ITER: tile_pipe<T, OP, JAC, E, true>(a, tile, S.alpha, S.beta, acc); break;
+    case PH_RESID: {
+        double r2[2] = {0.0, 0.0};
+        tile_resid<T, OP, E>(a, tile, r2);
+        acc[0] = r2[0];
+        acc[1] = r2[1];
+        break;
+    }
+    default: break;
+    }
+}
+
+template <typename T, int OP>
+__device__ __forceinline__ void batch_tile_op(const BatchSys &D, const BatchState &S, int tile, double (&acc)[3])
+{
+    const PassArgs<T> a = batch_args<T>(D, S);
+    if (D.jac) batch_tile<T, OP, true>(a, S, tile, acc);
+    else batch_tile<T, OP, false>(a, S, tile, acc);
+}
+
+// Pass: every item (system, tile) of every active system.
+template <typename T>
+__global__ void __launch_bounds__(kBatchBlock) k_batch_pass(BatchTables tb)
+{
+    __shared__ double lds_red[kMaxWaves * kFields];
+    const int nitems = tb.counts[0];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t s = tb.item_sys[it], tile = tb.item_tile[it];
+        const BatchState S = tb.st[s];
+        if (S.phase >= PH_DONE) continue;
+        const BatchSys &D = tb.sys[s];
+        double acc[3] = {0.0, 0.0, 0.0};
+        switch (D.kind) {
+        case PCG_OP_STENCIL2D5: batch_tile_op<T, OP_2D5>(D, S, tile, acc); break;
+        case PCG_OP_STENCIL3D7: batch_tile_op<T, OP_3D7>(D, S, tile, acc); break;
+        default: batch_tile_op<T, OP_CSR>(D, S, tile, acc); break;
+        }
+        block_sum<3>(acc, lds_red);
+        if (threadIdx.x == 0) {
+            double *pp = D.part + (size_t)tile * kFields;
+            pp[0] = acc[0];
+            pp[1] = acc[1];
+            pp[2] = acc[2];
+        }
+    }
+}
+
+__device__ __forceinline__ void batch_hist(const BatchSys &D, int i, double res, double alpha, double beta,
+                                           double gamma, double delta)
+{
+    if (D.hist && i >= 0 && i < D.hist_cap) {
+        double *row = D.hist + (size_t)i * 5;
+        row[0] = res;
+        row[1] = alpha;
+        row[2] = beta;
+        row[3] = gamma;
+        row[4] = delta;
+    }
+}
+
+// Decision of the top of iteration i from gamma_i, delta_i, rho_i (the same
+// rules as the single-system pass head).  Returns the new state.
+__device__ BatchState batch_decide(const BatchSys &D, BatchState S, double gamma, double delta, double rho)
+{
+    const int i = S.iter;
+    int status = RUNNING;
+    double alpha = __builtin_nan(""), beta = __builtin_nan("");
+    if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rho)) {
+        status = ST_NONFINITE;
+    } else if (sqrt(rho) <= D.rtol * sqrt(S.bnorm2)) {
+        status = ST_CONVERGED;
+    } else if (i >= D.max_iter) {
+        status = ST_MAX_ITER;
+    } else if (!(gamma > 0.0) || !(delta > 0.0)) {
+        status = ST_BREAKDOWN;
+    } else {
+        if (i > S.i_start) {
+            beta = gamma / S.gamma;                          // gamma_{i-1}
+            alpha = 1.0 / (delta / gamma - beta / S.alpha);  // alpha_{i-1}
+        } else {
+            beta = 0.0;
+            alpha = gamma / delta;
+        }
+        if (!(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
+    }
+    batch_hist(D, i, sqrt(rho / S.bnorm2), alpha, beta, gamma, delta);
+    S.rho = rho;
+    if (status == RUNNING) {
+        S.phase = PH_ITER;
+        S.alpha = alpha;
+        S.beta = beta;
+        S.gamma = gamma;
+    } else {
+        S.status = status;
+        S.phase = PH_RESID;
+    }
+    return S;
+}
+
+// Finalize: per active system, the fixed-order sum of its tile partials and
+// the transition to the next phase.
+template <typename T>
+__global__ void __launch_bounds__(kBatchBlock) k_batch_final(BatchTables tb)
+{
+    __shared__ double lds_red[kMaxWaves * kFields];
+    const int nact = tb.counts[1];
+    for (int k = blockIdx.x; k < nact; k += gridDim.x) {
+        const uint32_t s = tb.active[k];
+        BatchState S = tb.st[s];
+        if (S.phase >= PH_DONE) continue;
+        const BatchSys &D = tb.sys[s];
+        double tot[3];
+        stage2<3>(D.part, D.ntiles, tot, lds_red);
+        ++S.passes;
+        switch (S.phase) {
+        case PH_COPYIN: S.phase = PH_INIT0; break;
+        case PH_INIT0:
+            S.bnorm2 = tot[0];
+            if (!isfinite(tot[0])) {
+                S.status = ST_NONFINITE;
+                S.phase = PH_COPYOUT;
+            } else {
+                S.phase = PH_INIT1;
+            }
+            break;
+        case PH_INIT1: S = batch_decide(D, S, tot[0], tot[1], tot[2]); break;
+        case PH_ITER:
+            S.iter += 1;
+            S.wcur ^= 1;
+            S = batch_decide(D, S, tot[0], tot[1], tot[2]);
+            break;
+        case PH_RESID: {
+            S.true_res2 = tot[0];
+            const bool restart = S.status == ST_CONVERGED && D.true_check && S.restarts < D.replace_max &&
+                                 S.iter < D.max_iter && sqrt(tot[0]) > D.rtol * sqrt(S.bnorm2);
+            if (restart) {
+                S.restarts += 1;
+                S.status = RUNNING;
+                S.i_start = S.iter;
+                S.wcur = 0;
+                S.phase = PH_INIT0;
+            } else {
+                S.phase = PH_COPYOUT;
+            }
+            break;
+        }
+        case PH_COPYOUT: S.phase = PH_DONE; break;
+        default: break;
+        }
+        if (threadIdx.x == 0) tb.st[s] = S;
+        __syncthreads();
+    }
+}
+
+template __global__ void k_batch_pass<double>(BatchTables);
+template __global__ void k_batch_pass<float>(BatchTables);
+template __global__ void k_batch_final<double>(BatchTables);
+template __global__ void k_batch_final<float>(BatchTables);
+
+// ----------------------------------------------------------------- engine
+
+#define BCHK(call)                                        \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(e_, #call); \
+    } while (0)
+
+static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
+
+size_t BatchEngine::table_bytes(int max_sys, int64_t max_items)
+{
+    return up256(sizeof(BatchSys) * max_sys) + up256(sizeof(BatchState) * max_sys) +
+           up256(sizeof(uint32_t) * (size_t)max_items) * 2 + up256(sizeof(uint32_t) * max_sys) + 256;
+}
+
+pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options *opt, SysLayout *L)
+{
+    const size_t n = (size_t)op->n;
+    const uint32_t es = opt->prec == PCG_FP64 ? 8 : 4;
+    const bool jac = opt->pc == PCG_PC_JACOBI;
+    SysLayout l{};
+    for (int k = 0; k < V_COUNT; ++k) l.off_slot[k] = kNoSlot;
+    uint32_t tb = 0;
+    auto slot = [&](int k, uint32_t bytes_per) {
+        l.off_slot[k] = tb;
+        tb += kBlk * bytes_per;
+    };
+    slot(V_X, 8);
+    slot(V_R, es);
+    slot(V_W0, es);
+    slot(V_W1, es);
+    slot(V_S, es);
+    slot(V_Z, es);
+    slot(V_T, es);
+    if (jac) {
+        slot(V_U, es);
+        slot(V_Q, es);
+        slot(V_P, es);
+    }
+    l.tile_bytes = tb;
+    l.ntiles = (int32_t)((n + kBlk - 1) / kBlk);
+    size_t off = 0;
+    l.blk = off;
+    off += up256((size_t)l.ntiles * tb);
+    l.part = off;
+    off += up256((size_t)l.ntiles * kFields * 8);
+    l.dinv = SIZE_MAX;
+    if (op->kind == PCG_OP_CSR && jac) {
+        l.dinv = off;
+        off += up256(n * es);
+    }
+    l.hist = SIZE_MAX;
+    if (opt->history_cap > 0) {
+        l.hist = off;
+        off += up256((size_t)opt->history_cap * PCG_HISTORY_FIELDS * 8);
+    }
+    l.flag = off;
+    off += 256;
+    l.gersh = off;
+    off += up256((size_t)kGershBlocks * 2 * 8);
+    l.bytes = off;
+    *L = l;
+    return PCG_OK;
+}
+
+pcg_status BatchEngine::validate(const pcg_operator *op, const pcg_options *opt)
+{
+    pcg_status st = validate_options(opt);
+    if (st) return st;
+    if ((st = validate_operator(op, opt->prec))) return st;
+    if (opt->method == PCG_CG) return invalid("the batched pass runs the pipelined methods (PCG_PIPE, PCG_PIPE_SHIFT)");
+    if (opt->prec != prec_) return invalid("every system of a batch must use the batch's precision");
+    return PCG_OK;
+}
+
+pcg_status BatchEngine::init(char *tables, int max_sys, int64_t max_items, int prec, hipStream_t stream, int K)
+{
+    max_sys_ = max_sys;
+    max_items_ = max_items;
+    prec_ = prec;
+    stream_ = stream;
+    K_ = K > 0 ? K : 8;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        char *p = tables + off;
+        off += up256(b);
+        return p;
+    };
+    d_sys_ = (BatchSys *)take(sizeof(BatchSys) * max_sys);
+    d_st_ = (BatchState *)take(sizeof(BatchState) * max_sys);
+    d_item_sys_ = (uint32_t *)take(sizeof(uint32_t) * (size_t)max_items);
+    d_item_tile_ = (uint32_t *)take(sizeof(uint32_t) * (size_t)max_items);
+    d_active_ = (uint32_t *)take(sizeof(uint32_t) * max_sys);
+    d_counts_ = (int32_t *)take(256);
+    sys_.assign(max_sys, BatchSys{});
+    in_use_.assign(max_sys, 0);
+    listed_.assign(max_sys, 0);
+    BCHK(hipHostMalloc((void **)&h_st_, sizeof(BatchState) * max_sys, hipHostMallocDefault));
+    BCHK(hipHostMalloc((void **)&h_items_, sizeof(uint32_t) * (size_t)max_items * 2 + sizeof(uint32_t) * max_sys + 64,
+                       hipHostMallocDefault));
+    BCHK(hipEventCreate(&ev0_));
+    BCHK(hipEventCreate(&ev1_));
+    for (int k = 0; k < max_sys; ++k) {
+        h_st_[k] = BatchState{};
+        h_st_[k].phase = PH_FREE;
+    }
+    BCHK(hipMemcpyAsync(d_st_, h_st_, sizeof(BatchState) * max_sys, hipMemcpyHostToDevice, stream_));
+    int32_t zero[2] = {0, 0};
+    BCHK(hipMemcpyAsync(d_counts_, zero, sizeof(zero), hipMemcpyHostToDevice, stream_));
+    BCHK(hipStreamSynchronize(stream_));
+    return PCG_OK;
+}
+
+BatchEngine::~BatchEngine()
+{
+    if (gexec_) (void)hipGraphExecDestroy(gexec_);
+    if (graph_) (void)hipGraphDestroy(graph_);
+    if (h_st_) (void)hipHostFree(h_st_);
+    if (h_items_) (void)hipHostFree(h_items_);
+    if (ev0_) (void)hipEventDestroy(ev0_);
+    if (ev1_) (void)hipEventDestroy(ev1_);
+}
+
+pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, const double *b, double *x, char *region,
+                              int *slot_out)
+{
+    pcg_status st = validate(op, opt);
+    if (st) return st;
+    if (!b || !x || b == x) return invalid("b and x must be non-null and distinct");
+    if (((uintptr_t)b % 8) || ((uintptr_t)x % 8)) return invalid("b and x must be 8-byte aligned");
+    if (!region || ((uintptr_t)region % 256)) return invalid("system region must be 256-byte aligned");
+    int slot = -1;
+    for (int k = 0; k < max_sys_; ++k)
+        if (!in_use_[k]) {
+            slot = k;
+            break;
+        }
+    if (slot < 0) return PCG_ERR_BUDGET;
+    SysLayout L;
+    system_layout(op, opt, &L);
+    const int jac = opt->pc == PCG_PC_JACOBI;
+    double gersh[2] = {0.0, 0.0};
+    if (op->kind == PCG_OP_CSR) {
+        if ((st = csr_setup(op, opt->prec, jac, jac ? region + L.dinv : nullptr, (int *)(region + L.flag), stream_)))
+            return st;
+        if (opt->method == PCG_PIPE_SHIFT && std::isnan(opt->sigma) &&
+            (st = csr_gershgorin(op, opt->prec, jac, (double *)(region + L.gersh), stream_, &gersh[0], &gersh[1])))
+            return st;
+    }
+    BatchSys D{};
+    D.kind = op->kind;
+    D.jac = jac;
+    D.n = (int32_t)op->n;
+    D.ntiles = L.ntiles;
+    D.nx = op->nx;
+    D.ny = op->ny;
+    D.nz = op->kind == PCG_OP_STENCIL3D7 ? op->nz : 1;
+    D.max_iter = opt->max_iter;
+    if (op->kind != PCG_OP_CSR) {
+        D.dx = make_fastdiv((uint32_t)op->nx);
+        D.dxy = make_fastdiv((uint32_t)op->nx * (uint32_t)op->ny);
+    }
+    D.centre = op->diag + op->shift;
+    D.off = op->offdiag;
+    D.dinv_s = 1.0;
+    if (jac && op->kind != PCG_OP_CSR)
+        D.dinv_s = opt->prec == PCG_FP64 ? 1.0 / D.centre : (double)(float)(1.0 / D.centre);
+    D.sigma = default_sigma(op, opt, gersh);
+    D.rtol = opt->rtol;
+    D.row_ptr = op->row_ptr;
+    D.col = op->col_idx;
+    D.val = op->vals;
+    D.dinv = L.dinv == SIZE_MAX ? nullptr : region + L.dinv;
+    D.b = b;
+    D.x = x;
+    D.blk = region + L.blk;
+    D.tile_bytes = L.tile_bytes;
+    for (int k = 0; k < V_COUNT; ++k) D.off_slot[k] = L.off_slot[k];
+    D.part = (double *)(region + L.part);
+    D.hist = L.hist == SIZE_MAX ? nullptr : (double *)(region + L.hist);
+    D.hist_cap = opt->history_cap;
+    D.replace_max = opt->replace_max;
+    D.true_check = opt->true_residual_check;
+    sys_[slot] = D;
+    in_use_[slot] = 1;
+    BatchState S{};
+    S.phase = PH_COPYIN;
+    S.status = RUNNING;
+    h_st_[slot] = S;
+    // descriptor and state go up on the stream, ordered before the next launch
+    BCHK(hipMemcpyAsync(d_sys_ + slot, &sys_[slot], sizeof(BatchSys), hipMemcpyHostToDevice, stream_));
+    BCHK(hipMemcpyAsync(d_st_ + slot, &h_st_[slot], sizeof(BatchState), hipMemcpyHostToDevice, stream_));
+    if (D.hist) BCHK(hipMemsetAsync(D.hist, 0xff, (size_t)D.hist_cap * PCG_HISTORY_FIELDS * 8, stream_));
+    BCHK(hipStreamSynchronize(stream_));  // the host copies above read sys_[slot] / h_st_[slot]
+    tables_dirty_ = true;
+    *slot_out = slot;
+    return PCG_OK;
+}
+
+void BatchEngine::release(int slot)
+{
+    in_use_[slot] = 0;
+    h_st_[slot].phase = PH_FREE;
+    tables_dirty_ = true;
+}
+
+pcg_status BatchEngine::upload_tables()
+{
+    // items of every system still working, in slot order; active list the same
+    uint32_t *isys = h_items_, *itile = h_items_ + max_items_, *act = h_items_ + 2 * max_items_;
+    int64_t ni = 0;
+    int na = 0;
+    for (int s = 0; s < max_sys_; ++s) {
+        listed_[s] = 0;
+        if (!in_use_[s] || h_st_[s].phase >= PH_DONE) continue;
+        listed_[s] = 1;
+        act[na++] = (uint32_t)s;
+        for (int t = 0; t < sys_[s].ntiles; ++t) {
+            if (ni >= max_items_) return PCG_ERR_BUDGET;
+            isys[ni] = (uint32_t)s;
+            itile[ni] = (uint32_t)t;
+            ++ni;
+        }
+    }
+    counts_h_[0] = (int32_t)ni;
+    counts_h_[1] = na;
+    if (ni) {
+        BCHK(hipMemcpyAsync(d_item_sys_, isys, sizeof(uint32_t) * ni, hipMemcpyHostToDevice, stream_));
+        BCHK(hipMemcpyAsync(d_item_tile_, itile, sizeof(uint32_t) * ni, hipMemcpyHostToDevice, stream_));
+    }
+    if (na) BCHK(hipMemcpyAsync(d_active_, act, sizeof(uint32_t) * na, hipMemcpyHostToDevice, stream_));
+    BCHK(hipMemcpyAsync(d_counts_, counts_h_, sizeof(counts_h_), hipMemcpyHostToDevice, stream_));
+    BCHK(hipStreamSynchronize(stream_));
+    tables_dirty_ = false;
+    items_ = ni;
+    active_ = na;
+    return PCG_OK;
+}
+
+void BatchEngine::enqueue_passes(hipStream_t st)
+{
+    BatchTables tb{d_sys_, d_st_, d_item_sys_, d_item_tile_, d_active_, d_counts_};
+    for (int k = 0; k < K_; ++k) {
+        if (prec_ == PCG_FP64) {
+            hipLaunchKernelGGL(k_batch_pass<double>, dim3(pass_grid_), dim3(kBatchBlock), 0, st, tb);
+            hipLaunchKernelGGL(k_batch_final<double>, dim3(final_grid_), dim3(kBatchBlock), 0, st, tb);
+        } else {
+            hipLaunchKernelGGL(k_batch_pass<float>, dim3(pass_grid_), dim3(kBatchBlock), 0, st, tb);
+            hipLaunchKernelGGL(k_batch_final<float>, dim3(final_grid_), dim3(kBatchBlock), 0, st, tb);
+        }
+    }
+}
+
+pcg_status BatchEngine::ensure_graph()
+{
+    if (gexec_) return PCG_OK;
+    hipStream_t cs;
+    BCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cs);
+        return hip_fail(e, "hipStreamBeginCapture");
+    }
+    enqueue_passes(cs);
+    e = hipStreamEndCapture(cs, &graph_);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    BCHK(hipGraphInstantiate(&gexec_, graph_, nullptr, nullptr, 0));
+    return PCG_OK;
+}
+
+pcg_status BatchEngine::step(double *gpu_ms)
+{
+    pcg_status st;
+    if (tables_dirty_ && (st = upload_tables())) return st;
+    if (active_ == 0) return PCG_OK;
+    if ((st = ensure_graph())) return st;
+    BCHK(hipEventRecord(ev0_, stream_));
+    BCHK(hipGraphLaunch(gexec_, stream_));
+    BCHK(hipEventRecord(ev1_, stream_));
+    BCHK(hipMemcpyAsync(h_st_, d_st_, sizeof(BatchState) * max_sys_, hipMemcpyDeviceToHost, stream_));
+    BCHK(hipStreamSynchronize(stream_));
+    float ms = 0.f;
+    BCHK(hipEventElapsedTime(&ms, ev0_, ev1_));
+    if (gpu_ms) *gpu_ms += ms;
+    ++launches_;
+    // drop finished systems from the tables before the next launch
+    for (int s = 0; s < max_sys_; ++s)
+        if (listed_[s] && h_st_[s].phase >= PH_DONE) tables_dirty_ = true;
+    return PCG_OK;
+}
+
+void BatchEngine::result(int slot, pcg_result *r) const
+{
+    const BatchState &S = h_st_[slot];
+    std::memset(r, 0, sizeof(*r));
+    const double bn = std::sqrt(S.bnorm2);
+    r->status = S.status == RUNNING ? PCG_MAX_ITER : S.status;
+    r->iterations = S.iter;
+    r->replacements = S.restarts;
+    r->launches = launches_;
+    r->rel_res_recursive = bn > 0 ? std::sqrt(S.rho) / bn : std::sqrt(S.rho);
+    r->rel_res_true = bn > 0 ? std::sqrt(S.true_res2) / bn : std::sqrt(S.true_res2);
+    r->iter_passes = S.passes;
+    r->sigma = sys_[slot].sigma;
+}
+
+pcg_status BatchEngine::copy_history(int slot, double *host, int cap)
+{
+    const BatchSys &D = sys_[slot];
+    if (!D.hist || !host || cap <= 0) return PCG_OK;
+    BCHK(hipMemcpyAsync(host, D.hist, (size_t)std::min(cap, D.hist_cap) * PCG_HISTORY_FIELDS * 8,
+                        hipMemcpyDeviceToHost, stream_));
+    BCHK(hipStreamSynchronize(stream_));
+    return PCG_OK;
+}
+
+}  // namespace pcg
+
+using namespace pcg;
+
+// ------------------------------------------------------------------ C ABI
+
+static pcg_status batch_plan(int32_t count, const pcg_operator *ops, const pcg_options *opts, size_t *tables,
+                             std::vector<size_t> *offsets, size_t *total, int64_t *items)
+{
+    if (count < 1) return invalid("count must be >= 1");
+    if (!ops || !opts) return invalid("ops and opts must be non-null");
+    size_t off = 0;
+    int64_t ni = 0;
+    std::vector<size_t> sys_off(count);
+    for (int k = 0; k < count; ++k) {
+        pcg_status st = validate_options(&opts[k]);
+        if (st) return st;
+        if ((st = validate_operator(&ops[k], opts[0].prec))) return st;
+        if (opts[k].prec != opts[0].prec) return invalid("every system of a batch must use the same precision");
+        if (opts[k].method == PCG_CG) return invalid("the batched pass runs the pipelined methods");
+        BatchEngine::SysLayout L;
+        BatchEngine::system_layout(&ops[k], &opts[k], &L);
+        sys_off[k] = off;
+        off += L.bytes;
+        ni += L.ntiles;
+    }
+    const size_t tb = (BatchEngine::table_bytes(count, ni) + 255) & ~size_t(255);
+    for (auto &o : sys_off) o += tb;
+    *tables = tb;
+    *total = tb + off;
+    *items = ni;
+    if (offsets) *offsets = sys_off;
+    return PCG_OK;
+}
+
+extern "C" pcg_status pcg_batch_workspace_size(int32_t count, const pcg_operator *ops, const pcg_options *opts,
+                                               size_t *bytes)
+{
+    if (!bytes) return invalid("bytes is null");
+    size_t tables, total;
+    int64_t items;
+    pcg_status st = batch_plan(count, ops, opts, &tables, nullptr, &total, &items);
+    if (st) return st;
+    *bytes = total;
+    return PCG_OK;
+}
+
+extern "C" pcg_status pcg_batch_solve(int32_t count, const pcg_operator *ops, const pcg_options *opts,
+                                      const double *const *b, double *const *x, pcg_result *results, void *workspace,
+                                      size_t bytes, void *hip_stream)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!b || !x || !results) return invalid("b, x and results must be non-null");
+    if (!workspace || ((uintptr_t)workspace % 256)) return invalid("workspace must be non-null and 256-byte aligned");
+    size_t tables, total;
+    int64_t items;
+    std::vector<size_t> offs;
+    pcg_status st = batch_plan(count, ops, opts, &tables, &offs, &total, &items);
+    if (st) return st;
+    if (bytes < total) return invalid("workspace too small");
+    char *ws = (char *)workspace;
+    BatchEngine eng;
+    const int K = opts[0].iters_per_launch ? opts[0].iters_per_launch : 8;
+    if ((st = eng.init(ws, count, items, opts[0].prec, (hipStream_t)hip_stream, K))) return st;
+    if (opts[0].grid_blocks) eng.set_pass_grid(opts[0].grid_blocks);
+    std::vector<int> slot(count);
+    for (int k = 0; k < count; ++k)
+        if ((st = eng.admit(&ops[k], &opts[k], b[k], x[k], ws + offs[k], &slot[k]))) return st;
+    double gpu_ms = 0.0;
+    for (;;) {
+        if ((st = eng.step(&gpu_ms))) return st;
+        bool all = true;
+        for (int k = 0; k < count; ++k)
+            if (!eng.done(slot[k])) {
+                all = false;
+                break;
+            }
+        if (all) break;
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    for (int k = 0; k < count; ++k) {
+        eng.result(slot[k], &results[k]);
+        results[k].seconds = secs;
+        results[k].iter_kernel_ms = gpu_ms;
+        if (opts[k].history_cap > 0 && (st = eng.copy_history(slot[k], opts[k].history, opts[k].history_cap)))
+            return st;
+    }
+    return PCG_OK;
+}

@@ -1,0 +1,83 @@
+// pcg_batch_engine.h -- host side of the batched persistent pass: system
+// slots, device tables, the captured graph of K (pass, finalize) pairs and
+// the step / poll cycle.  Used by pcg_batch_solve and by the server.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+#include "pcg_batch.h"
+
+namespace pcg {
+
+class BatchEngine {
+public:
+    // Byte layout of one system's device region (offsets from its start).
+    struct SysLayout {
+        size_t blk, part, dinv, hist, flag, gersh, bytes;
+        uint32_t tile_bytes;
+        int32_t ntiles;
+        uint32_t off_slot[V_COUNT];
+    };
+
+    BatchEngine() = default;
+    ~BatchEngine();
+    BatchEngine(const BatchEngine &) = delete;
+    BatchEngine &operator=(const BatchEngine &) = delete;
+
+    static size_t table_bytes(int max_sys, int64_t max_items);
+    static pcg_status system_layout(const pcg_operator *op, const pcg_options *opt, SysLayout *L);
+
+    // tables: device memory of table_bytes(max_sys, max_items), 256-aligned.
+    pcg_status init(char *tables, int max_sys, int64_t max_items, int prec, hipStream_t stream, int K);
+    void set_pass_grid(int g) { pass_grid_ = g; }
+    pcg_status validate(const pcg_operator *op, const pcg_options *opt);
+    // Admit a system whose device region (system_layout bytes) starts at
+    // `region`; it joins the batch at the next step.  PCG_ERR_BUDGET when
+    // every slot is taken.
+    pcg_status admit(const pcg_operator *op, const pcg_options *opt, const double *b, double *x, char *region,
+                     int *slot);
+    void release(int slot);
+    // One graph launch (K passes), then the per-system states are read back.
+    pcg_status step(double *gpu_ms);
+    bool done(int slot) const { return h_st_[slot].phase == PH_DONE; }
+    void result(int slot, pcg_result *r) const;
+    pcg_status copy_history(int slot, double *host, int cap);
+    int active() const { return active_; }
+    int64_t items() const { return items_; }
+    int launches() const { return launches_; }
+
+private:
+    pcg_status upload_tables();
+    pcg_status ensure_graph();
+    void enqueue_passes(hipStream_t st);
+
+    int max_sys_ = 0;
+    int64_t max_items_ = 0;
+    int prec_ = 0;
+    int K_ = 8;
+    int pass_grid_ = 1024;   // persistent blocks of the pass (4 per CU)
+    int final_grid_ = 256;
+    hipStream_t stream_ = nullptr;
+    BatchSys *d_sys_ = nullptr;
+    BatchState *d_st_ = nullptr;
+    uint32_t *d_item_sys_ = nullptr, *d_item_tile_ = nullptr, *d_active_ = nullptr;
+    int32_t *d_counts_ = nullptr;
+    std::vector<BatchSys> sys_;
+    std::vector<char> in_use_;
+    std::vector<char> listed_;   // the system's items are in the device tables
+    BatchState *h_st_ = nullptr;  // pinned: admission staging and read-back
+    uint32_t *h_items_ = nullptr; // pinned: item / active table staging
+    int32_t counts_h_[2] = {0, 0};
+    bool tables_dirty_ = true;
+    int64_t items_ = 0;
+    int active_ = 0;
+    int launches_ = 0;
+    hipGraph_t graph_ = nullptr;
+    hipGraphExec_t gexec_ = nullptr;
+    hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+};
+
+}  // namespace pcg

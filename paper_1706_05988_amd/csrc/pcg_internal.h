@@ -44,10 +44,40 @@ struct PassArgsAny {
     alignas(16) unsigned char bytes[320];
 };
 
+template <typename T>
+inline OpDev<T> make_opdev(const pcg_operator *op)
+{
+    OpDev<T> A{};
+    A.n = (int32_t)op->n;
+    A.nx = op->nx;
+    A.ny = op->ny;
+    A.nz = op->kind == PCG_OP_STENCIL3D7 ? op->nz : 1;
+    if (op->kind != PCG_OP_CSR) {
+        A.dx = make_fastdiv((uint32_t)op->nx);
+        A.dxy = make_fastdiv((uint32_t)op->nx * (uint32_t)op->ny);
+    }
+    A.centre = op->diag + op->shift;
+    A.off = op->offdiag;
+    A.row_ptr = op->row_ptr;
+    A.col = op->col_idx;
+    A.val = (const T *)op->vals;
+    return A;
+}
+
 extern thread_local std::string g_last_error;
 pcg_status hip_fail(hipError_t e, const char *what);
 pcg_status invalid(const char *why);
 pcg_status validate_operator(const pcg_operator *op, int prec);
 pcg_status validate_options(const pcg_options *o);
+// Validate a CSR operator's structure on the device (synchronous on stream);
+// with jac, also fill dinv (n values of the storage type) with 1 / a_kk.
+pcg_status csr_setup(const pcg_operator *op, int prec, int jac, void *dinv, int *flag_dev, hipStream_t stream);
+// The shift in use: 0 for CG / p-CG, the caller's sigma, or (NaN) the
+// midpoint of the spectrum bounds of A M^-1 -- closed form for stencils,
+// gersh_host[0..1] (Gershgorin) for CSR.
+double default_sigma(const pcg_operator *op, const pcg_options *opt, const double *gersh_host);
+// Gershgorin bounds of spec(M^-1 A) of a CSR operator (synchronous).
+pcg_status csr_gershgorin(const pcg_operator *op, int prec, int jac, double *scratch_dev, hipStream_t stream,
+                          double *lo, double *hi);
 
 }  // namespace pcg

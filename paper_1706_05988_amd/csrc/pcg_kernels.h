@@ -203,20 +203,23 @@ __device__ __forceinline__ bool pipe_head(const PassArgs<T> &a, double *lds_red,
 // ----------------------------------------------------------------- copy x
 
 template <typename T, int EPT>
+__device__ __forceinline__ void tile_copy_x(const PassArgs<T> &a, int tile)
+{
+    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (!ti.live[j]) continue;
+        double *xi = vp<double>(a, a.off_x, ti.e[j]);
+        if (a.copy_out) a.x_user[ti.e[j]] = *xi;
+        else *xi = a.x_user[ti.e[j]];
+    }
+}
+
+template <typename T, int EPT>
 __global__ void __launch_bounds__(kMaxBlock) k_copy_x(PassArgs<T> a)
 {
-    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (!ti.live[j]) continue;
-            double *xi = vp<double>(a, a.off_x, ti.e[j]);
-            if (a.copy_out) a.x_user[ti.e[j]] = *xi;
-            else *xi = a.x_user[ti.e[j]];
-        }
-    }
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_copy_x<T, EPT>(a, tile);
 }
 
 // ----------------------------------------------------------------- init 0
@@ -225,44 +228,71 @@ __global__ void __launch_bounds__(kMaxBlock) k_copy_x(PassArgs<T> a)
 // preconditioner u_0 := M^-1 r_0 (stored).  Clears the slots in a.clear (so
 // the first iteration's beta = 0 terms are exact zeros).  Partials of (b, b).
 template <typename T, int OP, bool JAC, bool STORE_U, int EPT, bool NT>
+__device__ __forceinline__ void tile_init0(const PassArgs<T> &a, int tile, double (&acc)[1])
+{
+    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+    double be[EPT], ax[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        be[j] = lds<NT>(a.b + ti.e[j]);
+        ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (!ti.live[j]) continue;
+        const uint32_t e = ti.e[j];
+        const double r = rnd<T>(be[j] - ax[j]);
+        sts<NT>(vp<T>(a, a.off_r, e), r);
+        if constexpr (STORE_U) sts<NT>(vp<T>(a, a.off_u, e), minv<T, JAC, OP>(a, e, r));
+        if (a.clear & CLR_Z) sts<NT>(vp<T>(a, a.off_z, e), 0.0);
+        if (a.clear & CLR_Q) sts<NT>(vp<T>(a, a.off_q, e), 0.0);
+        if (a.clear & CLR_S) sts<NT>(vp<T>(a, a.off_s, e), 0.0);
+        if (a.clear & CLR_T) sts<NT>(vp<T>(a, a.off_t, e), 0.0);
+        if (a.clear & CLR_P) sts<NT>(vp<T>(a, a.off_p, e), 0.0);
+        if (a.clear & CLR_WIN) sts<NT>(vp<T>(a, a.off_win, e), 0.0);
+        acc[0] += be[j] * be[j];
+    }
+}
+
+template <typename T, int OP, bool JAC, bool STORE_U, int EPT, bool NT>
 __global__ void __launch_bounds__(kMaxBlock) k_init0(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     double acc[1] = {0.0};
-    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
-        double be[EPT], ax[EPT];
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            be[j] = lds<NT>(a.b + ti.e[j]);
-            ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
-        }
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (!ti.live[j]) continue;
-            const uint32_t e = ti.e[j];
-            const double r = rnd<T>(be[j] - ax[j]);
-            sts<NT>(vp<T>(a, a.off_r, e), r);
-            if constexpr (STORE_U) sts<NT>(vp<T>(a, a.off_u, e), minv<T, JAC, OP>(a, e, r));
-            if (a.clear & CLR_Z) sts<NT>(vp<T>(a, a.off_z, e), 0.0);
-            if (a.clear & CLR_Q) sts<NT>(vp<T>(a, a.off_q, e), 0.0);
-            if (a.clear & CLR_S) sts<NT>(vp<T>(a, a.off_s, e), 0.0);
-            if (a.clear & CLR_T) sts<NT>(vp<T>(a, a.off_t, e), 0.0);
-            if (a.clear & CLR_P) sts<NT>(vp<T>(a, a.off_p, e), 0.0);
-            if (a.clear & CLR_WIN) sts<NT>(vp<T>(a, a.off_win, e), 0.0);
-            acc[0] += be[j] * be[j];
-        }
-    }
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_init0<T, OP, JAC, STORE_U, EPT, NT>(a, tile, acc);
     block_sum<1>(acc, lds_red);
     store_partial<1>(a.part_out, acc);
 }
 
 // ----------------------------------------------------------------- init 1 (pipelined)
 
-// head: ||b||^2 from the init-0 partials; w_0 := A u_0 - sigma r_0 into
-// w_out; partials of gamma_0 = (r, u), delta_0 = (w + sigma r, u), rho_0.
+// w_0 := A u_0 - sigma r_0 into w_out; partials of gamma_0 = (r, u),
+// delta_0 = (w + sigma r, u), rho_0.
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+__device__ __forceinline__ void tile_init1(const PassArgs<T> &a, int tile, double (&acc)[3])
+{
+    const uint32_t off_u = JAC ? a.off_u : a.off_r;
+    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+    double au[EPT], re[EPT], ue[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        au[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return ld(vp<T>(a, off_u, k), 0); });
+        re[j] = lds<NT>(vp<T>(a, a.off_r, ti.e[j]));
+        ue[j] = JAC ? ld(vp<T>(a, off_u, ti.e[j]), 0) : re[j];
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (!ti.live[j]) continue;
+        const double w = rnd<T>(au[j] - a.sigma * re[j]);
+        sts<NT>(vp<T>(a, a.off_wout, ti.e[j]), w);
+        acc[0] += re[j] * ue[j];
+        acc[1] += (w + a.sigma * re[j]) * ue[j];
+        acc[2] += re[j] * re[j];
+    }
+}
+
+// head: ||b||^2 from the init-0 partials; then tile_init1 over the grid.
 // Block 0 writes the state for iteration i0.
 template <typename T, int OP, bool JAC, int EPT, bool NT>
 __global__ void __launch_bounds__(kMaxBlock) k_init1(PassArgs<T> a)
@@ -279,29 +309,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_init1(PassArgs<T> a)
         o.true_res2 = __builtin_nan("");
         *a.st_out = o;
     }
-    const uint32_t off_u = JAC ? a.off_u : a.off_r;
     double acc[3] = {0.0, 0.0, 0.0};
-    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
-        double au[EPT], re[EPT], ue[EPT];
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            au[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return ld(vp<T>(a, off_u, k), 0); });
-            re[j] = lds<NT>(vp<T>(a, a.off_r, ti.e[j]));
-            ue[j] = JAC ? ld(vp<T>(a, off_u, ti.e[j]), 0) : re[j];
-        }
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (!ti.live[j]) continue;
-            const double w = rnd<T>(au[j] - a.sigma * re[j]);
-            sts<NT>(vp<T>(a, a.off_wout, ti.e[j]), w);
-            acc[0] += re[j] * ue[j];
-            acc[1] += (w + a.sigma * re[j]) * ue[j];
-            acc[2] += re[j] * re[j];
-        }
-    }
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_init1<T, OP, JAC, EPT, NT>(a, tile, acc);
     block_sum<3>(acc, lds_red);
     store_partial<3>(a.part_out, acc);
 }
@@ -324,82 +334,86 @@ __global__ void __launch_bounds__(kMaxBlock) k_init1(PassArgs<T> a)
 //     delta_{i+1} = (w_{i+1} + sigma r, u), rho_{i+1} = (r, r).
 // All loads of a tile are issued before any of its stores.
 template <typename T, int OP, bool JAC, int EPT, bool NT>
+__device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, double alpha, double beta,
+                                          double (&acc)[3])
+{
+    const double sigma = a.sigma, as = alpha * sigma;
+    const uint32_t off_u = JAC ? a.off_u : a.off_r;
+    const uint32_t off_q = JAC ? a.off_q : a.off_s;
+    const uint32_t off_p = JAC ? a.off_p : a.off_t;
+    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+    double ne[EPT], we[EPT], re[EPT], ue[EPT], zo[EPT], so[EPT], to[EPT], qo[EPT], po[EPT], xo[EPT];
+    // loads: the stencil / CSR operand w_i (cached), then the streams
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const uint32_t e = ti.e[j];
+        we[j] = ld(vp<T>(a, a.off_win, e), 0);
+        ne[j] = apply_row<OP>(a.A, e, [&](uint32_t k) {
+            return minv<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_win, k), 0));
+        });
+        re[j] = lds<NT>(vp<T>(a, a.off_r, e));
+        zo[j] = lds<NT>(vp<T>(a, a.off_z, e));
+        so[j] = lds<NT>(vp<T>(a, a.off_s, e));
+        to[j] = lds<NT>(vp<T>(a, a.off_t, e));
+        xo[j] = lds<NT>(vp<double>(a, a.off_x, e));
+        if constexpr (JAC) {
+            ue[j] = lds<NT>(vp<T>(a, off_u, e));
+            qo[j] = lds<NT>(vp<T>(a, off_q, e));
+            po[j] = lds<NT>(vp<T>(a, off_p, e));
+        } else {
+            ue[j] = re[j];
+            qo[j] = so[j];
+            po[j] = to[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (!ti.live[j]) continue;
+        const uint32_t e = ti.e[j];
+        const double me = minv<T, JAC, OP>(a, e, we[j]);
+        // beta-recurrences
+        const double z = rnd<T>(ne[j] + beta * zo[j]);
+        const double s = rnd<T>(we[j] + beta * so[j]);
+        const double t = rnd<T>(re[j] + beta * to[j]);
+        double qv = s, pv = t;
+        if constexpr (JAC) {
+            qv = rnd<T>(me + beta * qo[j]);
+            pv = rnd<T>(ue[j] + beta * po[j]);
+        }
+        // alpha-recurrences, the shift terms grouped first
+        const double xn = xo[j] + alpha * pv;
+        const double rn = rnd<T>(re[j] - (alpha * s + as * t));
+        double un = rn;
+        if constexpr (JAC) un = rnd<T>(ue[j] - (alpha * qv + as * pv));
+        const double wn = rnd<T>(we[j] - alpha * z);
+        sts<NT>(vp<T>(a, a.off_z, e), z);
+        sts<NT>(vp<T>(a, a.off_s, e), s);
+        sts<NT>(vp<T>(a, a.off_t, e), t);
+        if constexpr (JAC) {
+            sts<NT>(vp<T>(a, off_q, e), qv);
+            sts<NT>(vp<T>(a, off_p, e), pv);
+            sts<NT>(vp<T>(a, off_u, e), un);
+        }
+        sts<NT>(vp<double>(a, a.off_x, e), xn);
+        sts<NT>(vp<T>(a, a.off_r, e), rn);
+        sts<NT>(vp<T>(a, a.off_wout, e), wn);
+        // next iteration's dot products
+        acc[0] += rn * un;
+        acc[1] += (wn + sigma * rn) * un;
+        acc[2] += rn * rn;
+    }
+}
+
+template <typename T, int OP, bool JAC, int EPT, bool NT>
 __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     PipeScalars sc;
     if (!pipe_head(a, lds_red, sc)) return;
-    const double alpha = sc.alpha, beta = sc.beta;
-    const double sigma = a.sigma, as = alpha * sigma;
-    const uint32_t off_u = JAC ? a.off_u : a.off_r;
-    const uint32_t off_q = JAC ? a.off_q : a.off_s;
-    const uint32_t off_p = JAC ? a.off_p : a.off_t;
     double acc[3] = {0.0, 0.0, 0.0};
-    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
-        double ne[EPT], we[EPT], re[EPT], ue[EPT], zo[EPT], so[EPT], to[EPT], qo[EPT], po[EPT], xo[EPT];
-        // loads: the stencil / CSR operand w_i (cached), then the streams
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            const uint32_t e = ti.e[j];
-            we[j] = ld(vp<T>(a, a.off_win, e), 0);
-            ne[j] = apply_row<OP>(a.A, e, [&](uint32_t k) {
-                return minv<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_win, k), 0));
-            });
-            re[j] = lds<NT>(vp<T>(a, a.off_r, e));
-            zo[j] = lds<NT>(vp<T>(a, a.off_z, e));
-            so[j] = lds<NT>(vp<T>(a, a.off_s, e));
-            to[j] = lds<NT>(vp<T>(a, a.off_t, e));
-            xo[j] = lds<NT>(vp<double>(a, a.off_x, e));
-            if constexpr (JAC) {
-                ue[j] = lds<NT>(vp<T>(a, off_u, e));
-                qo[j] = lds<NT>(vp<T>(a, off_q, e));
-                po[j] = lds<NT>(vp<T>(a, off_p, e));
-            } else {
-                ue[j] = re[j];
-                qo[j] = so[j];
-                po[j] = to[j];
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (!ti.live[j]) continue;
-            const uint32_t e = ti.e[j];
-            const double me = minv<T, JAC, OP>(a, e, we[j]);
-            // beta-recurrences
-            const double z = rnd<T>(ne[j] + beta * zo[j]);
-            const double s = rnd<T>(we[j] + beta * so[j]);
-            const double t = rnd<T>(re[j] + beta * to[j]);
-            double qv = s, pv = t;
-            if constexpr (JAC) {
-                qv = rnd<T>(me + beta * qo[j]);
-                pv = rnd<T>(ue[j] + beta * po[j]);
-            }
-            // alpha-recurrences, the shift terms grouped first
-            const double xn = xo[j] + alpha * pv;
-            const double rn = rnd<T>(re[j] - (alpha * s + as * t));
-            double un = rn;
-            if constexpr (JAC) un = rnd<T>(ue[j] - (alpha * qv + as * pv));
-            const double wn = rnd<T>(we[j] - alpha * z);
-            sts<NT>(vp<T>(a, a.off_z, e), z);
-            sts<NT>(vp<T>(a, a.off_s, e), s);
-            sts<NT>(vp<T>(a, a.off_t, e), t);
-            if constexpr (JAC) {
-                sts<NT>(vp<T>(a, off_q, e), qv);
-                sts<NT>(vp<T>(a, off_p, e), pv);
-                sts<NT>(vp<T>(a, off_u, e), un);
-            }
-            sts<NT>(vp<double>(a, a.off_x, e), xn);
-            sts<NT>(vp<T>(a, a.off_r, e), rn);
-            sts<NT>(vp<T>(a, a.off_wout, e), wn);
-            // next iteration's dot products
-            acc[0] += rn * un;
-            acc[1] += (wn + sigma * rn) * un;
-            acc[2] += rn * rn;
-        }
-    }
+    for (int tile = tr.first; tile < tr.end; tile += tr.step)
+        tile_pipe<T, OP, JAC, EPT, NT>(a, tile, sc.alpha, sc.beta, acc);
     block_sum<3>(acc, lds_red);
     store_partial<3>(a.part_out, acc);
 }
@@ -585,38 +599,41 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_b(PassArgs<T> a)
 // partials of ||b - A x||^2 and ||b||^2 in binary64 (A in its storage
 // precision); x is the internal copy, or the caller's when x_plain is set.
 template <typename T, int OP, int EPT>
+__device__ __forceinline__ void tile_resid(const PassArgs<T> &a, int tile, double (&acc)[2])
+{
+    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+    double be[EPT], ax[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        be[j] = a.b[ti.e[j]];
+        if (a.x_plain)
+            ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return a.x_user[k]; });
+        else
+            ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (!ti.live[j]) continue;
+        const double d = be[j] - ax[j];
+        acc[0] += d * d;
+        acc[1] += be[j] * be[j];
+    }
+}
+
+template <typename T, int OP, int EPT>
 __global__ void __launch_bounds__(kMaxBlock) k_resid(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     double acc[2] = {0.0, 0.0};
-    const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-        const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
-        double be[EPT], ax[EPT];
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            be[j] = a.b[ti.e[j]];
-            if (a.x_plain)
-                ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return a.x_user[k]; });
-            else
-                ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
-        }
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (!ti.live[j]) continue;
-            const double d = be[j] - ax[j];
-            acc[0] += d * d;
-            acc[1] += be[j] * be[j];
-        }
-    }
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_resid<T, OP, EPT>(a, tile, acc);
     block_sum<2>(acc, lds_red);
     store_partial<2>(a.part_out, acc);
 }
 
 // One block: stage 2 of `nparts` residual partials into out->true_res2 and
 // out->spare[0] (= ||b||^2).
-__global__ void __launch_bounds__(1024) k_reduce_true(const double *part, int nparts, DevState *out)
+static __global__ void __launch_bounds__(1024) k_reduce_true(const double *part, int nparts, DevState *out)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     double tot[2];

@@ -229,26 +229,6 @@ static_assert(sizeof(PassArgs<float>) <= sizeof(PassArgsAny), "PassArgsAny too s
 
 namespace {
 
-template <typename T>
-OpDev<T> make_opdev(const pcg_operator *op)
-{
-    OpDev<T> A{};
-    A.n = (int32_t)op->n;
-    A.nx = op->nx;
-    A.ny = op->ny;
-    A.nz = op->kind == PCG_OP_STENCIL3D7 ? op->nz : 1;
-    if (op->kind != PCG_OP_CSR) {
-        A.dx = make_fastdiv((uint32_t)op->nx);
-        A.dxy = make_fastdiv((uint32_t)op->nx * (uint32_t)op->ny);
-    }
-    A.centre = op->diag + op->shift;
-    A.off = op->offdiag;
-    A.row_ptr = op->row_ptr;
-    A.col = op->col_idx;
-    A.val = (const T *)op->vals;
-    return A;
-}
-
 using LaunchFn = void (*)(PassArgsAny, int, int, hipStream_t);
 
 // Kernel table for one (T, OP, JAC, EPT, NT) combination.
@@ -468,6 +448,60 @@ pcg_status pcg_solver_::run_true_residual(const double *b, const double *x_plain
     return PCG_OK;
 }
 
+// ------------------------------------------------------------- CSR set-up
+
+namespace pcg {
+
+pcg_status csr_setup(const pcg_operator *op, int prec, int jac, void *dinv, int *flag, hipStream_t stream)
+{
+    // validate the structure on the device before any pass reads it
+    HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), stream));
+    if (prec == PCG_FP64)
+        hipLaunchKernelGGL(k_csr_check<double>, dim3(kGershBlocks), dim3(256), 0, stream, make_opdev<double>(op), jac,
+                           op->nnz, flag);
+    else
+        hipLaunchKernelGGL(k_csr_check<float>, dim3(kGershBlocks), dim3(256), 0, stream, make_opdev<float>(op), jac,
+                           op->nnz, flag);
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (bad) return invalid("CSR structure invalid (row_ptr, col_idx or missing diagonal)");
+    if (jac) {
+        const int g = (int)((op->n + 255) / 256);
+        if (prec == PCG_FP64)
+            hipLaunchKernelGGL(k_jacobi<double>, dim3(g), dim3(256), 0, stream, make_opdev<double>(op), (double *)dinv);
+        else
+            hipLaunchKernelGGL(k_jacobi<float>, dim3(g), dim3(256), 0, stream, make_opdev<float>(op), (float *)dinv);
+    }
+    HIPCHK(hipGetLastError());
+    return PCG_OK;
+}
+
+pcg_status csr_gershgorin(const pcg_operator *op, int prec, int jac, double *gb, hipStream_t stream, double *lo,
+                          double *hi)
+{
+    if (prec == PCG_FP64)
+        hipLaunchKernelGGL(k_gershgorin<double>, dim3(kGershBlocks), dim3(256), 0, stream, make_opdev<double>(op), jac,
+                           gb);
+    else
+        hipLaunchKernelGGL(k_gershgorin<float>, dim3(kGershBlocks), dim3(256), 0, stream, make_opdev<float>(op), jac,
+                           gb);
+    HIPCHK(hipGetLastError());
+    std::vector<double> h(2 * kGershBlocks);
+    HIPCHK(hipMemcpyAsync(h.data(), gb, h.size() * 8, hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    double l = INFINITY, u = -INFINITY;
+    for (int k = 0; k < kGershBlocks; ++k) {
+        l = std::fmin(l, h[2 * k]);
+        u = std::fmax(u, h[2 * k + 1]);
+    }
+    *lo = std::fmax(l, 0.0);  // SPD: the spectrum is positive
+    *hi = u;
+    return PCG_OK;
+}
+
+}  // namespace pcg
+
 // ------------------------------------------------------------- C ABI
 
 extern "C" pcg_status pcg_workspace_size(const pcg_operator *op, const pcg_options *opt, size_t *bytes)
@@ -480,7 +514,7 @@ extern "C" pcg_status pcg_workspace_size(const pcg_operator *op, const pcg_optio
     return PCG_OK;
 }
 
-static double default_sigma(const pcg_operator *op, const pcg_options *opt, const double *gersh_host)
+double pcg::default_sigma(const pcg_operator *op, const pcg_options *opt, const double *gersh_host)
 {
     if (opt->method != PCG_PIPE_SHIFT) return 0.0;
     if (!std::isnan(opt->sigma)) return opt->sigma;
@@ -539,51 +573,14 @@ extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const 
 
     double gersh[2] = {0.0, 0.0};
     if (op->kind == PCG_OP_CSR) {
-        // validate the CSR structure on the device before any pass reads it
-        int *flag = reinterpret_cast<int *>(s->ws + L.flag);
-        if ((he = hipMemsetAsync(flag, 0, sizeof(int), s->stream)) != hipSuccess) return fail(hip_fail(he, "memset"));
-        const int need_diag = opt->pc == PCG_PC_JACOBI;
-        if (opt->prec == PCG_FP64)
-            hipLaunchKernelGGL(k_csr_check<double>, dim3(kGershBlocks), dim3(256), 0, s->stream,
-                               make_opdev<double>(op), need_diag, op->nnz, flag);
-        else
-            hipLaunchKernelGGL(k_csr_check<float>, dim3(kGershBlocks), dim3(256), 0, s->stream,
-                               make_opdev<float>(op), need_diag, op->nnz, flag);
-        int bad = 0;
-        if ((he = hipMemcpyAsync(&bad, flag, sizeof(int), hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
-            return fail(hip_fail(he, "copy"));
-        if ((he = hipStreamSynchronize(s->stream)) != hipSuccess) return fail(hip_fail(he, "sync"));
-        if (bad) return fail(invalid("CSR structure invalid (row_ptr, col_idx or missing diagonal)"));
-        if (opt->pc == PCG_PC_JACOBI) {
-            const int g = (int)((op->n + 255) / 256);
-            if (opt->prec == PCG_FP64)
-                hipLaunchKernelGGL(k_jacobi<double>, dim3(g), dim3(256), 0, s->stream, make_opdev<double>(op),
-                                   reinterpret_cast<double *>(s->ws + L.dinv));
-            else
-                hipLaunchKernelGGL(k_jacobi<float>, dim3(g), dim3(256), 0, s->stream, make_opdev<float>(op),
-                                   reinterpret_cast<float *>(s->ws + L.dinv));
-        }
-        if (opt->method == PCG_PIPE_SHIFT && std::isnan(opt->sigma)) {
-            double *gb = reinterpret_cast<double *>(s->ws + L.gersh);
-            if (opt->prec == PCG_FP64)
-                hipLaunchKernelGGL(k_gershgorin<double>, dim3(kGershBlocks), dim3(256), 0, s->stream,
-                                   make_opdev<double>(op), need_diag, gb);
-            else
-                hipLaunchKernelGGL(k_gershgorin<float>, dim3(kGershBlocks), dim3(256), 0, s->stream,
-                                   make_opdev<float>(op), need_diag, gb);
-            std::vector<double> h(2 * kGershBlocks);
-            if ((he = hipMemcpyAsync(h.data(), gb, h.size() * 8, hipMemcpyDeviceToHost, s->stream)) != hipSuccess)
-                return fail(hip_fail(he, "copy"));
-            if ((he = hipStreamSynchronize(s->stream)) != hipSuccess) return fail(hip_fail(he, "sync"));
-            gersh[0] = INFINITY;
-            gersh[1] = -INFINITY;
-            for (int k = 0; k < kGershBlocks; ++k) {
-                gersh[0] = std::fmin(gersh[0], h[2 * k]);
-                gersh[1] = std::fmax(gersh[1], h[2 * k + 1]);
-            }
-            gersh[0] = std::fmax(gersh[0], 0.0);  // SPD: the spectrum is positive
-        }
-        if ((he = hipGetLastError()) != hipSuccess) return fail(hip_fail(he, "setup kernels"));
+        const int jac = opt->pc == PCG_PC_JACOBI;
+        if ((st = csr_setup(op, opt->prec, jac, jac ? s->ws + L.dinv : nullptr, reinterpret_cast<int *>(s->ws + L.flag),
+                            s->stream)))
+            return fail(st);
+        if (opt->method == PCG_PIPE_SHIFT && std::isnan(opt->sigma) &&
+            (st = csr_gershgorin(op, opt->prec, jac, reinterpret_cast<double *>(s->ws + L.gersh), s->stream, &gersh[0],
+                                 &gersh[1])))
+            return fail(st);
     }
     s->sigma = default_sigma(op, opt, gersh);
     *out = s;

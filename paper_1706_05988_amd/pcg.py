@@ -320,3 +320,32 @@ def result_dict(r: pcg_result, hist=None) -> dict:
         d.update(res=hist[:k, 0].copy(), alpha=hist[:k, 1].copy(), beta=hist[:k, 2].copy(),
                  gamma=hist[:k, 3].copy(), delta=hist[:k, 4].copy())
     return d
+
+
+class Batch:
+    """A batch of independent systems solved by pcg_batch_solve: device
+    operators, torch-allocated workspace, per-system options."""
+
+    def __init__(self, ops, options, device="cuda"):
+        import numpy as np
+        torch = _torch()
+        self.devs = [DeviceOperator(op, o.prec, device) for op, o in zip(ops, options)]
+        self.opts = list(options)
+        self.hists = []
+        for o in self.opts:
+            if o.history_cap > 0:
+                h = np.full((o.history_cap, PCG_HISTORY_FIELDS), np.nan)
+                o.history = h.ctypes.data
+                self.hists.append(h)
+            else:
+                self.hists.append(None)
+        self.structs = [d.struct for d in self.devs]
+        self.nbytes = pcg_batch_workspace_size(self.structs, self.opts)
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        self.ws_ptr = (self.ws.data_ptr() + 255) & ~255
+
+    def solve(self, bs, xs, stream: Optional[int] = None) -> list:
+        st = current_stream_handle() if stream is None else stream
+        res = pcg_batch_solve(self.structs, self.opts, [b.data_ptr() for b in bs], [x.data_ptr() for x in xs],
+                              self.ws_ptr, self.nbytes, st)
+        return [result_dict(r, h) for r, h in zip(res, self.hists)]

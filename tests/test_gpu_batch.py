@@ -1,0 +1,106 @@
+"""The batched persistent pass (pcg_batch_solve) against the oracle, and the
+independence of each system's result from the rest of the batch."""
+import numpy as np
+import pytest
+
+import oracle
+import problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def opts_for(P, p, fp32=False, hist=True, **kw):
+    mi = kw.pop("max_iter", p.max_iter)
+    return P.make_options(method=kw.pop("method", "pipe_shift"), jacobi=p.jacobi, fp32=fp32, sigma=p.sigma,
+                          rtol=kw.pop("rtol", p.rtol), max_iter=mi, history_cap=(mi + 2) if hist else 0, **kw)
+
+
+def run_batch(torch, probs, fp32=False, **kw):
+    from paper_1706_05988_amd import pcg as P
+    opts = [opts_for(P, p, fp32=fp32, **dict(kw)) for p in probs]
+    B = P.Batch([p.op for p in probs], opts)
+    bs = [torch.from_numpy(p.b).cuda() for p in probs]
+    xs = [torch.from_numpy(p.x0).clone().cuda() for p in probs]
+    res = B.solve(bs, xs)
+    torch.cuda.synchronize()
+    for r, x in zip(res, xs):
+        r["x"] = x.cpu().numpy()
+    return res
+
+
+def mixed_set():
+    ps = []
+    for k, (nx, ny) in enumerate([(37, 11), (64, 64), (5, 3), (130, 41)]):
+        op = problems.stencil2d(nx, ny, shift=0.01 * (k + 1))
+        b = np.random.default_rng(k).uniform(-1, 1, op.n)
+        ps.append(problems.Problem(f"r{k}", op, b, np.zeros(op.n), None, sigma=4.0 + op.shift, rtol=1e-10,
+                                   max_iter=3000))
+    ps.append(problems.poisson3d(19, seed=3))
+    ps.append(problems.anisotropic_csr(24, seed=2))
+    ps[-1].rtol, ps[-1].max_iter = 1e-10, 5000
+    ps.append(problems.banded_csr(3001, seed=4))
+    ps[-1].rtol = 1e-10
+    return ps
+
+
+def test_batch_matches_oracle_fp64(torch):
+    ps = mixed_set()
+    res = run_batch(torch, ps, true_residual_check=False)
+    for p, g in zip(ps, res):
+        o = oracle.solve(p.op, p.b, p.x0, method="pipe_shift", sigma=p.sigma, rtol=p.rtol, max_iter=p.max_iter,
+                         jacobi=p.jacobi)
+        assert g["status"] == o["status"] == "converged", p.name
+        assert abs(g["iterations"] - o["iterations"]) <= 2, p.name
+        k = min(40, o["iterations"], g["iterations"])
+        below = np.nonzero(o["res"][: k + 1] < 1e-12)[0]
+        if below.size:
+            k = max(1, int(below[0]) - 1)
+        np.testing.assert_allclose(g["res"][: k + 1], o["res"][: k + 1], rtol=1e-9, err_msg=p.name)
+        assert g["rel_res_true"] <= max(2 * o["rel_res_true"], 1e-11), p.name
+
+
+def test_batch_result_independent_of_batch_mix(torch):
+    """A system's tiling and reduction order depend only on itself: solved
+    alone or inside a batch it gives the same bits."""
+    ps = mixed_set()
+    together = run_batch(torch, ps)
+    for k in (0, 4, 6):
+        alone = run_batch(torch, [ps[k]])[0]
+        assert np.array_equal(alone["x"], together[k]["x"]), ps[k].name
+        assert alone["iterations"] == together[k]["iterations"]
+        assert np.array_equal(alone["res"], together[k]["res"], equal_nan=True)
+
+
+def test_batch_fp32_stream_with_restarts(torch):
+    """FP32-stream batch: every system reaches the tolerance through
+    restarts from its binary64 x."""
+    ps = problems.batch_rectangles(24, seed=3, side_min=16, side_max=80)
+    res = run_batch(torch, ps, fp32=True, replace_max=10, hist=False)
+    for p, g in zip(ps, res):
+        assert g["status"] == "converged", p.name
+        assert g["rel_res_true"] <= 1e-8, (p.name, g["rel_res_true"])
+
+
+def test_batch_fp32_attainable_accuracy_vs_oracle_emulation(torch):
+    ps = problems.batch_rectangles(6, seed=5, side_min=20, side_max=60)
+    res = run_batch(torch, ps, fp32=True, rtol=1e-30, max_iter=300, true_residual_check=False)
+    for p, g in zip(ps, res):
+        o = oracle.solve(p.op, p.b, p.x0, method="pipe_shift", sigma=p.sigma, rtol=1e-30, max_iter=300,
+                         fp32_storage=True, ignore_breakdown=True)
+        assert g["rel_res_true"] <= 10 * o["rel_res_true"], p.name
+
+
+def test_batch_status_edge_cases(torch):
+    ps = mixed_set()[:3]
+    ps[1] = problems.Problem("capped", ps[1].op, ps[1].b, ps[1].x0, None, sigma=ps[1].sigma, rtol=1e-12,
+                             max_iter=5)
+    res = run_batch(torch, ps)
+    assert res[1]["status"] == "max_iter" and res[1]["iterations"] == 5
+    assert res[0]["status"] == "converged" and res[2]["status"] == "converged"

@@ -61,7 +61,7 @@ def check_history(g, o, upto=50, rtol=1e-10):
     k = min(upto, len(o["res"]) - 1, len(g["res"]) - 1)
     below = np.nonzero(o["res"][: k + 1] < 1e-12)[0]
     if below.size:
-        k = max(1, int(below[0]))
+        k = max(1, int(below[0]) - 1)
     np.testing.assert_allclose(g["res"][: k + 1], o["res"][: k + 1], rtol=rtol)
     # alpha and beta of the same iterations
     np.testing.assert_allclose(g["alpha"][:k], o["alpha"][:k], rtol=rtol)
