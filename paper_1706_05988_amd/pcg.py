@@ -349,3 +349,50 @@ class Batch:
         res = pcg_batch_solve(self.structs, self.opts, [b.data_ptr() for b in bs], [x.data_ptr() for x in xs],
                               self.ws_ptr, self.nbytes, st)
         return [result_dict(r, h) for r, h in zip(res, self.hists)]
+
+
+class Server:
+    """A continuously batching solve server over a torch-allocated HBM arena."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 256, device="cuda", stream: Optional[int] = None):
+        torch = _torch()
+        self.arena = torch.empty(int(arena_bytes) + 256, dtype=torch.uint8, device=device)
+        self.arena_ptr = (self.arena.data_ptr() + 255) & ~255
+        self.device = device
+        st = current_stream_handle() if stream is None else stream
+        self.handle = pcg_server_create(self.arena_ptr, int(arena_bytes), int(max_slots), st)
+        self._keep = {}
+
+    def submit(self, op, options: pcg_options, b, x) -> int:
+        """Enqueue a solve; b, x are device tensors (binary64) kept alive by
+        the server object until the ticket is collected."""
+        import numpy as np
+        dev = DeviceOperator(op, options.prec, self.device)
+        hist = None
+        if options.history_cap > 0:
+            hist = np.full((options.history_cap, PCG_HISTORY_FIELDS), np.nan)
+            options.history = hist.ctypes.data
+        t = pcg_submit(self.handle, dev.struct, options, b.data_ptr(), x.data_ptr())
+        self._keep[t] = (dev, options, b, x, hist)
+        return t
+
+    def poll(self, ticket: int):
+        r = pcg_poll(self.handle, ticket)
+        if r is None:
+            return None
+        return result_dict(r, self._keep.pop(ticket)[4])
+
+    def wait(self, ticket: int) -> dict:
+        r = pcg_wait(self.handle, ticket)
+        return result_dict(r, self._keep.pop(ticket)[4])
+
+    def close(self):
+        if self.handle:
+            pcg_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

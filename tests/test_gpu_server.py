@@ -1,0 +1,119 @@
+"""The continuously batching server: results equal the same solve alone,
+requests join while others run, admission respects the HBM budget."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import problems
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def request_set():
+    ps = []
+    for k, (nx, ny) in enumerate([(40, 17), (64, 64), (9, 7), (100, 30)]):
+        op = problems.stencil2d(nx, ny, shift=0.02 * (k + 1))
+        b = np.random.default_rng(10 + k).uniform(-1, 1, op.n)
+        ps.append(problems.Problem(f"r{k}", op, b, np.zeros(op.n), None, sigma=4.0 + op.shift, rtol=1e-8,
+                                   max_iter=4000))
+    ps.append(problems.poisson3d(21, seed=8))
+    ps[-1].rtol = 1e-8
+    ps.append(problems.banded_csr(4000, seed=9))
+    ps.append(problems.anisotropic_csr(20, seed=3))
+    ps[-1].rtol = 1e-8
+    return ps
+
+
+def opts(P, p, fp32=True):
+    return P.make_options(method="pipe_shift", jacobi=p.jacobi, fp32=fp32, sigma=p.sigma, rtol=p.rtol,
+                          max_iter=p.max_iter, replace_max=8, history_cap=64)
+
+
+def solve_alone(torch, P, p):
+    srv = P.Server(64 << 20, max_slots=4)
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.zeros_like(b)
+    r = srv.wait(srv.submit(p.op, opts(P, p), b, x))
+    r["x"] = x.cpu().numpy()
+    srv.close()
+    return r
+
+
+def test_server_results_equal_alone(torch):
+    from paper_1706_05988_amd import pcg as P
+    ps = request_set()
+    srv = P.Server(256 << 20, max_slots=16)
+    bs = [torch.from_numpy(p.b).cuda() for p in ps]
+    xs = [torch.zeros_like(b) for b in bs]
+    tickets = [srv.submit(p.op, opts(P, p), b, x) for p, b, x in zip(ps, bs, xs)]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for p, r, x in zip(ps, res, xs):
+        assert r["status"] == "converged", p.name
+        assert r["rel_res_true"] <= 1e-8, (p.name, r["rel_res_true"])
+        alone = solve_alone(torch, P, p)
+        assert np.array_equal(alone["x"], x.cpu().numpy()), p.name
+        assert alone["iterations"] == r["iterations"]
+
+
+def test_server_admits_while_running_and_respects_budget(torch):
+    """Arrivals spread in time join the running batch; a small arena holds
+    only a few systems at once, so the rest wait for memory."""
+    from paper_1706_05988_amd import pcg as P
+    ps = request_set() * 3
+    srv = P.Server(6 << 20, max_slots=64)  # a few MB: admission by footprint matters
+    bs = [torch.from_numpy(p.b).cuda() for p in ps]
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    tickets = []
+
+    def producer():
+        for p, b, x in zip(ps, bs, xs):
+            tickets.append(srv.submit(p.op, opts(P, p), b, x))
+            time.sleep(0.002)
+
+    th = threading.Thread(target=producer)
+    th.start()
+    th.join()
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    for p, r in zip(ps, res):
+        assert r["status"] == "converged", p.name
+        assert r["rel_res_true"] <= 1e-8
+    # identical requests give identical bits whenever they ran
+    n = len(request_set())
+    for k in range(n):
+        assert np.array_equal(xs[k].cpu().numpy(), xs[k + n].cpu().numpy())
+        assert np.array_equal(xs[k].cpu().numpy(), xs[k + 2 * n].cpu().numpy())
+
+
+def test_server_budget_error_and_poll(torch):
+    from paper_1706_05988_amd import pcg as P
+    srv = P.Server(2 << 20, max_slots=4)
+    big = problems.poisson3d(64, seed=1)  # needs far more than 2 MB
+    b = torch.from_numpy(big.b).cuda()
+    x = torch.zeros_like(b)
+    with pytest.raises(P.PcgError) as ei:
+        srv.submit(big.op, opts(P, big), b, x)
+    assert ei.value.status == P.PCG_ERR_BUDGET
+    p = request_set()[2]
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.zeros_like(b)
+    t = srv.submit(p.op, opts(P, p), b, x)
+    r = None
+    for _ in range(2000):
+        r = srv.poll(t)
+        if r is not None:
+            break
+        time.sleep(0.001)
+    assert r is not None and r["status"] == "converged"
+    srv.close()
