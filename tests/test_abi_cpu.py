@@ -1,0 +1,118 @@
+"""The C ABI without a GPU: the library loads, exports every function
+include/pcg.h declares, and rejects invalid arguments before any device
+work (these paths make no HIP call)."""
+import ctypes as C
+import math
+
+import pytest
+
+from paper_1706_05988_amd import pcg as P
+
+
+def test_library_exports_every_declared_function():
+    lib = P.lib()
+    declared = P.header_functions()
+    assert len(declared) >= 15
+    missing = [f for f in declared if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_binding_names_match_header():
+    for f in P.header_functions():
+        assert hasattr(P, f), f
+
+
+def test_status_strings():
+    assert P.pcg_status_str(P.PCG_OK) == "ok"
+    assert "invalid" in P.pcg_status_str(P.PCG_ERR_INVALID)
+    assert P.pcg_status_str(12345) == "unknown status"
+
+
+def stencil_op(kind=P.PCG_OP_STENCIL3D7, nx=16, ny=16, nz=16):
+    op = P.pcg_operator()
+    op.kind, op.nx, op.ny, op.nz = kind, nx, ny, nz
+    op.n = nx * ny * nz
+    op.diag, op.offdiag = 6.0, -1.0
+    return op
+
+
+def test_workspace_size_scales_with_vectors():
+    op = stencil_op()
+    o = P.make_options()
+    base = P.pcg_workspace_size(op, o)
+    o.pc = P.PCG_PC_JACOBI
+    jac = P.pcg_workspace_size(op, o)
+    o.prec = P.PCG_FP32_STREAM
+    f32 = P.pcg_workspace_size(op, o)
+    assert jac > base > 0 and f32 < jac
+    # 10 blocked slots (x + 9 vectors) of binary64 per unknown, plus small tables
+    assert jac >= op.n * 8 * 10
+
+
+@pytest.mark.parametrize("field,value", [
+    ("n", 0), ("nx", 0), ("kind", 7), ("n", 17),
+])
+def test_invalid_operator(field, value):
+    op = stencil_op()
+    setattr(op, field, value)
+    with pytest.raises(P.PcgError) as ei:
+        P.pcg_workspace_size(op, P.make_options())
+    assert ei.value.status == P.PCG_ERR_INVALID
+
+
+@pytest.mark.parametrize("field,value", [
+    ("method", 5), ("pc", 3), ("prec", 2), ("max_iter", -1), ("rtol", 0.0), ("rtol", math.inf),
+    ("sigma", -1.0), ("iters_per_launch", 3), ("block_size", 96), ("block_size", 512), ("history_cap", 4),
+    ("replace_max", -2),
+])
+def test_invalid_options(field, value):
+    o = P.make_options()
+    setattr(o, field, value)
+    with pytest.raises(P.PcgError) as ei:
+        P.pcg_workspace_size(stencil_op(), o)
+    assert ei.value.status == P.PCG_ERR_INVALID
+    assert "invalid argument" in P.pcg_last_error()
+
+
+def test_csr_needs_arrays():
+    op = P.pcg_operator()
+    op.kind, op.n, op.nnz = P.PCG_OP_CSR, 10, 10
+    with pytest.raises(P.PcgError):
+        P.pcg_workspace_size(op, P.make_options())
+
+
+def test_create_rejects_before_device_work():
+    op = stencil_op()
+    o = P.make_options()
+    need = P.pcg_workspace_size(op, o)
+    lib = P.lib()
+    h = C.c_void_p()
+    # null workspace, misaligned workspace, too small workspace
+    assert lib.pcg_create(C.byref(h), C.byref(op), C.byref(o), None, need, None) == P.PCG_ERR_INVALID
+    assert lib.pcg_create(C.byref(h), C.byref(op), C.byref(o), 0x1008, need, None) == P.PCG_ERR_INVALID
+    assert lib.pcg_create(C.byref(h), C.byref(op), C.byref(o), 0x100000, need - 256, None) == P.PCG_ERR_INVALID
+    assert lib.pcg_solve(None, None, None, None) == P.PCG_ERR_STATE
+    assert lib.pcg_destroy(None) == P.PCG_OK
+
+
+def test_batch_rejects_cg_and_mixed_precision():
+    op = stencil_op()
+    a, b = P.make_options(), P.make_options(method="cg")
+    with pytest.raises(P.PcgError):
+        P.pcg_batch_workspace_size([op, op], [a, b])
+    c = P.make_options(fp32=True)
+    with pytest.raises(P.PcgError):
+        P.pcg_batch_workspace_size([op, op], [a, c])
+    n1 = P.pcg_batch_workspace_size([op], [a])
+    n2 = P.pcg_batch_workspace_size([op, op], [a, a])
+    assert n2 > n1
+
+
+def test_server_argument_checks():
+    lib = P.lib()
+    h = C.c_void_p()
+    assert lib.pcg_server_create(C.byref(h), None, 1 << 20, 4, None) == P.PCG_ERR_INVALID
+    assert lib.pcg_server_create(C.byref(h), 0x1000, 1 << 20, 0, None) == P.PCG_ERR_INVALID
+    r = P.pcg_result()
+    assert lib.pcg_poll(None, 1, C.byref(r)) == P.PCG_ERR_STATE
+    assert lib.pcg_server_destroy(None) == P.PCG_OK
