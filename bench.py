@@ -163,6 +163,156 @@ def ingest_profiles(trace_dir: str, fetch_dir: str, write_dir: str, kernel: str,
     return out
 
 
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v), q)) if len(v) else None
+
+
+def bench_batched(P, torch, count: int = 512, seed: int = 0) -> dict:
+    """The 512-system batch: 2-D rectangles with sides U{32..256}, A = L + c I,
+    FP32-stream shifted p-CG to 1e-8 (binary64 explicit check) in one
+    persistent pass per iteration, against the same systems solved one after
+    another, one launch sequence per system, with plain binary64 CG."""
+    import numpy as np
+    import problems
+    ps = problems.batch_rectangles(count, seed=seed)
+    bs = [torch.from_numpy(p.b).cuda() for p in ps]
+    xs = [torch.zeros_like(b) for b in bs]
+    opts = [P.make_options(method="pipe_shift", fp32=True, sigma=p.sigma, rtol=1e-8, max_iter=20000,
+                           replace_max=8) for p in ps]
+    B = P.Batch([p.op for p in ps], opts)
+    B.solve(bs, xs)  # warm-up (graph capture, first touch)
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = B.solve(bs, xs)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    its = np.array([r["iterations"] for r in res])
+    # comparator: each system alone, binary64 classic CG, solvers created up front
+    solvers = [P.Solver(p.op, P.make_options(method="cg", rtol=1e-8, max_iter=20000)) for p in ps]
+    ys = [torch.zeros_like(b) for b in bs]
+    solvers[0].solve(bs[0], ys[0])
+    ys[0].zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [sv.solve(b, y) for sv, b, y in zip(solvers, bs, ys)]
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t0
+    for sv in solvers:
+        sv.close()
+    return {
+        "workload": f"{count} 2-D Poisson rectangles (sides U{{32..256}}, A = L + cI, c ~ U(0, 0.1)), "
+                    f"sum n = {sum(p.op.n for p in ps)}, FP32-stream shifted p-CG sigma = 4 + c to 1e-8",
+        "solves_per_s": count / t_batch,
+        "seconds": t_batch,
+        "converged": int(sum(r["status"] == "converged" for r in res)),
+        "max_true_residual": float(max(r["rel_res_true"] for r in res)),
+        "iterations_min_median_max": [int(its.min()), int(np.median(its)), int(its.max())],
+        "sequential_fp64_cg": {"solves_per_s": count / t_seq, "seconds": t_seq,
+                               "max_true_residual": float(max(r["rel_res_true"] for r in seq))},
+        "speedup_vs_sequential": t_seq / t_batch,
+    }
+
+
+def _serving_pool(log10_max: float, seed: int):
+    """Operators for the serving stream: sizes on a grid of quarter decades
+    from 1e3 to 10^log10_max; per size a 3-D cube (side round(n^(1/3))) and a
+    random banded CSR matrix (generated once, shared by the requests that draw
+    that size class)."""
+    import numpy as np
+    import problems
+    levels = np.arange(3.0, log10_max + 1e-9, 0.25)
+    pool = {}
+    for lv in levels:
+        n = int(round(10 ** lv))
+        side = max(2, int(round(n ** (1.0 / 3.0))))
+        pool[(lv, "3d7")] = problems.stencil3d(side)
+        pool[(lv, "csr")] = problems.banded_csr(n, seed=seed + int(lv * 100)).op
+    return levels, pool
+
+
+def bench_serving(P, torch, count: int, log10_max: float, seed: int = 0) -> dict:
+    """Poisson arrivals of FP32-stream shifted p-CG requests (to 1e-8, binary64
+    explicit check): half 3-D cubes with Jacobi, half banded CSR with Jacobi,
+    sigma = 1, sizes log-uniform (quantised to quarter decades).  First a
+    saturated run (all requests at t = 0) measures capacity; then arrivals at
+    0.7 x that rate give p50 / p99 latency (arrival -> result).  Comparator:
+    the same requests solved one at a time in arrival order with plain
+    binary64 CG, latencies from a FIFO schedule of their measured service
+    times against the same arrival times."""
+    import numpy as np
+    levels, pool = _serving_pool(log10_max, seed)
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for k in range(count):
+        lv = levels[np.abs(levels - rng.uniform(3.0, log10_max)).argmin()]
+        kind = "3d7" if rng.uniform() < 0.5 else "csr"
+        op = pool[(lv, kind)]
+        b = torch.from_numpy(rng.uniform(-1.0, 1.0, op.n)).cuda()
+        reqs.append((op, b))
+    arena = int(16 << 30)
+
+    def opts():
+        return P.make_options(method="pipe_shift", jacobi=True, fp32=True, sigma=1.0, rtol=1e-8,
+                              max_iter=20000, replace_max=8)
+
+    def run(arrivals):
+        srv = P.Server(arena, max_slots=512)
+        xs = [torch.zeros_like(b) for _, b in reqs]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = []
+        for (op, b), x, ta in zip(reqs, xs, arrivals):
+            dt = t0 + ta - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            tickets.append(srv.submit(op, opts(), b, x))
+        res = [srv.wait(t) for t in tickets]
+        total = time.perf_counter() - t0
+        srv.close()
+        return res, total
+
+    run([0.0] * min(8, count))  # warm-up
+    sat, t_sat = run([0.0] * count)
+    capacity = count / t_sat
+    rate = 0.7 * capacity
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
+    live, t_live = run(list(arrivals))
+    lat = [r["seconds"] for r in live]
+    # comparator: one request at a time, binary64 CG, service times measured alone
+    service = []
+    for op, b in reqs:
+        sv = P.Solver(op, P.make_options(method="cg", jacobi=True, rtol=1e-8, max_iter=20000))
+        y = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv.solve(b, y)
+        torch.cuda.synchronize()
+        service.append(time.perf_counter() - t0)
+        sv.close()
+    done, fifo_lat = 0.0, []
+    for ta, sv_t in zip(arrivals, service):
+        start = max(done, ta)
+        done = start + sv_t
+        fifo_lat.append(done - ta)
+    return {
+        "workload": f"{count} requests, n log-uniform 1e3..1e{log10_max:g} (quarter-decade size classes), "
+                    f"half 3-D 7-point cubes, half banded CSR (7-27 nnz/row), Jacobi, sigma = 1, "
+                    f"FP32-stream shifted p-CG to 1e-8",
+        "capacity_solves_per_s": capacity,
+        "arrival_rate_hz": rate,
+        "solves_per_s": count / t_live,
+        "p50_latency_s": _pct(lat, 50),
+        "p99_latency_s": _pct(lat, 99),
+        "converged": int(sum(r["status"] == "converged" for r in live)),
+        "max_true_residual": float(max(r["rel_res_true"] for r in live)),
+        "sequential_fp64_cg": {"solves_per_s": count / sum(service), "p50_latency_s": _pct(fifo_lat, 50),
+                               "p99_latency_s": _pct(fifo_lat, 99)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,13 +322,18 @@ def main():
     ap.add_argument("--fp32", action="store_true", help="FP32-stream form instead of binary64")
     ap.add_argument("--method", default="pipe_shift", choices=["cg", "pipe", "pipe_shift"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=240)
+    ap.add_argument("--cpu-iters", type=int, default=600)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--K", type=int, default=0)
     ap.add_argument("--variant", type=int, default=0)
     ap.add_argument("--max-iter", type=int, default=5000,
                     help="iteration cap (profiling runs use a short fixed count)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 512-system batch leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
+    ap.add_argument("--serving-requests", type=int, default=200)
+    ap.add_argument("--serving-max-log10", type=float, default=6.0,
+                    help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
     ap.add_argument("--ingest-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarise rocprofv3 output of this benchmark into profiles/ and exit")
     ap.add_argument("--calib-copy", action="store_true",
@@ -294,9 +449,18 @@ def main():
         },
         "cpu_baseline": None,
     }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, args.cpu_iters)
     solver.close()
+    del solver, b, x
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("[bench] batched leg", flush=True)
+        out["batched"] = bench_batched(P, torch)
+    if not args.no_serving:
+        print("[bench] serving leg", flush=True)
+        out["serving"] = bench_serving(P, torch, args.serving_requests, args.serving_max_log10)
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline", flush=True)
+        out["cpu_baseline"] = cpu_baseline(p, args.cpu_iters)
     print(json.dumps(out), flush=True)
 
 
