@@ -313,6 +313,100 @@ def bench_serving(P, torch, count: int, log10_max: float, seed: int = 0) -> dict
     }
 
 
+def lanczos_extremes(alpha, beta):
+    """Extreme Ritz values of the CG Lanczos matrix (diagonal 1/alpha_i +
+    beta_i/alpha_{i-1}, off-diagonal sqrt(beta_i)/alpha_{i-1}) from an
+    alpha / beta history: estimates of the spectrum bounds of A M^-1."""
+    import numpy as np
+    from scipy.linalg import eigh_tridiagonal
+    a = np.asarray(alpha, dtype=np.float64)
+    b = np.asarray(beta, dtype=np.float64)
+    k = int(np.argmax(~np.isfinite(a))) if not np.all(np.isfinite(a)) else len(a)
+    a, b = a[:k], b[:k]
+    d = 1.0 / a
+    d[1:] += b[1:] / a[:-1]
+    e = np.sqrt(b[1:]) / a[:-1]
+    ev = eigh_tridiagonal(d, e, eigvals_only=True)
+    return float(ev[0]), float(ev[-1])
+
+
+def _timed_solve(P, torch, op, opts, b):
+    s = P.Solver(op, opts)
+    x = torch.zeros_like(b)
+    s.solve(b, x)  # warm-up (graph)
+    x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = s.solve(b, x)
+    torch.cuda.synchronize()
+    r["wall_s"] = time.perf_counter() - t0
+    s.close()
+    return r
+
+
+def report_c3(P, torch, N: int, max_iter: int) -> dict:
+    """2-D anisotropic diffusion (CSR), Jacobi: attainable explicit residual
+    per storage form and shift sigma in {0, lambda_min estimate, midpoint 1,
+    lambda_max bound 2}, running to the iteration cap with no stop; plus the
+    iteration rate and effective bandwidth of each form."""
+    import problems
+    p = problems.anisotropic_csr(N, seed=0)
+    b = torch.from_numpy(p.b).cuda()
+    # lambda_min of spec(D^-1 A) from the Lanczos values of a CG run
+    h = _timed_solve(P, torch, p.op, P.make_options(method="cg", jacobi=True, rtol=1e-10, max_iter=max_iter,
+                                                    history_cap=max_iter + 2, true_residual_check=False), b)
+    k = h["iterations"]
+    lmin, lmax = lanczos_extremes(h["alpha"][:k], h["beta"][:k])
+    out = {"workload": f"2-D anisotropic diffusion {N}x{N} CSR (n={p.op.n}, nnz={p.op.nnz}), Jacobi",
+           "lanczos_lambda_min": lmin, "lanczos_lambda_max": lmax, "kappa_estimate": lmax / lmin,
+           "cg_fp64_iterations_to_1e-10": h["iterations"], "runs": []}
+    nnz, n = p.op.nnz, p.op.n
+    for fp32 in (False, True):
+        es = 4 if fp32 else 8
+        # streams: x rw 16 + 7 vectors rw + w r/w, CSR values + indices + row_ptr + dinv
+        bytes_it = n * (16 + es * 16) + nnz * (4 + es) + 4 * (n + 1) + es * n
+        for name, sig in (("0", 0.0), ("lambda_min", lmin), ("mid", 1.0), ("lambda_max_bound", 2.0)):
+            r = _timed_solve(P, torch, p.op, P.make_options(method="pipe_shift", jacobi=True, fp32=fp32, sigma=sig,
+                                                            rtol=1e-30, max_iter=max_iter,
+                                                            true_residual_check=False, timing=True), b)
+            out["runs"].append({"form": "fp32-stream" if fp32 else "fp64", "sigma": name, "sigma_value": sig,
+                                "status": r["status"], "iterations": r["iterations"],
+                                "true_residual": r["rel_res_true"],
+                                "iters_per_s": r["iterations"] / r["wall_s"],
+                                "gbs_algorithmic": bytes_it * r["iter_passes"] / (r["iter_kernel_ms"] * 1e-3) / 1e9})
+    return out
+
+
+def report_small(P, torch) -> dict:
+    """Latency-bound cases: 2-D Poisson 100x100 (all three methods, to 1e-12)
+    and the 1000x1000 Poisson problem of Section 5.2 (b = A*1, x0 = 0, to
+    1e-6 and, as in the accuracy run, to the explicit residual floor)."""
+    import problems
+    out = {}
+    p = problems.poisson2d_manufactured(100)
+    b = torch.from_numpy(p.b).cuda()
+    for m in ("cg", "pipe", "pipe_shift"):
+        r = _timed_solve(P, torch, p.op, P.make_options(method=m, sigma=p.sigma if m == "pipe_shift" else 0.0,
+                                                        rtol=1e-12, max_iter=2000, true_residual_check=False,
+                                                        timing=True), b)
+        out[f"poisson2d_100_{m}"] = {"iterations": r["iterations"], "true_residual": r["rel_res_true"],
+                                     "seconds": r["wall_s"], "iters_per_s": r["iterations"] / r["wall_s"],
+                                     "us_per_pass": r["iter_kernel_ms"] * 1e3 / max(1, r["iter_passes"])}
+    p = problems.paper_parallel_workload(1000)
+    b = torch.from_numpy(p.b).cuda()
+    for m in ("cg", "pipe", "pipe_shift"):
+        sig = 4.0 if m == "pipe_shift" else 0.0
+        r = _timed_solve(P, torch, p.op, P.make_options(method=m, sigma=sig, rtol=1e-6, max_iter=2500,
+                                                        true_residual_check=False), b)
+        r2 = _timed_solve(P, torch, p.op, P.make_options(method=m, sigma=sig, rtol=1e-30, max_iter=2500,
+                                                         true_residual_check=False), b)
+        out[f"paper_poisson2d_1000_{m}"] = {"iterations_to_1e-6": r["iterations"], "seconds_to_1e-6": r["wall_s"],
+                                            "true_residual_after_2500_or_breakdown": r2["rel_res_true"],
+                                            "status_long_run": r2["status"], "iterations_long_run": r2["iterations"],
+                                            "seconds_long_run": r2["wall_s"]}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -334,6 +428,10 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-max-log10", type=float, default=6.0,
                     help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
+    ap.add_argument("--report", choices=["c3", "small"],
+                    help="print a measurement report (C3 accuracy per shift, or the latency-bound cases) and exit")
+    ap.add_argument("--c3-N", type=int, default=1024)
+    ap.add_argument("--c3-max-iter", type=int, default=12000)
     ap.add_argument("--ingest-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarise rocprofv3 output of this benchmark into profiles/ and exit")
     ap.add_argument("--calib-copy", action="store_true",
@@ -361,6 +459,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.report:
+        rep = report_c3(P, torch, args.c3_N, args.c3_max_iter) if args.report == "c3" else report_small(P, torch)
+        print(json.dumps(rep), flush=True)
+        return
     if args.calib_copy:
         src = torch.ones(2 ** 27, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)

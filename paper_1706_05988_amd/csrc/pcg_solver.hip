@@ -147,7 +147,10 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
     } else {
         s.nt = 1;
         const bool pipe = o->method != PCG_CG, jac = o->pc == PCG_PC_JACOBI, fp64 = o->prec == PCG_FP64;
-        if (pipe && jac) {
+        if (pipe && op->kind == PCG_OP_CSR) {
+            // gathers need more waves in flight than the stencil streams
+            s.ept = 2, s.block = 256, blocks_per_cu = fp64 ? 2 : 4;
+        } else if (pipe && jac) {
             s.ept = 2, s.block = 256, blocks_per_cu = 1;
         } else if (pipe) {
             s.ept = 1, s.block = 128, blocks_per_cu = 4;

@@ -340,3 +340,29 @@ def test_blocked_layout_tile_edges(torch, n):
         g = gpu_solve(torch, p, m, max_iter=60, rtol=1e-30, true_residual_check=False)
         o = oracle_solve(p, m, max_iter=60, rtol=1e-30)
         check_history(g, o)
+
+
+# ---------------------------------------------------------------- C3 recipe, every shift
+
+@pytest.mark.parametrize("sigma", [0.0, 0.02, 1.0, 2.0])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_anisotropic_csr_attainable_accuracy_per_shift(torch, sigma, fp32):
+    """The anisotropic-diffusion CSR recipe (reduced to 64^2, Jacobi) run to
+    a fixed iteration cap for shifts 0, near lambda_min, the midpoint and the
+    lambda_max bound: the explicit residual the GPU attains matches the
+    oracle's in the same storage form.  Where the oracle stops at a breakdown
+    (its iteration is set by rounding), the GPU's level lies between the
+    oracle's level at that breakdown and the level it reaches running on."""
+    p = problems.anisotropic_csr(64, seed=0)
+    kw = dict(fp32=fp32, sigma=sigma, rtol=1e-30, max_iter=1500)
+    g = gpu_solve(torch, p, "pipe_shift", true_residual_check=False, hist=False, **kw)
+    o = oracle_solve(p, "pipe_shift", **kw)
+    if o["status"] == "max_iter":
+        assert g["status"] == "max_iter"
+        assert 0.1 * o["rel_res_true"] - 1e-14 <= g["rel_res_true"] <= 10 * o["rel_res_true"] + 1e-14
+    else:
+        assert o["status"] == "breakdown"
+        on = oracle_solve(p, "pipe_shift", ignore_breakdown=True, **kw)
+        assert g["status"] in ("breakdown", "max_iter")
+        lo, hi = sorted((o["rel_res_true"], on["rel_res_true"]))
+        assert lo / 100 <= g["rel_res_true"] <= hi * 100
