@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-METHODS = {"cg": 0, "pipe": 1, "pipe_shift": 2}
+METHODS = {"cg": 0, "pipe": 1, "pipe_shift": 2, "pipe_var": 3}
 STATUS = {0: "converged", 1: "max_iter", 2: "breakdown", 3: "nonfinite"}
 KINDS = {"2d5": 0, "3d7": 1, "csr": 2}
 
@@ -54,7 +54,9 @@ class _Opts(C.Structure):
     _fields_ = [("method", C.c_int32), ("max_iter", C.c_int32), ("sigma", C.c_double),
                 ("rtol", C.c_double), ("jacobi", C.c_int32), ("fp32_storage", C.c_int32),
                 ("record_true", C.c_int32), ("record_gaps", C.c_int32), ("threads", C.c_int32),
-                ("replace_max", C.c_int32), ("ignore_breakdown", C.c_int32)]
+                ("replace_max", C.c_int32), ("ignore_breakdown", C.c_int32),
+                ("sigma_sched", C.c_void_p), ("sigma_sched_len", C.c_int32),
+                ("w0_perturb", C.c_void_p)]
 
 
 _HIST = ["h_res", "h_true", "h_alpha", "h_beta", "h_gamma", "h_delta", "h_f", "h_g", "h_h", "h_j"]
@@ -133,7 +135,7 @@ def solve(op, b: np.ndarray, x0: Optional[np.ndarray] = None, method: str = "pip
           sigma: float = 0.0, rtol: float = 1e-10, max_iter: int = 1000, jacobi: bool = False,
           fp32_storage: bool = False, record: bool = True, record_true: bool = False,
           record_gaps: bool = False, threads: int = 1, replace_max: int = 0,
-          ignore_breakdown: bool = False) -> dict:
+          ignore_breakdown: bool = False, sigma_schedule=None, w0_perturb=None) -> dict:
     """Run the oracle.  Returns a dict with x, status, iterations, norms and
     (if ``record``) histories indexed by iteration (NaN where not reached)."""
     lib = _load()
@@ -141,6 +143,18 @@ def solve(op, b: np.ndarray, x0: Optional[np.ndarray] = None, method: str = "pip
     opts = _Opts(METHODS[method], int(max_iter), float(sigma), float(rtol), int(bool(jacobi)),
                  int(bool(fp32_storage)), int(bool(record_true)), int(bool(record_gaps)),
                  int(threads), int(replace_max), int(bool(ignore_breakdown)))
+    sched = None
+    if method == "pipe_var":
+        if sigma_schedule is None or len(sigma_schedule) < 1:
+            raise ValueError("pipe_var needs sigma_schedule = [sigma_-1, sigma_0, sigma_1, ...]")
+        sched = np.ascontiguousarray(sigma_schedule, dtype=np.float64)
+        opts.sigma_sched = _ptr(sched)
+        opts.sigma_sched_len = len(sched)
+    pert = None
+    if w0_perturb is not None:
+        pert = np.ascontiguousarray(w0_perturb, dtype=np.float64)
+        assert pert.shape == (op.n,)
+        opts.w0_perturb = _ptr(pert)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(op.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     res = _Res()

@@ -10,6 +10,7 @@
  *   - classic preconditioned CG ............... Alg. 1 (Section 1)
  *   - preconditioned pipelined CG (p-CG) ....... Alg. 2 (Section 2.1)
  *   - shifted preconditioned pipelined CG ...... Alg. 3 (Section 2.2)
+ *   - p-CG with a variable shift sigma_i ........ Alg. 4 (Section 4.1)
  * on an SPD operator given as a 2-D 5-point stencil, a 3-D 7-point stencil
  * (homogeneous Dirichlet, interior unknowns, x fastest) or a CSR matrix, with
  * no preconditioner or the Jacobi (diagonal) preconditioner.
@@ -41,8 +42,16 @@
  *     method restarts from the current x -- the initialisation steps are run
  *     again with x_0 := x_i and the next iteration takes the i = 0 branch
  *     (beta = 0) -- while the iteration count continues.
+ *   - Alg. 4: each recurrence that carries a shift-difference correction
+ *     forms the two-term recurrence first and subtracts the correction last,
+ *     (a + beta y) - (sigma_i - sigma_{i-1}) c, and w_{i+1} is formed
+ *     before r_i is overwritten, as the derivation of Section 4.1 requires;
+ *     the shift schedule holds sigma_{-1}, sigma_0, sigma_1, ... and its
+ *     last entry repeats past its end.
  * Diagnostics: the explicit residual ||b - A x_i|| per iteration and the gap
- * norms ||f||, ||g||, ||h||, ||j|| of Section 3.1 from their definitions.
+ * norms ||f||, ||g||, ||h||, ||j|| of Section 3.1 from their definitions; a
+ * test hook adds a given vector to w_0, planting a known gap h_0 whose
+ * propagation the tests follow through the propagation matrices.
  */
 #include <math.h>
 #include <stdint.h>
@@ -55,7 +64,7 @@
 #define ORC_CHUNK 4096
 
 enum { ORC_2D5 = 0, ORC_3D7 = 1, ORC_CSR = 2 };
-enum { ORC_CG = 0, ORC_PIPE = 1, ORC_PIPE_SHIFT = 2 };
+enum { ORC_CG = 0, ORC_PIPE = 1, ORC_PIPE_SHIFT = 2, ORC_PIPE_VAR = 3 };
 enum { ORC_CONVERGED = 0, ORC_MAX_ITER = 1, ORC_BREAKDOWN = 2, ORC_NONFINITE = 3 };
 
 typedef struct {
@@ -82,6 +91,9 @@ typedef struct {
     int32_t threads;       /* OpenMP threads, <= 0: library default */
     int32_t replace_max;   /* max residual replacements (0: none) */
     int32_t ignore_breakdown; /* 1: run to max_iter as the paper's accuracy runs do */
+    const double *sigma_sched; /* Alg. 4: sigma_{-1}, sigma_0, ... (last entry repeats) */
+    int32_t sigma_sched_len;
+    const double *w0_perturb;  /* test hook: added to w_0 after the initialisation (NULL: none) */
 } orc_opts;
 
 typedef struct {
@@ -231,6 +243,28 @@ static void ymax3(int64_t n, double alpha, const double *a, double as, const dou
     for (int64_t i = 0; i < n; ++i) y[i] = st(y[i] - (alpha * a[i] + as * c[i]));
 }
 
+/* y = (a + beta * y) - d * c   (stored; Alg. 4 recurrences with a shift correction) */
+static void aypx_corr(int64_t n, const double *a, double beta, double d, const double *c, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) y[i] = st((a[i] + beta * y[i]) - d * c[i]);
+}
+
+/* z = (nn + beta z) - d (s + sig t)   (stored; the z recurrence of Alg. 4) */
+static void z_var(int64_t n, const double *nn, double beta, double d, const double *s, double sig,
+                  const double *t, double *z)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) z[i] = st((nn[i] + beta * z[i]) - d * (s[i] + sig * t[i]));
+}
+
+/* y = (y - alpha a) - d c   (stored; the w recurrence of Alg. 4) */
+static void ymax_corr(int64_t n, double alpha, const double *a, double d, const double *c, double *y)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) y[i] = st((y[i] - alpha * a[i]) - d * c[i]);
+}
+
 /* out = b - A x  (explicit residual, binary64) */
 static void true_residual(const orc_op *A, const double *b, const double *x, double *tmp, double *out)
 {
@@ -351,6 +385,8 @@ static int solve_pipe(const orc_op *A, const double *dinv, const orc_opts *o, in
         for (int64_t k = 0; k < n; ++k) w[k] = st(w[k] - sigma * r[k]);
     else
         for (int64_t k = 0; k < n; ++k) w[k] = st(w[k]);
+    if (o->w0_perturb)
+        for (int64_t k = 0; k < n; ++k) w[k] = st(w[k] + o->w0_perturb[k]);
     /* z_{-1} = q_{-1} = s_{-1} = t_{-1} = p_{-1} = 0 (calloc) */
 
     double alpha_prev = 0.0, gamma_prev = 0.0, rho = 0.0;
@@ -474,10 +510,153 @@ static int solve_pipe(const orc_op *A, const double *dinv, const orc_opts *o, in
 
 /* Solve A x = b; x holds x_0 on entry and the final iterate on return.
  * Returns 0, or -1 on invalid arguments. */
+/* sigma_k of the schedule, k >= -1 (entry k + 1; the last entry repeats) */
+static double sched_at(const orc_opts *o, int k)
+{
+    int idx = k + 1;
+    if (idx > o->sigma_sched_len - 1) idx = o->sigma_sched_len - 1;
+    return o->sigma_sched[idx];
+}
+
+/* Alg. 4 (Section 4.1): pipelined CG with the shift sigma_i of iteration i
+ * taken from a schedule.  w_i is kept equal to A u_i - sigma_{i-1} r_i and
+ * s_i to A p_i - sigma_i t_i, the corrections (sigma_i - sigma_{i-1}) (.)
+ * keeping the auxiliary recurrences consistent with the changing shift. */
+static int solve_pipe_var(const orc_op *A, const double *dinv, const orc_opts *o, const double *b, double *x,
+                          orc_result *res)
+{
+    const int64_t n = A->n;
+    double *r = vec(n), *u = vec(n), *w = vec(n), *m = vec(n), *nn = vec(n);
+    double *z = vec(n), *q = vec(n), *s = vec(n), *t = vec(n), *p = vec(n);
+    double *tmp = vec(n), *tr = vec(n), *gap = vec(n);
+    const double bnorm = norm2(n, b);
+    res->bnorm = bnorm;
+    int replacements = 0;
+
+    /* r_0 := b - A x_0; u_0 := M^{-1} r_0; w_0 := A u_0 - sigma_{-1} r_0 */
+    apply_A(A, x, tmp);
+    for (int64_t k = 0; k < n; ++k) r[k] = st(b[k] - tmp[k]);
+    apply_Minv(n, dinv, r, u);
+    for (int64_t k = 0; k < n; ++k) u[k] = st(u[k]);
+    apply_A(A, u, w);
+    {
+        const double s_m1 = sched_at(o, -1);
+        for (int64_t k = 0; k < n; ++k) w[k] = st(w[k] - s_m1 * r[k]);
+    }
+    if (o->w0_perturb)
+        for (int64_t k = 0; k < n; ++k) w[k] = st(w[k] + o->w0_perturb[k]);
+
+    double alpha_prev = 0.0, gamma_prev = 0.0, rho = 0.0;
+    int status = ORC_MAX_ITER, i = 0, i_start = 0;
+    for (i = 0;; ++i) {
+        const double sig_prev = sched_at(o, i - 1), sig = sched_at(o, i), d = sig - sig_prev;
+        const double gamma = dot(n, r, u);                     /* gamma_i := (r_i, u_i)              */
+        const double delta = dot_shift(n, w, sig_prev, r, u);  /* (w_i + sigma_{i-1} r_i, u_i)       */
+        rho = dot(n, r, r);
+        if (res->h_res) res->h_res[i] = sqrt(rho) / bnorm;
+        if (res->h_gamma) res->h_gamma[i] = gamma;
+        if (res->h_delta) res->h_delta[i] = delta;
+        if (res->h_true) {
+            true_residual(A, b, x, tmp, tr);
+            res->h_true[i] = norm2(n, tr) / bnorm;
+        }
+        if (!isfinite(rho) || !isfinite(gamma) || !isfinite(delta)) { status = ORC_NONFINITE; break; }
+        if (sqrt(rho) <= o->rtol * bnorm) {
+            if (replacements < o->replace_max) {
+                true_residual(A, b, x, tmp, tr);
+                if (norm2(n, tr) > o->rtol * bnorm) {
+                    /* restart from x: w := A u - sigma_{i-1} r keeps w's definition */
+                    ++replacements;
+                    for (int64_t k = 0; k < n; ++k) r[k] = st(tr[k]);
+                    apply_Minv(n, dinv, r, u);
+                    for (int64_t k = 0; k < n; ++k) u[k] = st(u[k]);
+                    apply_A(A, u, w);
+                    for (int64_t k = 0; k < n; ++k) w[k] = st(w[k] - sig_prev * r[k]);
+                    memset(z, 0, (size_t)n * sizeof(double));
+                    memset(q, 0, (size_t)n * sizeof(double));
+                    memset(s, 0, (size_t)n * sizeof(double));
+                    memset(t, 0, (size_t)n * sizeof(double));
+                    memset(p, 0, (size_t)n * sizeof(double));
+                    i_start = i;
+                    --i;
+                    continue;
+                }
+            }
+            status = ORC_CONVERGED;
+            break;
+        }
+        if (i >= o->max_iter) { status = ORC_MAX_ITER; break; }
+        if (!o->ignore_breakdown && (!(gamma > 0.0) || !(delta > 0.0))) { status = ORC_BREAKDOWN; break; }
+
+        apply_Minv(n, dinv, w, m);                 /* m_i := M^{-1} w_i   */
+        apply_A(A, m, nn);                         /* n_i := A m_i        */
+        double alpha, beta;
+        if (i > i_start) {
+            beta = gamma / gamma_prev;
+            alpha = 1.0 / (delta / gamma - beta / alpha_prev);
+        } else {
+            beta = 0.0;
+            alpha = gamma / delta;
+        }
+        if (res->h_alpha) res->h_alpha[i] = alpha;
+        if (res->h_beta) res->h_beta[i] = beta;
+        if (!o->ignore_breakdown && !finite_pos(alpha)) { status = ORC_BREAKDOWN; break; }
+
+        aypx(n, r, beta, t);                       /* t_i := r_i + beta t_{i-1} */
+        aypx(n, u, beta, p);                       /* p_i := u_i + beta p_{i-1} */
+        aypx_corr(n, w, beta, d, t, s);            /* s_i := w_i + beta s_{i-1} - d t_i */
+        aypx_corr(n, m, beta, d, p, q);            /* q_i := m_i + beta q_{i-1} - d p_i */
+        z_var(n, nn, beta, d, s, sig, t, z);       /* z_i := n_i + beta z_{i-1} - d (s_i + sigma_i t_i) */
+        axpy_x(n, alpha, p, x);                    /* x_{i+1} := x_i + alpha p_i */
+        ymax_corr(n, alpha, z, d, r, w);           /* w_{i+1} := w_i - alpha z_i - d r_i (old r_i) */
+        {
+            const double as = alpha * sig;
+            ymax3(n, alpha, s, as, t, r);          /* r_{i+1} := r_i - alpha s_i - alpha sigma_i t_i */
+            ymax3(n, alpha, q, as, p, u);          /* u_{i+1} := u_i - alpha q_i - alpha sigma_i p_i */
+        }
+
+        if (o->record_gaps) {
+            if (res->h_f) {                        /* f_{i+1} = (b - A x_{i+1}) - r_{i+1} */
+                true_residual(A, b, x, tmp, gap);
+                for (int64_t k = 0; k < n; ++k) gap[k] = gap[k] - r[k];
+                res->h_f[i + 1] = norm2(n, gap);
+            }
+            if (res->h_g) {                        /* g_i = (A p_i - sigma_i t_i) - s_i */
+                apply_A(A, p, tmp);
+                for (int64_t k = 0; k < n; ++k) gap[k] = (tmp[k] - sig * t[k]) - s[k];
+                res->h_g[i] = norm2(n, gap);
+            }
+            if (res->h_h) {                        /* h_{i+1} = (A u_{i+1} - sigma_i r_{i+1}) - w_{i+1} */
+                apply_A(A, u, tmp);
+                for (int64_t k = 0; k < n; ++k) gap[k] = (tmp[k] - sig * r[k]) - w[k];
+                res->h_h[i + 1] = norm2(n, gap);
+            }
+            if (res->h_j) {                        /* j_i = A q_i - z_i */
+                apply_A(A, q, tmp);
+                for (int64_t k = 0; k < n; ++k) gap[k] = tmp[k] - z[k];
+                res->h_j[i] = norm2(n, gap);
+            }
+        }
+        alpha_prev = alpha;
+        gamma_prev = gamma;
+    }
+    res->status = status;
+    res->iterations = i;
+    res->replacements = replacements;
+    res->rel_res_recursive = sqrt(rho) / bnorm;
+    true_residual(A, b, x, tmp, tr);
+    res->rel_res_true = norm2(n, tr) / bnorm;
+    free(r); free(u); free(w); free(m); free(nn);
+    free(z); free(q); free(s); free(t); free(p);
+    free(tmp); free(tr); free(gap);
+    return 0;
+}
+
 int orc_solve(const orc_op *A, const orc_opts *o, const double *b, double *x, orc_result *res)
 {
     if (!A || !o || !b || !x || !res || A->n <= 0) return -1;
-    if (o->method < ORC_CG || o->method > ORC_PIPE_SHIFT) return -1;
+    if (o->method < ORC_CG || o->method > ORC_PIPE_VAR) return -1;
+    if (o->method == ORC_PIPE_VAR && (!o->sigma_sched || o->sigma_sched_len < 1)) return -1;
 #ifdef _OPENMP
     int saved = omp_get_max_threads();
     if (o->threads > 0) omp_set_num_threads(o->threads);
@@ -491,6 +670,8 @@ int orc_solve(const orc_op *A, const orc_opts *o, const double *b, double *x, or
     int rc;
     if (o->method == ORC_CG)
         rc = solve_cg(A, dinv, o, b, x, res);
+    else if (o->method == ORC_PIPE_VAR)
+        rc = solve_pipe_var(A, dinv, o, b, x, res);
     else
         rc = solve_pipe(A, dinv, o, o->method == ORC_PIPE_SHIFT, b, x, res);
     free(dinv);

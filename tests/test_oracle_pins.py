@@ -408,3 +408,99 @@ def test_zero_iterations_and_exact_start():
     assert np.array_equal(r["x"], p.x0)
     r = oracle.solve(p.op, p.b, x0=p.x_true, method="pipe_shift", sigma=4.0, rtol=1e-10)
     assert r["status"] == "converged" and r["iterations"] == 0
+
+
+# ------------------------------------------------------------ Alg. 4: variable shift (Section 4)
+
+def _var_schedule(count, seed=0, lo=0.5, hi=7.5):
+    """sigma_{-1}, sigma_0, ... drawn inside the 2-D Laplacian's spectrum (0, 8)."""
+    return np.random.default_rng(seed).uniform(lo, hi, count)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_variable_shift_with_constant_schedule_is_alg3_bitwise(jacobi, fp32):
+    """With sigma_i = sigma for every i the corrections vanish exactly, so
+    Alg. 4 performs Alg. 3's arithmetic (Section 4.1)."""
+    p = problems.poisson3d(12, seed=3, jacobi=jacobi) if jacobi else problems.poisson2d_manufactured(24)
+    sig = 1.0 if jacobi else 4.0
+    kw = dict(jacobi=jacobi, fp32_storage=fp32, rtol=1e-12, max_iter=400)
+    a = oracle.solve(p.op, p.b, p.x0, method="pipe_shift", sigma=sig, **kw)
+    for sched in ([sig], [sig] * 7):
+        v = oracle.solve(p.op, p.b, p.x0, method="pipe_var", sigma_schedule=sched, **kw)
+        assert v["iterations"] == a["iterations"] and v["status"] == a["status"]
+        assert np.array_equal(v["x"], a["x"])
+        k = a["iterations"]
+        assert np.array_equal(v["res"][: k + 1], a["res"][: k + 1])
+        assert np.array_equal(v["alpha"][:k], a["alpha"][:k])
+
+
+def test_variable_shift_same_krylov_iterates_as_cg():
+    """The shift only changes auxiliary vectors: in exact arithmetic Alg. 4
+    produces CG's iterates for any schedule, so early on the recursive
+    residual, alpha and beta agree with CG's to rounding level."""
+    p = problems.poisson2d_manufactured(100)
+    c = oracle.solve_problem(p, "cg", max_iter=60, rtol=1e-30)
+    v = oracle.solve_problem(p, "pipe_var", max_iter=60, rtol=1e-30, sigma_schedule=_var_schedule(80))
+    np.testing.assert_allclose(v["res"][:51], c["res"][:51], rtol=1e-9)
+    np.testing.assert_allclose(v["alpha"][:50], c["alpha"][:50], rtol=1e-9)
+    np.testing.assert_allclose(v["beta"][1:50], c["beta"][1:50], rtol=1e-9)
+
+
+def test_variable_shift_auxiliary_definitions_hold():
+    """w_i = A u_i - sigma_{i-1} r_i, s_i = A p_i - sigma_i t_i and z_i = A q_i
+    stay true under a changing shift (the gaps h, g, j of Section 4.2 stay at
+    rounding level early on); dropping any correction term would leave a gap
+    of the order of (sigma_i - sigma_{i-1}) times the vector."""
+    rng = np.random.default_rng(4)
+    op = problems.stencil2d(20)
+    b = rng.uniform(-1, 1, op.n)
+    r = oracle.solve(op, b, None, method="pipe_var", sigma_schedule=_var_schedule(60, seed=5), rtol=1e-30,
+                     max_iter=30, record_gaps=True, ignore_breakdown=True)
+    bn = np.linalg.norm(b)
+    for key in ("g", "h", "j", "f"):
+        h = r[key][1:25]
+        assert np.all(h[np.isfinite(h)] <= 1e-12 * 8 * bn), key
+
+
+@pytest.mark.parametrize("variable", [False, True])
+def test_planted_gap_propagates_by_the_propagation_matrices(variable):
+    """Plant a gap h_0 = -eps e by perturbing w_0.  Every later gap is then a
+    multiple of e propagated by P_i(sigma_{i-1}, sigma_i) of Section 4.2
+    (P_i(sigma) of Section 3.2 for a constant shift) with the run's own alpha_i
+    and beta_i: [f_{i+1}, g_i, h_{i+1}, j_i] = P_i [f_i, g_{i-1}, h_i, j_{i-1}].
+    The recorded gap norms must follow the 4x4 product to many digits."""
+    rng = np.random.default_rng(11)
+    op = problems.stencil2d(16)
+    b = rng.uniform(-1, 1, op.n)
+    e = rng.normal(size=op.n)
+    e /= np.linalg.norm(e)
+    eps = 1e-6
+    K = 20
+    if variable:
+        sched = _var_schedule(K + 2, seed=12)
+        r = oracle.solve(op, b, None, method="pipe_var", sigma_schedule=sched, rtol=1e-30, max_iter=K,
+                         record_gaps=True, ignore_breakdown=True, w0_perturb=eps * e)
+    else:
+        sched = np.full(K + 2, 4.0)
+        r = oracle.solve(op, b, None, method="pipe_shift", sigma=4.0, rtol=1e-30, max_iter=K,
+                         record_gaps=True, ignore_breakdown=True, w0_perturb=eps * e)
+    c = np.array([0.0, 0.0, -eps, 0.0])  # [f_0, g_-1, h_0, j_-1] in units of e
+    for i in range(K):
+        a, bt = r["alpha"][i], r["beta"][i]
+        P = (psi_mod.propagation_matrix_variable(a, bt, sched[i], sched[i + 1]) if variable
+             else psi_mod.propagation_matrix(a, bt, 4.0))
+        c = P @ c
+        got = [r["f"][i + 1], r["g"][i], r["h"][i + 1], r["j"][i]]
+        for k in range(4):
+            assert got[k] == pytest.approx(abs(c[k]), rel=1e-5, abs=1e-13), (i, k)
+
+
+def test_variable_shift_converges_to_the_solution():
+    """Alg. 4 with a changing shift solves the system (dense Cholesky check)."""
+    p = problems.dense_spd(48, cond=1e3, seed=2)
+    x_ref = sl.cho_solve(sl.cho_factor(problems.to_scipy(p.op).toarray()), p.b)
+    sched = np.random.default_rng(3).uniform(1.0, 500.0, 40)
+    r = oracle.solve(p.op, p.b, None, method="pipe_var", sigma_schedule=sched, rtol=1e-13, max_iter=500)
+    assert r["status"] == "converged"
+    assert np.linalg.norm(r["x"] - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
