@@ -8,6 +8,10 @@
  *   - classic preconditioned CG ........................ Alg. 1  (PCG_CG)
  *   - preconditioned pipelined CG ...................... Alg. 2  (PCG_PIPE)
  *   - shifted preconditioned pipelined CG .............. Alg. 3  (PCG_PIPE_SHIFT)
+ *   - the same with an iteration-dependent shift ........ Alg. 4  (PCG_PIPE_VAR_SHIFT,
+ *     Section 4.1: sigma_i from a caller-given schedule; the corrections
+ *     (sigma_i - sigma_{i-1}) t_i, p_i, (s_i + sigma_i t_i), r_i of s, q, z
+ *     and w ride in the same fused pass with no extra vector traffic)
  * Alg. 3 with sigma = 0 is Alg. 2 (end of Section 2.2); both run the same
  * fused kernel.  Each pipelined iteration is ONE device pass: the
  * preconditioner apply and SPMV (m_i = M^-1 w_i, n_i = A m_i), the five
@@ -61,7 +65,7 @@ typedef int32_t pcg_status;
 #define PCG_BREAKDOWN  2   /* gamma <= 0, delta <= 0, (s,p) <= 0 or alpha not > 0     */
 #define PCG_NONFINITE  3   /* a reduction produced NaN / Inf                         */
 
-typedef enum { PCG_CG = 0, PCG_PIPE = 1, PCG_PIPE_SHIFT = 2 } pcg_method;
+typedef enum { PCG_CG = 0, PCG_PIPE = 1, PCG_PIPE_SHIFT = 2, PCG_PIPE_VAR_SHIFT = 3 } pcg_method;
 typedef enum { PCG_OP_STENCIL2D5 = 0, PCG_OP_STENCIL3D7 = 1, PCG_OP_CSR = 2 } pcg_op_kind;
 typedef enum { PCG_PC_NONE = 0, PCG_PC_JACOBI = 1 } pcg_pc_kind;
 typedef enum { PCG_FP64 = 0, PCG_FP32_STREAM = 1 } pcg_precision;
@@ -127,7 +131,15 @@ typedef struct {
     int32_t use_graph;          /* 1: capture the K passes of a launch in a HIP graph
                                    (pcg_default_options' choice); 0: launch them one by one  */
     int32_t variant;            /* 0: the tuned kernel variant; else PCG_VAR_SET | bits below */
-    int32_t reserved[3];
+    int32_t sigma_schedule_len; /* PCG_PIPE_VAR_SHIFT: entries of sigma_schedule, 1 .. 2^24    */
+    int32_t reserved[2];
+    const double *sigma_schedule; /* PCG_PIPE_VAR_SHIFT: HOST array sigma_{-1}, sigma_0,
+                                   sigma_1, ... (each finite, >= 0); entry k + 1 is the shift
+                                   of iteration k and the last entry repeats past the end.
+                                   w_i is kept equal to A u_i - sigma_{i-1} r_i (w_0 uses
+                                   sigma_{-1}).  Copied at pcg_create; ignored by the other
+                                   methods.  The batch and server entry points reject this
+                                   method.                                                   */
 } pcg_options;
 
 /* Kernel variant bits (pcg_options.variant).  Every variant performs the same
@@ -228,6 +240,42 @@ pcg_status pcg_submit(pcg_server server, const pcg_operator *op, const pcg_optio
 pcg_status pcg_poll(pcg_server server, uint64_t ticket, pcg_result *result);   /* PCG_PENDING until done */
 pcg_status pcg_wait(pcg_server server, uint64_t ticket, pcg_result *result);
 pcg_status pcg_server_destroy(pcg_server server);
+
+/* ------------------------------------------------------- shift selection */
+
+/*
+ * Rounding-error amplification of pipelined CG (Section 3.2) and the
+ * a-posteriori choice of the shift (Section 5.1).  Host functions: every
+ * pointer is a HOST array; nothing touches the device.
+ *
+ * alpha[k], beta[k] (k = 0 .. i) are iteration k's coefficients, as a solve
+ * records them in columns 1 and 2 of pcg_options.history (a p-CG run,
+ * PCG_PIPE, is the one Section 5.1 analyses).  The local rounding errors of
+ * iteration j reach iteration i through P_i ... P_j, with the 4x4 local
+ * propagation matrix
+ *     P_k = [ 1   -a b        -a        0   ]
+ *           [ 0    b           1        0   ]   a = alpha_k, b = beta_k,
+ *           [ 0   -a b s'      1 - a s' -a b]   s' = sigma_{k-1}, s = sigma_k,
+ *           [ 0   -b (s - s') -(s - s')  b  ]
+ * of Section 4.2 (with s' = s it is P_k(sigma) of Section 3.2), and
+ *     psi_i = max over 1 <= j <= i of || P_i ... P_j ||_2 .
+ * Errors: PCG_ERR_INVALID for null pointers, i < 1, a non-finite alpha_k or
+ * beta_k (1 <= k <= i), or a non-finite shift.
+ */
+/* psi_i(sigma) for a constant shift. */
+pcg_status pcg_psi(const double *alpha, const double *beta, int32_t i, double sigma, double *psi);
+/* psi_i for a shift schedule sigma_{-1}, sigma_0, ... (the layout of
+ * pcg_options.sigma_schedule; the last entry repeats). */
+pcg_status pcg_psi_variable(const double *alpha, const double *beta, int32_t i, const double *sigma_schedule,
+                            int32_t sigma_schedule_len, double *psi);
+/* psi_i on a grid of grid_len shifts (written to psi_out unless NULL) and the
+ * chosen shift: the smallest grid shift whose psi_i is at most `slack` (>= 1)
+ * times the grid minimum.  psi_i falls slowly towards the top of the
+ * spectrum and explodes there, and Section 5.1 warns that a too large shift
+ * may destroy convergence, so the smallest near-minimal shift is taken;
+ * slack = 1 is the plain argmin (ties to the smaller shift). */
+pcg_status pcg_select_shift(const double *alpha, const double *beta, int32_t i, const double *grid,
+                            int32_t grid_len, double slack, double *psi_out, double *sigma_best);
 
 /* ------------------------------------------------------------------ misc */
 

@@ -58,16 +58,46 @@ def psi(alphas, betas, sigma: float, i: int | None = None) -> float:
     return best
 
 
+def psi_variable(alphas, betas, sigma_schedule, i: int | None = None) -> float:
+    """psi_i with the variable-shift matrices P_k(sigma_{k-1}, sigma_k);
+    ``sigma_schedule`` holds sigma_{-1}, sigma_0, ... and its last entry
+    repeats."""
+    alphas = np.asarray(alphas, dtype=np.float64)
+    betas = np.asarray(betas, dtype=np.float64)
+    sched = np.asarray(sigma_schedule, dtype=np.float64)
+    if i is None:
+        i = len(alphas) - 1
+
+    def sig(k):  # sigma_k, k >= -1
+        return sched[min(k + 1, len(sched) - 1)]
+
+    Q = np.eye(4)
+    best = 0.0
+    for j in range(i, 0, -1):
+        Q = Q @ propagation_matrix_variable(alphas[j], betas[j], sig(j - 1), sig(j))
+        best = max(best, float(np.linalg.norm(Q, 2)))
+    return best
+
+
 def psi_history(alphas, betas, sigma: float) -> np.ndarray:
     """psi_i(sigma) for every i = 1 .. len(alphas) - 1 (the right panel of
     Fig. 2).  Quadratic in the number of iterations; fine for a few thousand."""
     return np.array([psi(alphas, betas, sigma, i) for i in range(1, len(alphas))])
 
 
-def select_shift(alphas, betas, sigmas, i: int | None = None):
+def select_shift(alphas, betas, sigmas, i: int | None = None, slack: float = 1.0):
     """Evaluate psi_i on a grid of shifts (Fig. 1) and return (sigma*, values).
-    Ties go to the smaller shift, since a too large shift may destroy
-    convergence (Section 5.1)."""
-    vals = np.array([psi(alphas, betas, s, i) for s in sigmas])
-    k = int(np.argmin(vals))  # argmin returns the first, i.e. smallest sigma on ties
-    return float(np.asarray(sigmas)[k]), vals
+
+    sigma* is the smallest shift whose psi_i is within a factor ``slack`` of
+    the smallest value on the grid: Section 5.1 picks a shift at which psi is
+    (close to) minimal and warns that a too large shift may destroy
+    convergence, and psi_i keeps falling slowly towards the top of the
+    spectrum before it explodes there, so the smallest near-minimal shift is
+    taken.  slack = 1 is the plain argmin with ties going to the smaller
+    shift."""
+    sig = np.asarray(sigmas, dtype=np.float64)
+    vals = np.array([psi(alphas, betas, s, i) for s in sig])
+    best = vals.min()
+    ok = np.nonzero(vals <= slack * best)[0]
+    k = int(ok[np.argmin(sig[ok])])
+    return float(sig[k]), vals

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpcg.so")
 ARCH = os.environ.get("PCG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["pcg_solver.hip", "pcg_batch.hip", "pcg_server.hip"]
+SOURCES = ["pcg_solver.hip", "pcg_batch.hip", "pcg_server.hip", "pcg_shift.cpp"]
 
 # -Xclang -target-feature -Xclang -packed-fp32-ops keeps the compiler from
 # emitting packed FP32 VALU instructions on gfx950.
@@ -29,6 +29,9 @@ HIPCC_FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
+
+
+CXX_FLAGS = ["-O2", "-std=c++17", "-fPIC", "-Wall", "-Wextra"]
 
 
 def hipcc() -> str:
@@ -48,7 +51,10 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src):
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
-        cmd = [hipcc()] + compile_flags + ["-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        if src.endswith(".cpp"):  # host-only sources
+            cmd = ["g++"] + CXX_FLAGS + ["-I", INCLUDE, "-c", src, "-o", obj]
+        else:
+            cmd = [hipcc()] + compile_flags + ["-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -70,7 +70,15 @@ __device__ __forceinline__ void batch_tile(const PassArgs<T> &a, const BatchStat
         break;
     }
     case PH_INIT1: tile_init1<T, OP, JAC, E, true>(a, tile, acc); break;
-    case PH_ITER: tile_pipe<T, OP, JAC, E, true>(a, tile, S.alpha, S.beta, acc); break;
+    case PH_ITER: {
+        PipeScalars sc;
+        sc.alpha = S.alpha;
+        sc.beta = S.beta;
+        sc.sigma = a.sigma;
+        sc.dsig = 0.0;
+        tile_pipe<T, OP, JAC, E, true>(a, tile, sc, acc);
+        break;
+    }
     case PH_RESID: {
         double r2[2] = {0.0, 0.0};
         tile_resid<T, OP, E>(a, tile, r2);
@@ -300,7 +308,8 @@ pcg_status BatchEngine::validate(const pcg_operator *op, const pcg_options *opt)
     pcg_status st = validate_options(opt);
     if (st) return st;
     if ((st = validate_operator(op, opt->prec))) return st;
-    if (opt->method == PCG_CG) return invalid("the batched pass runs the pipelined methods (PCG_PIPE, PCG_PIPE_SHIFT)");
+    if (opt->method == PCG_CG || opt->method == PCG_PIPE_VAR_SHIFT)
+        return invalid("the batched pass runs the constant-shift pipelined methods (PCG_PIPE, PCG_PIPE_SHIFT)");
     if (opt->prec != prec_) return invalid("every system of a batch must use the batch's precision");
     return PCG_OK;
 }
@@ -566,7 +575,8 @@ static pcg_status batch_plan(int32_t count, const pcg_operator *ops, const pcg_o
         if (st) return st;
         if ((st = validate_operator(&ops[k], opts[0].prec))) return st;
         if (opts[k].prec != opts[0].prec) return invalid("every system of a batch must use the same precision");
-        if (opts[k].method == PCG_CG) return invalid("the batched pass runs the pipelined methods");
+        if (opts[k].method == PCG_CG || opts[k].method == PCG_PIPE_VAR_SHIFT)
+            return invalid("the batched pass runs the constant-shift pipelined methods");
         BatchEngine::SysLayout L;
         BatchEngine::system_layout(&ops[k], &opts[k], &L);
         sys_off[k] = off;

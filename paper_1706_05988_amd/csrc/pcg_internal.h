@@ -33,6 +33,7 @@ struct LaunchShape {
 // byte offsets into the caller's workspace (SIZE_MAX: absent)
 struct Layout {
     size_t state, part[2], gersh, flag, hist, dinv;
+    size_t sched;                // variable-shift schedule (SIZE_MAX: none)
     size_t blk;                  // blocked vectors: ceil(n / 512) tiles of tile_bytes
     uint32_t tile_bytes;
     uint32_t slot_off[V_COUNT];  // byte offset of each slot in a tile (kNoSlot: absent)

@@ -66,6 +66,9 @@ struct PassArgs {
     int32_t xcd_map;
     int32_t copy_out;     // k_copy_x: 0 = caller -> internal, 1 = internal -> caller
     int32_t x_plain;      // k_resid: read the caller's x instead of the internal one
+    const double *sched;  // variable shift: sigma_{-1}, sigma_0, ... (last entry repeats)
+    int32_t sched_len;
+    int32_t pad_;
 };
 
 template <typename V, typename T>
@@ -148,9 +151,18 @@ __device__ __forceinline__ TileIdx<EPT> tile_idx(int tile, uint32_t n)
 // Returns false when the iteration has ended (or had ended before).
 struct PipeScalars {
     double alpha, beta;
+    double sigma;  // sigma_i
+    double dsig;   // sigma_i - sigma_{i-1} (0 for a constant shift)
 };
 
-template <typename T>
+// sigma_k of a shift schedule, k >= -1
+__device__ __forceinline__ double sched_at(const double *sched, int len, int k)
+{
+    const int idx = k + 1 < len ? k + 1 : len - 1;
+    return sched[idx];
+}
+
+template <typename T, bool VAR = false>
 __device__ __forceinline__ bool pipe_head(const PassArgs<T> &a, double *lds_red, PipeScalars &sc)
 {
     const DevState S = *a.st_in;
@@ -197,6 +209,14 @@ __device__ __forceinline__ bool pipe_head(const PassArgs<T> &a, double *lds_red,
     }
     sc.alpha = alpha;
     sc.beta = beta;
+    if constexpr (VAR) {
+        const double sp = sched_at(a.sched, a.sched_len, i - 1);
+        sc.sigma = sched_at(a.sched, a.sched_len, i);
+        sc.dsig = sc.sigma - sp;
+    } else {
+        sc.sigma = a.sigma;
+        sc.dsig = 0.0;
+    }
     return status == RUNNING;
 }
 
@@ -333,11 +353,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_init1(PassArgs<T> a)
 //   tail: block partials of gamma_{i+1} = (r, u),
 //     delta_{i+1} = (w_{i+1} + sigma r, u), rho_{i+1} = (r, r).
 // All loads of a tile are issued before any of its stores.
-template <typename T, int OP, bool JAC, int EPT, bool NT>
-__device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, double alpha, double beta,
-                                          double (&acc)[3])
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
+__device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const PipeScalars &sc, double (&acc)[3])
 {
-    const double sigma = a.sigma, as = alpha * sigma;
+    const double alpha = sc.alpha, beta = sc.beta;
+    const double sigma = sc.sigma, as = alpha * sigma, ds = sc.dsig;
     const uint32_t off_u = JAC ? a.off_u : a.off_r;
     const uint32_t off_q = JAC ? a.off_q : a.off_s;
     const uint32_t off_p = JAC ? a.off_p : a.off_t;
@@ -371,21 +391,35 @@ __device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, double
         if (!ti.live[j]) continue;
         const uint32_t e = ti.e[j];
         const double me = minv<T, JAC, OP>(a, e, we[j]);
-        // beta-recurrences
-        const double z = rnd<T>(ne[j] + beta * zo[j]);
-        const double s = rnd<T>(we[j] + beta * so[j]);
-        const double t = rnd<T>(re[j] + beta * to[j]);
-        double qv = s, pv = t;
-        if constexpr (JAC) {
-            qv = rnd<T>(me + beta * qo[j]);
-            pv = rnd<T>(ue[j] + beta * po[j]);
+        double z, s, t, qv, pv, wn;
+        if constexpr (!VAR) {
+            // beta-recurrences
+            z = rnd<T>(ne[j] + beta * zo[j]);
+            s = rnd<T>(we[j] + beta * so[j]);
+            t = rnd<T>(re[j] + beta * to[j]);
+            qv = s, pv = t;
+            if constexpr (JAC) {
+                qv = rnd<T>(me + beta * qo[j]);
+                pv = rnd<T>(ue[j] + beta * po[j]);
+            }
+            wn = rnd<T>(we[j] - alpha * z);
+        } else {
+            // Alg. 4: t, p first; s, q, z carry the shift-difference
+            // correction, subtracted after the two-term recurrence
+            t = rnd<T>(re[j] + beta * to[j]);
+            pv = t;
+            if constexpr (JAC) pv = rnd<T>(ue[j] + beta * po[j]);
+            s = rnd<T>((we[j] + beta * so[j]) - ds * t);
+            qv = s;
+            if constexpr (JAC) qv = rnd<T>((me + beta * qo[j]) - ds * pv);
+            z = rnd<T>((ne[j] + beta * zo[j]) - ds * (s + sigma * t));
+            wn = rnd<T>((we[j] - alpha * z) - ds * re[j]);  // the old r_i
         }
         // alpha-recurrences, the shift terms grouped first
         const double xn = xo[j] + alpha * pv;
         const double rn = rnd<T>(re[j] - (alpha * s + as * t));
         double un = rn;
         if constexpr (JAC) un = rnd<T>(ue[j] - (alpha * qv + as * pv));
-        const double wn = rnd<T>(we[j] - alpha * z);
         sts<NT>(vp<T>(a, a.off_z, e), z);
         sts<NT>(vp<T>(a, a.off_s, e), s);
         sts<NT>(vp<T>(a, a.off_t, e), t);
@@ -404,16 +438,16 @@ __device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, double
     }
 }
 
-template <typename T, int OP, bool JAC, int EPT, bool NT>
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
 __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     PipeScalars sc;
-    if (!pipe_head(a, lds_red, sc)) return;
+    if (!pipe_head<T, VAR>(a, lds_red, sc)) return;
     double acc[3] = {0.0, 0.0, 0.0};
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
     for (int tile = tr.first; tile < tr.end; tile += tr.step)
-        tile_pipe<T, OP, JAC, EPT, NT>(a, tile, sc.alpha, sc.beta, acc);
+        tile_pipe<T, OP, JAC, EPT, NT, VAR>(a, tile, sc, acc);
     block_sum<3>(acc, lds_red);
     store_partial<3>(a.part_out, acc);
 }

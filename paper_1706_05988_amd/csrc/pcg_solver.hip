@@ -4,6 +4,7 @@
 // device status polled one launch behind, explicit residual, restarts).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
@@ -107,7 +108,14 @@ pcg_status validate_operator(const pcg_operator *op, int prec)
 pcg_status validate_options(const pcg_options *o)
 {
     if (!o) return invalid("options is null");
-    if (o->method < PCG_CG || o->method > PCG_PIPE_SHIFT) return invalid("unknown method");
+    if (o->method < PCG_CG || o->method > PCG_PIPE_VAR_SHIFT) return invalid("unknown method");
+    if (o->method == PCG_PIPE_VAR_SHIFT) {
+        if (!o->sigma_schedule || o->sigma_schedule_len < 1 || o->sigma_schedule_len > (1 << 24))
+            return invalid("PCG_PIPE_VAR_SHIFT needs sigma_schedule with 1 .. 2^24 entries");
+        for (int k = 0; k < o->sigma_schedule_len; ++k)
+            if (!(o->sigma_schedule[k] >= 0.0 && std::isfinite(o->sigma_schedule[k])))
+                return invalid("every sigma_schedule entry must be finite and >= 0");
+    }
     if (o->pc < PCG_PC_NONE || o->pc > PCG_PC_JACOBI) return invalid("unknown preconditioner");
     if (o->prec < PCG_FP64 || o->prec > PCG_FP32_STREAM) return invalid("unknown precision");
     if (o->max_iter < 0) return invalid("max_iter must be >= 0");
@@ -195,6 +203,7 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
     l.flag = take(64);
     l.hist = take(size_t(o->history_cap) * PCG_HISTORY_FIELDS * 8);
     l.dinv = (op->kind == PCG_OP_CSR && jac) ? take(n * es) : SIZE_MAX;
+    l.sched = o->method == PCG_PIPE_VAR_SHIFT ? take(size_t(o->sigma_schedule_len) * 8) : SIZE_MAX;
     // slots of a 512-unknown tile: x (binary64) first, then the stored vectors
     for (int k = 0; k < V_COUNT; ++k) l.slot_off[k] = kNoSlot;
     uint32_t tb = 0;
@@ -236,7 +245,7 @@ using LaunchFn = void (*)(PassArgsAny, int, int, hipStream_t);
 
 // Kernel table for one (T, OP, JAC, EPT, NT) combination.
 struct Kernels {
-    LaunchFn copy_x, init0_pipe, init0_cg, init1, pipe, cg_init1, cg_a, cg_b, resid;
+    LaunchFn copy_x, init0_pipe, init0_cg, init1, pipe, pipe_var, cg_init1, cg_a, cg_b, resid;
 };
 
 template <typename T, int OP, bool JAC, int EPT, bool NT>
@@ -252,6 +261,8 @@ struct KernelSet {
     { hipLaunchKernelGGL((k_init1<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void pipe(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void pipe_var(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, true>), dim3(g), dim3(b), 0, s, A(a)); }
     static void cg_init1(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_cg_init1<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void cg_a(PassArgsAny a, int g, int b, hipStream_t s)
@@ -260,7 +271,8 @@ struct KernelSet {
     { hipLaunchKernelGGL((k_cg_b<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void resid(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_resid<T, OP, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static Kernels table() { return Kernels{copy_x, init0_pipe, init0_cg, init1, pipe, cg_init1, cg_a, cg_b, resid}; }
+    static Kernels table()
+    { return Kernels{copy_x, init0_pipe, init0_cg, init1, pipe, pipe_var, cg_init1, cg_a, cg_b, resid}; }
 };
 
 template <typename T, int OP, bool JAC, int EPT>
@@ -314,6 +326,7 @@ struct pcg_solver_ {
     LaunchShape sh;
     Kernels kern;
     double sigma;            // shift in use (0 for CG / p-CG)
+    std::vector<double> sched;  // variable shift: sigma_{-1}, sigma_0, ... (host copy)
     double dinv_s;           // stencil Jacobi scalar
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -375,6 +388,8 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
         a.xcd_map = sh.xcd_map;
         a.copy_out = 0;
         a.x_plain = 0;
+        a.sched = L.sched == SIZE_MAX ? nullptr : reinterpret_cast<const double *>(ws + L.sched);
+        a.sched_len = (int32_t)sched.size();
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
     else fill((float *)nullptr);
@@ -386,6 +401,7 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
 static_assert(offsetof(PassArgs<double>, clear) == offsetof(PassArgs<float>, clear), "PassArgs layout");
 static_assert(offsetof(PassArgs<double>, copy_out) == offsetof(PassArgs<float>, copy_out), "PassArgs layout");
 static_assert(offsetof(PassArgs<double>, x_plain) == offsetof(PassArgs<float>, x_plain), "PassArgs layout");
+static_assert(offsetof(PassArgs<double>, sigma) == offsetof(PassArgs<float>, sigma), "PassArgs layout");
 static PassArgs<double> &head(PassArgsAny &a) { return *reinterpret_cast<PassArgs<double> *>(a.bytes); }
 
 // K iterations: pipelined = K passes, CG = 2K passes.  Pass k reads slot
@@ -400,7 +416,8 @@ static void enqueue_iterations(pcg_solver_ *s, hipStream_t st, const double *b)
             s->kern.cg_b(s->args(1, b, nullptr, 0, it & 1), s->sh.grid, s->sh.block, st);
         }
     } else {
-        for (int k = 0; k < K; ++k) s->kern.pipe(s->args(k & 1, b, nullptr), s->sh.grid, s->sh.block, st);
+        const LaunchFn pass = s->opt.method == PCG_PIPE_VAR_SHIFT ? s->kern.pipe_var : s->kern.pipe;
+        for (int k = 0; k < K; ++k) pass(s->args(k & 1, b, nullptr), s->sh.grid, s->sh.block, st);
     }
 }
 
@@ -428,7 +445,13 @@ pcg_status pcg_solver_::run_init(const double *b, int i0)
         if (opt.pc == PCG_PC_JACOBI) clr |= CLR_Q | CLR_P;
         head(a0).clear = clr;
         kern.init0_pipe(a0, sh.grid, sh.block, stream);
-        kern.init1(args(1, b, nullptr, i0, 1), sh.grid, sh.block, stream);  // w_par 1: w_out = w[0]
+        PassArgsAny a1 = args(1, b, nullptr, i0, 1);  // w_par 1: w_out = w[0]
+        if (opt.method == PCG_PIPE_VAR_SHIFT) {
+            // w_{i0} := A u - sigma_{i0 - 1} r keeps the definition of w under a (re)start
+            const size_t k = std::min(size_t(i0), sched.size() - 1);
+            head(a1).sigma = sched[k];
+        }
+        kern.init1(a1, sh.grid, sh.block, stream);
     }
     HIPCHK(hipGetLastError());
     return PCG_OK;
@@ -586,6 +609,14 @@ extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const 
             return fail(st);
     }
     s->sigma = default_sigma(op, opt, gersh);
+    if (opt->method == PCG_PIPE_VAR_SHIFT) {
+        s->sched.assign(opt->sigma_schedule, opt->sigma_schedule + opt->sigma_schedule_len);
+        s->opt.sigma_schedule = nullptr;  // the caller's array is not kept
+        if ((he = hipMemcpyAsync(s->ws + L.sched, s->sched.data(), s->sched.size() * 8, hipMemcpyHostToDevice,
+                                 s->stream)) != hipSuccess)
+            return fail(hip_fail(he, "hipMemcpyAsync"));
+        if ((he = hipStreamSynchronize(s->stream)) != hipSuccess) return fail(hip_fail(he, "hipStreamSynchronize"));
+    }
     *out = s;
     return PCG_OK;
 }
@@ -732,6 +763,8 @@ extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_re
     res->rel_res_true = bn > 0 ? std::sqrt(tr2) / bn : std::sqrt(tr2);
     res->iter_kernel_ms = kernel_ms;
     res->iter_passes = (o.method == PCG_CG ? 2 : 1) * S.iter;
+    if (o.method == PCG_PIPE_VAR_SHIFT)  // sigma_{i-1}: the shift of the final w_i
+        res->sigma = s->sched[std::min(size_t(S.iter), s->sched.size() - 1)];
     if (o.history_cap > 0)
         HIPCHK(hipMemcpyAsync(o.history, s->ws + s->L.hist, size_t(o.history_cap) * PCG_HISTORY_FIELDS * 8,
                               hipMemcpyDeviceToHost, s->stream));

@@ -21,14 +21,14 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pcg.h")
 PCG_OK, PCG_PENDING = 0, 1
 PCG_ERR_INVALID, PCG_ERR_NONFINITE, PCG_ERR_HIP, PCG_ERR_BUDGET, PCG_ERR_STATE = -1, -2, -3, -4, -5
 PCG_CONVERGED, PCG_MAX_ITER, PCG_BREAKDOWN, PCG_NONFINITE = 0, 1, 2, 3
-PCG_CG, PCG_PIPE, PCG_PIPE_SHIFT = 0, 1, 2
+PCG_CG, PCG_PIPE, PCG_PIPE_SHIFT, PCG_PIPE_VAR_SHIFT = 0, 1, 2, 3
 PCG_OP_STENCIL2D5, PCG_OP_STENCIL3D7, PCG_OP_CSR = 0, 1, 2
 PCG_PC_NONE, PCG_PC_JACOBI = 0, 1
 PCG_FP64, PCG_FP32_STREAM = 0, 1
 PCG_HISTORY_FIELDS = 5
 PCG_VAR_SET, PCG_VAR_XCD_MAP, PCG_VAR_NT, PCG_VAR_EPT1, PCG_VAR_EPT4 = 0x01, 0x02, 0x04, 0x10, 0x20
 
-METHOD = {"cg": PCG_CG, "pipe": PCG_PIPE, "pipe_shift": PCG_PIPE_SHIFT}
+METHOD = {"cg": PCG_CG, "pipe": PCG_PIPE, "pipe_shift": PCG_PIPE_SHIFT, "pipe_var": PCG_PIPE_VAR_SHIFT}
 OUTCOME = {PCG_CONVERGED: "converged", PCG_MAX_ITER: "max_iter", PCG_BREAKDOWN: "breakdown",
            PCG_NONFINITE: "nonfinite"}
 OPKIND = {"2d5": PCG_OP_STENCIL2D5, "3d7": PCG_OP_STENCIL3D7, "csr": PCG_OP_CSR}
@@ -47,7 +47,8 @@ class pcg_options(C.Structure):
                 ("replace_max", C.c_int32), ("iters_per_launch", C.c_int32), ("history_cap", C.c_int32),
                 ("history", C.c_void_p), ("block_size", C.c_int32), ("grid_blocks", C.c_int32),
                 ("timing", C.c_int32), ("use_graph", C.c_int32), ("variant", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("sigma_schedule_len", C.c_int32), ("reserved", C.c_int32 * 2),
+                ("sigma_schedule", C.c_void_p)]
 
 
 class pcg_result(C.Structure):
@@ -85,6 +86,11 @@ _SIGS = {
     "pcg_wait": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(pcg_result)]),
     "pcg_server_destroy": (C.c_int32, [C.c_void_p]),
     "pcg_status_str": (C.c_char_p, [C.c_int32]),
+    "pcg_psi": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
+    "pcg_psi_variable": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
+                                     C.POINTER(C.c_double)]),
+    "pcg_select_shift": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
+                                     C.c_void_p, C.POINTER(C.c_double)]),
     "pcg_last_error": (C.c_char_p, []),
 }
 
@@ -248,11 +254,52 @@ class DeviceOperator:
         self.struct = s
 
 
+def _f64(a):
+    import numpy as np
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def pcg_psi(alpha, beta, i: int, sigma: float) -> float:
+    """psi_i(sigma) from a recorded alpha / beta history (host)."""
+    a, b = _f64(alpha), _f64(beta)
+    if len(a) <= i or len(b) <= i:
+        raise ValueError("alpha and beta need i + 1 entries")
+    out = C.c_double()
+    _check(lib().pcg_psi(a.ctypes.data, b.ctypes.data, int(i), float(sigma), C.byref(out)), "pcg_psi")
+    return out.value
+
+
+def pcg_psi_variable(alpha, beta, i: int, sigma_schedule) -> float:
+    a, b, s = _f64(alpha), _f64(beta), _f64(sigma_schedule)
+    if len(a) <= i or len(b) <= i:
+        raise ValueError("alpha and beta need i + 1 entries")
+    out = C.c_double()
+    _check(lib().pcg_psi_variable(a.ctypes.data, b.ctypes.data, int(i), s.ctypes.data, len(s), C.byref(out)),
+           "pcg_psi_variable")
+    return out.value
+
+
+def pcg_select_shift(alpha, beta, i: int, grid, slack: float = 2.0):
+    """(sigma*, psi values on the grid)."""
+    import numpy as np
+    a, b, g = _f64(alpha), _f64(beta), _f64(grid)
+    if len(a) <= i or len(b) <= i:
+        raise ValueError("alpha and beta need i + 1 entries")
+    vals = np.empty(len(g))
+    best = C.c_double()
+    _check(lib().pcg_select_shift(a.ctypes.data, b.ctypes.data, int(i), g.ctypes.data, len(g), float(slack),
+                                  vals.ctypes.data, C.byref(best)), "pcg_select_shift")
+    return best.value, vals
+
+
 def make_options(method: str = "pipe_shift", jacobi: bool = False, fp32: bool = False,
                  sigma: Optional[float] = None, rtol: float = 1e-10, max_iter: int = 1000,
                  true_residual_check: bool = True, replace_max: int = 4, iters_per_launch: int = 0,
                  history_cap: int = 0, block_size: int = 0, grid_blocks: int = 0, timing: bool = False,
-                 use_graph: bool = True, variant: int = 0) -> pcg_options:
+                 use_graph: bool = True, variant: int = 0, sigma_schedule=None) -> pcg_options:
+    """Options for pcg_create.  ``sigma_schedule`` (method "pipe_var") lists
+    sigma_{-1}, sigma_0, sigma_1, ...; the returned struct keeps the array
+    alive until the solver copies it at creation."""
     o = pcg_default_options()
     o.method = METHOD[method]
     o.pc = PCG_PC_JACOBI if jacobi else PCG_PC_NONE
@@ -269,6 +316,12 @@ def make_options(method: str = "pipe_shift", jacobi: bool = False, fp32: bool = 
     o.timing = int(bool(timing))
     o.use_graph = int(bool(use_graph))
     o.variant = int(variant)
+    if sigma_schedule is not None:
+        import numpy as np
+        sched = np.ascontiguousarray(sigma_schedule, dtype=np.float64)
+        o._sched_keep = sched
+        o.sigma_schedule = sched.ctypes.data
+        o.sigma_schedule_len = len(sched)
     return o
 
 

@@ -366,3 +366,95 @@ def test_anisotropic_csr_attainable_accuracy_per_shift(torch, sigma, fp32):
         assert g["status"] in ("breakdown", "max_iter")
         lo, hi = sorted((o["rel_res_true"], on["rel_res_true"]))
         assert lo / 100 <= g["rel_res_true"] <= hi * 100
+
+
+# ---------------------------------------------------------------- Alg. 4: variable shift
+
+def _sched(count, seed, lo, hi):
+    return np.random.default_rng(seed).uniform(lo, hi, count)
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_variable_shift_constant_schedule_matches_alg3_on_gpu(torch, jacobi):
+    """A constant schedule makes every correction term zero: the Alg. 4 pass
+    gives Alg. 3's iterates (to the last bits that FMA contraction choices
+    can move: the compiler may fuse either product of a sum of two)."""
+    p = problems.poisson3d(30, seed=1, jacobi=jacobi)
+    sig = 1.0 if jacobi else 6.0
+    a = gpu_solve(torch, p, "pipe_shift", sigma=sig, max_iter=120, true_residual_check=False)
+    v = gpu_solve(torch, p, "pipe_var", sigma_schedule=[sig], max_iter=120, true_residual_check=False)
+    assert v["iterations"] == a["iterations"]
+    k = a["iterations"]
+    np.testing.assert_allclose(v["res"][: k + 1], a["res"][: k + 1], rtol=1e-12)
+    np.testing.assert_allclose(v["x"], a["x"], rtol=1e-10, atol=1e-14)
+    assert v["sigma"] == sig
+
+
+@pytest.mark.parametrize("prob", ["2d_none", "3d_jacobi_ragged", "csr_jacobi"])
+def test_variable_shift_history_and_solution(torch, prob):
+    """Alg. 4 with a shift that changes every iteration: GPU histories follow
+    the oracle's (same schedule) and the solve reaches the oracle's residual."""
+    if prob == "2d_none":
+        p = problems.poisson2d_manufactured(100)
+        sched = _sched(300, 1, 2.0, 6.0)
+    elif prob == "3d_jacobi_ragged":
+        op = problems.stencil3d(37, 41, 43)
+        xt = np.random.default_rng(11).uniform(-1, 1, op.n)
+        p = problems.Problem("ragged3d", op, problems.to_scipy(op) @ xt, np.zeros(op.n), xt, jacobi=True,
+                             sigma=1.0, rtol=1e-10, max_iter=2000)
+        sched = _sched(300, 2, 0.2, 1.8)
+    else:
+        p = problems.anisotropic_csr(48, seed=5)
+        p.rtol, p.max_iter = 1e-10, 5000
+        sched = _sched(50, 3, 0.5, 1.5)
+    g = gpu_solve(torch, p, "pipe_var", sigma_schedule=sched, true_residual_check=False)
+    o = oracle_solve(p, "pipe_var", sigma_schedule=sched)
+    assert g["status"] == o["status"] == "converged"
+    assert abs(g["iterations"] - o["iterations"]) <= 2
+    check_history(g, o, upto=30 if prob == "csr_jacobi" else 50, rtol=1e-9 if prob == "csr_jacobi" else 1e-10)
+    assert g["rel_res_true"] <= max(10 * o["rel_res_true"], 1e-10)
+    assert g["sigma"] == sched[min(g["iterations"], len(sched) - 1)]
+
+
+def test_variable_shift_fp32_stream(torch):
+    """FP32-stream form of Alg. 4: early history to binary32 resolution and the
+    attainable accuracy within 10x of the oracle's emulation of that form."""
+    p = problems.poisson2d_manufactured(64)
+    sched = _sched(40, 4, 2.0, 6.0)
+    kw = dict(fp32=True, rtol=1e-30, max_iter=400, sigma_schedule=sched)
+    g = gpu_solve(torch, p, "pipe_var", true_residual_check=False, **kw)
+    o = oracle_solve(p, "pipe_var", ignore_breakdown=True, **kw)
+    np.testing.assert_allclose(g["res"][:15], o["res"][:15], rtol=1e-4)
+    assert g["rel_res_true"] <= 10 * o["rel_res_true"]
+
+
+def test_variable_shift_restart_uses_sigma_prev(torch):
+    """A restart from x at iteration i rebuilds w_i with sigma_{i-1}: the
+    FP32-stream solve with restarts reaches the binary64 tolerance."""
+    p = problems.poisson3d(40, seed=2)
+    sched = _sched(500, 5, 0.5, 1.5)
+    g = gpu_solve(torch, p, "pipe_var", fp32=True, rtol=1e-10, max_iter=4000, replace_max=10, hist=False,
+                  sigma_schedule=sched)
+    assert g["status"] == "converged"
+    assert g["replacements"] >= 1
+    assert g["rel_res_true"] <= 1e-10
+
+
+# ---------------------------------------------------------------- shift selection from a GPU history
+
+def test_select_shift_from_gpu_recorded_history(torch):
+    """Section 5.1's workflow: record alpha / beta on the device (500
+    iterations of lapl200), then pick sigma from psi_499 on a grid.  The
+    library's psi values equal the oracle's on the same coefficients and the
+    choice is Table 1's sigma* = 4.00."""
+    import oracle.psi as psi_mod
+    from paper_1706_05988_amd import pcg as P
+    p = problems.lapl200()
+    g = gpu_solve(torch, p, "cg", rtol=1e-30, max_iter=500, true_residual_check=False)
+    assert g["iterations"] == 500
+    a, b = g["alpha"][:500], g["beta"][:500]
+    grid = np.arange(0.0, 8.01, 0.5)
+    s, vals = P.pcg_select_shift(a, b, 499, grid, slack=2.0)
+    so, ovals = psi_mod.select_shift(a, b, grid, 499, slack=2.0)
+    np.testing.assert_allclose(vals, ovals, rtol=1e-9)
+    assert s == so == 4.0

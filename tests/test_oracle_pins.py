@@ -504,3 +504,14 @@ def test_variable_shift_converges_to_the_solution():
     r = oracle.solve(p.op, p.b, None, method="pipe_var", sigma_schedule=sched, rtol=1e-13, max_iter=500)
     assert r["status"] == "converged"
     assert np.linalg.norm(r["x"] - x_ref) <= 1e-10 * np.linalg.norm(x_ref)
+
+
+def test_select_shift_slack_rule_gives_table1_shift():
+    """Smallest grid shift within a factor 2 of the minimal psi_500 is the
+    sigma* = 4.00 of Table 1 for lapl200 (grid 0, 0.5, .., 8)."""
+    g = golden("psi_lapl200.json")
+    p = problems.lapl200()
+    r = oracle.solve_problem(p, "pipe", max_iter=g["i"], rtol=1e-30, ignore_breakdown=True, threads=4)
+    a, b = r["alpha"][: g["i"]], r["beta"][: g["i"]]
+    s, vals = psi_mod.select_shift(a, b, np.arange(0.0, 8.01, 0.5), slack=2.0)
+    assert s == g["sigma_star"]

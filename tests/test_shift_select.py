@@ -1,0 +1,79 @@
+"""A-posteriori shift selection (Section 3.2, Section 5.1): the library's
+host routines pcg_psi / pcg_psi_variable / pcg_select_shift against the
+oracle's psi (numpy SVD norms) on the oracle's own alpha / beta histories,
+and against the values the paper prints for lapl200."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.psi as psi_mod
+import problems
+from paper_1706_05988_amd import pcg as P
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def lapl200_pcg():
+    g = json.load(open(os.path.join(GOLDEN, "psi_lapl200.json")))
+    p = problems.lapl200()
+    r = oracle.solve_problem(p, "pipe", max_iter=g["i"], rtol=1e-30, ignore_breakdown=True, threads=4)
+    return g, r["alpha"][: g["i"]], r["beta"][: g["i"]]
+
+
+def test_psi_matches_oracle_and_the_paper(lapl200_pcg):
+    g, a, b = lapl200_pcg
+    i = len(a) - 1
+    for s in (0.0, 1.0, 4.0, 7.5, 8.0):
+        assert P.pcg_psi(a, b, i, s) == pytest.approx(psi_mod.psi(a, b, s, i), rel=1e-9)
+    # Section 5.1: psi_500(sigma* = 4) = 3.46e+02 for lapl200
+    assert P.pcg_psi(a, b, i, g["sigma_star"]) == pytest.approx(g["psi_sigma_star"], rel=0.01)
+
+
+def test_select_shift_gives_the_table_shift(lapl200_pcg):
+    """On the grid 0, 0.5, .., 8 the smallest shift within a factor 2 of the
+    smallest psi is 4.00, the sigma* Table 1 lists for lapl200; the plain
+    argmin sits next to the top of the spectrum (lambda_max ~ 8)."""
+    g, a, b = lapl200_pcg
+    i = len(a) - 1
+    grid = np.arange(0.0, 8.01, 0.5)
+    s2, vals = P.pcg_select_shift(a, b, i, grid, slack=2.0)
+    o2, ovals = psi_mod.select_shift(a, b, grid, i, slack=2.0)
+    np.testing.assert_allclose(vals, ovals, rtol=1e-9)
+    assert s2 == o2 == g["sigma_star"]
+    s1, _ = P.pcg_select_shift(a, b, i, grid, slack=1.0)
+    assert s1 == psi_mod.select_shift(a, b, grid, i)[0]
+    assert 6.0 < s1 < 8.0
+
+
+def test_psi_variable_matches_oracle_and_reduces_to_constant(lapl200_pcg):
+    _, a, b = lapl200_pcg
+    i = 200
+    assert P.pcg_psi_variable(a, b, i, [3.0]) == P.pcg_psi(a, b, i, 3.0)
+    sched = np.random.default_rng(0).uniform(1.0, 6.0, 150)
+    assert P.pcg_psi_variable(a, b, i, sched) == pytest.approx(psi_mod.psi_variable(a, b, sched, i), rel=1e-9)
+
+
+def test_psi_small_cases_by_hand():
+    """alpha = 0 leaves diag-like matrices: P = [[1,0,0,0],[0,b,1,0],[0,0,1,0],
+    [0,0,0,b]]; with b = 0.5, ||P|| and its powers have closed forms checked
+    by numpy; one iteration (i = 1) is just ||P_1||."""
+    a = [0.0, 0.0, 0.0, 0.0]
+    b = [0.0, 0.5, 0.5, 0.5]
+    Pm = psi_mod.propagation_matrix(0.0, 0.5, 0.0)
+    want = max(np.linalg.norm(np.linalg.matrix_power(Pm, k), 2) for k in (1, 2, 3))
+    assert P.pcg_psi(a, b, 3, 0.0) == pytest.approx(want, rel=1e-12)
+    assert P.pcg_psi([0.0, 0.7], [0.0, 0.3], 1, 2.0) == pytest.approx(
+        np.linalg.norm(psi_mod.propagation_matrix(0.7, 0.3, 2.0), 2), rel=1e-12)
+
+
+def test_psi_argument_errors():
+    with pytest.raises(P.PcgError):
+        P.pcg_psi([1.0, 1.0], [0.0, 0.5], 0, 1.0)
+    with pytest.raises(P.PcgError):
+        P.pcg_psi([1.0, float("nan")], [0.0, 0.5], 1, 1.0)
+    with pytest.raises(P.PcgError):
+        P.pcg_select_shift([1.0, 1.0], [0.0, 0.5], 1, [0.0, 1.0], slack=0.5)
