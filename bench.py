@@ -35,11 +35,11 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pipe_3d7_jacobi_fp64_256.
 # the rocprofv3 runs whose output --ingest-profile summarises (run from the repo root)
 PROFILE_COMMANDS = [
     "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- "
-    "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+    "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batched --no-serving",
     "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch --output-format csv -- "
-    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --max-iter 24 --calib-copy",
+    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-serving --max-iter 24 --calib-copy",
     "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write -o write --output-format csv -- "
-    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --max-iter 24 --calib-copy",
+    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-serving --max-iter 24 --calib-copy",
     "python3 bench.py --ingest-profile gpurun_out/prof_trace gpurun_out/prof_fetch gpurun_out/prof_write",
 ]
 KERNEL_SOURCES = ["paper_1706_05988_amd/csrc/pcg_kernels.h", "paper_1706_05988_amd/csrc/pcg_device.h"]
