@@ -27,7 +27,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pcg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-METHODS = {"cg": 0, "pipe": 1, "pipe_shift": 2, "pipe_var": 3}
+METHODS = {"cg": 0, "pipe": 1, "pipe_shift": 2, "pipe_var": 3, "pipe_rr": 4}
 STATUS = {0: "converged", 1: "max_iter", 2: "breakdown", 3: "nonfinite"}
 KINDS = {"2d5": 0, "3d7": 1, "csr": 2}
 
@@ -56,7 +56,8 @@ class _Opts(C.Structure):
                 ("record_true", C.c_int32), ("record_gaps", C.c_int32), ("threads", C.c_int32),
                 ("replace_max", C.c_int32), ("ignore_breakdown", C.c_int32),
                 ("sigma_sched", C.c_void_p), ("sigma_sched_len", C.c_int32),
-                ("w0_perturb", C.c_void_p)]
+                ("w0_perturb", C.c_void_p), ("rr_tau", C.c_double), ("rr_period", C.c_int32),
+                ("rr_floor", C.c_double)]
 
 
 _HIST = ["h_res", "h_true", "h_alpha", "h_beta", "h_gamma", "h_delta", "h_f", "h_g", "h_h", "h_j"]
@@ -135,7 +136,8 @@ def solve(op, b: np.ndarray, x0: Optional[np.ndarray] = None, method: str = "pip
           sigma: float = 0.0, rtol: float = 1e-10, max_iter: int = 1000, jacobi: bool = False,
           fp32_storage: bool = False, record: bool = True, record_true: bool = False,
           record_gaps: bool = False, threads: int = 1, replace_max: int = 0,
-          ignore_breakdown: bool = False, sigma_schedule=None, w0_perturb=None) -> dict:
+          ignore_breakdown: bool = False, sigma_schedule=None, w0_perturb=None,
+          rr_tau: Optional[float] = None, rr_period: int = 8, rr_floor: float = 100.0) -> dict:
     """Run the oracle.  Returns a dict with x, status, iterations, norms and
     (if ``record``) histories indexed by iteration (NaN where not reached)."""
     lib = _load()
@@ -150,6 +152,10 @@ def solve(op, b: np.ndarray, x0: Optional[np.ndarray] = None, method: str = "pip
         sched = np.ascontiguousarray(sigma_schedule, dtype=np.float64)
         opts.sigma_sched = _ptr(sched)
         opts.sigma_sched_len = len(sched)
+    # p-CG-rr: tau defaults to the square root of the storage unit roundoff
+    opts.rr_tau = float(rr_tau) if rr_tau is not None else (2.0 ** -12 if fp32_storage else 2.0 ** -26.5)
+    opts.rr_period = int(rr_period)
+    opts.rr_floor = float(rr_floor)
     pert = None
     if w0_perturb is not None:
         pert = np.ascontiguousarray(w0_perturb, dtype=np.float64)

@@ -11,6 +11,9 @@
  *   - preconditioned pipelined CG (p-CG) ....... Alg. 2 (Section 2.1)
  *   - shifted preconditioned pipelined CG ...... Alg. 3 (Section 2.2)
  *   - p-CG with a variable shift sigma_i ........ Alg. 4 (Section 4.1)
+ *   - p-CG with automated residual replacement (p-CG-rr, Section 5.2): a
+ *     design of this project, since the criterion's source is not available
+ *     (see the conventions below)
  * on an SPD operator given as a 2-D 5-point stencil, a 3-D 7-point stencil
  * (homogeneous Dirichlet, interior unknowns, x fastest) or a CSR matrix, with
  * no preconditioner or the Jacobi (diagonal) preconditioner.
@@ -48,6 +51,14 @@
  *     before r_i is overwritten, as the derivation of Section 4.1 requires;
  *     the shift schedule holds sigma_{-1}, sigma_0, sigma_1, ... and its
  *     last entry repeats past its end.
+ *   - p-CG-rr: at the top of iteration i (after the stop test and the cap,
+ *     before the breakdown checks), when i > i_start and i is a multiple of
+ *     the monitoring period m, the gap f_i = (b - A x_i) - r_i is measured;
+ *     if ||f_i|| > tau ||r_i|| the residual and the auxiliary vectors are
+ *     reset to their true values -- r := b - A x_i, u := M^{-1} r,
+ *     w := A u, s := A p_{i-1}, q := M^{-1} s, z := A q -- and iteration i
+ *     starts again from its dot products, its beta continuing the old
+ *     recurrence (gamma_{i-1}, alpha_{i-1} are kept).
  * Diagnostics: the explicit residual ||b - A x_i|| per iteration and the gap
  * norms ||f||, ||g||, ||h||, ||j|| of Section 3.1 from their definitions; a
  * test hook adds a given vector to w_0, planting a known gap h_0 whose
@@ -64,7 +75,7 @@
 #define ORC_CHUNK 4096
 
 enum { ORC_2D5 = 0, ORC_3D7 = 1, ORC_CSR = 2 };
-enum { ORC_CG = 0, ORC_PIPE = 1, ORC_PIPE_SHIFT = 2, ORC_PIPE_VAR = 3 };
+enum { ORC_CG = 0, ORC_PIPE = 1, ORC_PIPE_SHIFT = 2, ORC_PIPE_VAR = 3, ORC_PIPE_RR = 4 };
 enum { ORC_CONVERGED = 0, ORC_MAX_ITER = 1, ORC_BREAKDOWN = 2, ORC_NONFINITE = 3 };
 
 typedef struct {
@@ -94,6 +105,9 @@ typedef struct {
     const double *sigma_sched; /* Alg. 4: sigma_{-1}, sigma_0, ... (last entry repeats) */
     int32_t sigma_sched_len;
     const double *w0_perturb;  /* test hook: added to w_0 after the initialisation (NULL: none) */
+    double rr_tau;             /* p-CG-rr: replace when ||f_i|| > rr_tau ||r_i|| */
+    int32_t rr_period;         /* p-CG-rr: measure the gap every rr_period iterations */
+    double rr_floor;           /* p-CG-rr: ... and only when ||f_i|| > rr_floor * eps || |A||x| + |b| || */
 } orc_opts;
 
 typedef struct {
@@ -265,6 +279,38 @@ static void ymax_corr(int64_t n, double alpha, const double *a, double d, const 
     for (int64_t i = 0; i < n; ++i) y[i] = st((y[i] - alpha * a[i]) - d * c[i]);
 }
 
+/* out = |A| |v| + |c|  (rounding scale of computing c - A v; entrywise) */
+static void abs_scale(const orc_op *A, const double *v, const double *c, double *out)
+{
+    const int64_t n = A->n;
+    if (A->kind == ORC_CSR) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i) {
+            double acc = 0.0;
+            for (int64_t k = A->row_ptr[i]; k < A->row_ptr[i + 1]; ++k) acc = acc + fabs(A->val[k]) * fabs(v[A->col[k]]);
+            out[i] = acc + fabs(c[i]);
+        }
+        return;
+    }
+    const int64_t nx = A->nx, ny = A->ny, nz = (A->kind == ORC_3D7) ? A->nz : 1;
+    const int64_t sxy = nx * ny;
+    const double ac = fabs(A->centre), ao = fabs(A->off);
+#pragma omp parallel for schedule(static)
+    for (int64_t idx = 0; idx < n; ++idx) {
+        const int64_t i = idx % nx, j = (idx / nx) % ny, k = idx / sxy;
+        double acc = ac * fabs(v[idx]);
+        if (i > 0) acc = acc + ao * fabs(v[idx - 1]);
+        if (i < nx - 1) acc = acc + ao * fabs(v[idx + 1]);
+        if (j > 0) acc = acc + ao * fabs(v[idx - nx]);
+        if (j < ny - 1) acc = acc + ao * fabs(v[idx + nx]);
+        if (A->kind == ORC_3D7) {
+            if (k > 0) acc = acc + ao * fabs(v[idx - sxy]);
+            if (k < nz - 1) acc = acc + ao * fabs(v[idx + sxy]);
+        }
+        out[idx] = acc + fabs(c[idx]);
+    }
+}
+
 /* out = b - A x  (explicit residual, binary64) */
 static void true_residual(const orc_op *A, const double *b, const double *x, double *tmp, double *out)
 {
@@ -389,8 +435,10 @@ static int solve_pipe(const orc_op *A, const double *dinv, const orc_opts *o, in
         for (int64_t k = 0; k < n; ++k) w[k] = st(w[k] + o->w0_perturb[k]);
     /* z_{-1} = q_{-1} = s_{-1} = t_{-1} = p_{-1} = 0 (calloc) */
 
+    const int rr = o->method == ORC_PIPE_RR;
+    int rr_count = 0;
     double alpha_prev = 0.0, gamma_prev = 0.0, rho = 0.0;
-    int status = ORC_MAX_ITER, i = 0, i_start = 0;
+    int status = ORC_MAX_ITER, i = 0, i_start = 0, last_check = -1;
     for (i = 0;; ++i) {
         const double gamma = dot(n, r, u);                              /* gamma_i := (r_i, u_i) */
         const double delta = shifted ? dot_shift(n, w, sigma, r, u)     /* (w_i + sigma r_i, u_i) */
@@ -433,6 +481,32 @@ static int solve_pipe(const orc_op *A, const double *dinv, const orc_opts *o, in
             break;
         }
         if (i >= o->max_iter) { status = ORC_MAX_ITER; break; }
+        if (rr && i > i_start && i % o->rr_period == 0 && i != last_check) {
+            /* p-CG-rr: measure the residual gap; reset r, u, w, s, q, z to their
+             * true values when it has grown past tau ||r_i|| */
+            last_check = i;
+            true_residual(A, b, x, tmp, tr);
+            for (int64_t k = 0; k < n; ++k) gap[k] = tr[k] - r[k];
+            const double gnorm = norm2(n, gap);
+            abs_scale(A, x, b, tmp);
+            const double floor = 0x1p-53 * norm2(n, tmp);   /* rounding scale of b - A x */
+            if (gnorm > o->rr_tau * sqrt(rho) && gnorm > o->rr_floor * floor) {
+                ++rr_count;
+                for (int64_t k = 0; k < n; ++k) r[k] = st(tr[k]);     /* r := b - A x_i      */
+                apply_Minv(n, dinv, r, u);
+                for (int64_t k = 0; k < n; ++k) u[k] = st(u[k]);      /* u := M^{-1} r       */
+                apply_A(A, p, tmp);
+                for (int64_t k = 0; k < n; ++k) s[k] = st(tmp[k]);    /* s := A p_{i-1}      */
+                apply_Minv(n, dinv, s, q);
+                for (int64_t k = 0; k < n; ++k) q[k] = st(q[k]);      /* q := M^{-1} s       */
+                apply_A(A, u, w);
+                for (int64_t k = 0; k < n; ++k) w[k] = st(w[k]);      /* w := A u            */
+                apply_A(A, q, z);
+                for (int64_t k = 0; k < n; ++k) z[k] = st(z[k]);      /* z := A q            */
+                --i;  /* redo the top of iteration i from its dot products */
+                continue;
+            }
+        }
         if (!o->ignore_breakdown && (!(gamma > 0.0) || !(delta > 0.0))) { status = ORC_BREAKDOWN; break; }
 
         apply_Minv(n, dinv, w, m);                 /* m_i := M^{-1} w_i   */
@@ -496,7 +570,7 @@ static int solve_pipe(const orc_op *A, const double *dinv, const orc_opts *o, in
     }
     res->status = status;
     res->iterations = i;
-    res->replacements = replacements;
+    res->replacements = replacements + rr_count;
     res->rel_res_recursive = sqrt(rho) / bnorm;
     true_residual(A, b, x, tmp, tr);
     res->rel_res_true = norm2(n, tr) / bnorm;
@@ -655,7 +729,8 @@ static int solve_pipe_var(const orc_op *A, const double *dinv, const orc_opts *o
 int orc_solve(const orc_op *A, const orc_opts *o, const double *b, double *x, orc_result *res)
 {
     if (!A || !o || !b || !x || !res || A->n <= 0) return -1;
-    if (o->method < ORC_CG || o->method > ORC_PIPE_VAR) return -1;
+    if (o->method < ORC_CG || o->method > ORC_PIPE_RR) return -1;
+    if (o->method == ORC_PIPE_RR && (o->rr_period < 1 || !(o->rr_tau > 0.0))) return -1;
     if (o->method == ORC_PIPE_VAR && (!o->sigma_sched || o->sigma_sched_len < 1)) return -1;
 #ifdef _OPENMP
     int saved = omp_get_max_threads();

@@ -515,3 +515,91 @@ def test_select_shift_slack_rule_gives_table1_shift():
     a, b = r["alpha"][: g["i"]], r["beta"][: g["i"]]
     s, vals = psi_mod.select_shift(a, b, np.arange(0.0, 8.01, 0.5), slack=2.0)
     assert s == g["sigma_star"]
+
+
+# ------------------------------------------------------------ p-CG-rr (Section 5.2)
+
+TAU64 = (2.0 ** -53) ** (1 / 3)
+TAU32 = (2.0 ** -24) ** (1 / 3)
+
+
+def test_pcg_rr_without_replacement_is_pcg_bitwise():
+    """With a threshold no gap can pass, p-CG-rr performs p-CG's arithmetic."""
+    p = problems.poisson2d_manufactured(60)
+    a = oracle.solve_problem(p, "pipe", rtol=1e-12)
+    b = oracle.solve_problem(p, "pipe_rr", rtol=1e-12, rr_tau=1e300)
+    assert b["replacements"] == 0
+    assert np.array_equal(a["x"], b["x"]) and a["iterations"] == b["iterations"]
+
+
+def test_pcg_rr_attains_cg_accuracy_on_lapl200():
+    """Section 5.2: residual replacement restores classic CG's attainable
+    accuracy (there: 7.5e-12 against CG's 9.4e-12 and p-CG's 1.1e-7).  On
+    lapl200 after 500 and 1000 iterations p-CG-rr stays within 3x of CG,
+    where p-CG stagnates two orders of magnitude higher (Table 1)."""
+    p = problems.lapl200()
+    for it in (500, 1000):
+        cg = oracle.solve_problem(p, "cg", max_iter=it, rtol=1e-30, threads=4)["rel_res_true"]
+        pc = oracle.solve_problem(p, "pipe", max_iter=it, rtol=1e-30, ignore_breakdown=True, threads=4)
+        rr = oracle.solve_problem(p, "pipe_rr", max_iter=it, rtol=1e-30, ignore_breakdown=True, threads=4,
+                                  rr_tau=TAU64)
+        assert rr["replacements"] >= 1
+        assert rr["rel_res_true"] <= 3 * cg
+        assert pc["rel_res_true"] >= 100 * cg
+
+
+def test_pcg_rr_replacement_resets_the_gap():
+    """Right after a replacement the residual gap f = (b - A x) - r is the
+    rounding of one explicit residual; the recorded gap norms drop there."""
+    p = problems.poisson2d_manufactured(100)
+    r = oracle.solve_problem(p, "pipe_rr", max_iter=300, rtol=1e-30, ignore_breakdown=True, record_gaps=True,
+                             rr_tau=TAU64, threads=4)
+    q = oracle.solve_problem(p, "pipe", max_iter=300, rtol=1e-30, ignore_breakdown=True, record_gaps=True, threads=4)
+    assert r["replacements"] >= 1
+    # the final gap of p-CG-rr is far below p-CG's
+    assert r["f"][300] <= 1e-2 * q["f"][300]
+
+
+def test_pcg_rr_fp32_storage_reaches_binary64_level():
+    """Replacement recomputes r from the binary64 x, so with binary32 storage
+    p-CG-rr refines past the binary32 level that CG stagnates at."""
+    p = problems.poisson2d_manufactured(64)
+    cg = oracle.solve_problem(p, "cg", fp32_storage=True, rtol=1e-30, max_iter=400, threads=4)
+    rr = oracle.solve_problem(p, "pipe_rr", fp32_storage=True, rtol=1e-30, max_iter=400, ignore_breakdown=True,
+                              rr_tau=TAU32, threads=4)
+    assert cg["rel_res_true"] > 1e-8
+    assert rr["rel_res_true"] < 1e-11
+
+
+def test_pcg_rr_same_iteration_count_on_the_parallel_workload():
+    """Fig. 3 caption: every method, p-CG-rr included, converges in the same
+    number of iterations to 1e-6 (checked on the 200 x 200 version)."""
+    p = problems.paper_parallel_workload(200)
+    a = oracle.solve_problem(p, "pipe", rtol=1e-6, record=False, threads=4)["iterations"]
+    b = oracle.solve_problem(p, "pipe_rr", rtol=1e-6, record=False, threads=4, rr_tau=TAU64)["iterations"]
+    assert a == b
+
+
+def test_pcg_rr_dots_restart_from_the_replaced_vectors():
+    """At a replacement iteration the residual is reset to b - A x_i and the
+    iteration's dot products are formed again from the reset vectors: there
+    the recorded recursive residual equals the explicit one to the last bit,
+    while one iteration earlier their norms differed visibly."""
+    p = problems.lapl200()
+    r = oracle.solve_problem(p, "pipe_rr", max_iter=500, rtol=1e-30, ignore_breakdown=True, record_true=True,
+                             rr_tau=TAU64, threads=4)
+    rel = np.abs(r["res"] - r["true"]) / r["true"]
+    hits = [i for i in range(1, 500) if rel[i] <= 1e-15 and rel[i - 1] >= 1e-9]
+    assert r["replacements"] >= 1
+    assert len(hits) == r["replacements"]
+    assert all(i % 8 == 0 for i in hits)
+
+
+def test_pcg_rr_paper_workload_1000():
+    """The 1000 x 1000 workload: p-CG-rr also converges to 1e-6 in 1474
+    iterations (Fig. 3 caption)."""
+    g = golden("parallel_workload.json")
+    p = problems.paper_parallel_workload(g["N"])
+    r = oracle.solve_problem(p, "pipe_rr", rtol=g["rtol"], record=False, threads=0, rr_tau=TAU64)
+    assert r["status"] == "converged"
+    assert r["iterations"] == g["iterations"]
