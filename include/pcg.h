@@ -12,6 +12,16 @@
  *     Section 4.1: sigma_i from a caller-given schedule; the corrections
  *     (sigma_i - sigma_{i-1}) t_i, p_i, (s_i + sigma_i t_i), r_i of s, q, z
  *     and w ride in the same fused pass with no extra vector traffic)
+ *   - Alg. 2 with automated residual replacement ....... p-CG-rr (PCG_PIPE_RR,
+ *     Section 5.2): every rr_period iterations one pass measures the gap
+ *     f_i = (b - A x_i) - r_i in binary64; when ||f_i|| exceeds rr_tau ||r_i||
+ *     and rr_floor times the rounding scale 2^-53 || |A||x_i| + |b| || of that
+ *     explicit residual, two passes reset r, u, w, s, q, z to their true
+ *     values (r = b - A x_i, u = M^-1 r, w = A u, s = A p_{i-1},
+ *     q = M^-1 s, z = A q) and iteration i restarts from the reset vectors'
+ *     dot products while beta continues the old recurrence.  The criterion
+ *     is this library's own (the paper cites it from elsewhere); all of it
+ *     runs inside the K-pass graph, with no host round trip.
  * Alg. 3 with sigma = 0 is Alg. 2 (end of Section 2.2); both run the same
  * fused kernel.  Each pipelined iteration is ONE device pass: the
  * preconditioner apply and SPMV (m_i = M^-1 w_i, n_i = A m_i), the five
@@ -65,7 +75,7 @@ typedef int32_t pcg_status;
 #define PCG_BREAKDOWN  2   /* gamma <= 0, delta <= 0, (s,p) <= 0 or alpha not > 0     */
 #define PCG_NONFINITE  3   /* a reduction produced NaN / Inf                         */
 
-typedef enum { PCG_CG = 0, PCG_PIPE = 1, PCG_PIPE_SHIFT = 2, PCG_PIPE_VAR_SHIFT = 3 } pcg_method;
+typedef enum { PCG_CG = 0, PCG_PIPE = 1, PCG_PIPE_SHIFT = 2, PCG_PIPE_VAR_SHIFT = 3, PCG_PIPE_RR = 4 } pcg_method;
 typedef enum { PCG_OP_STENCIL2D5 = 0, PCG_OP_STENCIL3D7 = 1, PCG_OP_CSR = 2 } pcg_op_kind;
 typedef enum { PCG_PC_NONE = 0, PCG_PC_JACOBI = 1 } pcg_pc_kind;
 typedef enum { PCG_FP64 = 0, PCG_FP32_STREAM = 1 } pcg_precision;
@@ -132,7 +142,8 @@ typedef struct {
                                    (pcg_default_options' choice); 0: launch them one by one  */
     int32_t variant;            /* 0: the tuned kernel variant; else PCG_VAR_SET | bits below */
     int32_t sigma_schedule_len; /* PCG_PIPE_VAR_SHIFT: entries of sigma_schedule, 1 .. 2^24    */
-    int32_t reserved[2];
+    int32_t rr_period;          /* PCG_PIPE_RR: gap check every rr_period iterations (0: 8)  */
+    int32_t reserved;
     const double *sigma_schedule; /* PCG_PIPE_VAR_SHIFT: HOST array sigma_{-1}, sigma_0,
                                    sigma_1, ... (each finite, >= 0); entry k + 1 is the shift
                                    of iteration k and the last entry repeats past the end.
@@ -140,6 +151,11 @@ typedef struct {
                                    sigma_{-1}).  Copied at pcg_create; ignored by the other
                                    methods.  The batch and server entry points reject this
                                    method.                                                   */
+    double rr_tau;              /* PCG_PIPE_RR: relative gap threshold; NaN or <= 0: the cube
+                                   root of the storage unit roundoff (binary64 4.8e-6,
+                                   binary32 3.9e-3)                                          */
+    double rr_floor;            /* PCG_PIPE_RR: gap must also exceed rr_floor times the
+                                   rounding scale of b - A x; NaN or <= 0: 100               */
 } pcg_options;
 
 /* Kernel variant bits (pcg_options.variant).  Every variant performs the same

@@ -152,8 +152,8 @@ def solve(op, b: np.ndarray, x0: Optional[np.ndarray] = None, method: str = "pip
         sched = np.ascontiguousarray(sigma_schedule, dtype=np.float64)
         opts.sigma_sched = _ptr(sched)
         opts.sigma_sched_len = len(sched)
-    # p-CG-rr: tau defaults to the square root of the storage unit roundoff
-    opts.rr_tau = float(rr_tau) if rr_tau is not None else (2.0 ** -12 if fp32_storage else 2.0 ** -26.5)
+    # p-CG-rr: tau defaults to the cube root of the storage unit roundoff
+    opts.rr_tau = float(rr_tau) if rr_tau is not None else (2.0 ** -8 if fp32_storage else 2.0 ** (-53 / 3))
     opts.rr_period = int(rr_period)
     opts.rr_floor = float(rr_floor)
     pert = None

@@ -308,7 +308,7 @@ pcg_status BatchEngine::validate(const pcg_operator *op, const pcg_options *opt)
     pcg_status st = validate_options(opt);
     if (st) return st;
     if ((st = validate_operator(op, opt->prec))) return st;
-    if (opt->method == PCG_CG || opt->method == PCG_PIPE_VAR_SHIFT)
+    if (opt->method == PCG_CG || opt->method == PCG_PIPE_VAR_SHIFT || opt->method == PCG_PIPE_RR)
         return invalid("the batched pass runs the constant-shift pipelined methods (PCG_PIPE, PCG_PIPE_SHIFT)");
     if (opt->prec != prec_) return invalid("every system of a batch must use the batch's precision");
     return PCG_OK;
@@ -575,7 +575,7 @@ static pcg_status batch_plan(int32_t count, const pcg_operator *ops, const pcg_o
         if (st) return st;
         if ((st = validate_operator(&ops[k], opts[0].prec))) return st;
         if (opts[k].prec != opts[0].prec) return invalid("every system of a batch must use the same precision");
-        if (opts[k].method == PCG_CG || opts[k].method == PCG_PIPE_VAR_SHIFT)
+        if (opts[k].method == PCG_CG || opts[k].method == PCG_PIPE_VAR_SHIFT || opts[k].method == PCG_PIPE_RR)
             return invalid("the batched pass runs the constant-shift pipelined methods");
         BatchEngine::SysLayout L;
         BatchEngine::system_layout(&ops[k], &opts[k], &L);

@@ -48,10 +48,20 @@ struct DevState {
     int32_t iter;       // i at the top of the next pass
     int32_t i_start;    // iteration of the last (re)start: takes the i = 0 branch
     int32_t status;     // RunStatus
+    int32_t rr_phase;   // residual replacement: RrPhase of the next pass
+    double spare[2];    // [0]: ||b||^2 of an explicit-residual pass; [1]: delta_i held across a gap check
+    int32_t wflip;      // residual replacement: w_i sits in the slot the pass would write
+    int32_t last_check; // residual replacement: iteration of the last gap check
+    int32_t rr_count;   // residual replacements performed
     int32_t pad;
-    double spare[2];
 };
-static_assert(sizeof(DevState) == 80, "DevState layout");
+static_assert(sizeof(DevState) == 96, "DevState layout");
+
+// Residual-replacement pass sequence (pipelined CG with replacement):
+// ITER passes iterate or, every rr_period iterations, measure the gap
+// (b - A x) - r instead; the CHECK pass that follows either iterates or
+// starts a replacement, which takes two passes (the second is RR2).
+enum RrPhase : int32_t { RR_ITER = 0, RR_CHECK = 1, RR_RR2 = 2 };
 
 // ------------------------------------------------------------ fast division
 
@@ -152,7 +162,7 @@ __device__ __forceinline__ Nbhd<OP> neighbours(const OpDev<T> &A, uint32_t e)
 // (A v)_e.  v(k) returns the k-th entry of the operand.  Stencil rows sum
 // centre, -x, +x, -y, +y, -z, +z in that order (missing neighbours skipped);
 // CSR rows sum their entries in storage order.
-template <int OP, typename T, typename F>
+template <int OP, bool ABS = false, typename T, typename F>
 __device__ __forceinline__ double apply_row(const OpDev<T> &A, uint32_t e, F v)
 {
     if constexpr (OP == OP_CSR) {
@@ -177,7 +187,7 @@ __device__ __forceinline__ double apply_row(const OpDev<T> &A, uint32_t e, F v)
             for (int j = 0; j < kCsrChunk; ++j) g[j] = v((uint32_t)c[j]);
 #pragma unroll
             for (int j = 0; j < kCsrChunk; ++j)
-                if (k + j < k1) acc += (double)w[j] * g[j];
+                if (k + j < k1) acc += (ABS ? fabs((double)w[j]) : (double)w[j]) * g[j];
         }
         return acc;
     } else {
@@ -186,9 +196,10 @@ __device__ __forceinline__ double apply_row(const OpDev<T> &A, uint32_t e, F v)
         const double c = v(e);
 #pragma unroll
         for (int d = 0; d < Nbhd<OP>::ND; ++d) nv[d] = v(h.idx[d]);
-        double acc = A.centre * c;
+        const double cc = ABS ? fabs(A.centre) : A.centre, oo = ABS ? fabs(A.off) : A.off;
+        double acc = cc * c;
 #pragma unroll
-        for (int d = 0; d < Nbhd<OP>::ND; ++d) acc = h.ok[d] ? acc + A.off * nv[d] : acc;
+        for (int d = 0; d < Nbhd<OP>::ND; ++d) acc = h.ok[d] ? acc + oo * nv[d] : acc;
         return acc;
     }
 }

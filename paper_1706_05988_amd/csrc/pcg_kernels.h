@@ -68,7 +68,9 @@ struct PassArgs {
     int32_t x_plain;      // k_resid: read the caller's x instead of the internal one
     const double *sched;  // variable shift: sigma_{-1}, sigma_0, ... (last entry repeats)
     int32_t sched_len;
-    int32_t pad_;
+    int32_t rr_period;    // residual replacement: gap check every rr_period iterations
+    double rr_tau;        // ... replace when ||f|| > rr_tau ||r||
+    double rr_floor;      // ... and ||f|| > rr_floor * 2^-53 || |A||x| + |b| ||
 };
 
 template <typename V, typename T>
@@ -448,6 +450,213 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
     for (int tile = tr.first; tile < tr.end; tile += tr.step)
         tile_pipe<T, OP, JAC, EPT, NT, VAR>(a, tile, sc, acc);
+    block_sum<3>(acc, lds_red);
+    store_partial<3>(a.part_out, acc);
+}
+
+// ------------------------------------------------- p-CG with residual replacement
+
+// Gap check: partials of ||(b - A x) - r||^2 and || |A||x| + |b| ||^2 (the
+// rounding scale of the explicit residual), x the internal binary64 copy.
+template <typename T, int OP, int EPT>
+__device__ __forceinline__ void tile_gap(const PassArgs<T> &a, int tile, double (&acc)[3])
+{
+    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+    double be[EPT], ax[EPT], aax[EPT], re[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const uint32_t e = ti.e[j];
+        be[j] = a.b[e];
+        ax[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
+        aax[j] = apply_row<OP, true>(a.A, e, [&](uint32_t k) { return fabs(*vp<double>(a, a.off_x, k)); });
+        re[j] = ld(vp<T>(a, a.off_r, e), 0);
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (!ti.live[j]) continue;
+        const double f = (be[j] - ax[j]) - re[j];
+        const double fl = aax[j] + fabs(be[j]);
+        acc[0] += f * f;
+        acc[1] += fl * fl;
+    }
+}
+
+// Replacement, first pass: r := b - A x, u := M^-1 r, s := A p, q := M^-1 s
+// (p = p_{i-1}; the method runs without shift).
+template <typename T, int OP, bool JAC, int EPT>
+__device__ __forceinline__ void tile_rr1(const PassArgs<T> &a, int tile)
+{
+    const uint32_t off_p = JAC ? a.off_p : a.off_t;
+    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+    double be[EPT], ax[EPT], ap[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const uint32_t e = ti.e[j];
+        be[j] = a.b[e];
+        ax[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
+        ap[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return ld(vp<T>(a, off_p, k), 0); });
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (!ti.live[j]) continue;
+        const uint32_t e = ti.e[j];
+        const double r = rnd<T>(be[j] - ax[j]);
+        const double sv = rnd<T>(ap[j]);
+        *vp<T>(a, a.off_r, e) = (T)r;
+        *vp<T>(a, a.off_s, e) = (T)sv;
+        if constexpr (JAC) {
+            *vp<T>(a, a.off_u, e) = (T)minv<T, JAC, OP>(a, e, r);
+            *vp<T>(a, a.off_q, e) = (T)minv<T, JAC, OP>(a, e, sv);
+        }
+    }
+}
+
+// Replacement, second pass: w := A u, z := A q (neighbours written by the
+// first pass); partials of gamma_i, delta_i, rho_i from the reset vectors.
+template <typename T, int OP, bool JAC, int EPT>
+__device__ __forceinline__ void tile_rr2(const PassArgs<T> &a, uint32_t off_wout, int tile, double (&acc)[3])
+{
+    const uint32_t off_u = JAC ? a.off_u : a.off_r;
+    const uint32_t off_q = JAC ? a.off_q : a.off_s;
+    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+    double au[EPT], aq[EPT], re[EPT], ue[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const uint32_t e = ti.e[j];
+        au[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return ld(vp<T>(a, off_u, k), 0); });
+        aq[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return ld(vp<T>(a, off_q, k), 0); });
+        re[j] = ld(vp<T>(a, a.off_r, e), 0);
+        ue[j] = JAC ? ld(vp<T>(a, off_u, e), 0) : re[j];
+    }
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (!ti.live[j]) continue;
+        const uint32_t e = ti.e[j];
+        const double w = rnd<T>(au[j]);
+        *vp<T>(a, off_wout, e) = (T)w;
+        *vp<T>(a, a.off_z, e) = (T)rnd<T>(aq[j]);
+        acc[0] += re[j] * ue[j];
+        acc[1] += w * ue[j];
+        acc[2] += re[j] * re[j];
+    }
+}
+
+// One pass of pipelined CG with automated residual replacement.  Its role is
+// decided at the head from the state and the previous pass's partials (the
+// same bits in every block):
+//   ITER phase: stop test / cap; then every rr_period iterations a GAP pass
+//     (partials of ||f||^2 and the rounding scale; gamma, delta, rho are kept
+//     in the state), else an iteration exactly as k_pipe (sigma = 0);
+//   CHECK phase (after a gap pass): if ||f|| > tau ||r|| and ||f|| > floor,
+//     the pass does replacement step 1, else it iterates;
+//   RR2 phase: replacement step 2, whose partials restart iteration i.
+// Passes that leave w alone flip `wflip`, so w_i is always found.
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+__global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
+{
+    enum { ROLE_ITER, ROLE_GAP, ROLE_RR1, ROLE_RR2, ROLE_STOP };
+    __shared__ double lds_red[kMaxWaves * kFields];
+    const DevState S = *a.st_in;
+    if (S.status != RUNNING) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = S;
+        return;
+    }
+    double tot[4];
+    stage2<4>(a.part_in, a.nparts, tot, lds_red);
+    const int i = S.iter;
+    int role = ROLE_ITER, status = RUNNING;
+    double gamma = 0.0, delta = 0.0, rho = S.rho;
+    double alpha = __builtin_nan(""), beta = __builtin_nan("");
+    if (S.rr_phase == RR_RR2) {
+        role = ROLE_RR2;
+    } else {
+        if (S.rr_phase == RR_CHECK) {
+            gamma = S.gamma, delta = S.spare[1], rho = S.rho;
+            const double gap = sqrt(tot[0]), floor = 0x1p-53 * sqrt(tot[1]);
+            if (gap > a.rr_tau * sqrt(rho) && gap > a.rr_floor * floor) role = ROLE_RR1;
+        } else {
+            gamma = tot[0], delta = tot[1], rho = tot[2];
+            if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rho)) status = ST_NONFINITE;
+            else if (sqrt(rho) <= a.rtol * sqrt(S.bnorm2)) status = ST_CONVERGED;
+            else if (i >= a.max_iter) status = ST_MAX_ITER;
+            else if (i > S.i_start && i % a.rr_period == 0 && S.last_check != i) role = ROLE_GAP;
+        }
+        if (status != RUNNING) {
+            role = ROLE_STOP;
+        } else if (role == ROLE_ITER) {
+            if (!(gamma > 0.0) || !(delta > 0.0)) {
+                status = ST_BREAKDOWN;
+            } else {
+                if (i > S.i_start) {
+                    beta = gamma / S.gamma_prev;
+                    alpha = 1.0 / (delta / gamma - beta / S.alpha_prev);
+                } else {
+                    beta = 0.0;
+                    alpha = gamma / delta;
+                }
+                if (!(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
+            }
+            if (status != RUNNING) role = ROLE_STOP;
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        DevState o = S;
+        switch (role) {
+        case ROLE_STOP:
+            o.status = status;
+            o.rho = rho;
+            break;
+        case ROLE_GAP:
+            o.rr_phase = RR_CHECK;
+            o.gamma = gamma;
+            o.spare[1] = delta;
+            o.rho = rho;
+            o.last_check = i;
+            o.wflip ^= 1;
+            break;
+        case ROLE_RR1:
+            o.rr_phase = RR_RR2;
+            o.rr_count += 1;
+            o.wflip ^= 1;
+            break;
+        case ROLE_RR2:
+            o.rr_phase = RR_ITER;
+            break;
+        default:
+            o.rr_phase = RR_ITER;
+            o.iter = i + 1;
+            o.alpha_prev = alpha;
+            o.gamma_prev = gamma;
+            o.rho = rho;
+            break;
+        }
+        if (role == ROLE_ITER || role == ROLE_STOP)
+            write_hist(a.hist, a.hist_cap, i, sqrt(rho / S.bnorm2), alpha, beta, gamma, delta);
+        *a.st_out = o;
+    }
+    if (role == ROLE_STOP) return;
+    // the w slots of this pass, swapped while w_i sits in the other one
+    PassArgs<T> w = a;
+    if (S.wflip) {
+        w.off_win = a.off_wout;
+        w.off_wout = a.off_win;
+    }
+    double acc[3] = {0.0, 0.0, 0.0};
+    const TileRange tr = tile_range(a.ntiles, a.xcd_map);
+    if (role == ROLE_ITER) {
+        PipeScalars sc;
+        sc.alpha = alpha;
+        sc.beta = beta;
+        sc.sigma = 0.0;
+        sc.dsig = 0.0;
+        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_pipe<T, OP, JAC, EPT, NT>(w, tile, sc, acc);
+    } else if (role == ROLE_GAP) {
+        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_gap<T, OP, EPT>(a, tile, acc);
+    } else if (role == ROLE_RR1) {
+        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_rr1<T, OP, JAC, EPT>(a, tile);
+    } else {
+        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_rr2<T, OP, JAC, EPT>(a, w.off_wout, tile, acc);
+    }
     block_sum<3>(acc, lds_red);
     store_partial<3>(a.part_out, acc);
 }

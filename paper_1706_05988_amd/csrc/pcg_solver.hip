@@ -108,7 +108,9 @@ pcg_status validate_operator(const pcg_operator *op, int prec)
 pcg_status validate_options(const pcg_options *o)
 {
     if (!o) return invalid("options is null");
-    if (o->method < PCG_CG || o->method > PCG_PIPE_VAR_SHIFT) return invalid("unknown method");
+    if (o->method < PCG_CG || o->method > PCG_PIPE_RR) return invalid("unknown method");
+    if (o->method == PCG_PIPE_RR && (o->rr_period < 0 || o->rr_period > (1 << 20)))
+        return invalid("rr_period must be in [0, 2^20] (0: default)");
     if (o->method == PCG_PIPE_VAR_SHIFT) {
         if (!o->sigma_schedule || o->sigma_schedule_len < 1 || o->sigma_schedule_len > (1 << 24))
             return invalid("PCG_PIPE_VAR_SHIFT needs sigma_schedule with 1 .. 2^24 entries");
@@ -245,7 +247,7 @@ using LaunchFn = void (*)(PassArgsAny, int, int, hipStream_t);
 
 // Kernel table for one (T, OP, JAC, EPT, NT) combination.
 struct Kernels {
-    LaunchFn copy_x, init0_pipe, init0_cg, init1, pipe, pipe_var, cg_init1, cg_a, cg_b, resid;
+    LaunchFn copy_x, init0_pipe, init0_cg, init1, pipe, pipe_var, pipe_rr, cg_init1, cg_a, cg_b, resid;
 };
 
 template <typename T, int OP, bool JAC, int EPT, bool NT>
@@ -263,6 +265,8 @@ struct KernelSet {
     { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void pipe_var(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, true>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void pipe_rr(PassArgsAny a, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_pipe_rr<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void cg_init1(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_cg_init1<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void cg_a(PassArgsAny a, int g, int b, hipStream_t s)
@@ -272,7 +276,7 @@ struct KernelSet {
     static void resid(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_resid<T, OP, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
     static Kernels table()
-    { return Kernels{copy_x, init0_pipe, init0_cg, init1, pipe, pipe_var, cg_init1, cg_a, cg_b, resid}; }
+    { return Kernels{copy_x, init0_pipe, init0_cg, init1, pipe, pipe_var, pipe_rr, cg_init1, cg_a, cg_b, resid}; }
 };
 
 template <typename T, int OP, bool JAC, int EPT>
@@ -390,6 +394,9 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
         a.x_plain = 0;
         a.sched = L.sched == SIZE_MAX ? nullptr : reinterpret_cast<const double *>(ws + L.sched);
         a.sched_len = (int32_t)sched.size();
+        a.rr_period = opt.rr_period > 0 ? opt.rr_period : 8;
+        a.rr_tau = opt.rr_tau > 0.0 ? opt.rr_tau : std::cbrt(opt.prec == PCG_FP64 ? 0x1p-53 : 0x1p-24);
+        a.rr_floor = opt.rr_floor > 0.0 ? opt.rr_floor : 100.0;
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
     else fill((float *)nullptr);
@@ -416,7 +423,9 @@ static void enqueue_iterations(pcg_solver_ *s, hipStream_t st, const double *b)
             s->kern.cg_b(s->args(1, b, nullptr, 0, it & 1), s->sh.grid, s->sh.block, st);
         }
     } else {
-        const LaunchFn pass = s->opt.method == PCG_PIPE_VAR_SHIFT ? s->kern.pipe_var : s->kern.pipe;
+        const LaunchFn pass = s->opt.method == PCG_PIPE_VAR_SHIFT ? s->kern.pipe_var
+                              : s->opt.method == PCG_PIPE_RR      ? s->kern.pipe_rr
+                                                                  : s->kern.pipe;
         for (int k = 0; k < K; ++k) pass(s->args(k & 1, b, nullptr), s->sh.grid, s->sh.block, st);
     }
 }
@@ -699,7 +708,7 @@ extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_re
     DevState S{};
     int launches = 0;
     double kernel_ms = 0.0;
-    int replacements = 0;
+    int replacements = 0, rr_before = 0;
     auto add_time = [&](int slot) -> pcg_status {
         if (o.timing) {
             float ms = 0.f;
@@ -745,6 +754,7 @@ extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_re
             // restart from x when the explicit residual misses the tolerance
             if (std::sqrt(tr2) > o.rtol * std::sqrt(S.bnorm2)) {
                 ++replacements;
+                rr_before += S.rr_count;  // the restart starts a fresh device state
                 if ((st = s->run_init(b, S.iter))) return st;
                 continue;
             }
@@ -757,7 +767,7 @@ extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_re
     const double bn = std::sqrt(S.bnorm2);
     res->status = S.status;
     res->iterations = S.iter;
-    res->replacements = replacements;
+    res->replacements = replacements + rr_before + S.rr_count;
     res->launches = launches;
     res->rel_res_recursive = bn > 0 ? std::sqrt(S.rho) / bn : std::sqrt(S.rho);
     res->rel_res_true = bn > 0 ? std::sqrt(tr2) / bn : std::sqrt(tr2);

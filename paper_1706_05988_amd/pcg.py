@@ -21,14 +21,14 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "pcg.h")
 PCG_OK, PCG_PENDING = 0, 1
 PCG_ERR_INVALID, PCG_ERR_NONFINITE, PCG_ERR_HIP, PCG_ERR_BUDGET, PCG_ERR_STATE = -1, -2, -3, -4, -5
 PCG_CONVERGED, PCG_MAX_ITER, PCG_BREAKDOWN, PCG_NONFINITE = 0, 1, 2, 3
-PCG_CG, PCG_PIPE, PCG_PIPE_SHIFT, PCG_PIPE_VAR_SHIFT = 0, 1, 2, 3
+PCG_CG, PCG_PIPE, PCG_PIPE_SHIFT, PCG_PIPE_VAR_SHIFT, PCG_PIPE_RR = 0, 1, 2, 3, 4
 PCG_OP_STENCIL2D5, PCG_OP_STENCIL3D7, PCG_OP_CSR = 0, 1, 2
 PCG_PC_NONE, PCG_PC_JACOBI = 0, 1
 PCG_FP64, PCG_FP32_STREAM = 0, 1
 PCG_HISTORY_FIELDS = 5
 PCG_VAR_SET, PCG_VAR_XCD_MAP, PCG_VAR_NT, PCG_VAR_EPT1, PCG_VAR_EPT4 = 0x01, 0x02, 0x04, 0x10, 0x20
 
-METHOD = {"cg": PCG_CG, "pipe": PCG_PIPE, "pipe_shift": PCG_PIPE_SHIFT, "pipe_var": PCG_PIPE_VAR_SHIFT}
+METHOD = {"cg": PCG_CG, "pipe": PCG_PIPE, "pipe_shift": PCG_PIPE_SHIFT, "pipe_var": PCG_PIPE_VAR_SHIFT, "pipe_rr": PCG_PIPE_RR}
 OUTCOME = {PCG_CONVERGED: "converged", PCG_MAX_ITER: "max_iter", PCG_BREAKDOWN: "breakdown",
            PCG_NONFINITE: "nonfinite"}
 OPKIND = {"2d5": PCG_OP_STENCIL2D5, "3d7": PCG_OP_STENCIL3D7, "csr": PCG_OP_CSR}
@@ -47,8 +47,8 @@ class pcg_options(C.Structure):
                 ("replace_max", C.c_int32), ("iters_per_launch", C.c_int32), ("history_cap", C.c_int32),
                 ("history", C.c_void_p), ("block_size", C.c_int32), ("grid_blocks", C.c_int32),
                 ("timing", C.c_int32), ("use_graph", C.c_int32), ("variant", C.c_int32),
-                ("sigma_schedule_len", C.c_int32), ("reserved", C.c_int32 * 2),
-                ("sigma_schedule", C.c_void_p)]
+                ("sigma_schedule_len", C.c_int32), ("rr_period", C.c_int32), ("reserved", C.c_int32),
+                ("sigma_schedule", C.c_void_p), ("rr_tau", C.c_double), ("rr_floor", C.c_double)]
 
 
 class pcg_result(C.Structure):
@@ -296,7 +296,8 @@ def make_options(method: str = "pipe_shift", jacobi: bool = False, fp32: bool = 
                  sigma: Optional[float] = None, rtol: float = 1e-10, max_iter: int = 1000,
                  true_residual_check: bool = True, replace_max: int = 4, iters_per_launch: int = 0,
                  history_cap: int = 0, block_size: int = 0, grid_blocks: int = 0, timing: bool = False,
-                 use_graph: bool = True, variant: int = 0, sigma_schedule=None) -> pcg_options:
+                 use_graph: bool = True, variant: int = 0, sigma_schedule=None, rr_tau: float = 0.0,
+                 rr_period: int = 0, rr_floor: float = 0.0) -> pcg_options:
     """Options for pcg_create.  ``sigma_schedule`` (method "pipe_var") lists
     sigma_{-1}, sigma_0, sigma_1, ...; the returned struct keeps the array
     alive until the solver copies it at creation."""
@@ -316,6 +317,9 @@ def make_options(method: str = "pipe_shift", jacobi: bool = False, fp32: bool = 
     o.timing = int(bool(timing))
     o.use_graph = int(bool(use_graph))
     o.variant = int(variant)
+    o.rr_tau = float(rr_tau)
+    o.rr_period = int(rr_period)
+    o.rr_floor = float(rr_floor)
     if sigma_schedule is not None:
         import numpy as np
         sched = np.ascontiguousarray(sigma_schedule, dtype=np.float64)

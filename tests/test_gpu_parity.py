@@ -458,3 +458,78 @@ def test_select_shift_from_gpu_recorded_history(torch):
     so, ovals = psi_mod.select_shift(a, b, grid, 499, slack=2.0)
     np.testing.assert_allclose(vals, ovals, rtol=1e-9)
     assert s == so == 4.0
+
+
+# ---------------------------------------------------------------- p-CG-rr (residual replacement)
+
+TAU64 = 2.0 ** (-53 / 3)
+TAU32 = 2.0 ** -8
+
+
+@pytest.mark.parametrize("prob", ["lapl200", "3d_jacobi", "csr_jacobi"])
+def test_pcg_rr_history_replacements_and_accuracy(torch, prob):
+    """p-CG-rr on the GPU follows the oracle: same replacement decisions
+    (count), the same early history, the final explicit residual at the
+    oracle's level (both near CG's, far below p-CG's where it stagnates)."""
+    if prob == "lapl200":
+        p = problems.lapl200()
+        kw = dict(rtol=1e-30, max_iter=500)
+    elif prob == "3d_jacobi":
+        op = problems.stencil3d(37, 41, 43)
+        xt = np.random.default_rng(11).uniform(-1, 1, op.n)
+        p = problems.Problem("ragged3d", op, problems.to_scipy(op) @ xt, np.zeros(op.n), xt, jacobi=True,
+                             sigma=1.0, rtol=1e-30, max_iter=400)
+        kw = dict(rtol=1e-30, max_iter=400)
+    else:
+        p = problems.anisotropic_csr(48, seed=5)
+        kw = dict(rtol=1e-30, max_iter=800)
+    g = gpu_solve(torch, p, "pipe_rr", true_residual_check=False, rr_tau=TAU64, **kw)
+    o = oracle_solve(p, "pipe_rr", rr_tau=TAU64, **kw)
+    # after stagnation a breakdown (delta <= 0) comes at a rounding-determined
+    # iteration; before it both run to the cap
+    assert g["status"] in ("max_iter", "breakdown") and o["status"] in ("max_iter", "breakdown")
+    if g["status"] == o["status"] == "max_iter":
+        assert g["iterations"] == o["iterations"]
+    assert g["replacements"] >= 1
+    assert abs(g["replacements"] - o["replacements"]) <= 1
+    check_history(g, o, upto=30, rtol=1e-9)
+    assert g["rel_res_true"] <= max(10 * o["rel_res_true"], 1e-14)
+
+
+def test_pcg_rr_no_replacement_equals_pipe(torch):
+    p = problems.poisson3d(30, seed=1)
+    a = gpu_solve(torch, p, "pipe", max_iter=150, true_residual_check=False)
+    b = gpu_solve(torch, p, "pipe_rr", max_iter=150, true_residual_check=False, rr_tau=1e300)
+    assert b["replacements"] == 0 and a["iterations"] == b["iterations"]
+    k = a["iterations"]
+    np.testing.assert_allclose(b["res"][: k + 1], a["res"][: k + 1], rtol=1e-12)
+
+
+def test_pcg_rr_replacement_history_matches_oracle_exactly_at_the_reset(torch):
+    """At the replacement iteration the recorded residual is the explicit one:
+    GPU and oracle agree there too (the dot products were formed again)."""
+    p = problems.lapl200()
+    g = gpu_solve(torch, p, "pipe_rr", true_residual_check=False, rr_tau=TAU64, rtol=1e-30, max_iter=300)
+    o = oracle_solve(p, "pipe_rr", rr_tau=TAU64, rtol=1e-30, max_iter=300, record_true=True)
+    rel = np.abs(o["res"] - o["true"]) / o["true"]
+    hits = [i for i in range(1, 300) if rel[i] <= 1e-15 and rel[i - 1] >= 1e-9]
+    assert hits
+    for i in hits:
+        assert g["res"][i] == pytest.approx(o["res"][i], rel=1e-6)
+
+
+def test_pcg_rr_fp32_stream_refines_to_binary64_level(torch):
+    """FP32-stream p-CG-rr: replacements recompute r from the binary64 x, so
+    the attainable accuracy (the lowest level reached; the recursive residual
+    tracks the explicit one under replacement) falls far below binary32 and
+    lands within 10x of the oracle's in the same form.  Near the end a
+    breakdown can stop either run at a rounding-determined iteration."""
+    p = problems.poisson2d_manufactured(64)
+    kw = dict(fp32=True, rtol=1e-30, max_iter=400, rr_tau=TAU32)
+    g = gpu_solve(torch, p, "pipe_rr", true_residual_check=False, **kw)
+    o = oracle_solve(p, "pipe_rr", record_true=True, **kw)
+    assert g["replacements"] >= 1
+    g_best = np.nanmin(g["res"][: g["iterations"] + 1])
+    o_best = np.nanmin(o["true"][: o["iterations"] + 1])
+    assert g_best < 1e-11
+    assert g_best <= 10 * o_best
