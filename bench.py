@@ -380,7 +380,8 @@ def report_c3(P, torch, N: int, max_iter: int) -> dict:
 def report_small(P, torch) -> dict:
     """Latency-bound cases: 2-D Poisson 100x100 (all three methods, to 1e-12)
     and the 1000x1000 Poisson problem of Section 5.2 (b = A*1, x0 = 0, to
-    1e-6 and, as in the accuracy run, to the explicit residual floor)."""
+    1e-6 and, as in the accuracy run, 2500 iterations) with CG, p-CG, p-CG-sh
+    and p-CG-rr."""
     import problems
     out = {}
     p = problems.poisson2d_manufactured(100)
@@ -394,13 +395,15 @@ def report_small(P, torch) -> dict:
                                      "us_per_pass": r["iter_kernel_ms"] * 1e3 / max(1, r["iter_passes"])}
     p = problems.paper_parallel_workload(1000)
     b = torch.from_numpy(p.b).cuda()
-    for m in ("cg", "pipe", "pipe_shift"):
+    for m in ("cg", "pipe", "pipe_shift", "pipe_rr"):
         sig = 4.0 if m == "pipe_shift" else 0.0
         r = _timed_solve(P, torch, p.op, P.make_options(method=m, sigma=sig, rtol=1e-6, max_iter=2500,
                                                         true_residual_check=False), b)
         r2 = _timed_solve(P, torch, p.op, P.make_options(method=m, sigma=sig, rtol=1e-30, max_iter=2500,
                                                          true_residual_check=False), b)
         out[f"paper_poisson2d_1000_{m}"] = {"iterations_to_1e-6": r["iterations"], "seconds_to_1e-6": r["wall_s"],
+                                            "replacements_to_1e-6": r["replacements"],
+                                            "replacements_long_run": r2["replacements"],
                                             "true_residual_after_2500_or_breakdown": r2["rel_res_true"],
                                             "status_long_run": r2["status"], "iterations_long_run": r2["iterations"],
                                             "seconds_long_run": r2["wall_s"]}

@@ -247,9 +247,24 @@ __device__ __forceinline__ void stage2(const double *part, int P, double (&tot)[
 {
 #pragma unroll
     for (int f = 0; f < NF; ++f) tot[f] = 0.0;
-    for (int k = threadIdx.x; k < P; k += blockDim.x) {
+    // thread t sums partials t, t + B, t + 2B, ... in that order; the loads of
+    // four of them are issued before the first is added, so a grid of P
+    // blocks costs ceil(P / 4B) memory latencies here, not ceil(P / B)
+    const int B = blockDim.x;
+    for (int k0 = threadIdx.x; k0 < P; k0 += 4 * B) {
+        double v[4][NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) tot[f] += part[k * kFields + f];
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u * B < P ? k0 + u * B : P - 1;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) v[u][f] = part[k * kFields + f];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k0 + u * B < P) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) tot[f] += v[u][f];
+            }
     }
     block_sum<NF>(tot, lds);
 }

@@ -157,6 +157,21 @@ struct PipeScalars {
     double dsig;   // sigma_i - sigma_{i-1} (0 for a constant shift)
 };
 
+// The pass state is read field by field where it is used (uniform loads),
+// and only the thread that writes the next state copies the whole record:
+// a per-thread copy of the struct held across the pass would be placed in
+// LDS or scratch by the compiler and cost every pass a round trip at its head.
+__device__ __forceinline__ bool state_writer() { return blockIdx.x == 0 && threadIdx.x == 0; }
+
+// dst := src field by field (one thread; no local copy of the record)
+__device__ __forceinline__ void copy_state(DevState *dst, const DevState *src)
+{
+    const double *s = reinterpret_cast<const double *>(src);
+    double *d = reinterpret_cast<double *>(dst);
+#pragma unroll
+    for (int k = 0; k < int(sizeof(DevState) / 8); ++k) d[k] = s[k];
+}
+
 // sigma_k of a shift schedule, k >= -1
 __device__ __forceinline__ double sched_at(const double *sched, int len, int k)
 {
@@ -167,47 +182,47 @@ __device__ __forceinline__ double sched_at(const double *sched, int len, int k)
 template <typename T, bool VAR = false>
 __device__ __forceinline__ bool pipe_head(const PassArgs<T> &a, double *lds_red, PipeScalars &sc)
 {
-    const DevState S = *a.st_in;
-    if (S.status != RUNNING) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = S;
+    const DevState *S = a.st_in;
+    if (S->status != RUNNING) {
+        if (state_writer()) copy_state(a.st_out, S);
         return false;
     }
     double tot[3];
     stage2<3>(a.part_in, a.nparts, tot, lds_red);
     const double gamma = tot[0], delta = tot[1], rho = tot[2];
-    const int i = S.iter;
+    const int i = S->iter;
     int status = RUNNING;
     double alpha = __builtin_nan(""), beta = __builtin_nan("");
     if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rho)) {
         status = ST_NONFINITE;
-    } else if (sqrt(rho) <= a.rtol * sqrt(S.bnorm2)) {
+    } else if (sqrt(rho) <= a.rtol * sqrt(S->bnorm2)) {
         status = ST_CONVERGED;
     } else if (i >= a.max_iter) {
         status = ST_MAX_ITER;
     } else if (!(gamma > 0.0) || !(delta > 0.0)) {
         status = ST_BREAKDOWN;
     } else {
-        if (i > S.i_start) {
-            beta = gamma / S.gamma_prev;                             // beta_i
-            alpha = 1.0 / (delta / gamma - beta / S.alpha_prev);     // alpha_i
+        if (i > S->i_start) {
+            beta = gamma / S->gamma_prev;                            // beta_i
+            alpha = 1.0 / (delta / gamma - beta / S->alpha_prev);    // alpha_i
         } else {
             beta = 0.0;
             alpha = gamma / delta;
         }
         if (!(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        DevState o = S;
-        o.rho = rho;
+    if (state_writer()) {
+        DevState *o = a.st_out;
+        copy_state(o, S);
+        o->rho = rho;
         if (status != RUNNING) {
-            o.status = status;
+            o->status = status;
         } else {
-            o.iter = i + 1;
-            o.alpha_prev = alpha;
-            o.gamma_prev = gamma;
+            o->iter = i + 1;
+            o->alpha_prev = alpha;
+            o->gamma_prev = gamma;
         }
-        write_hist(a.hist, a.hist_cap, i, sqrt(rho / S.bnorm2), alpha, beta, gamma, delta);
-        *a.st_out = o;
+        write_hist(a.hist, a.hist_cap, i, sqrt(rho / S->bnorm2), alpha, beta, gamma, delta);
     }
     sc.alpha = alpha;
     sc.beta = beta;
@@ -556,30 +571,30 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
 {
     enum { ROLE_ITER, ROLE_GAP, ROLE_RR1, ROLE_RR2, ROLE_STOP };
     __shared__ double lds_red[kMaxWaves * kFields];
-    const DevState S = *a.st_in;
-    if (S.status != RUNNING) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = S;
+    const DevState *S = a.st_in;
+    if (S->status != RUNNING) {
+        if (state_writer()) copy_state(a.st_out, S);
         return;
     }
     double tot[4];
     stage2<4>(a.part_in, a.nparts, tot, lds_red);
-    const int i = S.iter;
+    const int i = S->iter, phase = S->rr_phase;
     int role = ROLE_ITER, status = RUNNING;
-    double gamma = 0.0, delta = 0.0, rho = S.rho;
+    double gamma = 0.0, delta = 0.0, rho = S->rho;
     double alpha = __builtin_nan(""), beta = __builtin_nan("");
-    if (S.rr_phase == RR_RR2) {
+    if (phase == RR_RR2) {
         role = ROLE_RR2;
     } else {
-        if (S.rr_phase == RR_CHECK) {
-            gamma = S.gamma, delta = S.spare[1], rho = S.rho;
+        if (phase == RR_CHECK) {
+            gamma = S->gamma, delta = S->spare[1], rho = S->rho;
             const double gap = sqrt(tot[0]), floor = 0x1p-53 * sqrt(tot[1]);
             if (gap > a.rr_tau * sqrt(rho) && gap > a.rr_floor * floor) role = ROLE_RR1;
         } else {
             gamma = tot[0], delta = tot[1], rho = tot[2];
             if (!isfinite(gamma) || !isfinite(delta) || !isfinite(rho)) status = ST_NONFINITE;
-            else if (sqrt(rho) <= a.rtol * sqrt(S.bnorm2)) status = ST_CONVERGED;
+            else if (sqrt(rho) <= a.rtol * sqrt(S->bnorm2)) status = ST_CONVERGED;
             else if (i >= a.max_iter) status = ST_MAX_ITER;
-            else if (i > S.i_start && i % a.rr_period == 0 && S.last_check != i) role = ROLE_GAP;
+            else if (i > S->i_start && i % a.rr_period == 0 && S->last_check != i) role = ROLE_GAP;
         }
         if (status != RUNNING) {
             role = ROLE_STOP;
@@ -587,9 +602,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
             if (!(gamma > 0.0) || !(delta > 0.0)) {
                 status = ST_BREAKDOWN;
             } else {
-                if (i > S.i_start) {
-                    beta = gamma / S.gamma_prev;
-                    alpha = 1.0 / (delta / gamma - beta / S.alpha_prev);
+                if (i > S->i_start) {
+                    beta = gamma / S->gamma_prev;
+                    alpha = 1.0 / (delta / gamma - beta / S->alpha_prev);
                 } else {
                     beta = 0.0;
                     alpha = gamma / delta;
@@ -599,45 +614,45 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
             if (status != RUNNING) role = ROLE_STOP;
         }
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        DevState o = S;
+    if (state_writer()) {
+        DevState *o = a.st_out;
+        copy_state(o, S);
         switch (role) {
         case ROLE_STOP:
-            o.status = status;
-            o.rho = rho;
+            o->status = status;
+            o->rho = rho;
             break;
         case ROLE_GAP:
-            o.rr_phase = RR_CHECK;
-            o.gamma = gamma;
-            o.spare[1] = delta;
-            o.rho = rho;
-            o.last_check = i;
-            o.wflip ^= 1;
+            o->rr_phase = RR_CHECK;
+            o->gamma = gamma;
+            o->spare[1] = delta;
+            o->rho = rho;
+            o->last_check = i;
+            o->wflip = S->wflip ^ 1;
             break;
         case ROLE_RR1:
-            o.rr_phase = RR_RR2;
-            o.rr_count += 1;
-            o.wflip ^= 1;
+            o->rr_phase = RR_RR2;
+            o->rr_count = S->rr_count + 1;
+            o->wflip = S->wflip ^ 1;
             break;
         case ROLE_RR2:
-            o.rr_phase = RR_ITER;
+            o->rr_phase = RR_ITER;
             break;
         default:
-            o.rr_phase = RR_ITER;
-            o.iter = i + 1;
-            o.alpha_prev = alpha;
-            o.gamma_prev = gamma;
-            o.rho = rho;
+            o->rr_phase = RR_ITER;
+            o->iter = i + 1;
+            o->alpha_prev = alpha;
+            o->gamma_prev = gamma;
+            o->rho = rho;
             break;
         }
         if (role == ROLE_ITER || role == ROLE_STOP)
-            write_hist(a.hist, a.hist_cap, i, sqrt(rho / S.bnorm2), alpha, beta, gamma, delta);
-        *a.st_out = o;
+            write_hist(a.hist, a.hist_cap, i, sqrt(rho / S->bnorm2), alpha, beta, gamma, delta);
     }
     if (role == ROLE_STOP) return;
     // the w slots of this pass, swapped while w_i sits in the other one
     PassArgs<T> w = a;
-    if (S.wflip) {
+    if (S->wflip) {
         w.off_win = a.off_wout;
         w.off_wout = a.off_win;
     }
@@ -704,36 +719,36 @@ template <typename T, int OP, bool JAC, int EPT, bool NT>
 __global__ void __launch_bounds__(kMaxBlock) k_cg_a(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
-    const DevState S = *a.st_in;
-    if (S.status != RUNNING) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = S;
+    const DevState *S = a.st_in;
+    if (S->status != RUNNING) {
+        if (state_writer()) copy_state(a.st_out, S);
         return;
     }
     double tot[2];
     stage2<2>(a.part_in, a.nparts, tot, lds_red);
     const double gamma = tot[0], rho = tot[1];
-    const int i = S.iter;
+    const int i = S->iter;
     int status = RUNNING;
     double beta = 0.0;
     if (!isfinite(gamma) || !isfinite(rho)) {
         status = ST_NONFINITE;
-    } else if (sqrt(rho) <= a.rtol * sqrt(S.bnorm2)) {
+    } else if (sqrt(rho) <= a.rtol * sqrt(S->bnorm2)) {
         status = ST_CONVERGED;
     } else if (i >= a.max_iter) {
         status = ST_MAX_ITER;
     } else if (!(gamma > 0.0)) {
         status = ST_BREAKDOWN;
-    } else if (i > S.i_start) {
-        beta = gamma / S.gamma_prev;  // beta_i = (r_i, u_i) / (r_{i-1}, u_{i-1})
+    } else if (i > S->i_start) {
+        beta = gamma / S->gamma_prev;  // beta_i = (r_i, u_i) / (r_{i-1}, u_{i-1})
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        DevState o = S;
-        o.rho = rho;
-        o.gamma = gamma;
-        if (status != RUNNING) o.status = status;
-        write_hist(a.hist, a.hist_cap, i, sqrt(rho / S.bnorm2), __builtin_nan(""),
+    if (state_writer()) {
+        DevState *o = a.st_out;
+        copy_state(o, S);
+        o->rho = rho;
+        o->gamma = gamma;
+        if (status != RUNNING) o->status = status;
+        write_hist(a.hist, a.hist_cap, i, sqrt(rho / S->bnorm2), __builtin_nan(""),
                    status == RUNNING ? beta : __builtin_nan(""), gamma, __builtin_nan(""));
-        *a.st_out = o;
     }
     if (status != RUNNING) return;
 
@@ -772,15 +787,16 @@ template <typename T, int OP, bool JAC, int EPT, bool NT>
 __global__ void __launch_bounds__(kMaxBlock) k_cg_b(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
-    const DevState S = *a.st_in;
-    if (S.status != RUNNING) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) *a.st_out = S;
+    const DevState *S = a.st_in;
+    if (S->status != RUNNING) {
+        if (state_writer()) copy_state(a.st_out, S);
         return;
     }
     double tot[1];
     stage2<1>(a.part_in, a.nparts, tot, lds_red);
     const double sp = tot[0];
-    const int i = S.iter;
+    const int i = S->iter;
+    const double gamma_i = S->gamma;
     int status = RUNNING;
     double alpha = __builtin_nan("");
     if (!isfinite(sp)) {
@@ -788,23 +804,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_b(PassArgs<T> a)
     } else if (!(sp > 0.0)) {
         status = ST_BREAKDOWN;
     } else {
-        alpha = S.gamma / sp;  // alpha_i = (r_i, u_i) / (s_i, p_i)
+        alpha = gamma_i / sp;  // alpha_i = (r_i, u_i) / (s_i, p_i)
         if (!(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        DevState o = S;
+    if (state_writer()) {
+        DevState *o = a.st_out;
+        copy_state(o, S);
         if (status != RUNNING) {
-            o.status = status;
+            o->status = status;
         } else {
-            o.iter = i + 1;
-            o.gamma_prev = S.gamma;
-            o.alpha_prev = alpha;
+            o->iter = i + 1;
+            o->gamma_prev = gamma_i;
+            o->alpha_prev = alpha;
         }
         if (a.hist && i < a.hist_cap) {
             a.hist[(size_t)i * 5 + 1] = alpha;
             a.hist[(size_t)i * 5 + 4] = sp;
         }
-        *a.st_out = o;
     }
     if (status != RUNNING) return;
 
