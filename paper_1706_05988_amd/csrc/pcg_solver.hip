@@ -161,7 +161,10 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
             // gathers need more waves in flight than the stencil streams
             s.ept = 2, s.block = 256, blocks_per_cu = fp64 ? 2 : 4;
         } else if (pipe && jac) {
-            s.ept = 2, s.block = 256, blocks_per_cu = 1;
+            // 4 unknowns per thread keep ~70 independent loads in flight per
+            // thread; binary64 runs best as one block per CU, the lighter
+            // binary32 streams with four
+            s.ept = 4, s.block = 256, blocks_per_cu = fp64 ? 1 : 4;
         } else if (pipe) {
             s.ept = 1, s.block = 128, blocks_per_cu = 4;
         } else if (fp64) {

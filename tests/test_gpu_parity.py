@@ -311,6 +311,8 @@ VARIANTS = {
     "ept1_nt_xcd": 0x01 | 0x10 | 0x02 | 0x04,
     "ept2": 0x01,
     "ept2_nt_xcd": 0x01 | 0x02 | 0x04,
+    "ept4": 0x01 | 0x20,
+    "ept4_nt_xcd": 0x01 | 0x20 | 0x02 | 0x04,
 }
 
 
