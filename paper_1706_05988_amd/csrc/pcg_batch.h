@@ -1,6 +1,7 @@
 // pcg_batch.h -- many independent solves advanced by one persistent pass.
 //
 // Every active system moves one phase or one iteration per pass:
+//   ADMIT   (admitted, nothing done yet)
 //   COPYIN  caller x -> internal (blocked) x
 //   INIT0   r_0 := b - A x_0, u_0 := M^-1 r_0, z = q = s = t = p := 0; (b, b)
 //   INIT1   w_0 := A u_0 - sigma r_0; gamma_0, delta_0, rho_0
@@ -9,12 +10,19 @@
 //   COPYOUT internal x -> caller x
 // The pass kernel works on a table of (system, tile) items; each tile is
 // 512 unknowns (256 threads x 2) and writes one block partial into its
-// system's partial array.  The finalize kernel that follows each pass sums
-// each system's partials in tile order (so a system's results depend only on
-// that system, never on the rest of the batch), takes the stop / breakdown /
-// restart decisions and the scalar recurrences, and moves the system to its
-// next phase.  Kernel boundaries order the two, so no atomics or fences are
-// needed across the XCDs.
+// system's partial array.  At its head, every item block sums its system's
+// partials of the previous pass in tile order (so a system's results depend
+// only on that system, never on the rest of the batch), takes the stop /
+// breakdown / restart decisions and the scalar recurrences -- the same bits
+// in every block of the system -- and performs the next phase on its tile;
+// the block of tile 0 writes the system's new state.  State and partials
+// ping-pong between two slots (pass k reads slot k%2), so one kernel per
+// iteration suffices and no atomics or fences are needed across the XCDs.
+// With many items that head (a chain of dependent loads and a block
+// reduction before the tile's own loads) costs more than a kernel launch,
+// so large batches run split: a transition kernel (one block per system)
+// followed by the pass without the head.  Both compute the same transition
+// with the same reduction, so the results do not depend on the mode.
 #pragma once
 
 #include "pcg_internal.h"
@@ -22,8 +30,9 @@
 
 namespace pcg {
 
+// A state's phase is the one its system performed in the pass that wrote it.
 enum Phase : int32_t {
-    PH_COPYIN = 0, PH_INIT0, PH_INIT1, PH_ITER, PH_RESID, PH_COPYOUT, PH_DONE, PH_FREE
+    PH_ADMIT = 0, PH_COPYIN, PH_INIT0, PH_INIT1, PH_ITER, PH_RESID, PH_COPYOUT, PH_DONE, PH_FREE
 };
 
 constexpr int kBatchBlock = 256;      // threads of a pass block: one 512-unknown tile
@@ -45,7 +54,7 @@ struct BatchSys {
     uint32_t tile_bytes;
     uint32_t off_slot[V_COUNT];
     uint32_t pad0;
-    double *part;       // ntiles * kFields
+    double *part;       // 2 slots of ntiles * kFields
     double *hist;       // history rows or nullptr
     int32_t hist_cap, replace_max, true_check, pad1;
 };
@@ -61,11 +70,13 @@ struct BatchState {
 
 struct BatchTables {
     const BatchSys *sys;
-    BatchState *st;
+    BatchState *st;          // 2 slots of max_sys states
     const uint32_t *item_sys;
     const uint32_t *item_tile;
-    const uint32_t *active;
-    const int32_t *counts;  // [0] = items, [1] = active systems
+    const uint32_t *active;  // listed systems (split mode)
+    const int32_t *counts;   // [0] = items, [1] = listed systems
+    int32_t max_sys;
+    int32_t pad;
 };
 
 }  // namespace pcg

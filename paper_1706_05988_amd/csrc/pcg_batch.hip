@@ -98,33 +98,6 @@ __device__ __forceinline__ void batch_tile_op(const BatchSys &D, const BatchStat
     else batch_tile<T, OP, false>(a, S, tile, acc);
 }
 
-// Pass: every item (system, tile) of every active system.
-template <typename T>
-__global__ void __launch_bounds__(kBatchBlock) k_batch_pass(BatchTables tb)
-{
-    __shared__ double lds_red[kMaxWaves * kFields];
-    const int nitems = tb.counts[0];
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint32_t s = tb.item_sys[it], tile = tb.item_tile[it];
-        const BatchState S = tb.st[s];
-        if (S.phase >= PH_DONE) continue;
-        const BatchSys &D = tb.sys[s];
-        double acc[3] = {0.0, 0.0, 0.0};
-        switch (D.kind) {
-        case PCG_OP_STENCIL2D5: batch_tile_op<T, OP_2D5>(D, S, tile, acc); break;
-        case PCG_OP_STENCIL3D7: batch_tile_op<T, OP_3D7>(D, S, tile, acc); break;
-        default: batch_tile_op<T, OP_CSR>(D, S, tile, acc); break;
-        }
-        block_sum<3>(acc, lds_red);
-        if (threadIdx.x == 0) {
-            double *pp = D.part + (size_t)tile * kFields;
-            pp[0] = acc[0];
-            pp[1] = acc[1];
-            pp[2] = acc[2];
-        }
-    }
-}
-
 __device__ __forceinline__ void batch_hist(const BatchSys &D, int i, double res, double alpha, double beta,
                                            double gamma, double delta)
 {
@@ -139,8 +112,10 @@ __device__ __forceinline__ void batch_hist(const BatchSys &D, int i, double res,
 }
 
 // Decision of the top of iteration i from gamma_i, delta_i, rho_i (the same
-// rules as the single-system pass head).  Returns the new state.
-__device__ BatchState batch_decide(const BatchSys &D, BatchState S, double gamma, double delta, double rho)
+// rules as the single-system pass head).  Returns the new state; the writer
+// block records the history row.
+__device__ __forceinline__ BatchState batch_decide(const BatchSys &D, BatchState S, double gamma, double delta,
+                                                   double rho, bool writer)
 {
     const int i = S.iter;
     int status = RUNNING;
@@ -163,7 +138,7 @@ __device__ BatchState batch_decide(const BatchSys &D, BatchState S, double gamma
         }
         if (!(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
     }
-    batch_hist(D, i, sqrt(rho / S.bnorm2), alpha, beta, gamma, delta);
+    if (writer) batch_hist(D, i, sqrt(rho / S.bnorm2), alpha, beta, gamma, delta);
     S.rho = rho;
     if (status == RUNNING) {
         S.phase = PH_ITER;
@@ -177,65 +152,123 @@ __device__ BatchState batch_decide(const BatchSys &D, BatchState S, double gamma
     return S;
 }
 
-// Finalize: per active system, the fixed-order sum of its tile partials and
-// the transition to the next phase.
-template <typename T>
-__global__ void __launch_bounds__(kBatchBlock) k_batch_final(BatchTables tb)
+// The phase after the one S records, from that pass's partial sums `tot`.
+__device__ __forceinline__ BatchState batch_next(const BatchSys &D, BatchState S, const double (&tot)[3], bool writer)
+{
+    switch (S.phase) {
+    case PH_ADMIT: S.phase = PH_COPYIN; break;
+    case PH_COPYIN: S.phase = PH_INIT0; break;
+    case PH_INIT0:
+        S.bnorm2 = tot[0];
+        if (!isfinite(tot[0])) {
+            S.status = ST_NONFINITE;
+            S.phase = PH_COPYOUT;
+        } else {
+            S.phase = PH_INIT1;
+        }
+        break;
+    case PH_INIT1: S = batch_decide(D, S, tot[0], tot[1], tot[2], writer); break;
+    case PH_ITER:
+        S.iter += 1;
+        S.wcur ^= 1;
+        S = batch_decide(D, S, tot[0], tot[1], tot[2], writer);
+        break;
+    case PH_RESID: {
+        S.true_res2 = tot[0];
+        const bool restart = S.status == ST_CONVERGED && D.true_check && S.restarts < D.replace_max &&
+                             S.iter < D.max_iter && sqrt(tot[0]) > D.rtol * sqrt(S.bnorm2);
+        if (restart) {
+            S.restarts += 1;
+            S.status = RUNNING;
+            S.i_start = S.iter;
+            S.wcur = 0;
+            S.phase = PH_INIT0;
+        } else {
+            S.phase = PH_COPYOUT;
+        }
+        break;
+    }
+    case PH_COPYOUT: S.phase = PH_DONE; break;
+    default: break;
+    }
+    if (S.phase < PH_DONE) ++S.passes;
+    return S;
+}
+
+// One pass over every item (system, tile).  Pass parity `par`: states and
+// partials are read from slot par and written to slot 1 - par.  HEAD: the
+// item block takes its system's transition itself; otherwise k_batch_trans
+// has already written the transitioned state into slot 1 - par.
+template <typename T, bool HEAD>
+__global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int par)
+{
+    __shared__ double lds_red[kMaxWaves * kFields];
+    const int nitems = tb.counts[0];
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const uint32_t s = tb.item_sys[it], tile = tb.item_tile[it];
+        const BatchState *Sin = tb.st + (size_t)par * tb.max_sys + s;
+        BatchState *Sout = tb.st + (size_t)(1 - par) * tb.max_sys + s;
+        const BatchSys &D = tb.sys[s];
+        BatchState S;
+        if constexpr (HEAD) {
+            const bool writer = tile == 0 && threadIdx.x == 0;
+            const int phase = Sin->phase;
+            if (phase >= PH_DONE) {
+                if (writer) *Sout = *Sin;
+                continue;
+            }
+            double tot[3] = {0.0, 0.0, 0.0};
+            if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT)
+                stage2<3>(D.part + (size_t)par * D.ntiles * kFields, D.ntiles, tot, lds_red);
+            S = batch_next(D, *Sin, tot, writer);
+            if (writer) *Sout = S;
+        } else {
+            S = *Sout;
+        }
+        double acc[3] = {0.0, 0.0, 0.0};
+        if (S.phase >= PH_DONE) continue;
+        switch (D.kind) {
+        case PCG_OP_STENCIL2D5: batch_tile_op<T, OP_2D5>(D, S, tile, acc); break;
+        case PCG_OP_STENCIL3D7: batch_tile_op<T, OP_3D7>(D, S, tile, acc); break;
+        default: batch_tile_op<T, OP_CSR>(D, S, tile, acc); break;
+        }
+        block_sum<3>(acc, lds_red);
+        if (threadIdx.x == 0) {
+            double *pp = D.part + ((size_t)(1 - par) * D.ntiles + tile) * kFields;
+            pp[0] = acc[0];
+            pp[1] = acc[1];
+            pp[2] = acc[2];
+        }
+    }
+}
+
+// Split mode: the transition of every listed system, one block per system.
+__global__ void __launch_bounds__(kBatchBlock) k_batch_trans(BatchTables tb, int par)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     const int nact = tb.counts[1];
     for (int k = blockIdx.x; k < nact; k += gridDim.x) {
         const uint32_t s = tb.active[k];
-        BatchState S = tb.st[s];
-        if (S.phase >= PH_DONE) continue;
+        const BatchState *Sin = tb.st + (size_t)par * tb.max_sys + s;
+        BatchState *Sout = tb.st + (size_t)(1 - par) * tb.max_sys + s;
         const BatchSys &D = tb.sys[s];
-        double tot[3];
-        stage2<3>(D.part, D.ntiles, tot, lds_red);
-        ++S.passes;
-        switch (S.phase) {
-        case PH_COPYIN: S.phase = PH_INIT0; break;
-        case PH_INIT0:
-            S.bnorm2 = tot[0];
-            if (!isfinite(tot[0])) {
-                S.status = ST_NONFINITE;
-                S.phase = PH_COPYOUT;
-            } else {
-                S.phase = PH_INIT1;
-            }
-            break;
-        case PH_INIT1: S = batch_decide(D, S, tot[0], tot[1], tot[2]); break;
-        case PH_ITER:
-            S.iter += 1;
-            S.wcur ^= 1;
-            S = batch_decide(D, S, tot[0], tot[1], tot[2]);
-            break;
-        case PH_RESID: {
-            S.true_res2 = tot[0];
-            const bool restart = S.status == ST_CONVERGED && D.true_check && S.restarts < D.replace_max &&
-                                 S.iter < D.max_iter && sqrt(tot[0]) > D.rtol * sqrt(S.bnorm2);
-            if (restart) {
-                S.restarts += 1;
-                S.status = RUNNING;
-                S.i_start = S.iter;
-                S.wcur = 0;
-                S.phase = PH_INIT0;
-            } else {
-                S.phase = PH_COPYOUT;
-            }
-            break;
+        const int phase = Sin->phase;
+        if (phase >= PH_DONE) {
+            if (threadIdx.x == 0) *Sout = *Sin;
+            continue;
         }
-        case PH_COPYOUT: S.phase = PH_DONE; break;
-        default: break;
-        }
-        if (threadIdx.x == 0) tb.st[s] = S;
-        __syncthreads();
+        double tot[3] = {0.0, 0.0, 0.0};
+        if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT)
+            stage2<3>(D.part + (size_t)par * D.ntiles * kFields, D.ntiles, tot, lds_red);
+        const BatchState S = batch_next(D, *Sin, tot, threadIdx.x == 0);
+        if (threadIdx.x == 0) *Sout = S;
     }
 }
 
-template __global__ void k_batch_pass<double>(BatchTables);
-template __global__ void k_batch_pass<float>(BatchTables);
-template __global__ void k_batch_final<double>(BatchTables);
-template __global__ void k_batch_final<float>(BatchTables);
+template __global__ void k_batch_step<double, true>(BatchTables, int);
+template __global__ void k_batch_step<float, true>(BatchTables, int);
+template __global__ void k_batch_step<double, false>(BatchTables, int);
+template __global__ void k_batch_step<float, false>(BatchTables, int);
 
 // ----------------------------------------------------------------- engine
 
@@ -249,7 +282,7 @@ static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
 size_t BatchEngine::table_bytes(int max_sys, int64_t max_items)
 {
-    return up256(sizeof(BatchSys) * max_sys) + up256(sizeof(BatchState) * max_sys) +
+    return up256(sizeof(BatchSys) * max_sys) + up256(sizeof(BatchState) * 2 * (size_t)max_sys) +
            up256(sizeof(uint32_t) * (size_t)max_items) * 2 + up256(sizeof(uint32_t) * max_sys) + 256;
 }
 
@@ -283,7 +316,7 @@ pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options 
     l.blk = off;
     off += up256((size_t)l.ntiles * tb);
     l.part = off;
-    off += up256((size_t)l.ntiles * kFields * 8);
+    off += up256((size_t)2 * l.ntiles * kFields * 8);  // two partial slots
     l.dinv = SIZE_MAX;
     if (op->kind == PCG_OP_CSR && jac) {
         l.dinv = off;
@@ -320,7 +353,7 @@ pcg_status BatchEngine::init(char *tables, int max_sys, int64_t max_items, int p
     max_items_ = max_items;
     prec_ = prec;
     stream_ = stream;
-    K_ = K > 0 ? K : 8;
+    K_ = K > 0 ? K + (K & 1) : 32;  // even: a launch starts at state slot 0
     size_t off = 0;
     auto take = [&](size_t b) {
         char *p = tables + off;
@@ -328,7 +361,7 @@ pcg_status BatchEngine::init(char *tables, int max_sys, int64_t max_items, int p
         return p;
     };
     d_sys_ = (BatchSys *)take(sizeof(BatchSys) * max_sys);
-    d_st_ = (BatchState *)take(sizeof(BatchState) * max_sys);
+    d_st_ = (BatchState *)take(sizeof(BatchState) * 2 * (size_t)max_sys);
     d_item_sys_ = (uint32_t *)take(sizeof(uint32_t) * (size_t)max_items);
     d_item_tile_ = (uint32_t *)take(sizeof(uint32_t) * (size_t)max_items);
     d_active_ = (uint32_t *)take(sizeof(uint32_t) * max_sys);
@@ -346,6 +379,7 @@ pcg_status BatchEngine::init(char *tables, int max_sys, int64_t max_items, int p
         h_st_[k].phase = PH_FREE;
     }
     BCHK(hipMemcpyAsync(d_st_, h_st_, sizeof(BatchState) * max_sys, hipMemcpyHostToDevice, stream_));
+    BCHK(hipMemcpyAsync(d_st_ + max_sys, h_st_, sizeof(BatchState) * max_sys, hipMemcpyHostToDevice, stream_));
     int32_t zero[2] = {0, 0};
     BCHK(hipMemcpyAsync(d_counts_, zero, sizeof(zero), hipMemcpyHostToDevice, stream_));
     BCHK(hipStreamSynchronize(stream_));
@@ -354,8 +388,10 @@ pcg_status BatchEngine::init(char *tables, int max_sys, int64_t max_items, int p
 
 BatchEngine::~BatchEngine()
 {
-    if (gexec_) (void)hipGraphExecDestroy(gexec_);
-    if (graph_) (void)hipGraphDestroy(graph_);
+    for (int k = 0; k < 2; ++k) {
+        if (gexec_[k]) (void)hipGraphExecDestroy(gexec_[k]);
+        if (graph_[k]) (void)hipGraphDestroy(graph_[k]);
+    }
     if (h_st_) (void)hipHostFree(h_st_);
     if (h_items_) (void)hipHostFree(h_items_);
     if (ev0_) (void)hipEventDestroy(ev0_);
@@ -425,14 +461,11 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
     sys_[slot] = D;
     in_use_[slot] = 1;
     BatchState S{};
-    S.phase = PH_COPYIN;
+    S.phase = PH_ADMIT;
     S.status = RUNNING;
     h_st_[slot] = S;
-    // descriptor and state go up on the stream, ordered before the next launch
-    BCHK(hipMemcpyAsync(d_sys_ + slot, &sys_[slot], sizeof(BatchSys), hipMemcpyHostToDevice, stream_));
-    BCHK(hipMemcpyAsync(d_st_ + slot, &h_st_[slot], sizeof(BatchState), hipMemcpyHostToDevice, stream_));
+    // descriptor and state go up with the next table upload, before the next launch
     if (D.hist) BCHK(hipMemsetAsync(D.hist, 0xff, (size_t)D.hist_cap * PCG_HISTORY_FIELDS * 8, stream_));
-    BCHK(hipStreamSynchronize(stream_));  // the host copies above read sys_[slot] / h_st_[slot]
     tables_dirty_ = true;
     *slot_out = slot;
     return PCG_OK;
@@ -447,7 +480,8 @@ void BatchEngine::release(int slot)
 
 pcg_status BatchEngine::upload_tables()
 {
-    // items of every system still working, in slot order; active list the same
+    // items of every system still working, in slot order; the list of those
+    // systems the same
     uint32_t *isys = h_items_, *itile = h_items_ + max_items_, *act = h_items_ + 2 * max_items_;
     int64_t ni = 0;
     int na = 0;
@@ -465,6 +499,11 @@ pcg_status BatchEngine::upload_tables()
     }
     counts_h_[0] = (int32_t)ni;
     counts_h_[1] = na;
+    // descriptors and states of every slot: between launches the host copy
+    // of a running system's state equals the device one (it was just read
+    // back), and admitted or released slots carry their new state
+    BCHK(hipMemcpyAsync(d_sys_, sys_.data(), sizeof(BatchSys) * max_sys_, hipMemcpyHostToDevice, stream_));
+    BCHK(hipMemcpyAsync(d_st_, h_st_, sizeof(BatchState) * max_sys_, hipMemcpyHostToDevice, stream_));
     if (ni) {
         BCHK(hipMemcpyAsync(d_item_sys_, isys, sizeof(uint32_t) * ni, hipMemcpyHostToDevice, stream_));
         BCHK(hipMemcpyAsync(d_item_tile_, itile, sizeof(uint32_t) * ni, hipMemcpyHostToDevice, stream_));
@@ -478,23 +517,26 @@ pcg_status BatchEngine::upload_tables()
     return PCG_OK;
 }
 
-void BatchEngine::enqueue_passes(hipStream_t st)
+void BatchEngine::enqueue_passes(hipStream_t st, int split)
 {
-    BatchTables tb{d_sys_, d_st_, d_item_sys_, d_item_tile_, d_active_, d_counts_};
+    BatchTables tb{d_sys_, d_st_, d_item_sys_, d_item_tile_, d_active_, d_counts_, max_sys_, 0};
+    const dim3 pg(pass_grid_), bk(kBatchBlock);
     for (int k = 0; k < K_; ++k) {
-        if (prec_ == PCG_FP64) {
-            hipLaunchKernelGGL(k_batch_pass<double>, dim3(pass_grid_), dim3(kBatchBlock), 0, st, tb);
-            hipLaunchKernelGGL(k_batch_final<double>, dim3(final_grid_), dim3(kBatchBlock), 0, st, tb);
+        const int par = k & 1;
+        if (split) {
+            hipLaunchKernelGGL(k_batch_trans, dim3(trans_grid_), bk, 0, st, tb, par);
+            if (prec_ == PCG_FP64) hipLaunchKernelGGL((k_batch_step<double, false>), pg, bk, 0, st, tb, par);
+            else hipLaunchKernelGGL((k_batch_step<float, false>), pg, bk, 0, st, tb, par);
         } else {
-            hipLaunchKernelGGL(k_batch_pass<float>, dim3(pass_grid_), dim3(kBatchBlock), 0, st, tb);
-            hipLaunchKernelGGL(k_batch_final<float>, dim3(final_grid_), dim3(kBatchBlock), 0, st, tb);
+            if (prec_ == PCG_FP64) hipLaunchKernelGGL((k_batch_step<double, true>), pg, bk, 0, st, tb, par);
+            else hipLaunchKernelGGL((k_batch_step<float, true>), pg, bk, 0, st, tb, par);
         }
     }
 }
 
-pcg_status BatchEngine::ensure_graph()
+pcg_status BatchEngine::ensure_graph(int split)
 {
-    if (gexec_) return PCG_OK;
+    if (gexec_[split]) return PCG_OK;
     hipStream_t cs;
     BCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -502,11 +544,11 @@ pcg_status BatchEngine::ensure_graph()
         (void)hipStreamDestroy(cs);
         return hip_fail(e, "hipStreamBeginCapture");
     }
-    enqueue_passes(cs);
-    e = hipStreamEndCapture(cs, &graph_);
+    enqueue_passes(cs, split);
+    e = hipStreamEndCapture(cs, &graph_[split]);
     (void)hipStreamDestroy(cs);
     if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-    BCHK(hipGraphInstantiate(&gexec_, graph_, nullptr, nullptr, 0));
+    BCHK(hipGraphInstantiate(&gexec_[split], graph_[split], nullptr, nullptr, 0));
     return PCG_OK;
 }
 
@@ -515,9 +557,10 @@ pcg_status BatchEngine::step(double *gpu_ms)
     pcg_status st;
     if (tables_dirty_ && (st = upload_tables())) return st;
     if (active_ == 0) return PCG_OK;
-    if ((st = ensure_graph())) return st;
+    const int split = items_ > split_items_ ? 1 : 0;
+    if ((st = ensure_graph(split))) return st;
     BCHK(hipEventRecord(ev0_, stream_));
-    BCHK(hipGraphLaunch(gexec_, stream_));
+    BCHK(hipGraphLaunch(gexec_[split], stream_));
     BCHK(hipEventRecord(ev1_, stream_));
     BCHK(hipMemcpyAsync(h_st_, d_st_, sizeof(BatchState) * max_sys_, hipMemcpyDeviceToHost, stream_));
     BCHK(hipStreamSynchronize(stream_));
@@ -619,7 +662,7 @@ extern "C" pcg_status pcg_batch_solve(int32_t count, const pcg_operator *ops, co
     if (bytes < total) return invalid("workspace too small");
     char *ws = (char *)workspace;
     BatchEngine eng;
-    const int K = opts[0].iters_per_launch ? opts[0].iters_per_launch : 8;
+    const int K = opts[0].iters_per_launch;  // 0: the engine default
     if ((st = eng.init(ws, count, items, opts[0].prec, (hipStream_t)hip_stream, K))) return st;
     if (opts[0].grid_blocks) eng.set_pass_grid(opts[0].grid_blocks);
     std::vector<int> slot(count);

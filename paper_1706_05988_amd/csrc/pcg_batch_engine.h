@@ -1,5 +1,5 @@
 // pcg_batch_engine.h -- host side of the batched persistent pass: system
-// slots, device tables, the captured graph of K (pass, finalize) pairs and
+// slots, device tables, the captured graph of K passes and
 // the step / poll cycle.  Used by pcg_batch_solve and by the server.
 #pragma once
 
@@ -51,15 +51,18 @@ public:
 
 private:
     pcg_status upload_tables();
-    pcg_status ensure_graph();
-    void enqueue_passes(hipStream_t st);
+    pcg_status ensure_graph(int split);
+    void enqueue_passes(hipStream_t st, int split);
 
     int max_sys_ = 0;
     int64_t max_items_ = 0;
     int prec_ = 0;
     int K_ = 8;
     int pass_grid_ = 1024;   // persistent blocks of the pass (4 per CU)
-    int final_grid_ = 256;
+    int trans_grid_ = 256;
+    // above this many items a launch runs split (measured: the fused head
+    // costs ~100 us per pass on a full 512-system batch, the extra kernel ~5 us)
+    int64_t split_items_ = 4096;
     hipStream_t stream_ = nullptr;
     BatchSys *d_sys_ = nullptr;
     BatchState *d_st_ = nullptr;
@@ -75,8 +78,9 @@ private:
     int64_t items_ = 0;
     int active_ = 0;
     int launches_ = 0;
-    hipGraph_t graph_ = nullptr;
-    hipGraphExec_t gexec_ = nullptr;
+    // [0]: fused passes (few items), [1]: transition + pass (many items)
+    hipGraph_t graph_[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec_[2] = {nullptr, nullptr};
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
 };
 

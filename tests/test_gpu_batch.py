@@ -78,6 +78,28 @@ def test_batch_result_independent_of_batch_mix(torch):
         assert np.array_equal(alone["res"], together[k]["res"], equal_nan=True)
 
 
+def test_batch_result_independent_of_launch_mode(torch):
+    """A large batch (more than 4096 tile items) starts in the split launch
+    mode (transition kernel + pass) and moves to the fused mode as systems
+    finish; a system solved alone runs fused all the way.  Both modes take
+    the same transition with the same reduction: identical bits."""
+    ps = []
+    for k in range(40):
+        op = problems.stencil2d(256, 256 - k, shift=0.02)
+        b = np.random.default_rng(100 + k).uniform(-1, 1, op.n)
+        ps.append(problems.Problem(f"big{k}", op, b, np.zeros(op.n), None, sigma=4.02, rtol=1e-8, max_iter=3000))
+    small = mixed_set()[1]
+    ps.append(small)
+    assert sum((p.op.n + 511) // 512 for p in ps) > 4096
+    together = run_batch(torch, ps, fp32=True, hist=False)
+    for k in (0, 17, len(ps) - 1):
+        alone = run_batch(torch, [ps[k]], fp32=True, hist=False)[0]
+        assert together[k]["status"] == "converged", ps[k].name
+        assert np.array_equal(alone["x"], together[k]["x"]), ps[k].name
+        assert alone["iterations"] == together[k]["iterations"]
+        assert alone["rel_res_true"] == together[k]["rel_res_true"]
+
+
 def test_batch_fp32_stream_with_restarts(torch):
     """FP32-stream batch: every system reaches the tolerance through
     restarts from its binary64 x."""
