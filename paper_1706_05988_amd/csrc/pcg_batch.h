@@ -9,7 +9,7 @@
 //   RESID   ||b - A x|| in binary64 (after the iteration ends)
 //   COPYOUT internal x -> caller x
 // The pass kernel works on a table of (system, tile) items; each tile is
-// 512 unknowns (256 threads x 2) and writes one block partial into its
+// 256 * kBatchEPT unknowns and writes one block partial into its
 // system's partial array.  At its head, every item block sums its system's
 // partials of the previous pass in tile order (so a system's results depend
 // only on that system, never on the rest of the batch), takes the stop /
@@ -35,12 +35,15 @@ enum Phase : int32_t {
     PH_ADMIT = 0, PH_COPYIN, PH_INIT0, PH_INIT1, PH_ITER, PH_RESID, PH_COPYOUT, PH_DONE, PH_FREE
 };
 
-constexpr int kBatchBlock = 256;      // threads of a pass block: one 512-unknown tile
-constexpr int kBatchEPT = 2;
+constexpr int kBatchBlock = 256;      // threads of a pass block
+#ifndef PCG_BATCH_EPT
+#define PCG_BATCH_EPT 4
+#endif
+constexpr int kBatchEPT = PCG_BATCH_EPT;  // unknowns per thread: a work tile is 256 * kBatchEPT unknowns
 
 // Per-system descriptor, written once at admission.
 struct BatchSys {
-    int32_t kind, jac, n, ntiles;
+    int32_t kind, jac, n, ntiles;  // ntiles: work tiles of the pass
     int32_t nx, ny, nz, max_iter;
     FastDiv dx, dxy;
     double centre, off, dinv_s, sigma, rtol;

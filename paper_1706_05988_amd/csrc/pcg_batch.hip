@@ -312,11 +312,12 @@ pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options 
     }
     l.tile_bytes = tb;
     l.ntiles = (int32_t)((n + kBlk - 1) / kBlk);
+    l.nwork = (int32_t)((n + kBatchBlock * kBatchEPT - 1) / (kBatchBlock * kBatchEPT));
     size_t off = 0;
     l.blk = off;
     off += up256((size_t)l.ntiles * tb);
     l.part = off;
-    off += up256((size_t)2 * l.ntiles * kFields * 8);  // two partial slots
+    off += up256((size_t)2 * l.nwork * kFields * 8);  // two partial slots
     l.dinv = SIZE_MAX;
     if (op->kind == PCG_OP_CSR && jac) {
         l.dinv = off;
@@ -428,7 +429,7 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
     D.kind = op->kind;
     D.jac = jac;
     D.n = (int32_t)op->n;
-    D.ntiles = L.ntiles;
+    D.ntiles = L.nwork;
     D.nx = op->nx;
     D.ny = op->ny;
     D.nz = op->kind == PCG_OP_STENCIL3D7 ? op->nz : 1;
@@ -624,7 +625,7 @@ static pcg_status batch_plan(int32_t count, const pcg_operator *ops, const pcg_o
         BatchEngine::system_layout(&ops[k], &opts[k], &L);
         sys_off[k] = off;
         off += L.bytes;
-        ni += L.ntiles;
+        ni += L.nwork;
     }
     const size_t tb = (BatchEngine::table_bytes(count, ni) + 255) & ~size_t(255);
     for (auto &o : sys_off) o += tb;

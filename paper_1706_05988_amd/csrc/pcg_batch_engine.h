@@ -18,7 +18,8 @@ public:
     struct SysLayout {
         size_t blk, part, dinv, hist, flag, gersh, bytes;
         uint32_t tile_bytes;
-        int32_t ntiles;
+        int32_t ntiles;   // layout tiles (kBlk unknowns)
+        int32_t nwork;    // work tiles of the pass (kBatchBlock * kBatchEPT unknowns)
         uint32_t off_slot[V_COUNT];
     };
 

@@ -235,6 +235,7 @@ class DeviceOperator:
     def __init__(self, op, prec: int = PCG_FP64, device="cuda"):
         torch = _torch()
         self.keep = []
+        self.prec = prec
         s = pcg_operator()
         s.kind = OPKIND[op.kind]
         s.n = int(op.n)
@@ -252,6 +253,16 @@ class DeviceOperator:
             s.nz = int(op.nz) if op.kind == "3d7" else 1
             s.diag, s.offdiag, s.shift = float(op.diag), float(op.off), float(op.shift)
         self.struct = s
+
+
+def _device_op(op, prec: int, device) -> "DeviceOperator":
+    """`op` itself when it is already a DeviceOperator of precision `prec`
+    (operators resident on the device, uploaded once), else a new upload."""
+    if isinstance(op, DeviceOperator):
+        if op.prec != prec:
+            raise ValueError("the device operator was uploaded for another precision")
+        return op
+    return DeviceOperator(op, prec, device)
 
 
 def _f64(a):
@@ -335,7 +346,7 @@ class Solver:
     def __init__(self, op, options: pcg_options, device="cuda", stream: Optional[int] = None):
         import numpy as np
         torch = _torch()
-        self.dev = DeviceOperator(op, options.prec, device)
+        self.dev = _device_op(op, options.prec, device)
         self.opt = options
         self.hist = None
         if options.history_cap > 0:
@@ -386,7 +397,7 @@ class Batch:
     def __init__(self, ops, options, device="cuda"):
         import numpy as np
         torch = _torch()
-        self.devs = [DeviceOperator(op, o.prec, device) for op, o in zip(ops, options)]
+        self.devs = [_device_op(op, o.prec, device) for op, o in zip(ops, options)]
         self.opts = list(options)
         self.hists = []
         for o in self.opts:
@@ -424,7 +435,7 @@ class Server:
         """Enqueue a solve; b, x are device tensors (binary64) kept alive by
         the server object until the ticket is collected."""
         import numpy as np
-        dev = DeviceOperator(op, options.prec, self.device)
+        dev = _device_op(op, options.prec, self.device)
         hist = None
         if options.history_cap > 0:
             hist = np.full((options.history_cap, PCG_HISTORY_FIELDS), np.nan)
