@@ -116,3 +116,64 @@ def test_server_argument_checks():
     r = P.pcg_result()
     assert lib.pcg_poll(None, 1, C.byref(r)) == P.PCG_ERR_STATE
     assert lib.pcg_server_destroy(None) == P.PCG_OK
+
+
+def test_variable_shift_schedule_validation():
+    """PCG_PIPE_VAR_SHIFT needs a host schedule of 1 .. 2^24 finite, >= 0
+    shifts; every violation is PCG_ERR_INVALID before any device work."""
+    op = stencil_op()
+    ok = P.make_options(method="pipe_var", sigma_schedule=[0.5, 1.0, 2.0])
+    assert P.pcg_workspace_size(op, ok) > 0
+    bad = [P.make_options(method="pipe_var"),                              # no schedule
+           P.make_options(method="pipe_var", sigma_schedule=[1.0, -0.5]),   # negative shift
+           P.make_options(method="pipe_var", sigma_schedule=[1.0, math.nan])]
+    for o in bad:
+        with pytest.raises(P.PcgError) as ei:
+            P.pcg_workspace_size(op, o)
+        assert ei.value.status == P.PCG_ERR_INVALID
+
+
+def test_variable_shift_workspace_holds_the_schedule():
+    op = stencil_op()
+    a = P.pcg_workspace_size(op, P.make_options(method="pipe_var", sigma_schedule=[1.0]))
+    b = P.pcg_workspace_size(op, P.make_options(method="pipe_var", sigma_schedule=[1.0] * 100_000))
+    assert b - a >= 8 * 100_000 - 256  # the schedule region, 256-byte rounded
+
+
+def test_pcg_rr_option_validation():
+    op = stencil_op()
+    assert P.pcg_workspace_size(op, P.make_options(method="pipe_rr", rr_period=16, rr_tau=1e-5)) > 0
+    with pytest.raises(P.PcgError) as ei:
+        P.pcg_workspace_size(op, P.make_options(method="pipe_rr", rr_period=-1))
+    assert ei.value.status == P.PCG_ERR_INVALID
+
+
+def test_option_struct_layout_matches_header():
+    """The ctypes mirrors have the C structs' sizes and field offsets
+    (compiled from include/pcg.h with the host C compiler)."""
+    import ctypes as C
+    import os
+    import subprocess
+    import tempfile
+    fields = {"pcg_options": [f for f, _ in P.pcg_options._fields_],
+              "pcg_operator": [f for f, _ in P.pcg_operator._fields_],
+              "pcg_result": [f for f, _ in P.pcg_result._fields_]}
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "pcg.h"', "int main(void) {"]
+    for st, fs in fields.items():
+        src.append(f'printf("{st} %zu\\n", sizeof({st}));')
+        for f in fs:
+            src.append(f'printf("{st}.{f} %zu\\n", offsetof({st}, {f}));')
+    src.append("return 0; }")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "layout.c")
+        open(c, "w").write("\n".join(src))
+        exe = os.path.join(d, "layout")
+        subprocess.run(["gcc", "-std=c99", "-I", inc, c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.split() for line in out if line)
+    for st, fs in fields.items():
+        cls = getattr(P, st)
+        assert int(got[st]) == C.sizeof(cls), st
+        for f in fs:
+            assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"
