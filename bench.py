@@ -415,6 +415,49 @@ def report_small(P, torch) -> dict:
     return out
 
 
+def report_tune(P, torch) -> dict:
+    """The autotuner against the built-in launch shapes on the main
+    workloads: time per iteration pass (HIP events, 400 timed passes) of
+    the default and of the tuned shape."""
+    import problems
+
+    def per_pass(op, opts, b):
+        o = P.pcg_options.from_buffer_copy(opts)
+        o.max_iter, o.rtol, o.true_residual_check, o.timing = 400, 1e-300, 0, 1
+        s = P.Solver(op, o)
+        x = torch.zeros_like(b)
+        s.solve(b, x)
+        x.zero_()
+        r = s.solve(b, x)
+        torch.cuda.synchronize()
+        s.close()
+        return r["iter_kernel_ms"] * 1e3 / max(1, r["iter_passes"])
+
+    out = {}
+    cases = [("3d256_jacobi_fp64_pipe_shift", problems.poisson3d(256, seed=0), dict(jacobi=True, sigma=1.0)),
+             ("3d256_jacobi_fp32_pipe_shift", problems.poisson3d(256, seed=0), dict(jacobi=True, fp32=True, sigma=1.0)),
+             ("csr_aniso1024_fp64_pipe_shift", problems.anisotropic_csr(1024, seed=0), dict(jacobi=True, sigma=1.0)),
+             ("csr_aniso1024_fp32_pipe_shift", problems.anisotropic_csr(1024, seed=0),
+              dict(jacobi=True, fp32=True, sigma=1.0)),
+             ("2d1000_fp64_pipe_shift", problems.paper_parallel_workload(1000), dict(sigma=4.0)),
+             ("2d1000_fp64_cg", problems.paper_parallel_workload(1000), dict(method="cg"))]
+    for name, p, kw in cases:
+        kw = dict(kw)
+        method = kw.pop("method", "pipe_shift")
+        opts = P.make_options(method=method, **kw)
+        b = torch.from_numpy(p.b).cuda()
+        dev = P.DeviceOperator(p.op, opts.prec)
+        t0 = per_pass(dev, opts, b)
+        tuned, us = P.tune(dev, opts, b)
+        t1 = per_pass(dev, tuned, b)
+        out[name] = {"default_us": round(t0, 2), "tuned_us": round(t1, 2), "tuner_us": round(us, 2),
+                     "variant": tuned.variant, "block": tuned.block_size, "grid": tuned.grid_blocks}
+        print(name, out[name], flush=True)
+        del b, dev
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -436,7 +479,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-max-log10", type=float, default=6.0,
                     help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
-    ap.add_argument("--report", choices=["c3", "small"],
+    ap.add_argument("--report", choices=["c3", "small", "tune"],
                     help="print a measurement report (C3 accuracy per shift, or the latency-bound cases) and exit")
     ap.add_argument("--c3-N", type=int, default=1024)
     ap.add_argument("--c3-max-iter", type=int, default=12000)
@@ -468,7 +511,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if args.report:
-        rep = report_c3(P, torch, args.c3_N, args.c3_max_iter) if args.report == "c3" else report_small(P, torch)
+        rep = (report_c3(P, torch, args.c3_N, args.c3_max_iter) if args.report == "c3" else
+               report_small(P, torch) if args.report == "small" else report_tune(P, torch))
         print(json.dumps(rep), flush=True)
         return
     if args.calib_copy:

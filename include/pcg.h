@@ -219,6 +219,34 @@ pcg_status pcg_true_residual(pcg_solver solver, const double *b, const double *x
 
 pcg_status pcg_destroy(pcg_solver solver);
 
+/* -------------------------------------------------------------- autotuner */
+
+/*
+ * Launch-shape autotuner.  The fused pass is bound by memory latency and
+ * bandwidth, and how many unknowns each thread handles (1, 2 or 4), the
+ * block size (128 or 256) and the number of resident blocks per CU (1, 2 or
+ * 4) decide how many independent loads are in flight; the best choice
+ * depends on the operator, the method, the preconditioner and the storage
+ * form.  pcg_tune measures every candidate (and the library's built-in
+ * choice) on the caller's operator -- a solver is created on `workspace`
+ * for each; an 8-pass probe sizes a run of about 3 ms of passes (24 to
+ * 4096) from a zero initial guess, timed with HIP events -- and writes the
+ * fastest into
+ * opt->variant (PCG_VAR_SET | unknowns-per-thread bits | PCG_VAR_NT),
+ * opt->block_size and opt->grid_blocks; *best_us (host, may be NULL)
+ * receives its time per pass.  b: device right-hand side (n binary64);
+ * x: device scratch of n binary64, overwritten.  workspace: at least
+ * pcg_tune_workspace_size() bytes, 256-byte aligned.
+ * When the environment variable PCG_TUNE_CACHE names a file, results are
+ * looked up there first (key: operator kind and sizes, nnz, method,
+ * preconditioner, precision) and new ones appended, one line per key, so a
+ * later process skips the measurement.  Errors: PCG_ERR_INVALID as for
+ * pcg_create; PCG_ERR_HIP from the device.  opt is changed only on success.
+ */
+pcg_status pcg_tune_workspace_size(const pcg_operator *op, const pcg_options *opt, size_t *bytes);
+pcg_status pcg_tune(const pcg_operator *op, pcg_options *opt, void *workspace, size_t bytes, const double *b,
+                    double *x, void *hip_stream, double *best_us);
+
 /* ------------------------------------------------------------ batched solve */
 
 /*

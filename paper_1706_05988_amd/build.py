@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpcg.so")
 ARCH = os.environ.get("PCG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["pcg_solver.hip", "pcg_batch.hip", "pcg_server.hip", "pcg_shift.cpp"]
+SOURCES = ["pcg_solver.hip", "pcg_batch.hip", "pcg_server.hip", "pcg_tune.hip", "pcg_shift.cpp"]
 
 # -Xclang -target-feature -Xclang -packed-fp32-ops keeps the compiler from
 # emitting packed FP32 VALU instructions on gfx950.

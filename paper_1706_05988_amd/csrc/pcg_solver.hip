@@ -159,7 +159,8 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
         const bool pipe = o->method != PCG_CG, jac = o->pc == PCG_PC_JACOBI, fp64 = o->prec == PCG_FP64;
         if (pipe && op->kind == PCG_OP_CSR) {
             // gathers need more waves in flight than the stencil streams
-            s.ept = 2, s.block = 256, blocks_per_cu = fp64 ? 2 : 4;
+            if (fp64) s.ept = 1, s.block = 128, blocks_per_cu = 4;
+            else s.ept = 2, s.block = 256, blocks_per_cu = 4;
         } else if (pipe && jac) {
             // 4 unknowns per thread keep ~70 independent loads in flight per
             // thread; binary64 runs best as one block per CU, the lighter

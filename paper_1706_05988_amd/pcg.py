@@ -86,6 +86,9 @@ _SIGS = {
     "pcg_wait": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(pcg_result)]),
     "pcg_server_destroy": (C.c_int32, [C.c_void_p]),
     "pcg_status_str": (C.c_char_p, [C.c_int32]),
+    "pcg_tune_workspace_size": (C.c_int32, [C.POINTER(pcg_operator), C.POINTER(pcg_options), C.POINTER(C.c_size_t)]),
+    "pcg_tune": (C.c_int32, [C.POINTER(pcg_operator), C.POINTER(pcg_options), C.c_void_p, C.c_size_t, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "pcg_psi": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_double, C.POINTER(C.c_double)]),
     "pcg_psi_variable": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32,
                                      C.POINTER(C.c_double)]),
@@ -263,6 +266,45 @@ def _device_op(op, prec: int, device) -> "DeviceOperator":
             raise ValueError("the device operator was uploaded for another precision")
         return op
     return DeviceOperator(op, prec, device)
+
+
+def pcg_tune_workspace_size(op: pcg_operator, opt: pcg_options) -> int:
+    n = C.c_size_t()
+    _check(lib().pcg_tune_workspace_size(C.byref(op), C.byref(opt), C.byref(n)), "pcg_tune_workspace_size")
+    return n.value
+
+
+def pcg_tune(op: pcg_operator, opt: pcg_options, workspace: int, nbytes: int, b: int, x: int,
+             stream: Optional[int]) -> float:
+    """Tune `opt` in place; returns microseconds per pass of the chosen shape."""
+    us = C.c_double()
+    _check(lib().pcg_tune(C.byref(op), C.byref(opt), workspace, nbytes, b, x, stream, C.byref(us)), "pcg_tune")
+    return us.value
+
+
+def tune(op, options: pcg_options, b=None, device="cuda", stream: Optional[int] = None):
+    """Run the launch-shape autotuner (pcg_tune) for `op` and `options`;
+    returns (tuned options, microseconds per pass).  b: a device right-hand
+    side (default: a seeded uniform random vector)."""
+    torch = _torch()
+    dev = _device_op(op, options.prec, device)
+    n = int(dev.struct.n)
+    if b is None:
+        g = torch.Generator(device=device)
+        g.manual_seed(0)
+        b = torch.rand(n, dtype=torch.float64, device=device, generator=g) * 2.0 - 1.0
+    x = torch.zeros(n, dtype=torch.float64, device=device)
+    nbytes = pcg_tune_workspace_size(dev.struct, options)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    ptr = (ws.data_ptr() + 255) & ~255
+    st = current_stream_handle() if stream is None else stream
+    out = pcg_options.from_buffer_copy(options)
+    for k in ("_sched_keep",):
+        if hasattr(options, k):
+            setattr(out, k, getattr(options, k))
+    us = pcg_tune(dev.struct, out, ptr, nbytes, b.data_ptr(), x.data_ptr(), st)
+    torch.cuda.synchronize()
+    return out, us
 
 
 def _f64(a):

@@ -177,3 +177,26 @@ def test_option_struct_layout_matches_header():
         assert int(got[st]) == C.sizeof(cls), st
         for f in fs:
             assert int(got[f"{st}.{f}"]) == getattr(cls, f).offset, f"{st}.{f}"
+
+
+def test_tune_workspace_covers_every_candidate():
+    import ctypes as C
+    op = stencil_op()
+    o = P.make_options(jacobi=True)
+    n = C.c_size_t()
+    assert P.lib().pcg_tune_workspace_size(C.byref(op), C.byref(o), C.byref(n)) == P.PCG_OK
+    assert n.value >= P.pcg_workspace_size(op, o)
+
+
+def test_tune_rejects_bad_arguments_before_device_work():
+    """Aliased b / x and a too-small workspace are PCG_ERR_INVALID; no device
+    pointer is touched (the ones passed here are not device memory)."""
+    import ctypes as C
+    op = stencil_op()
+    o = P.make_options()
+    us = C.c_double()
+    fake = 4096
+    assert P.lib().pcg_tune(C.byref(op), C.byref(o), fake, 1 << 40, fake, fake, None, C.byref(us)) == \
+        P.PCG_ERR_INVALID
+    assert P.lib().pcg_tune(C.byref(op), C.byref(o), fake, 16, fake, fake + 8, None, C.byref(us)) == \
+        P.PCG_ERR_INVALID

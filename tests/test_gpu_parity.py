@@ -535,3 +535,34 @@ def test_pcg_rr_fp32_stream_refines_to_binary64_level(torch):
     o_best = np.nanmin(o["true"][: o["iterations"] + 1])
     assert g_best < 1e-11
     assert g_best <= 10 * o_best
+
+
+# ---------------------------------------------------------------- autotuner
+
+def test_autotuner_shape_solves_like_the_oracle_and_caches(torch, tmp_path, monkeypatch):
+    """pcg_tune picks one of its candidate shapes; the solve with it follows
+    the oracle; with PCG_TUNE_CACHE set the result is stored and a second call
+    returns it without measuring."""
+    from paper_1706_05988_amd import pcg as P
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PCG_TUNE_CACHE", str(cache))
+    p = problems.poisson3d(48, seed=9)
+    base = P.make_options(method="pipe_shift", jacobi=True, sigma=1.0, rtol=1e-30, max_iter=60,
+                          true_residual_check=False, history_cap=62)
+    tuned, us = P.tune(p.op, base)
+    assert us > 0
+    assert tuned.block_size in (0, 128, 256) and tuned.grid_blocks >= 0
+    lines = cache.read_text().strip().split("\n")
+    assert len(lines) == 1
+    tuned2, us2 = P.tune(p.op, base)
+    assert (tuned2.variant, tuned2.block_size, tuned2.grid_blocks) == (tuned.variant, tuned.block_size,
+                                                                        tuned.grid_blocks)
+    assert us2 == pytest.approx(us, rel=1e-3)
+    assert len(cache.read_text().strip().split("\n")) == 1
+    s = P.Solver(p.op, tuned)
+    b = torch.from_numpy(p.b).cuda()
+    x = torch.zeros_like(b)
+    g = s.solve(b, x)
+    s.close()
+    o = oracle_solve(p, "pipe_shift", sigma=1.0, rtol=1e-30, max_iter=60)
+    check_history(g, o)
