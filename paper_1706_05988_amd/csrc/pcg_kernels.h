@@ -370,16 +370,25 @@ __global__ void __launch_bounds__(kMaxBlock) k_init1(PassArgs<T> a)
 //   tail: block partials of gamma_{i+1} = (r, u),
 //     delta_{i+1} = (w_{i+1} + sigma r, u), rho_{i+1} = (r, r).
 // All loads of a tile are issued before any of its stores.
-template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
-__device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const PipeScalars &sc, double (&acc)[3])
+// What a tile of the fused pass reads, and n = A M^-1 w on it: none of it
+// depends on the iteration's scalars, so a pass can issue the loads of its
+// first tile before it waits for the reduction at its head.
+template <int EPT>
+struct PipeTile {
+    TileIdx<EPT> ti;
+    double ne[EPT], we[EPT], re[EPT], ue[EPT], zo[EPT], so[EPT], to[EPT], qo[EPT], po[EPT], xo[EPT];
+};
+
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+__device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, PipeTile<EPT> &d)
 {
-    const double alpha = sc.alpha, beta = sc.beta;
-    const double sigma = sc.sigma, as = alpha * sigma, ds = sc.dsig;
     const uint32_t off_u = JAC ? a.off_u : a.off_r;
     const uint32_t off_q = JAC ? a.off_q : a.off_s;
     const uint32_t off_p = JAC ? a.off_p : a.off_t;
-    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
-    double ne[EPT], we[EPT], re[EPT], ue[EPT], zo[EPT], so[EPT], to[EPT], qo[EPT], po[EPT], xo[EPT];
+    d.ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+    const TileIdx<EPT> &ti = d.ti;
+    double *ne = d.ne, *we = d.we, *re = d.re, *ue = d.ue, *zo = d.zo, *so = d.so, *to = d.to, *qo = d.qo,
+           *po = d.po, *xo = d.xo;
     // loads: the stencil / CSR operand w_i (cached), then the streams
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
@@ -403,6 +412,21 @@ __device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const 
             po[j] = to[j];
         }
     }
+}
+
+// The recurrences and stores of a loaded tile, and its partials.
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
+__device__ __forceinline__ void tile_pipe_update(const PassArgs<T> &a, const PipeTile<EPT> &d, const PipeScalars &sc,
+                                                 double (&acc)[3])
+{
+    const double alpha = sc.alpha, beta = sc.beta;
+    const double sigma = sc.sigma, as = alpha * sigma, ds = sc.dsig;
+    const uint32_t off_u = JAC ? a.off_u : a.off_r;
+    const uint32_t off_q = JAC ? a.off_q : a.off_s;
+    const uint32_t off_p = JAC ? a.off_p : a.off_t;
+    const TileIdx<EPT> &ti = d.ti;
+    const double *ne = d.ne, *we = d.we, *re = d.re, *ue = d.ue, *zo = d.zo, *so = d.so, *to = d.to, *qo = d.qo,
+                 *po = d.po, *xo = d.xo;
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         if (!ti.live[j]) continue;
@@ -456,15 +480,30 @@ __device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const 
 }
 
 template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
+__device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const PipeScalars &sc, double (&acc)[3])
+{
+    PipeTile<EPT> d;
+    tile_pipe_load<T, OP, JAC, EPT, NT>(a, tile, d);
+    tile_pipe_update<T, OP, JAC, EPT, NT, VAR>(a, d, sc, acc);
+}
+
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
 __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
+    // The first tile's loads and SPMV go out before the head waits for the
+    // previous pass's partials: the global reduction overlaps the SPMV, the
+    // point of the pipelined method (Section 1), inside one pass.
+    const TileRange tr = tile_range(a.ntiles, a.xcd_map);
+    PipeTile<EPT> d;
+    if (tr.first < tr.end) tile_pipe_load<T, OP, JAC, EPT, NT>(a, tr.first, d);
     PipeScalars sc;
     if (!pipe_head<T, VAR>(a, lds_red, sc)) return;
     double acc[3] = {0.0, 0.0, 0.0};
-    const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step)
-        tile_pipe<T, OP, JAC, EPT, NT, VAR>(a, tile, sc, acc);
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        if (tile != tr.first) tile_pipe_load<T, OP, JAC, EPT, NT>(a, tile, d);
+        tile_pipe_update<T, OP, JAC, EPT, NT, VAR>(a, d, sc, acc);
+    }
     block_sum<3>(acc, lds_red);
     store_partial<3>(a.part_out, acc);
 }
