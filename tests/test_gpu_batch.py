@@ -100,6 +100,25 @@ def test_batch_result_independent_of_launch_mode(torch):
         assert alone["rel_res_true"] == together[k]["rel_res_true"]
 
 
+def test_config4_full_batch_sampled(torch):
+    """The 512-rectangle batch of the benchmark (FP32-stream p-CG-sh to 1e-8
+    with the binary64 explicit check): every system converges to <= 1e-8, and
+    three sampled systems (smallest, median, largest) reach within 10x of the
+    oracle's level in the same storage form at the iteration count the GPU
+    took."""
+    ps = problems.batch_rectangles(512, seed=0)
+    res = run_batch(torch, ps, fp32=True, rtol=1e-8, max_iter=20000, replace_max=8, hist=False)
+    assert all(r["status"] == "converged" and r["rel_res_true"] <= 1e-8 for r in res)
+    sizes = np.array([p.op.n for p in ps])
+    for k in (int(sizes.argmin()), int(np.argsort(sizes)[len(sizes) // 2]), int(sizes.argmax())):
+        p, g = ps[k], res[k]
+        o = oracle.solve(p.op, p.b, p.x0, method="pipe_shift", sigma=p.sigma, rtol=1e-8, max_iter=20000,
+                         fp32_storage=True, replace_max=8, threads=8)
+        assert o["status"] == "converged", p.name
+        assert abs(g["iterations"] - o["iterations"]) <= max(3, 0.05 * o["iterations"]), p.name
+        assert g["rel_res_true"] <= 10 * max(o["rel_res_true"], 1e-9), p.name
+
+
 def test_batch_fp32_stream_with_restarts(torch):
     """FP32-stream batch: every system reaches the tolerance through
     restarts from its binary64 x."""

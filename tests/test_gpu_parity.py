@@ -304,6 +304,22 @@ def test_config2_full_size_sampled(torch):
     assert err < 1e-6
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_config3_full_size_sampled(torch, fp32):
+    """2-D anisotropic diffusion 1024^2 CSR (5.24M nonzeros), Jacobi, sigma = 1,
+    in the report's launch configuration: the first 10 iterations' residual
+    history and x at sampled unknowns match the oracle (in the same storage
+    form) on the same input."""
+    p = problems.anisotropic_csr(1024, seed=0)
+    kw = dict(fp32=fp32, sigma=1.0, max_iter=10, rtol=1e-30)
+    o = oracle_solve(p, "pipe_shift", **kw)
+    g = gpu_solve(torch, p, "pipe_shift", true_residual_check=False, **kw)
+    tol = 1e-4 if fp32 else 1e-10
+    np.testing.assert_allclose(g["res"][:11], o["res"][:11], rtol=tol)
+    idx = np.random.default_rng(1).integers(0, p.op.n, 2000)
+    np.testing.assert_allclose(g["x"][idx], o["x"][idx], rtol=10 * tol, atol=10 * tol * np.abs(o["x"]).max())
+
+
 # ---------------------------------------------------------------- kernel variants
 
 VARIANTS = {
