@@ -56,13 +56,15 @@ def kernel_source_hash() -> str:
 def bytes_per_unknown(method: str, jacobi: bool, fp32: bool) -> int:
     """Algorithmic HBM bytes per unknown per iteration pass: every stored
     vector read once and written once, w read once (halo counted once) and
-    written once into the other buffer; x and b stay binary64."""
+    written once into the other buffer; x and b stay binary64.  The fused
+    pipelined pass reads and writes x every other iteration (8 bytes per
+    iteration on average), classic CG every iteration."""
     es = 4 if fp32 else 8
     if method == "cg":  # per iteration over both passes: r, p(x2), s + x
         return 8 * 2 + es * 8
-    if jacobi:  # x rw; r u z q s t p rw; w r, w' w
-        return 8 * 2 + es * (7 * 2 + 2)
-    return 8 * 2 + es * (4 * 2 + 2)  # x rw; r z s t rw; w r, w' w
+    if jacobi:  # x rw / 2; r u z q s t p rw; w r, w' w
+        return 8 + es * (7 * 2 + 2)
+    return 8 + es * (4 * 2 + 2)  # x rw / 2; r z s t rw; w r, w' w
 
 
 def traffic_entry():
@@ -118,6 +120,9 @@ def ingest_profiles(trace_dir: str, fetch_dir: str, write_dir: str, kernel: str,
     out["rocprof_average_ns_all"] = float(krow[0]["AverageNs"]) if krow else sum(durs) / len(durs)
     out["working_passes"] = len(work)
     out["average_ns_working"] = sum(work) / len(work)
+    ws = sorted(work)
+    lo, hi = sum(ws[: len(ws) // 2]) / max(1, len(ws) // 2), sum(ws[len(ws) // 2:]) / max(1, len(ws) - len(ws) // 2)
+    out.update(average_ns_fast_half=lo, average_ns_slow_half=hi)
 
     def counter(dirname, cname):
         rows = _csv(os.path.join(dirname, "**", "*counter_collection.csv"))
@@ -149,6 +154,8 @@ def ingest_profiles(trace_dir: str, fetch_dir: str, write_dir: str, kernel: str,
     lines += ["", f"Working passes of the fused kernel: {len(work)}, average {out['average_ns_working']:.0f} ns "
               f"(all {out['rocprof_calls']} dispatches incl. early-returning ones after convergence: "
               f"{out['rocprof_average_ns_all']:.0f} ns).",
+              "Passes alternate between skipping x and catching x up: the faster and slower halves of the "
+              f"working passes average {lo:.0f} ns and {hi:.0f} ns.",
               f"Algorithmic bytes per pass: {bpp} -> {bpp / out['average_ns_working']:.0f} GB/s "
               f"({bpp / out['average_ns_working'] / HBM_PEAK_GBS * 100:.1f}% of 8 TB/s).", "",
               "## HBM traffic (--pmc FETCH_SIZE, --pmc WRITE_SIZE; KiB per dispatch)", "",
@@ -368,8 +375,9 @@ def report_c3(P, torch, N: int, max_iter: int) -> dict:
     nnz, n = p.op.nnz, p.op.n
     for fp32 in (False, True):
         es = 4 if fp32 else 8
-        # streams: x rw 16 + 7 vectors rw + w r/w, CSR values + indices + row_ptr + dinv
-        bytes_it = n * (16 + es * 16) + nnz * (4 + es) + 4 * (n + 1) + es * n
+        # streams: x rw every other iteration (8) + 7 vectors rw + w r/w, CSR values +
+        # indices + row_ptr + dinv
+        bytes_it = n * (8 + es * 16) + nnz * (4 + es) + 4 * (n + 1) + es * n
         for name, sig in (("0", 0.0), ("lambda_min", lmin), ("mid", 1.0), ("lambda_max_bound", 2.0)):
             r = _timed_solve(P, torch, p.op, P.make_options(method="pipe_shift", jacobi=True, fp32=fp32, sigma=sig,
                                                             rtol=1e-30, max_iter=max_iter,

@@ -151,10 +151,21 @@ __device__ __forceinline__ TileIdx<EPT> tile_idx(int tile, uint32_t n)
 // previous pass's partials, the stop test and the scalar recurrences
 // (identical bits in every block), and block 0's state / history record.
 // Returns false when the iteration has ended (or had ended before).
+// How a pass treats x.  x is only read at the end of a solve, so the fused
+// pass may update it every other iteration: the pass of iteration i skips x
+// and the pass of i + 1 applies x_{i+2} = (x_i + alpha_i p_i) + alpha_{i+1}
+// p_{i+1} -- the same operations in the same order, p_i being the p it loads
+// for its own beta-recurrence -- which halves x's traffic.  A solve that
+// stops after a skipping pass completes x with k_x_fixup.
+enum XMode : int { X_EACH = 0, X_SKIP = 1, X_CATCHUP = 2 };
+
+__device__ __forceinline__ int lag_mode(int i, int i_start) { return ((i - i_start) & 1) ? X_CATCHUP : X_SKIP; }
+
 struct PipeScalars {
     double alpha, beta;
-    double sigma;  // sigma_i
-    double dsig;   // sigma_i - sigma_{i-1} (0 for a constant shift)
+    double sigma;       // sigma_i
+    double dsig;        // sigma_i - sigma_{i-1} (0 for a constant shift)
+    double alpha_prev = 0.0;  // alpha_{i-1} (X_CATCHUP)
 };
 
 // The pass state is read field by field where it is used (uniform loads),
@@ -226,6 +237,7 @@ __device__ __forceinline__ bool pipe_head(const PassArgs<T> &a, double *lds_red,
     }
     sc.alpha = alpha;
     sc.beta = beta;
+    sc.alpha_prev = S->alpha_prev;
     if constexpr (VAR) {
         const double sp = sched_at(a.sched, a.sched_len, i - 1);
         sc.sigma = sched_at(a.sched, a.sched_len, i);
@@ -379,7 +391,7 @@ struct PipeTile {
     double ne[EPT], we[EPT], re[EPT], ue[EPT], zo[EPT], so[EPT], to[EPT], qo[EPT], po[EPT], xo[EPT];
 };
 
-template <typename T, int OP, bool JAC, int EPT, bool NT>
+template <typename T, int OP, bool JAC, int EPT, bool NT, int XM = X_EACH>
 __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, PipeTile<EPT> &d)
 {
     const uint32_t off_u = JAC ? a.off_u : a.off_r;
@@ -401,7 +413,8 @@ __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, P
         zo[j] = lds<NT>(vp<T>(a, a.off_z, e));
         so[j] = lds<NT>(vp<T>(a, a.off_s, e));
         to[j] = lds<NT>(vp<T>(a, a.off_t, e));
-        xo[j] = lds<NT>(vp<double>(a, a.off_x, e));
+        if constexpr (XM != X_SKIP) xo[j] = lds<NT>(vp<double>(a, a.off_x, e));
+        else xo[j] = 0.0;
         if constexpr (JAC) {
             ue[j] = lds<NT>(vp<T>(a, off_u, e));
             qo[j] = lds<NT>(vp<T>(a, off_q, e));
@@ -415,7 +428,7 @@ __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, P
 }
 
 // The recurrences and stores of a loaded tile, and its partials.
-template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false, int XM = X_EACH>
 __device__ __forceinline__ void tile_pipe_update(const PassArgs<T> &a, const PipeTile<EPT> &d, const PipeScalars &sc,
                                                  double (&acc)[3])
 {
@@ -457,7 +470,9 @@ __device__ __forceinline__ void tile_pipe_update(const PassArgs<T> &a, const Pip
             wn = rnd<T>((we[j] - alpha * z) - ds * re[j]);  // the old r_i
         }
         // alpha-recurrences, the shift terms grouped first
-        const double xn = xo[j] + alpha * pv;
+        double xn = 0.0;
+        if constexpr (XM == X_EACH) xn = xo[j] + alpha * pv;
+        else if constexpr (XM == X_CATCHUP) xn = (xo[j] + sc.alpha_prev * po[j]) + alpha * pv;
         const double rn = rnd<T>(re[j] - (alpha * s + as * t));
         double un = rn;
         if constexpr (JAC) un = rnd<T>(ue[j] - (alpha * qv + as * pv));
@@ -469,7 +484,7 @@ __device__ __forceinline__ void tile_pipe_update(const PassArgs<T> &a, const Pip
             sts<NT>(vp<T>(a, off_p, e), pv);
             sts<NT>(vp<T>(a, off_u, e), un);
         }
-        sts<NT>(vp<double>(a, a.off_x, e), xn);
+        if constexpr (XM != X_SKIP) sts<NT>(vp<double>(a, a.off_x, e), xn);
         sts<NT>(vp<T>(a, a.off_r, e), rn);
         sts<NT>(vp<T>(a, a.off_wout, e), wn);
         // next iteration's dot products
@@ -487,6 +502,24 @@ __device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const 
     tile_pipe_update<T, OP, JAC, EPT, NT, VAR>(a, d, sc, acc);
 }
 
+// One pass with x's update mode fixed at compile time, so that the skipping
+// pass has no x loads or stores in its code at all.
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR, int XM>
+__device__ __forceinline__ void pipe_pass(const PassArgs<T> &a, const TileRange &tr, double *lds_red)
+{
+    PipeTile<EPT> d;
+    if (tr.first < tr.end) tile_pipe_load<T, OP, JAC, EPT, NT, XM>(a, tr.first, d);
+    PipeScalars sc;
+    if (!pipe_head<T, VAR>(a, lds_red, sc)) return;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
+        if (tile != tr.first) tile_pipe_load<T, OP, JAC, EPT, NT, XM>(a, tile, d);
+        tile_pipe_update<T, OP, JAC, EPT, NT, VAR, XM>(a, d, sc, acc);
+    }
+    block_sum<3>(acc, lds_red);
+    store_partial<3>(a.part_out, acc);
+}
+
 template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
 __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
 {
@@ -495,17 +528,28 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
     // previous pass's partials: the global reduction overlaps the SPMV, the
     // point of the pipelined method (Section 1), inside one pass.
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    PipeTile<EPT> d;
-    if (tr.first < tr.end) tile_pipe_load<T, OP, JAC, EPT, NT>(a, tr.first, d);
-    PipeScalars sc;
-    if (!pipe_head<T, VAR>(a, lds_red, sc)) return;
-    double acc[3] = {0.0, 0.0, 0.0};
+    if (lag_mode(a.st_in->iter, a.st_in->i_start) == X_SKIP)
+        pipe_pass<T, OP, JAC, EPT, NT, VAR, X_SKIP>(a, tr, lds_red);
+    else
+        pipe_pass<T, OP, JAC, EPT, NT, VAR, X_CATCHUP>(a, tr, lds_red);
+}
+
+// x := x + alpha p: completes x after a solve that stopped after a pass that
+// skipped x (alpha = alpha_i and p = p_i of that pass's iteration).
+template <typename T, bool JAC, int EPT>
+__global__ void __launch_bounds__(kMaxBlock) k_x_fixup(PassArgs<T> a, double alpha)
+{
+    const uint32_t off_p = JAC ? a.off_p : a.off_t;
+    const TileRange tr = tile_range(a.ntiles, a.xcd_map);
     for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-        if (tile != tr.first) tile_pipe_load<T, OP, JAC, EPT, NT>(a, tile, d);
-        tile_pipe_update<T, OP, JAC, EPT, NT, VAR>(a, d, sc, acc);
+        const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if (!ti.live[j]) continue;
+            double *xp = vp<double>(a, a.off_x, ti.e[j]);
+            *xp = *xp + alpha * ld(vp<T>(a, off_p, ti.e[j]), 0);
+        }
     }
-    block_sum<3>(acc, lds_red);
-    store_partial<3>(a.part_out, acc);
 }
 
 // ------------------------------------------------- p-CG with residual replacement

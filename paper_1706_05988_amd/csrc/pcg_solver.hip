@@ -252,6 +252,7 @@ using LaunchFn = void (*)(PassArgsAny, int, int, hipStream_t);
 // Kernel table for one (T, OP, JAC, EPT, NT) combination.
 struct Kernels {
     LaunchFn copy_x, init0_pipe, init0_cg, init1, pipe, pipe_var, pipe_rr, cg_init1, cg_a, cg_b, resid;
+    void (*x_fixup)(PassArgsAny, double, int, int, hipStream_t);
 };
 
 template <typename T, int OP, bool JAC, int EPT, bool NT>
@@ -279,8 +280,10 @@ struct KernelSet {
     { hipLaunchKernelGGL((k_cg_b<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void resid(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_resid<T, OP, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    static void x_fixup(PassArgsAny a, double alpha, int g, int b, hipStream_t s)
+    { hipLaunchKernelGGL((k_x_fixup<T, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a), alpha); }
     static Kernels table()
-    { return Kernels{copy_x, init0_pipe, init0_cg, init1, pipe, pipe_var, pipe_rr, cg_init1, cg_a, cg_b, resid}; }
+    { return Kernels{copy_x, init0_pipe, init0_cg, init1, pipe, pipe_var, pipe_rr, cg_init1, cg_a, cg_b, resid, x_fixup}; }
 };
 
 template <typename T, int OP, bool JAC, int EPT>
@@ -744,6 +747,13 @@ extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_re
                 if ((st = add_time(slot))) return st;
                 S = s->pinned[slot];
             }
+        }
+        // the fused pass updates x every other iteration (k_pipe); complete x
+        // when the last pass that ran skipped it
+        const bool lagged = o.method == PCG_PIPE || o.method == PCG_PIPE_SHIFT || o.method == PCG_PIPE_VAR_SHIFT;
+        if (lagged && S.iter > S.i_start && ((S.iter - 1 - S.i_start) & 1) == 0) {
+            s->kern.x_fixup(s->args(0, b, nullptr), S.alpha_prev, s->sh.grid, s->sh.block, s->stream);
+            HIPCHK(hipGetLastError());
         }
         if (S.status == ST_NONFINITE && !(std::isfinite(S.bnorm2))) {
             res->status = PCG_NONFINITE;

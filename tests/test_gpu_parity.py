@@ -523,6 +523,31 @@ def test_pcg_rr_no_replacement_equals_pipe(torch):
     np.testing.assert_allclose(b["res"][: k + 1], a["res"][: k + 1], rtol=1e-12)
 
 
+@pytest.mark.parametrize("method", ["pipe", "pipe_shift", "pipe_var"])
+def test_x_after_each_stop_parity_matches_oracle(torch, method):
+    """The fused pass updates x every other iteration and the host completes
+    x when a solve stops after a skipping pass: x after 1..8 iterations (both
+    parities) matches the oracle's x_k and the every-iteration update of the
+    p-CG-rr pass (no replacement) to rounding."""
+    p = problems.poisson3d(23, seed=5)
+    kw = {}
+    if method == "pipe_var":
+        kw["sigma_schedule"] = [0.5, 1.0, 0.8, 1.2, 0.9, 1.1, 1.0]
+    for k in range(1, 9):
+        g = gpu_solve(torch, p, method, max_iter=k, rtol=1e-30, true_residual_check=False, hist=False, **kw)
+        assert g["status"] == "max_iter" and g["iterations"] == k
+        o = oracle_solve(p, method, max_iter=k, rtol=1e-30, **kw)
+        # the dot products are summed in another order: entries near zero
+        # differ at rounding level relative to |x|; a missing or doubled
+        # alpha p term would differ by |alpha p|, many orders larger
+        np.testing.assert_allclose(g["x"], o["x"], rtol=1e-11, atol=1e-13 * np.abs(o["x"]).max(),
+                                   err_msg=f"{method} k={k}")
+        if method == "pipe":
+            e = gpu_solve(torch, p, "pipe_rr", max_iter=k, rtol=1e-30, true_residual_check=False, hist=False,
+                          rr_tau=1e300)
+            np.testing.assert_allclose(g["x"], e["x"], rtol=1e-13, atol=1e-15 * np.abs(e["x"]).max())
+
+
 def test_pcg_rr_replacement_history_matches_oracle_exactly_at_the_reset(torch):
     """At the replacement iteration the recorded residual is the explicit one:
     GPU and oracle agree there too (the dot products were formed again)."""
