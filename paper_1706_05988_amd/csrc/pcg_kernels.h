@@ -147,10 +147,6 @@ __device__ __forceinline__ TileIdx<EPT> tile_idx(int tile, uint32_t n)
     return t;
 }
 
-// Head of an iteration pass of the pipelined methods: stage 2 of the
-// previous pass's partials, the stop test and the scalar recurrences
-// (identical bits in every block), and block 0's state / history record.
-// Returns false when the iteration has ended (or had ended before).
 // How a pass treats x.  x is only read at the end of a solve, so the fused
 // pass may update it every other iteration: the pass of iteration i skips x
 // and the pass of i + 1 applies x_{i+2} = (x_i + alpha_i p_i) + alpha_{i+1}
@@ -190,6 +186,10 @@ __device__ __forceinline__ double sched_at(const double *sched, int len, int k)
     return sched[idx];
 }
 
+// Head of an iteration pass of the pipelined methods: stage 2 of the
+// previous pass's partials, the stop test and the scalar recurrences
+// (identical bits in every block), and block 0's state / history record.
+// Returns false when the iteration has ended (or had ended before).
 template <typename T, bool VAR = false>
 __device__ __forceinline__ bool pipe_head(const PassArgs<T> &a, double *lds_red, PipeScalars &sc)
 {
