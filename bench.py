@@ -430,6 +430,49 @@ def report_small(P, torch) -> dict:
     return out
 
 
+def report_psi(P, torch) -> dict:
+    """Section 5.1 for lapl200: psi_i(sigma) over sigma at i = 500 (the shift
+    figure) and psi_i(0), psi_i(sigma*) against i (the right panels of the
+    residual-history figure), from alpha / beta recorded on the device by
+    500-iteration runs, with the shift picked from them (smallest grid sigma
+    within a factor 2 of the smallest psi).  Classic CG's coefficients are
+    p-CG's in exact arithmetic and run the full 500 iterations; p-CG's own
+    are used when its run is not cut short by a breakdown.  The recursive
+    residual histories of p-CG and p-CG-sh at sigma* come along."""
+    import numpy as np
+    import problems
+    p = problems.lapl200()
+    b = torch.from_numpy(p.b).cuda()
+    runs = {}
+    for m in ("pipe", "cg"):
+        runs[m] = _timed_solve(P, torch, p.op, P.make_options(method=m, sigma=0.0, rtol=1e-30, max_iter=500,
+                                                              history_cap=502, true_residual_check=False), b)
+    src = "pipe" if runs["pipe"]["iterations"] == 500 else "cg"
+    a, bb = runs[src]["alpha"][:500], runs[src]["beta"][:500]
+    i = 499  # psi after 500 iterations (alpha_0 .. alpha_499)
+    grid = np.arange(0.0, 8.0001, 0.25)
+    t0 = time.perf_counter()
+    s_star, vals = P.pcg_select_shift(a, bb, i, grid, slack=2.0)
+    its = list(range(10, 500, 10)) + [i]
+    psi0 = [P.pcg_psi(a, bb, k, 0.0) for k in its]
+    psis = [P.pcg_psi(a, bb, k, s_star) for k in its]
+    host_s = time.perf_counter() - t0
+    sh = _timed_solve(P, torch, p.op, P.make_options(method="pipe_shift", sigma=s_star, rtol=1e-30, max_iter=500,
+                                                     history_cap=502, true_residual_check=False), b)
+    return {"problem": "lapl200 (2-D Laplacian 200^2, b = 1/sqrt(n), no preconditioner)",
+            "coefficients_from": src, "pipe_iterations": runs["pipe"]["iterations"],
+            "pipe_status": runs["pipe"]["status"],
+            "fig_shift": {"i": 500, "sigma": grid.tolist(), "psi": vals.tolist(), "sigma_star": s_star,
+                          "psi_at_0": float(vals[0]), "psi_at_sigma_star": float(vals[list(grid).index(s_star)]),
+                          "paper": {"psi_at_0": 1.78e8, "sigma_star": 4.0, "psi_at_sigma_star": 3.46e2}},
+            "fig_history_right": {"i": [k + 1 for k in its], "psi_0": psi0, "psi_sigma_star": psis},
+            "recursive_residual": {"pipe": runs["pipe"]["res"][:501].tolist(),
+                                   "pipe_shift_sigma_star": sh["res"][:501].tolist()},
+            "true_residual_after_500": {"pipe": runs["pipe"]["rel_res_true"], "cg": runs["cg"]["rel_res_true"],
+                                        "pipe_shift_sigma_star": sh["rel_res_true"]},
+            "host_seconds_for_psi": host_s}
+
+
 def report_tune(P, torch) -> dict:
     """The autotuner against the built-in launch shapes on the main
     workloads: time per iteration pass (HIP events, 400 timed passes) of
@@ -494,7 +537,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-max-log10", type=float, default=6.0,
                     help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
-    ap.add_argument("--report", choices=["c3", "small", "tune"],
+    ap.add_argument("--report", choices=["c3", "small", "tune", "psi"],
                     help="print a measurement report (C3 accuracy per shift, or the latency-bound cases) and exit")
     ap.add_argument("--c3-N", type=int, default=1024)
     ap.add_argument("--c3-max-iter", type=int, default=12000)
@@ -527,7 +570,8 @@ def main():
     dev = torch.device("cuda:0")
     if args.report:
         rep = (report_c3(P, torch, args.c3_N, args.c3_max_iter) if args.report == "c3" else
-               report_small(P, torch) if args.report == "small" else report_tune(P, torch))
+               report_small(P, torch) if args.report == "small" else
+               report_psi(P, torch) if args.report == "psi" else report_tune(P, torch))
         print(json.dumps(rep), flush=True)
         return
     if args.calib_copy:

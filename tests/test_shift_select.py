@@ -49,6 +49,26 @@ def test_select_shift_gives_the_table_shift(lapl200_pcg):
     assert 6.0 < s1 < 8.0
 
 
+def test_psi_against_iterations_fig2_right_panel(lapl200_pcg):
+    """psi_i(0) and psi_i(sigma*) against i for lapl200 (Section 5.1, the
+    right panels of the residual-history figure): the library equals the
+    oracle along the series; unshifted, psi_i grows by orders of magnitude
+    over the first hundred iterations, while at sigma* = 4 it stays within
+    1e2..1e3 from the start and ends several orders of magnitude below the
+    unshifted value, the gap-ratio estimate the paper reads off the panels."""
+    g, a, b = lapl200_pcg
+    lib0, lib4 = {}, {}
+    for i in (10, 25, 50, 100, 200, 300, 400, len(a) - 1):
+        lib0[i], lib4[i] = P.pcg_psi(a, b, i, 0.0), P.pcg_psi(a, b, i, g["sigma_star"])
+        assert lib0[i] == pytest.approx(psi_mod.psi(a, b, 0.0, i), rel=1e-9)
+        assert lib4[i] == pytest.approx(psi_mod.psi(a, b, g["sigma_star"], i), rel=1e-9)
+        assert 1e2 <= lib4[i] <= 1e3, i
+    assert lib0[100] >= 100 * lib0[10]
+    for i in lib0:
+        if i >= 100:
+            assert lib0[i] >= 1e3 * lib4[i], i
+
+
 def test_psi_variable_matches_oracle_and_reduces_to_constant(lapl200_pcg):
     _, a, b = lapl200_pcg
     i = 200
