@@ -35,13 +35,13 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pipe_3d7_jacobi_fp64_256.json")
 # the rocprofv3 runs whose output --ingest-profile summarises (run from the repo root)
 PROFILE_COMMANDS = [
-    "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- "
+    "rocprofv3 --kernel-trace --stats -d rocprof_out/prof_trace -o trace --output-format csv -- "
     "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batched --no-serving",
-    "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch --output-format csv -- "
+    "rocprofv3 --pmc FETCH_SIZE -d rocprof_out/prof_fetch -o fetch --output-format csv -- "
     "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-serving --max-iter 24 --calib-copy",
-    "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write -o write --output-format csv -- "
+    "rocprofv3 --pmc WRITE_SIZE -d rocprof_out/prof_write -o write --output-format csv -- "
     "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-serving --max-iter 24 --calib-copy",
-    "python3 bench.py --ingest-profile gpurun_out/prof_trace gpurun_out/prof_fetch gpurun_out/prof_write",
+    "python3 bench.py --ingest-profile rocprof_out/prof_trace rocprof_out/prof_fetch rocprof_out/prof_write",
 ]
 KERNEL_SOURCES = ["paper_1706_05988_amd/csrc/pcg_kernels.h", "paper_1706_05988_amd/csrc/pcg_device.h"]
 
@@ -151,7 +151,7 @@ def ingest_profiles(trace_dir: str, fetch_dir: str, write_dir: str, kernel: str,
         json.dump(out, f, indent=1)
     top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]
     lines = [f"# rocprofv3 summary: {kernel} ({name})", "",
-             "Commands (from the repository root on the GPU box):", ""]
+             "Commands (from the repository root, on the MI355X):", ""]
     lines += [f"    {c}" for c in commands]
     lines += ["", "## Kernel statistics (--kernel-trace --stats)", "",
               "| kernel | calls | average ns | % |", "|---|---|---|---|"]
@@ -556,7 +556,7 @@ def main():
         return
 
     if args.gpus != 1:
-        print(f"bench.py: this build runs the solver on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the solver runs on one GPU; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design, not built).", file=sys.stderr)
         sys.exit(2)
 
