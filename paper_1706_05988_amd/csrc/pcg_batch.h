@@ -36,6 +36,7 @@ enum Phase : int32_t {
 };
 
 constexpr int kBatchBlock = 256;      // threads of a pass block
+constexpr int kSpecAny = -1;          // pass kernels read operator kind and preconditioner per system
 #ifndef PCG_BATCH_EPT
 #define PCG_BATCH_EPT 4
 #endif
@@ -74,10 +75,9 @@ struct BatchState {
 struct BatchTables {
     const BatchSys *sys;
     BatchState *st;          // 2 slots of max_sys states
-    const uint32_t *item_sys;
-    const uint32_t *item_tile;
-    const uint32_t *active;  // listed systems (split mode)
     const int32_t *counts;   // [0] = items, [1] = listed systems
+    const uint32_t *active;  // listed systems (split mode)
+    const uint2 *items;      // (system, work tile) of each item
     int32_t max_sys;
     int32_t pad;
 };

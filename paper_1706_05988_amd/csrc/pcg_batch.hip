@@ -98,6 +98,26 @@ __device__ __forceinline__ void batch_tile_op(const BatchSys &D, const BatchStat
     else batch_tile<T, OP, false>(a, S, tile, acc);
 }
 
+// One item of a system.  SPEC = kind * 2 + jac fixes the operator and the
+// preconditioner at compile time for a batch whose systems all share them
+// (the kernel then holds one tile body instead of six, and needs far fewer
+// registers); kSpecAny reads them per system.
+template <typename T, int SPEC>
+__device__ __forceinline__ void batch_item(const BatchSys &D, const BatchState &S, int tile, double (&acc)[3])
+{
+    if constexpr (SPEC == kSpecAny) {
+        switch (D.kind) {
+        case PCG_OP_STENCIL2D5: batch_tile_op<T, OP_2D5>(D, S, tile, acc); break;
+        case PCG_OP_STENCIL3D7: batch_tile_op<T, OP_3D7>(D, S, tile, acc); break;
+        default: batch_tile_op<T, OP_CSR>(D, S, tile, acc); break;
+        }
+    } else {
+        constexpr int kind = SPEC >> 1;
+        constexpr int OP = kind == PCG_OP_STENCIL2D5 ? OP_2D5 : kind == PCG_OP_STENCIL3D7 ? OP_3D7 : OP_CSR;
+        batch_tile<T, OP, (SPEC & 1) != 0>(batch_args<T>(D, S), S, tile, acc);
+    }
+}
+
 __device__ __forceinline__ void batch_hist(const BatchSys &D, int i, double res, double alpha, double beta,
                                            double gamma, double delta)
 {
@@ -199,13 +219,14 @@ __device__ __forceinline__ BatchState batch_next(const BatchSys &D, BatchState S
 // partials are read from slot par and written to slot 1 - par.  HEAD: the
 // item block takes its system's transition itself; otherwise k_batch_trans
 // has already written the transitioned state into slot 1 - par.
-template <typename T, bool HEAD>
+template <typename T, bool HEAD, int SPEC>
 __global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int par)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     const int nitems = tb.counts[0];
     for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint32_t s = tb.item_sys[it], tile = tb.item_tile[it];
+        const uint2 si = tb.items[it];
+        const uint32_t s = si.x, tile = si.y;
         const BatchState *Sin = tb.st + (size_t)par * tb.max_sys + s;
         BatchState *Sout = tb.st + (size_t)(1 - par) * tb.max_sys + s;
         const BatchSys &D = tb.sys[s];
@@ -227,11 +248,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int 
         }
         double acc[3] = {0.0, 0.0, 0.0};
         if (S.phase >= PH_DONE) continue;
-        switch (D.kind) {
-        case PCG_OP_STENCIL2D5: batch_tile_op<T, OP_2D5>(D, S, tile, acc); break;
-        case PCG_OP_STENCIL3D7: batch_tile_op<T, OP_3D7>(D, S, tile, acc); break;
-        default: batch_tile_op<T, OP_CSR>(D, S, tile, acc); break;
-        }
+        batch_item<T, SPEC>(D, S, tile, acc);
         block_sum<3>(acc, lds_red);
         if (threadIdx.x == 0) {
             double *pp = D.part + ((size_t)(1 - par) * D.ntiles + tile) * kFields;
@@ -265,10 +282,19 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_trans(BatchTables tb, int
     }
 }
 
-template __global__ void k_batch_step<double, true>(BatchTables, int);
-template __global__ void k_batch_step<float, true>(BatchTables, int);
-template __global__ void k_batch_step<double, false>(BatchTables, int);
-template __global__ void k_batch_step<float, false>(BatchTables, int);
+template <typename T, bool HEAD>
+static void launch_step(int spec, dim3 g, dim3 b, hipStream_t st, const BatchTables &tb, int par)
+{
+    switch (spec) {
+    case 0: hipLaunchKernelGGL((k_batch_step<T, HEAD, 0>), g, b, 0, st, tb, par); break;
+    case 1: hipLaunchKernelGGL((k_batch_step<T, HEAD, 1>), g, b, 0, st, tb, par); break;
+    case 2: hipLaunchKernelGGL((k_batch_step<T, HEAD, 2>), g, b, 0, st, tb, par); break;
+    case 3: hipLaunchKernelGGL((k_batch_step<T, HEAD, 3>), g, b, 0, st, tb, par); break;
+    case 4: hipLaunchKernelGGL((k_batch_step<T, HEAD, 4>), g, b, 0, st, tb, par); break;
+    case 5: hipLaunchKernelGGL((k_batch_step<T, HEAD, 5>), g, b, 0, st, tb, par); break;
+    default: hipLaunchKernelGGL((k_batch_step<T, HEAD, kSpecAny>), g, b, 0, st, tb, par); break;
+    }
+}
 
 // ----------------------------------------------------------------- engine
 
@@ -280,10 +306,15 @@ template __global__ void k_batch_step<float, false>(BatchTables, int);
 
 static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// The work list, one block uploaded in one copy: the two counts (16 bytes),
+// the listed systems (padded to 8 bytes), then the (system, tile) pairs.
+static size_t list_items_off(int max_sys) { return 16 + 8 * (size_t)((max_sys + 1) / 2); }
+static size_t list_bytes(int max_sys, int64_t max_items) { return list_items_off(max_sys) + 8 * (size_t)max_items; }
+
 size_t BatchEngine::table_bytes(int max_sys, int64_t max_items)
 {
     return up256(sizeof(BatchSys) * max_sys) + up256(sizeof(BatchState) * 2 * (size_t)max_sys) +
-           up256(sizeof(uint32_t) * (size_t)max_items) * 2 + up256(sizeof(uint32_t) * max_sys) + 256;
+           up256(list_bytes(max_sys, max_items));
 }
 
 pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options *opt, SysLayout *L)
@@ -363,18 +394,15 @@ pcg_status BatchEngine::init(char *tables, int max_sys, int64_t max_items, int p
     };
     d_sys_ = (BatchSys *)take(sizeof(BatchSys) * max_sys);
     d_st_ = (BatchState *)take(sizeof(BatchState) * 2 * (size_t)max_sys);
-    d_item_sys_ = (uint32_t *)take(sizeof(uint32_t) * (size_t)max_items);
-    d_item_tile_ = (uint32_t *)take(sizeof(uint32_t) * (size_t)max_items);
-    d_active_ = (uint32_t *)take(sizeof(uint32_t) * max_sys);
-    d_counts_ = (int32_t *)take(256);
+    d_list_ = take(list_bytes(max_sys, max_items));
     sys_.assign(max_sys, BatchSys{});
     in_use_.assign(max_sys, 0);
     listed_.assign(max_sys, 0);
     BCHK(hipHostMalloc((void **)&h_st_, sizeof(BatchState) * max_sys, hipHostMallocDefault));
-    BCHK(hipHostMalloc((void **)&h_items_, sizeof(uint32_t) * (size_t)max_items * 2 + sizeof(uint32_t) * max_sys + 64,
-                       hipHostMallocDefault));
+    BCHK(hipHostMalloc((void **)&h_list_, list_bytes(max_sys, max_items), hipHostMallocDefault));
     BCHK(hipEventCreate(&ev0_));
     BCHK(hipEventCreate(&ev1_));
+    BCHK(hipEventCreate(&ev_up_));
     for (int k = 0; k < max_sys; ++k) {
         h_st_[k] = BatchState{};
         h_st_[k].phase = PH_FREE;
@@ -382,7 +410,7 @@ pcg_status BatchEngine::init(char *tables, int max_sys, int64_t max_items, int p
     BCHK(hipMemcpyAsync(d_st_, h_st_, sizeof(BatchState) * max_sys, hipMemcpyHostToDevice, stream_));
     BCHK(hipMemcpyAsync(d_st_ + max_sys, h_st_, sizeof(BatchState) * max_sys, hipMemcpyHostToDevice, stream_));
     int32_t zero[2] = {0, 0};
-    BCHK(hipMemcpyAsync(d_counts_, zero, sizeof(zero), hipMemcpyHostToDevice, stream_));
+    BCHK(hipMemcpyAsync(d_list_, zero, sizeof(zero), hipMemcpyHostToDevice, stream_));
     BCHK(hipStreamSynchronize(stream_));
     return PCG_OK;
 }
@@ -394,9 +422,10 @@ BatchEngine::~BatchEngine()
         if (graph_[k]) (void)hipGraphDestroy(graph_[k]);
     }
     if (h_st_) (void)hipHostFree(h_st_);
-    if (h_items_) (void)hipHostFree(h_items_);
+    if (h_list_) (void)hipHostFree(h_list_);
     if (ev0_) (void)hipEventDestroy(ev0_);
     if (ev1_) (void)hipEventDestroy(ev1_);
+    if (ev_up_) (void)hipEventDestroy(ev_up_);
 }
 
 pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, const double *b, double *x, char *region,
@@ -464,10 +493,12 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
     BatchState S{};
     S.phase = PH_ADMIT;
     S.status = RUNNING;
+    BCHK(hipEventSynchronize(ev_up_));  // h_st_ may still be the source of an upload
     h_st_[slot] = S;
     // descriptor and state go up with the next table upload, before the next launch
     if (D.hist) BCHK(hipMemsetAsync(D.hist, 0xff, (size_t)D.hist_cap * PCG_HISTORY_FIELDS * 8, stream_));
     tables_dirty_ = true;
+    slots_dirty_ = true;
     *slot_out = slot;
     return PCG_OK;
 }
@@ -475,15 +506,21 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
 void BatchEngine::release(int slot)
 {
     in_use_[slot] = 0;
+    (void)hipEventSynchronize(ev_up_);  // h_st_ may still be the source of an upload
     h_st_[slot].phase = PH_FREE;
     tables_dirty_ = true;
+    slots_dirty_ = true;
 }
 
 pcg_status BatchEngine::upload_tables()
 {
     // items of every system still working, in slot order; the list of those
     // systems the same
-    uint32_t *isys = h_items_, *itile = h_items_ + max_items_, *act = h_items_ + 2 * max_items_;
+    // the previous upload from the staging buffers has been carried out
+    BCHK(hipEventSynchronize(ev_up_));
+    int32_t *cnt = reinterpret_cast<int32_t *>(h_list_);
+    uint32_t *act = reinterpret_cast<uint32_t *>(h_list_ + 16);
+    uint32_t *items = reinterpret_cast<uint32_t *>(h_list_ + list_items_off(max_sys_));
     int64_t ni = 0;
     int na = 0;
     for (int s = 0; s < max_sys_; ++s) {
@@ -493,44 +530,83 @@ pcg_status BatchEngine::upload_tables()
         act[na++] = (uint32_t)s;
         for (int t = 0; t < sys_[s].ntiles; ++t) {
             if (ni >= max_items_) return PCG_ERR_BUDGET;
-            isys[ni] = (uint32_t)s;
-            itile[ni] = (uint32_t)t;
+            items[2 * ni] = (uint32_t)s;
+            items[2 * ni + 1] = (uint32_t)t;
             ++ni;
         }
     }
-    counts_h_[0] = (int32_t)ni;
-    counts_h_[1] = na;
-    // descriptors and states of every slot: between launches the host copy
-    // of a running system's state equals the device one (it was just read
-    // back), and admitted or released slots carry their new state
-    BCHK(hipMemcpyAsync(d_sys_, sys_.data(), sizeof(BatchSys) * max_sys_, hipMemcpyHostToDevice, stream_));
-    BCHK(hipMemcpyAsync(d_st_, h_st_, sizeof(BatchState) * max_sys_, hipMemcpyHostToDevice, stream_));
-    if (ni) {
-        BCHK(hipMemcpyAsync(d_item_sys_, isys, sizeof(uint32_t) * ni, hipMemcpyHostToDevice, stream_));
-        BCHK(hipMemcpyAsync(d_item_tile_, itile, sizeof(uint32_t) * ni, hipMemcpyHostToDevice, stream_));
+    cnt[0] = (int32_t)ni;
+    cnt[1] = na;
+    // descriptors and states only when a slot was admitted or released:
+    // between launches the host copy of a running system's state equals the
+    // device one (it was just read back), and admitted or released slots
+    // carry their new state
+    if (slots_dirty_) {
+        BCHK(hipMemcpyAsync(d_sys_, sys_.data(), sizeof(BatchSys) * max_sys_, hipMemcpyHostToDevice, stream_));
+        BCHK(hipMemcpyAsync(d_st_, h_st_, sizeof(BatchState) * max_sys_, hipMemcpyHostToDevice, stream_));
+        slots_dirty_ = false;
     }
-    if (na) BCHK(hipMemcpyAsync(d_active_, act, sizeof(uint32_t) * na, hipMemcpyHostToDevice, stream_));
-    BCHK(hipMemcpyAsync(d_counts_, counts_h_, sizeof(counts_h_), hipMemcpyHostToDevice, stream_));
-    BCHK(hipStreamSynchronize(stream_));
+    // the work list in one copy; stream order puts it before the next
+    // launch, and the staging buffer is next written after the read-back
+    // that follows that launch has been waited for
+    BCHK(hipMemcpyAsync(d_list_, h_list_, list_items_off(max_sys_) + 8 * (size_t)ni, hipMemcpyHostToDevice,
+                        stream_));
+    BCHK(hipEventRecord(ev_up_, stream_));
     tables_dirty_ = false;
     items_ = ni;
     active_ = na;
     return PCG_OK;
 }
 
+template <typename T, bool HEAD>
+static int step_occupancy(int spec)
+{
+    int nb = 0;
+    hipError_t e = hipSuccess;
+    switch (spec) {
+    case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<T, HEAD, 0>, kBatchBlock, 0); break;
+    case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<T, HEAD, 1>, kBatchBlock, 0); break;
+    case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<T, HEAD, 2>, kBatchBlock, 0); break;
+    case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<T, HEAD, 3>, kBatchBlock, 0); break;
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<T, HEAD, 4>, kBatchBlock, 0); break;
+    case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<T, HEAD, 5>, kBatchBlock, 0); break;
+    default:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_batch_step<T, HEAD, kSpecAny>, kBatchBlock, 0);
+        break;
+    }
+    return e == hipSuccess ? nb : 0;
+}
+
+// Blocks of the persistent pass when the caller gave none: as many as the
+// pass kernels keep resident (at most four per CU), so that every block
+// starts at once and the items are shared out evenly.
+int BatchEngine::default_pass_grid() const
+{
+    const int a = prec_ == PCG_FP64 ? step_occupancy<double, false>(spec_) : step_occupancy<float, false>(spec_);
+    const int b = prec_ == PCG_FP64 ? step_occupancy<double, true>(spec_) : step_occupancy<float, true>(spec_);
+    const int per_cu = std::min(4, std::max(1, std::min(a, b)));
+    return per_cu * kNumCU;
+}
+
 void BatchEngine::enqueue_passes(hipStream_t st, int split)
 {
-    BatchTables tb{d_sys_, d_st_, d_item_sys_, d_item_tile_, d_active_, d_counts_, max_sys_, 0};
-    const dim3 pg(pass_grid_), bk(kBatchBlock);
+    BatchTables tb{d_sys_,
+                   d_st_,
+                   reinterpret_cast<const int32_t *>(d_list_),
+                   reinterpret_cast<const uint32_t *>(d_list_ + 16),
+                   reinterpret_cast<const uint2 *>(d_list_ + list_items_off(max_sys_)),
+                   max_sys_,
+                   0};
+    const dim3 pg(pass_grid_ > 0 ? pass_grid_ : default_pass_grid()), bk(kBatchBlock);
     for (int k = 0; k < K_; ++k) {
         const int par = k & 1;
         if (split) {
             hipLaunchKernelGGL(k_batch_trans, dim3(trans_grid_), bk, 0, st, tb, par);
-            if (prec_ == PCG_FP64) hipLaunchKernelGGL((k_batch_step<double, false>), pg, bk, 0, st, tb, par);
-            else hipLaunchKernelGGL((k_batch_step<float, false>), pg, bk, 0, st, tb, par);
+            if (prec_ == PCG_FP64) launch_step<double, false>(spec_, pg, bk, st, tb, par);
+            else launch_step<float, false>(spec_, pg, bk, st, tb, par);
         } else {
-            if (prec_ == PCG_FP64) hipLaunchKernelGGL((k_batch_step<double, true>), pg, bk, 0, st, tb, par);
-            else hipLaunchKernelGGL((k_batch_step<float, true>), pg, bk, 0, st, tb, par);
+            if (prec_ == PCG_FP64) launch_step<double, true>(spec_, pg, bk, st, tb, par);
+            else launch_step<float, true>(spec_, pg, bk, st, tb, par);
         }
     }
 }
@@ -666,6 +742,10 @@ extern "C" pcg_status pcg_batch_solve(int32_t count, const pcg_operator *ops, co
     const int K = opts[0].iters_per_launch;  // 0: the engine default
     if ((st = eng.init(ws, count, items, opts[0].prec, (hipStream_t)hip_stream, K))) return st;
     if (opts[0].grid_blocks) eng.set_pass_grid(opts[0].grid_blocks);
+    int spec = ops[0].kind * 2 + (opts[0].pc == PCG_PC_JACOBI);
+    for (int k = 1; k < count; ++k)
+        if (ops[k].kind * 2 + (opts[k].pc == PCG_PC_JACOBI) != spec) spec = kSpecAny;
+    eng.set_spec(spec);
     std::vector<int> slot(count);
     for (int k = 0; k < count; ++k)
         if ((st = eng.admit(&ops[k], &opts[k], b[k], x[k], ws + offs[k], &slot[k]))) return st;

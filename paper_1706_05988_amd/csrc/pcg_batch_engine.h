@@ -34,6 +34,10 @@ public:
     // tables: device memory of table_bytes(max_sys, max_items), 256-aligned.
     pcg_status init(char *tables, int max_sys, int64_t max_items, int prec, hipStream_t stream, int K);
     void set_pass_grid(int g) { pass_grid_ = g; }
+    // Compile-time operator / preconditioner of the pass kernels (kind * 2 +
+    // jac) when every system that will ever be admitted shares them, else
+    // kSpecAny.  Set before the first step.
+    void set_spec(int spec) { spec_ = spec; }
     pcg_status validate(const pcg_operator *op, const pcg_options *opt);
     // Admit a system whose device region (system_layout bytes) starts at
     // `region`; it joins the batch at the next step.  PCG_ERR_BUDGET when
@@ -54,28 +58,29 @@ private:
     pcg_status upload_tables();
     pcg_status ensure_graph(int split);
     void enqueue_passes(hipStream_t st, int split);
+    int default_pass_grid() const;
 
     int max_sys_ = 0;
     int64_t max_items_ = 0;
     int prec_ = 0;
     int K_ = 8;
-    int pass_grid_ = 1024;   // persistent blocks of the pass (4 per CU)
+    int pass_grid_ = 0;      // persistent blocks of the pass; 0: default_pass_grid()
     int trans_grid_ = 256;
+    int spec_ = kSpecAny;
     // above this many items a launch runs split (measured: the fused head
     // costs ~100 us per pass on a full 512-system batch, the extra kernel ~5 us)
     int64_t split_items_ = 4096;
     hipStream_t stream_ = nullptr;
     BatchSys *d_sys_ = nullptr;
     BatchState *d_st_ = nullptr;
-    uint32_t *d_item_sys_ = nullptr, *d_item_tile_ = nullptr, *d_active_ = nullptr;
-    int32_t *d_counts_ = nullptr;
+    char *d_list_ = nullptr;      // counts, listed systems, (system, tile) items
     std::vector<BatchSys> sys_;
     std::vector<char> in_use_;
     std::vector<char> listed_;   // the system's items are in the device tables
     BatchState *h_st_ = nullptr;  // pinned: admission staging and read-back
-    uint32_t *h_items_ = nullptr; // pinned: item / active table staging
-    int32_t counts_h_[2] = {0, 0};
+    char *h_list_ = nullptr;      // pinned: staging of the work list
     bool tables_dirty_ = true;
+    bool slots_dirty_ = true;     // a slot was admitted or released since the last upload
     int64_t items_ = 0;
     int active_ = 0;
     int launches_ = 0;
@@ -83,6 +88,7 @@ private:
     hipGraph_t graph_[2] = {nullptr, nullptr};
     hipGraphExec_t gexec_[2] = {nullptr, nullptr};
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
+    hipEvent_t ev_up_ = nullptr;  // after the last upload from the staging buffers
 };
 
 }  // namespace pcg
