@@ -537,7 +537,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-max-log10", type=float, default=6.0,
                     help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
-    ap.add_argument("--report", choices=["c3", "small", "tune", "psi"],
+    ap.add_argument("--report", choices=["c3", "small", "tune", "psi", "batch"],
                     help="print a measurement report (C3 accuracy per shift, or the latency-bound cases) and exit")
     ap.add_argument("--c3-N", type=int, default=1024)
     ap.add_argument("--c3-max-iter", type=int, default=12000)
@@ -571,7 +571,8 @@ def main():
     if args.report:
         rep = (report_c3(P, torch, args.c3_N, args.c3_max_iter) if args.report == "c3" else
                report_small(P, torch) if args.report == "small" else
-               report_psi(P, torch) if args.report == "psi" else report_tune(P, torch))
+               report_psi(P, torch) if args.report == "psi" else
+               bench_batched(P, torch) if args.report == "batch" else report_tune(P, torch))
         print(json.dumps(rep), flush=True)
         return
     if args.calib_copy:
