@@ -397,6 +397,46 @@ def report_c3(P, torch, N: int, max_iter: int) -> dict:
     return out
 
 
+def report_c2(P, torch, N: int = 256) -> dict:
+    """The 3-D Poisson problem (N^3, Jacobi, x_true ~ U(-1, 1), x0 = 0):
+    classic CG, p-CG and p-CG-sh in binary64, and p-CG-sh in the FP32-stream
+    form, each to the recursive tolerance 1e-10 with the binary64 explicit
+    check (restarts from x until it holds): iterations, time, iterations/s,
+    time per iteration, algorithmic GB/s and the fraction of 8 TB/s, explicit
+    residual.  Then the attainable accuracy of p-CG and p-CG-sh in both forms:
+    the explicit residual after 1500 iterations with no stop."""
+    import problems
+    p = problems.poisson3d(N, seed=0)
+    n = p.op.n
+    b = torch.from_numpy(p.b).cuda()
+    out = {"workload": f"3-D Poisson 7-point {N}^3 (n={n}), Jacobi, x_true ~ U(-1, 1), x0 = 0", "runs": [],
+           "attainable_after_1500": []}
+    for method, fp32 in (("cg", False), ("pipe", False), ("pipe_shift", False), ("pipe_shift", True)):
+        sig = p.sigma if method == "pipe_shift" else 0.0
+        r = _timed_solve(P, torch, p.op, P.make_options(method=method, jacobi=True, fp32=fp32, sigma=sig, rtol=1e-10,
+                                                        max_iter=5000, replace_max=8, timing=True), b)
+        its = r["iterations"]
+        bytes_it = bytes_per_unknown(method, True, fp32) * n
+        kern_s = r["iter_kernel_ms"] * 1e-3
+        gbs = bytes_it * its / kern_s / 1e9 if kern_s > 0 else float("nan")
+        out["runs"].append({"method": method, "form": "fp32-stream" if fp32 else "fp64", "sigma": sig,
+                            "status": r["status"], "iterations": its, "restarts": r["replacements"],
+                            "true_residual": r["rel_res_true"], "seconds": r["wall_s"],
+                            "iters_per_s": its / r["wall_s"], "us_per_iteration": kern_s * 1e6 / max(1, its),
+                            "bytes_per_iteration": bytes_it, "gbs_algorithmic": gbs,
+                            "frac_of_8TBs": gbs / HBM_PEAK_GBS})
+    for method in ("pipe", "pipe_shift"):
+        for fp32 in (False, True):
+            sig = p.sigma if method == "pipe_shift" else 0.0
+            r = _timed_solve(P, torch, p.op, P.make_options(method=method, jacobi=True, fp32=fp32, sigma=sig,
+                                                            rtol=1e-30, max_iter=1500, true_residual_check=False),
+                             b)
+            out["attainable_after_1500"].append({"method": method, "form": "fp32-stream" if fp32 else "fp64",
+                                                 "status": r["status"], "iterations": r["iterations"],
+                                                 "true_residual": r["rel_res_true"]})
+    return out
+
+
 def report_small(P, torch) -> dict:
     """Latency-bound cases: 2-D Poisson 100x100 (all three methods, to 1e-12)
     and the 1000x1000 Poisson problem of Section 5.2 (b = A*1, x0 = 0, to
@@ -537,7 +577,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=200)
     ap.add_argument("--serving-max-log10", type=float, default=6.0,
                     help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
-    ap.add_argument("--report", choices=["c3", "small", "tune", "psi", "batch"],
+    ap.add_argument("--report", choices=["c2", "c3", "small", "tune", "psi", "batch"],
                     help="print a measurement report (C3 accuracy per shift, or the latency-bound cases) and exit")
     ap.add_argument("--c3-N", type=int, default=1024)
     ap.add_argument("--c3-max-iter", type=int, default=12000)
@@ -572,7 +612,8 @@ def main():
         rep = (report_c3(P, torch, args.c3_N, args.c3_max_iter) if args.report == "c3" else
                report_small(P, torch) if args.report == "small" else
                report_psi(P, torch) if args.report == "psi" else
-               bench_batched(P, torch) if args.report == "batch" else report_tune(P, torch))
+               bench_batched(P, torch) if args.report == "batch" else
+               report_c2(P, torch, args.N) if args.report == "c2" else report_tune(P, torch))
         print(json.dumps(rep), flush=True)
         return
     if args.calib_copy:
