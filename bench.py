@@ -367,7 +367,9 @@ def report_c3(P, torch, N: int, max_iter: int) -> dict:
     """2-D anisotropic diffusion (CSR), Jacobi: attainable explicit residual
     per storage form and shift sigma in {0, lambda_min estimate, midpoint 1,
     lambda_max bound 2}, running to the iteration cap with no stop; plus the
-    iteration rate and effective bandwidth of each form."""
+    iteration rate and effective bandwidth of each form, and solves to 1e-10
+    and 1e-13 with the explicit check in both forms (the FP32-stream one
+    refined by restarts from the binary64 x)."""
     import problems
     p = problems.anisotropic_csr(N, seed=0)
     b = torch.from_numpy(p.b).cuda()
@@ -394,6 +396,17 @@ def report_c3(P, torch, N: int, max_iter: int) -> dict:
                                 "true_residual": r["rel_res_true"],
                                 "iters_per_s": r["iterations"] / r["wall_s"],
                                 "gbs_algorithmic": bytes_it * r["iter_passes"] / (r["iter_kernel_ms"] * 1e-3) / 1e9})
+    # solves with the binary64 explicit check at sigma = 1: the FP32-stream
+    # form restarts from the binary64 x until the explicit residual holds
+    # (iterative refinement), against the all-binary64 form
+    out["refinement"] = []
+    for rtol in (1e-10, 1e-13):
+        for fp32 in (False, True):
+            r = _timed_solve(P, torch, p.op, P.make_options(method="pipe_shift", jacobi=True, fp32=fp32, sigma=1.0,
+                                                            rtol=rtol, max_iter=60000, replace_max=40), b)
+            out["refinement"].append({"form": "fp32-stream" if fp32 else "fp64", "rtol": rtol, "status": r["status"],
+                                      "iterations": r["iterations"], "restarts": r["replacements"],
+                                      "true_residual": r["rel_res_true"], "seconds": r["wall_s"]})
     return out
 
 

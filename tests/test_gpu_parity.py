@@ -192,6 +192,27 @@ def test_fp32_stream_csr(torch):
     assert g["rel_res_true"] <= 10 * o["rel_res_true"]
 
 
+def test_fp32_stream_refinement_reaches_fp64_oracle_attainable_csr(torch):
+    """The C3 recipe at 96^2 (anisotropic CSR, Jacobi, sigma = 1): the
+    FP32-stream form alone stalls near binary32 accuracy, but restarting
+    from the binary64 x whenever the binary64 explicit residual misses the
+    tolerance (iterative refinement) ends within 10x of the attainable
+    accuracy of the oracle's all-binary64 run (its explicit residual after it
+    has stagnated)."""
+    p = problems.anisotropic_csr(96, seed=3)
+    o = oracle_solve(p, "pipe_shift", sigma=1.0, rtol=1e-30, max_iter=4000, ignore_breakdown=True)
+    level = o["rel_res_true"]
+    assert level < 1e-13
+    alone = gpu_solve(torch, p, "pipe_shift", fp32=True, sigma=1.0, rtol=1e-30, max_iter=4000,
+                      true_residual_check=False, hist=False)
+    assert alone["rel_res_true"] > 100 * level  # binary32 storage alone cannot get there
+    g = gpu_solve(torch, p, "pipe_shift", fp32=True, sigma=1.0, rtol=5 * level, max_iter=40000, replace_max=40,
+                  hist=False)
+    assert g["status"] == "converged", (g["status"], g["rel_res_true"], level)
+    assert g["replacements"] >= 1
+    assert g["rel_res_true"] <= 10 * level, (g["rel_res_true"], level)
+
+
 # ---------------------------------------------------------------- identities, determinism
 
 def test_shift_zero_equals_pipe_bitwise_on_gpu(torch):
