@@ -196,6 +196,16 @@ def bench_batched(P, torch, count: int = 512, seed: int = 0) -> dict:
                            replace_max=8) for p in ps]
     B = P.Batch([p.op for p in ps], opts)
     B.solve(bs, xs)  # warm-up (graph capture, first touch)
+    # the default launch shape, then the autotuner's (tuning outside the timed region)
+    for x in xs:
+        x.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.solve(bs, xs)
+    torch.cuda.synchronize()
+    t_default = time.perf_counter() - t0
+    x0s = [torch.zeros_like(b) for b in bs]
+    shape = B.tune(bs, x0s, xs)
     for x in xs:
         x.zero_()
     torch.cuda.synchronize()
@@ -221,6 +231,9 @@ def bench_batched(P, torch, count: int = 512, seed: int = 0) -> dict:
                     f"sum n = {sum(p.op.n for p in ps)}, FP32-stream shifted p-CG sigma = 4 + c to 1e-8",
         "solves_per_s": count / t_batch,
         "seconds": t_batch,
+        "launch_shape": {"grid_blocks": shape["grid_blocks"], "passes_per_launch": shape["iters_per_launch"],
+                         "tuned_by": "pcg_batch_tune"},
+        "default_shape_solves_per_s": count / t_default,
         "converged": int(sum(r["status"] == "converged" for r in res)),
         "max_true_residual": float(max(r["rel_res_true"] for r in res)),
         "iterations_min_median_max": [int(its.min()), int(np.median(its)), int(its.max())],

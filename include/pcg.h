@@ -252,17 +252,41 @@ pcg_status pcg_tune(const pcg_operator *op, pcg_options *opt, void *workspace, s
 /*
  * Solve `count` independent systems A_k x_k = b_k in ONE persistent pass per
  * iteration (every active system advances one phase or iteration per pass).
- * ops[k], opts[k]: per-system operator and options; all systems must share
- * method, pc and prec (the shape parameters of opts[0] are used).  b[k], x[k]:
- * host arrays of device pointers.  Per-system results in results[k].  Each
- * system's arithmetic -- tiling, reduction order -- depends only on that
- * system, so its result does not depend on what else is in the batch.
+ * ops[k], opts[k]: per-system operator and options.  All systems must share
+ * the precision and use PCG_PIPE or PCG_PIPE_SHIFT; operator kind and
+ * preconditioner may differ (a batch whose systems all share them runs pass
+ * kernels compiled for that pair).  The launch shape comes from opts[0]:
+ * grid_blocks (0: as many blocks as the pass kernels keep resident, at most
+ * 4 per CU) and iters_per_launch (0: 32).  b[k], x[k]: host arrays of device
+ * pointers.  Per-system results in results[k].  Each system's arithmetic --
+ * tiling, reduction order -- depends only on that system, so its result does
+ * not depend on what else is in the batch nor on the launch shape.
  */
 pcg_status pcg_batch_workspace_size(int32_t count, const pcg_operator *ops, const pcg_options *opts,
                                     size_t *bytes);
 pcg_status pcg_batch_solve(int32_t count, const pcg_operator *ops, const pcg_options *opts,
                            const double *const *b, double *const *x, pcg_result *results,
                            void *workspace, size_t bytes, void *hip_stream);
+
+/*
+ * Launch-shape autotuner of the batched pass.  Times complete pcg_batch_solve
+ * calls on the caller's batch for every persistent grid of 1, 2, 3 or 4
+ * blocks per CU and every graph length K of 16, 32 or 64 passes (each
+ * candidate twice, its faster host wall time counting), and writes the
+ * fastest into opts[0].grid_blocks and opts[0].iters_per_launch; *best_ms
+ * (host, may be NULL) receives its solve time.  x0[k]: device initial guesses
+ * (n_k binary64, read only), copied into x[k] before every candidate solve;
+ * x[k]: device scratch, overwritten (it holds a solution on return).
+ * workspace, bytes, hip_stream: as for pcg_batch_solve.  With PCG_TUNE_CACHE
+ * naming a file, the result is looked up there first (key: precision, count
+ * and a hash of every system's operator kind, sizes, nnz, preconditioner and
+ * method) and a new one appended.  Errors: PCG_ERR_INVALID for null or
+ * aliased pointers and a short workspace, otherwise as pcg_batch_solve.
+ * opts is changed only on success.
+ */
+pcg_status pcg_batch_tune(int32_t count, const pcg_operator *ops, pcg_options *opts, const double *const *b,
+                          const double *const *x0, double *const *x, void *workspace, size_t bytes,
+                          void *hip_stream, double *best_ms);
 
 /* ---------------------------------------------------------------- serving */
 

@@ -1,4 +1,5 @@
-// pcg_tune.hip -- launch-shape autotuner with an on-disk cache (pcg_tune*).
+// pcg_tune.hip -- launch-shape autotuners with an on-disk cache (pcg_tune*,
+// pcg_batch_tune).
 //
 // Host code on top of the public entry points: every candidate shape runs a
 // short probe (8 passes) that sizes its timed run to about 3 ms of passes
@@ -168,5 +169,85 @@ extern "C" pcg_status pcg_tune(const pcg_operator *op, pcg_options *opt, void *w
     opt->block_size = best.block;
     opt->grid_blocks = best.grid;
     if (best_us) *best_us = best_t;
+    return PCG_OK;
+}
+
+// ------------------------------------------------------------ batched pass
+
+namespace {
+
+constexpr int kBatchK[3] = {16, 32, 64};
+
+// FNV-1a over the systems' operator kinds, sizes and preconditioners
+std::string batch_key(int32_t count, const pcg_operator *ops, const pcg_options *opts)
+{
+    uint64_t h = 1469598103934665603ull;
+    auto mix = [&](int64_t v) {
+        for (int k = 0; k < 8; ++k) {
+            h ^= (uint64_t)((v >> (8 * k)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    for (int k = 0; k < count; ++k) {
+        mix(ops[k].kind);
+        mix(ops[k].n);
+        mix(ops[k].nx);
+        mix(ops[k].ny);
+        mix(ops[k].nz);
+        mix(ops[k].kind == PCG_OP_CSR ? ops[k].nnz : 0);
+        mix(opts[k].pc);
+        mix(opts[k].method);
+    }
+    char buf[96];
+    std::snprintf(buf, sizeof(buf), "batch_p%d_c%d_%016llx", opts[0].prec, count, (unsigned long long)h);
+    return buf;
+}
+
+}  // namespace
+
+extern "C" pcg_status pcg_batch_tune(int32_t count, const pcg_operator *ops, pcg_options *opts,
+                                     const double *const *b, const double *const *x0, double *const *x,
+                                     void *workspace, size_t bytes, void *hip_stream, double *best_ms)
+{
+    if (count < 1 || !ops || !opts || !b || !x0 || !x)
+        return invalid("count >= 1 and non-null ops, opts, b, x0 and x are required");
+    for (int k = 0; k < count; ++k)
+        if (!x0[k] || !x[k] || x0[k] == x[k]) return invalid("x0[k] and x[k] must be non-null and distinct");
+    size_t need = 0;
+    pcg_status st = pcg_batch_workspace_size(count, ops, opts, &need);
+    if (st) return st;
+    if (bytes < need) return invalid("workspace smaller than pcg_batch_workspace_size");
+    const std::string key = batch_key(count, ops, opts);
+    Shape best{};  // variant: graph length K; grid: persistent blocks
+    double best_t = 0.0;
+    if (!cache_lookup(key, &best, &best_t)) {
+        std::vector<pcg_options> o(opts, opts + count);
+        std::vector<pcg_result> res(count);
+        const hipStream_t s = (hipStream_t)hip_stream;
+        best_t = INFINITY;
+        for (int per_cu = 1; per_cu <= 4; ++per_cu)
+            for (int K : kBatchK) {
+                o[0].grid_blocks = per_cu * kNumCU;
+                o[0].iters_per_launch = K;
+                double t = INFINITY;
+                for (int rep = 0; rep < 2; ++rep) {
+                    for (int k = 0; k < count; ++k)
+                        if (hipMemcpyAsync(x[k], x0[k], sizeof(double) * (size_t)ops[k].n, hipMemcpyDeviceToDevice,
+                                           s) != hipSuccess)
+                            return PCG_ERR_HIP;
+                    if ((st = pcg_batch_solve(count, ops, o.data(), b, x, res.data(), workspace, bytes, hip_stream)))
+                        return st;
+                    t = std::fmin(t, res[0].seconds * 1e3);
+                }
+                if (t < best_t) {
+                    best_t = t;
+                    best = Shape{K, 0, per_cu * kNumCU};
+                }
+            }
+        cache_store(key, best, best_t);
+    }
+    opts[0].grid_blocks = best.grid;
+    opts[0].iters_per_launch = best.variant;
+    if (best_ms) *best_ms = best_t;
     return PCG_OK;
 }

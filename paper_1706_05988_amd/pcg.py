@@ -79,6 +79,9 @@ _SIGS = {
     "pcg_batch_solve": (C.c_int32, [C.c_int32, C.POINTER(pcg_operator), C.POINTER(pcg_options),
                                     C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(pcg_result),
                                     C.c_void_p, C.c_size_t, C.c_void_p]),
+    "pcg_batch_tune": (C.c_int32, [C.c_int32, C.POINTER(pcg_operator), C.POINTER(pcg_options),
+                                   C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.c_void_p, C.c_size_t, C.c_void_p, C.POINTER(C.c_double)]),
     "pcg_server_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p]),
     "pcg_submit": (C.c_int32, [C.c_void_p, C.POINTER(pcg_operator), C.POINTER(pcg_options), C.c_void_p,
                                C.c_void_p, C.POINTER(C.c_uint64)]),
@@ -184,6 +187,20 @@ def pcg_batch_solve(ops, opts, b_ptrs, x_ptrs, workspace: int, nbytes: int, stre
     R = (pcg_result * k)()
     _check(lib().pcg_batch_solve(k, OA, PA, BA, XA, R, workspace, nbytes, stream), "pcg_batch_solve")
     return list(R)
+
+
+def pcg_batch_tune(ops, opts, b_ptrs, x0_ptrs, x_ptrs, workspace: int, nbytes: int, stream: int) -> float:
+    """Launch-shape autotuner of the batched pass: writes the fastest grid and
+    graph length into opts[0] (grid_blocks, iters_per_launch); returns the
+    winning solve time in ms.  x_ptrs are scratch, x0_ptrs the initial guesses."""
+    k = len(ops)
+    OA, PA = (pcg_operator * k)(*ops), (pcg_options * k)(*opts)
+    BA, X0, XA = (C.c_void_p * k)(*b_ptrs), (C.c_void_p * k)(*x0_ptrs), (C.c_void_p * k)(*x_ptrs)
+    best = C.c_double()
+    _check(lib().pcg_batch_tune(k, OA, PA, BA, X0, XA, workspace, nbytes, stream, C.byref(best)), "pcg_batch_tune")
+    opts[0].grid_blocks = PA[0].grid_blocks
+    opts[0].iters_per_launch = PA[0].iters_per_launch
+    return best.value
 
 
 def pcg_server_create(arena: int, nbytes: int, max_slots: int, stream: int) -> int:
@@ -459,6 +476,14 @@ class Batch:
         res = pcg_batch_solve(self.structs, self.opts, [b.data_ptr() for b in bs], [x.data_ptr() for x in xs],
                               self.ws_ptr, self.nbytes, st)
         return [result_dict(r, h) for r, h in zip(res, self.hists)]
+
+    def tune(self, bs, x0s, xs, stream: Optional[int] = None) -> dict:
+        """pcg_batch_tune on this batch; later solves use the chosen shape."""
+        st = current_stream_handle() if stream is None else stream
+        ms = pcg_batch_tune(self.structs, self.opts, [b.data_ptr() for b in bs], [x.data_ptr() for x in x0s],
+                            [x.data_ptr() for x in xs], self.ws_ptr, self.nbytes, st)
+        return {"grid_blocks": self.opts[0].grid_blocks, "iters_per_launch": self.opts[0].iters_per_launch,
+                "solve_ms": ms}
 
 
 class Server:

@@ -200,3 +200,22 @@ def test_tune_rejects_bad_arguments_before_device_work():
         P.PCG_ERR_INVALID
     assert P.lib().pcg_tune(C.byref(op), C.byref(o), fake, 16, fake, fake + 8, None, C.byref(us)) == \
         P.PCG_ERR_INVALID
+
+
+def test_batch_tune_rejects_bad_arguments_before_device_work():
+    """Null arrays, an x0 aliasing its x and a too-small workspace are
+    PCG_ERR_INVALID, found before any device call (the pointers passed here
+    are not device memory)."""
+    import ctypes as C
+    op = stencil_op()
+    o = P.make_options(method="pipe_shift", fp32=True)
+    OA, PA = (P.pcg_operator * 1)(op), (P.pcg_options * 1)(o)
+    fake = 4096
+    B, X0, X = (C.c_void_p * 1)(fake), (C.c_void_p * 1)(fake + 8), (C.c_void_p * 1)(fake + 16)
+    ms = C.c_double()
+    L = P.lib()
+    assert L.pcg_batch_tune(0, OA, PA, B, X0, X, fake, 1 << 40, None, C.byref(ms)) == P.PCG_ERR_INVALID
+    assert L.pcg_batch_tune(1, OA, PA, B, None, X, fake, 1 << 40, None, C.byref(ms)) == P.PCG_ERR_INVALID
+    assert L.pcg_batch_tune(1, OA, PA, B, X, X, fake, 1 << 40, None, C.byref(ms)) == P.PCG_ERR_INVALID
+    assert L.pcg_batch_tune(1, OA, PA, B, X0, X, fake, 16, None, C.byref(ms)) == P.PCG_ERR_INVALID
+    assert PA[0].grid_blocks == 0 and PA[0].iters_per_launch == 0  # unchanged on error

@@ -145,3 +145,45 @@ def test_batch_status_edge_cases(torch):
     res = run_batch(torch, ps)
     assert res[1]["status"] == "max_iter" and res[1]["iterations"] == 5
     assert res[0]["status"] == "converged" and res[2]["status"] == "converged"
+
+
+def test_batch_tune_picks_a_candidate_caches_it_and_keeps_the_bits(torch, tmp_path, monkeypatch):
+    """pcg_batch_tune times every candidate (1..4 blocks per CU x 16/32/64
+    passes per launch) on the caller's batch, writes the fastest into the
+    options and the cache file, and a second call reads it back without
+    measuring.  A solve with the chosen shape gives the same bits as one with
+    the default shape: a system's tiling and reduction order do not depend on
+    the grid or the graph length."""
+    from paper_1706_05988_amd import pcg as P
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("PCG_TUNE_CACHE", str(cache))
+    ps = problems.batch_rectangles(24, seed=7, side_min=16, side_max=96)
+
+    def make():
+        opts = [opts_for(P, p, fp32=True, hist=False, rtol=1e-8, max_iter=5000, replace_max=8) for p in ps]
+        return P.Batch([p.op for p in ps], opts)
+
+    bs = [torch.from_numpy(p.b).cuda() for p in ps]
+    x0s = [torch.from_numpy(p.x0).cuda() for p in ps]
+    xs = [torch.empty_like(x) for x in x0s]
+    B = make()
+    t = B.tune(bs, x0s, xs)
+    torch.cuda.synchronize()
+    assert t["grid_blocks"] in (256, 512, 768, 1024) and t["iters_per_launch"] in (16, 32, 64)
+    assert t["solve_ms"] > 0
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("batch_p1_c24_")
+    B2 = make()
+    t2 = B2.tune(bs, x0s, xs)
+    assert (t2["grid_blocks"], t2["iters_per_launch"]) == (t["grid_blocks"], t["iters_per_launch"])
+    assert len(cache.read_text().splitlines()) == 1
+    # tuned shape against the default shape
+    ys = [x.clone() for x in x0s]
+    tuned = B.solve(bs, ys)
+    zs = [x.clone() for x in x0s]
+    default = make().solve(bs, zs)
+    torch.cuda.synchronize()
+    for k in range(len(ps)):
+        assert tuned[k]["status"] == default[k]["status"] == "converged"
+        assert tuned[k]["iterations"] == default[k]["iterations"]
+        assert torch.equal(ys[k], zs[k])
