@@ -285,10 +285,20 @@ def bench_serving(P, torch, count: int, log10_max: float, seed: int = 0) -> dict
         b = torch.from_numpy(rng.uniform(-1.0, 1.0, pool[(lv, kind)].n)).cuda()
         reqs.append((dev32[(lv, kind)], b))
     arena = int(16 << 30)
+    shape = {"grid_blocks": 0, "iters_per_launch": 0}
 
     def opts():
-        return P.make_options(method="pipe_shift", jacobi=True, fp32=True, sigma=1.0, rtol=1e-8,
-                              max_iter=20000, replace_max=8)
+        o = P.make_options(method="pipe_shift", jacobi=True, fp32=True, sigma=1.0, rtol=1e-8,
+                           max_iter=20000, replace_max=8)
+        o.grid_blocks, o.iters_per_launch = shape["grid_blocks"], shape["iters_per_launch"]
+        return o
+
+    # launch shape of the server: pcg_batch_tune on a sample of the request mix
+    sample = list(range(min(48, count)))
+    tb = P.Batch([reqs[k][0] for k in sample], [opts() for _ in sample])
+    x0s = [torch.zeros_like(reqs[k][1]) for k in sample]
+    shape.update(tb.tune([reqs[k][1] for k in sample], x0s, [torch.zeros_like(x) for x in x0s]))
+    del tb, x0s
 
     def run(arrivals):
         srv = P.Server(arena, max_slots=512)
@@ -334,6 +344,8 @@ def bench_serving(P, torch, count: int, log10_max: float, seed: int = 0) -> dict
                     f"half 3-D 7-point cubes, half banded CSR (7-27 nnz/row), Jacobi, sigma = 1, "
                     f"FP32-stream shifted p-CG to 1e-8",
         "capacity_solves_per_s": capacity,
+        "launch_shape": {"grid_blocks": shape["grid_blocks"], "passes_per_launch": shape["iters_per_launch"],
+                         "tuned_by": f"pcg_batch_tune on the first {len(sample)} requests"},
         "arrival_rate_hz": rate,
         "solves_per_s": count / t_live,
         "p50_latency_s": _pct(lat, 50),

@@ -298,6 +298,10 @@ typedef struct pcg_server_ *pcg_server;
  * each admitted request's Krylov vectors; requests wait until their footprint
  * and a slot (max_slots) are free, and join the running batch at the next
  * launch boundary.  A scheduler thread owned by the server drives the device.
+ * Every request must use the precision of the first one, whose options also
+ * fix the launch shape of the whole run: grid_blocks (0: the pass kernels'
+ * resident blocks, at most 4 per CU) and iters_per_launch (0: 32), e.g. as
+ * pcg_batch_tune chose them on a sample of the expected requests.
  */
 pcg_status pcg_server_create(pcg_server *server, void *arena, size_t arena_bytes, int32_t max_slots,
                              void *hip_stream);

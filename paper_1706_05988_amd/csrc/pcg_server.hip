@@ -239,7 +239,11 @@ extern "C" pcg_status pcg_submit(pcg_server s, const pcg_operator *op, const pcg
         // bind the engine's precision to the first request (nothing runs yet)
         s->eng.reset(new BatchEngine());
         const int64_t max_items = (int64_t)(s->arena_bytes / (16 * 1024)) + s->max_slots;
-        if ((st = s->eng->init(s->arena, s->max_slots, max_items, opt->prec, s->stream, 0))) return st;
+        // the launch shape of the whole run comes from the first request
+        // (0: the engine's defaults), e.g. from pcg_batch_tune on a sample
+        if ((st = s->eng->init(s->arena, s->max_slots, max_items, opt->prec, s->stream, opt->iters_per_launch)))
+            return st;
+        if (opt->grid_blocks) s->eng->set_pass_grid(opt->grid_blocks);
         s->prec = opt->prec;
     } else if (opt->prec != s->prec) {
         return invalid("every request of a server must use the precision of its first request");
