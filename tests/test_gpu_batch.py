@@ -58,12 +58,12 @@ def test_batch_matches_oracle_fp64(torch):
                          jacobi=p.jacobi)
         assert g["status"] == o["status"] == "converged", p.name
         assert abs(g["iterations"] - o["iterations"]) <= 2, p.name
-        k = min(40, o["iterations"], g["iterations"])
+        k = min(50, o["iterations"], g["iterations"])
         below = np.nonzero(o["res"][: k + 1] < 1e-12)[0]
         if below.size:
             k = max(1, int(below[0]) - 1)
-        np.testing.assert_allclose(g["res"][: k + 1], o["res"][: k + 1], rtol=1e-9, err_msg=p.name)
-        assert g["rel_res_true"] <= max(2 * o["rel_res_true"], 1e-11), p.name
+        np.testing.assert_allclose(g["res"][: k + 1], o["res"][: k + 1], rtol=1e-10, err_msg=p.name)
+        assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-12, p.name
 
 
 def test_batch_result_independent_of_batch_mix(torch):

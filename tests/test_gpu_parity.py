@@ -132,8 +132,8 @@ def test_csr_anisotropic_jacobi(torch, method):
     o = oracle_solve(p, method)
     assert g["status"] == o["status"]
     assert abs(g["iterations"] - o["iterations"]) <= 2
-    check_history(g, o, upto=30, rtol=1e-9)
-    assert g["rel_res_true"] <= max(10 * o["rel_res_true"], 1e-9)
+    check_history(g, o)
+    assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-12
 
 
 @pytest.mark.parametrize("method", ["cg", "pipe_shift"])
@@ -450,8 +450,8 @@ def test_variable_shift_history_and_solution(torch, prob):
     o = oracle_solve(p, "pipe_var", sigma_schedule=sched)
     assert g["status"] == o["status"] == "converged"
     assert abs(g["iterations"] - o["iterations"]) <= 2
-    check_history(g, o, upto=30 if prob == "csr_jacobi" else 50, rtol=1e-9 if prob == "csr_jacobi" else 1e-10)
-    assert g["rel_res_true"] <= max(10 * o["rel_res_true"], 1e-10)
+    check_history(g, o)
+    assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-12
     assert g["sigma"] == sched[min(g["iterations"], len(sched) - 1)]
 
 
@@ -531,7 +531,7 @@ def test_pcg_rr_history_replacements_and_accuracy(torch, prob):
         assert g["iterations"] == o["iterations"]
     assert g["replacements"] >= 1
     assert abs(g["replacements"] - o["replacements"]) <= 1
-    check_history(g, o, upto=30, rtol=1e-9)
+    check_history(g, o)
     assert g["rel_res_true"] <= max(10 * o["rel_res_true"], 1e-14)
 
 
