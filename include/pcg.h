@@ -168,6 +168,9 @@ typedef struct {
 #define PCG_VAR_NT       0x04   /* non-temporal hint on the once-touched streams        */
 #define PCG_VAR_EPT1     0x10   /* 1 unknown per thread per tile (default 2)            */
 #define PCG_VAR_EPT4     0x20   /* 4 unknowns per thread per tile                       */
+#define PCG_VAR_CG_ZMARCH 0x40  /* PCG_CG, 3-D stencil: pass A marches along z through
+                                   LDS also where the built-in rule would not (grids
+                                   with fewer work items than CUs)                      */
 
 typedef struct {
     int32_t status;             /* PCG_CONVERGED .. PCG_NONFINITE                         */

@@ -28,6 +28,7 @@ struct LaunchShape {
     int xcd_map;  // XCD-slab tile order on/off
     int nt;       // non-temporal streams on/off
     int K;        // iterations per graph launch
+    int zm_rows, zm_seg, zm_nchunks, zm_nsegs;  // CG pass A z-marching split (zm_rows = 0: plain)
 };
 
 // byte offsets into the caller's workspace (SIZE_MAX: absent)

@@ -38,6 +38,13 @@ namespace pcg {
 // init-0 clear mask
 enum ClearBits : uint32_t { CLR_Z = 1, CLR_Q = 2, CLR_S = 4, CLR_T = 8, CLR_P = 16, CLR_WIN = 32 };
 
+// Work split of the z-marching CG pass A on a 3-D grid: a work item is
+// `rows` consecutive grid rows (y) of a plane over `seg` consecutive planes
+// (z); nchunks * nsegs items.  rows = 0: the plain pass A.
+struct CgZm {
+    int32_t rows, seg, nchunks, nsegs;
+};
+
 template <typename T>
 struct PassArgs {
     OpDev<T> A;
@@ -71,6 +78,7 @@ struct PassArgs {
     int32_t rr_period;    // residual replacement: gap check every rr_period iterations
     double rr_tau;        // ... replace when ||f|| > rr_tau ||r||
     double rr_floor;      // ... and ||f|| > rr_floor * 2^-53 || |A||x| + |b| ||
+    CgZm zm;              // CG pass A on a 3-D grid: z-marching split (rows = 0: plain)
 };
 
 template <typename V, typename T>
@@ -797,22 +805,23 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_init1(PassArgs<T> a)
     store_partial<2>(a.part_out, acc);
 }
 
-// Pass A of CG iteration i.  w_in = p_{i-1}, w_out = p_i.
-template <typename T, int OP, bool JAC, int EPT, bool NT>
-__global__ void __launch_bounds__(kMaxBlock) k_cg_a(PassArgs<T> a)
+// Head of CG pass A: stage 2 of (r_i, u_i) and (r_i, r_i), the stop test
+// and beta_i; block 0's state and history record.  false when the
+// iteration has ended.
+template <typename T>
+__device__ __forceinline__ bool cg_a_head(const PassArgs<T> &a, double *lds_red, double &beta)
 {
-    __shared__ double lds_red[kMaxWaves * kFields];
     const DevState *S = a.st_in;
     if (S->status != RUNNING) {
         if (state_writer()) copy_state(a.st_out, S);
-        return;
+        return false;
     }
     double tot[2];
     stage2<2>(a.part_in, a.nparts, tot, lds_red);
     const double gamma = tot[0], rho = tot[1];
     const int i = S->iter;
     int status = RUNNING;
-    double beta = 0.0;
+    beta = 0.0;
     if (!isfinite(gamma) || !isfinite(rho)) {
         status = ST_NONFINITE;
     } else if (sqrt(rho) <= a.rtol * sqrt(S->bnorm2)) {
@@ -833,14 +842,34 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_a(PassArgs<T> a)
         write_hist(a.hist, a.hist_cap, i, sqrt(rho / S->bnorm2), __builtin_nan(""),
                    status == RUNNING ? beta : __builtin_nan(""), gamma, __builtin_nan(""));
     }
-    if (status != RUNNING) return;
+    return status == RUNNING;
+}
+
+// p_i = M^{-1} r_i + beta_i p_{i-1} at index k, as stored (p_{-1} = 0 after
+// the init, so the first iteration needs no branch)
+template <typename T, bool JAC, int OP>
+__device__ __forceinline__ double cg_pnew_of(const PassArgs<T> &a, uint32_t k, double rk, double pk, double beta)
+{
+    const double uk = rnd<T>(minv<T, JAC, OP>(a, k, rk));
+    return rnd<T>(uk + beta * pk);
+}
+
+template <typename T, bool JAC, int OP>
+__device__ __forceinline__ double cg_pnew(const PassArgs<T> &a, uint32_t k, double beta)
+{
+    return cg_pnew_of<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_r, k), 0), ld(vp<T>(a, a.off_win, k), 0), beta);
+}
+
+// Pass A of CG iteration i.  w_in = p_{i-1}, w_out = p_i.
+template <typename T, int OP, bool JAC, int EPT, bool NT>
+__global__ void __launch_bounds__(kMaxBlock) k_cg_a(PassArgs<T> a)
+{
+    __shared__ double lds_red[kMaxWaves * kFields];
+    double beta;
+    if (!cg_a_head<T>(a, lds_red, beta)) return;
 
     // p_i at index k, recomputed identically wherever it is needed
-    // (p_{-1} = 0 after the init, so the first iteration needs no branch)
-    auto pnew = [&](uint32_t k) {
-        const double uk = rnd<T>(minv<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_r, k), 0)));
-        return rnd<T>(uk + beta * ld(vp<T>(a, a.off_win, k), 0));
-    };
+    auto pnew = [&](uint32_t k) { return cg_pnew<T, JAC, OP>(a, k, beta); };
     double acc[1] = {0.0};
     const uint32_t n = (uint32_t)a.A.n;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
@@ -860,6 +889,92 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_a(PassArgs<T> a)
             sts<NT>(vp<T>(a, a.off_s, ti.e[j]), sv);
             acc[0] += sv * pe[j];
         }
+    }
+    block_sum<1>(acc, lds_red);
+    store_partial<1>(a.part_out, acc);
+}
+
+// Pass A of CG iteration i on the 7-point stencil, marching along z.  For
+// each plane of its item a block forms p_i once per point -- over its rows
+// and one halo row on either side -- into one of four LDS plane slots
+// (extern shared: 4 x (rows + 2) x nx doubles), writes its own rows' p_i,
+// and after one barrier evaluates s = A p_i on the plane before it, from
+// that plane and its two neighbours in LDS.  The plain pass forms p_i anew
+// at each of the seven points of every row (14 loads per unknown); this
+// one loads r and p_{i-1} about (rows + 2) / rows times per unknown.  Four
+// slots need one barrier per plane: filling plane z + 2 never overwrites a
+// plane that s of plane z still reads.  The values and the order of every
+// sum are those of k_cg_a (apply_row reads its operands through the LDS
+// window); only the partial sums are grouped differently.
+template <typename T, bool JAC, bool NT>
+__global__ void __launch_bounds__(kMaxBlock) k_cg_a_zm(PassArgs<T> a, CgZm zm)
+{
+    __shared__ double lds_red[kMaxWaves * kFields];
+    extern __shared__ double zlds[];
+    double beta;
+    if (!cg_a_head<T>(a, lds_red, beta)) return;
+    const uint32_t nx = (uint32_t)a.A.nx, ny = (uint32_t)a.A.ny, nz = (uint32_t)a.A.nz, nxy = nx * ny;
+    const uint32_t slot = (uint32_t)(zm.rows + 2) * nx;
+    double acc[1] = {0.0};
+    const int nitems = zm.nchunks * zm.nsegs;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+        const uint32_t r0 = (uint32_t)(item % zm.nchunks) * (uint32_t)zm.rows;
+        const uint32_t r1 = min(r0 + (uint32_t)zm.rows, ny);
+        const uint32_t z0 = (uint32_t)(item / zm.nchunks) * (uint32_t)zm.seg;
+        const uint32_t z1 = min(z0 + (uint32_t)zm.seg, nz);
+        // window row w holds grid row r0 - 1 + w; rows outside the grid stay unfilled
+        const uint32_t wr0 = r0 > 0 ? r0 - 1 : 0, wr1 = min(r1 + 1, ny);
+        const uint32_t own0 = (r0 - wr0) * nx, own1 = (r1 - wr0) * nx;  // own rows, relative to wr0
+        // the loads of kZmBatch points per thread go out before any store
+        // (the stores could alias them as far as the compiler knows)
+        constexpr int kZmBatch = 8;
+        auto fill = [&](uint32_t zz) {
+            double *buf = zlds + (size_t)(zz & 3u) * slot + (size_t)(wr0 + 1 - r0) * nx;
+            const uint32_t cnt = (wr1 - wr0) * nx, g0 = zz * nxy + wr0 * nx;
+            const bool own = zz >= z0 && zz < z1;
+            for (uint32_t t0 = threadIdx.x; t0 < cnt; t0 += kZmBatch * blockDim.x) {
+                double rv[kZmBatch], pv[kZmBatch];
+#pragma unroll
+                for (int j = 0; j < kZmBatch; ++j) {
+                    const uint32_t k = g0 + min(t0 + j * blockDim.x, cnt - 1);  // in bounds
+                    rv[j] = ld(vp<T>(a, a.off_r, k), 0);
+                    pv[j] = ld(vp<T>(a, a.off_win, k), 0);
+                }
+#pragma unroll
+                for (int j = 0; j < kZmBatch; ++j) {
+                    const uint32_t t = t0 + j * blockDim.x;
+                    if (t >= cnt) continue;
+                    const double p = cg_pnew_of<T, JAC, OP_3D7>(a, g0 + t, rv[j], pv[j], beta);
+                    buf[t] = p;
+                    if (own && t >= own0 && t < own1) sts<NT>(vp<T>(a, a.off_wout, g0 + t), p);
+                }
+            }
+        };
+        if (z0 > 0) fill(z0 - 1);
+        fill(z0);
+        for (uint32_t z = z0; z < z1; ++z) {
+            if (z + 1 < nz) fill(z + 1);
+            __syncthreads();
+            const double *cur = zlds + (size_t)(z & 3u) * slot;
+            const double *prv = zlds + (size_t)((z + 3u) & 3u) * slot;
+            const double *nxt = zlds + (size_t)((z + 1u) & 3u) * slot;
+            const uint32_t cnt = (r1 - r0) * nx, g0 = z * nxy + r0 * nx;
+            for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+                const uint32_t e = g0 + t, w = nx + t;  // grid row r0 sits in window row 1
+                // apply_row asks for e (also in place of a missing
+                // neighbour), e -+ 1, e -+ nx and e -+ nx*ny
+                const double se = apply_row<OP_3D7>(a.A, e, [&](uint32_t k) {
+                    const int32_t d = (int32_t)(k - e);
+                    if (d == (int32_t)nxy) return nxt[w];
+                    if (d == -(int32_t)nxy) return prv[w];
+                    return cur[(int32_t)w + d];
+                });
+                const double sv = rnd<T>(se);
+                sts<NT>(vp<T>(a, a.off_s, e), sv);
+                acc[0] += sv * cur[w];
+            }
+        }
+        __syncthreads();  // the next item's fills reuse every slot
     }
     block_sum<1>(acc, lds_red);
     store_partial<1>(a.part_out, acc);

@@ -143,6 +143,8 @@ pcg_status validate_options(const pcg_options *o)
 // several unknowns per thread (a compact window of tiles in flight keeps HBM
 // pages open), the lighter passes as more, smaller blocks; the XCD slab map
 // measured slower everywhere and is off unless asked for.
+constexpr int kZmBlocksPerCU = 3;  // z-marching CG pass A: 48 KB of LDS per block
+
 LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
 {
     LaunchShape s{};
@@ -185,6 +187,46 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
     const bool want_xcd = set && (var & PCG_VAR_XCD_MAP) != 0;
     s.xcd_map = (want_xcd && g >= 64 && (g % 8) == 0) ? 1 : 0;
     s.K = o->iters_per_launch ? o->iters_per_launch : (op->n >= (1 << 20) ? 16 : 64);
+    // classic CG on a 3-D grid: pass A marches along z with the p_i planes in
+    // LDS when its window fits (4 planes of rows + 2 grid rows in 48 KB) and
+    // the grid is large enough (or the variant asks for it); segments of at
+    // least 8 planes keep the refill of the first two planes of a segment
+    // small
+    s.zm_rows = 0;
+    if (o->method == PCG_CG && op->kind == PCG_OP_STENCIL3D7) {
+        const size_t budget = 48 * 1024;
+        int rows = (int)(budget / (4 * sizeof(double) * (size_t)op->nx)) - 2;
+        rows = std::min(std::min(rows, 8), (int)op->ny);
+        if (rows >= 1) {
+            const int nchunks = (op->ny + rows - 1) / rows;
+            auto split = [&](int grid, int *seg, int *nsegs) {
+                const int want = (grid + nchunks - 1) / nchunks;
+                *seg = std::max(std::min(op->nz, 8), (op->nz + want - 1) / want);
+                *nsegs = (op->nz + *seg - 1) / *seg;
+            };
+            const bool forced = set && (var & PCG_VAR_CG_ZMARCH) != 0;
+            int seg, nsegs;
+            split(kZmBlocksPerCU * kNumCU, &seg, &nsegs);
+            // built in where it measured faster: at least 4 rows per item (the
+            // two halo rows are formed again by the neighbouring items: 320^3
+            // with 2 rows was slower, 693 vs 620 us per iteration) and an item
+            // for every resident block (128^3 with 256 items: 62 vs 53 us)
+            const bool pays = rows >= 4 && nchunks * nsegs >= kZmBlocksPerCU * kNumCU;
+            if (!set && pays) {
+                // the built-in shape of this case: 256 threads, as many
+                // blocks as the 48 KB plane window lets reside (3 per CU)
+                if (!o->block_size) s.block = 256;
+                s.ntiles = (int)((op->n + int64_t(s.block) * s.ept - 1) / (int64_t(s.block) * s.ept));
+                int g = o->grid_blocks ? o->grid_blocks : kZmBlocksPerCU * kNumCU;
+                if (g > s.ntiles) g = s.ntiles;
+                if (g >= 64) g &= ~7;
+                s.grid = std::max(g, 1);
+            }
+            split(s.grid, &seg, &nsegs);
+            if (forced || (!set && pays))
+                s.zm_rows = rows, s.zm_seg = seg, s.zm_nchunks = nchunks, s.zm_nsegs = nsegs;
+        }
+    }
     return s;
 }
 
@@ -275,7 +317,17 @@ struct KernelSet {
     static void cg_init1(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_cg_init1<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void cg_a(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_cg_a<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    {
+        if constexpr (OP == OP_3D7) {
+            const PassArgs<T> &p = A(a);
+            if (p.zm.rows > 0) {
+                const size_t lds = 4 * sizeof(double) * (size_t)(p.zm.rows + 2) * (size_t)p.A.nx;
+                hipLaunchKernelGGL((k_cg_a_zm<T, JAC, NT>), dim3(g), dim3(b), lds, s, p, p.zm);
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_cg_a<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a));
+    }
     static void cg_b(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_cg_b<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void resid(PassArgsAny a, int g, int b, hipStream_t s)
@@ -404,6 +456,7 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
         a.rr_period = opt.rr_period > 0 ? opt.rr_period : 8;
         a.rr_tau = opt.rr_tau > 0.0 ? opt.rr_tau : std::cbrt(opt.prec == PCG_FP64 ? 0x1p-53 : 0x1p-24);
         a.rr_floor = opt.rr_floor > 0.0 ? opt.rr_floor : 100.0;
+        a.zm = CgZm{sh.zm_rows, sh.zm_seg, sh.zm_nchunks, sh.zm_nsegs};
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
     else fill((float *)nullptr);

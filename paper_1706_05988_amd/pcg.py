@@ -27,6 +27,7 @@ PCG_PC_NONE, PCG_PC_JACOBI = 0, 1
 PCG_FP64, PCG_FP32_STREAM = 0, 1
 PCG_HISTORY_FIELDS = 5
 PCG_VAR_SET, PCG_VAR_XCD_MAP, PCG_VAR_NT, PCG_VAR_EPT1, PCG_VAR_EPT4 = 0x01, 0x02, 0x04, 0x10, 0x20
+PCG_VAR_CG_ZMARCH = 0x40
 
 METHOD = {"cg": PCG_CG, "pipe": PCG_PIPE, "pipe_shift": PCG_PIPE_SHIFT, "pipe_var": PCG_PIPE_VAR_SHIFT, "pipe_rr": PCG_PIPE_RR}
 OUTCOME = {PCG_CONVERGED: "converged", PCG_MAX_ITER: "max_iter", PCG_BREAKDOWN: "breakdown",

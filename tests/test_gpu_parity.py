@@ -122,6 +122,42 @@ def test_3d_ragged_grid(torch, method, jacobi):
     assert abs(g["rel_res_true"] - o["rel_res_true"]) <= (1e-11 if method == "pipe" else 1e-12)
 
 
+@pytest.mark.parametrize("dims,jacobi", [((37, 41, 43), True), ((24, 17, 30), False), ((5, 3, 11), True),
+                                         ((64, 64, 40), True)])
+def test_cg_zmarch_pass_matches_oracle(torch, dims, jacobi):
+    """Classic CG with pass A marching along z through LDS (forced here on
+    grids where the built-in rule would run the plain pass; 64x64x40 spans
+    several row chunks and segments): the oracle's history to 1e-10 over 50
+    iterations and its final explicit residual to 1e-12, and the plain
+    pass's history to rounding."""
+    from paper_1706_05988_amd import pcg as P
+    op = problems.stencil3d(*dims)
+    rng = np.random.default_rng(sum(dims))
+    xt = rng.uniform(-1, 1, op.n)
+    p = problems.Problem("zm3d", op, problems.to_scipy(op) @ xt, np.zeros(op.n), xt, jacobi=jacobi,
+                         sigma=0.0, rtol=1e-10, max_iter=3000)
+    zm = gpu_solve(torch, p, "cg", true_residual_check=False, variant=P.PCG_VAR_SET | P.PCG_VAR_CG_ZMARCH)
+    plain = gpu_solve(torch, p, "cg", true_residual_check=False)
+    o = oracle_solve(p, "cg")
+    assert zm["status"] == o["status"] == "converged"
+    assert abs(zm["iterations"] - o["iterations"]) <= 1
+    check_history(zm, o)
+    assert abs(zm["rel_res_true"] - o["rel_res_true"]) <= 1e-12
+    np.testing.assert_allclose(zm["x"], xt, atol=1e-8)
+    check_history(zm, plain, rtol=1e-12)
+
+
+def test_cg_zmarch_fp32_stream_with_restarts(torch):
+    """The z-marching pass A in the FP32-stream form (binary32 p and s in
+    HBM, binary64 values in LDS) reaches 1e-10 through restarts from x."""
+    from paper_1706_05988_amd import pcg as P
+    p = problems.poisson3d(40, seed=4)
+    g = gpu_solve(torch, p, "cg", fp32=True, rtol=1e-10, max_iter=4000, replace_max=10, hist=False,
+                  variant=P.PCG_VAR_SET | P.PCG_VAR_CG_ZMARCH)
+    assert g["status"] == "converged" and g["rel_res_true"] <= 1e-10
+    assert g["replacements"] >= 1
+
+
 # ---------------------------------------------------------------- CSR
 
 @pytest.mark.parametrize("method", METHODS)
