@@ -16,12 +16,16 @@
 //              block partials of (b, b)
 //   k_init1    head: ||b||^2 (stage 2);  w_0 := A u_0 - sigma r_0;
 //              partials of gamma_0, delta_0, rho_0
-//   k_pipe     one whole iteration i (see the kernel)
+//   k_pipe     one whole iteration i (see the kernel); x is written every
+//              other iteration, and k_x_fixup completes it when a solve
+//              stops after a pass that skipped it
+//   k_pipe_rr  the same with automated residual replacement (p-CG-rr)
 // Passes of classic CG (Alg. 1, two fused passes per iteration):
 //   k_init0    r_0 := b - A x_0; clears p_{-1}; partials of (b, b)
 //   k_cg_init1 head: ||b||^2; partials of gamma_0 = (r_0, u_0), rho_0
 //   k_cg_a     head: gamma_i, rho_i -> stop test, beta_i; p_i := u_i + beta_i p_{i-1}
 //              (recomputed at the stencil neighbours), s_i := A p_i; partial (s_i, p_i)
+//   k_cg_a_zm  the same on a 3-D grid, marching along z with the p_i planes in LDS
 //   k_cg_b     head: (s_i, p_i) -> alpha_i; x, r updates, u := M^-1 r;
 //              partials of gamma_{i+1}, rho_{i+1}
 // Support:
