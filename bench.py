@@ -231,7 +231,8 @@ def bench_batched(P, torch, count: int = 512, seed: int = 0) -> dict:
                     f"sum n = {sum(p.op.n for p in ps)}, FP32-stream shifted p-CG sigma = 4 + c to 1e-8",
         "solves_per_s": count / t_batch,
         "seconds": t_batch,
-        "launch_shape": {"grid_blocks": shape["grid_blocks"], "passes_per_launch": shape["iters_per_launch"],
+        "launch_shape": {"grid_blocks": shape["grid_blocks"] or "default", "passes_per_launch":
+                         shape["iters_per_launch"] or "default",
                          "tuned_by": "pcg_batch_tune"},
         "default_shape_solves_per_s": count / t_default,
         "converged": int(sum(r["status"] == "converged" for r in res)),
@@ -344,7 +345,8 @@ def bench_serving(P, torch, count: int, log10_max: float, seed: int = 0) -> dict
                     f"half 3-D 7-point cubes, half banded CSR (7-27 nnz/row), Jacobi, sigma = 1, "
                     f"FP32-stream shifted p-CG to 1e-8",
         "capacity_solves_per_s": capacity,
-        "launch_shape": {"grid_blocks": shape["grid_blocks"], "passes_per_launch": shape["iters_per_launch"],
+        "launch_shape": {"grid_blocks": shape["grid_blocks"] or "default", "passes_per_launch":
+                         shape["iters_per_launch"] or "default",
                          "tuned_by": f"pcg_batch_tune on the first {len(sample)} requests"},
         "arrival_rate_hz": rate,
         "solves_per_s": count / t_live,

@@ -273,10 +273,12 @@ pcg_status pcg_batch_solve(int32_t count, const pcg_operator *ops, const pcg_opt
 
 /*
  * Launch-shape autotuner of the batched pass.  Times complete pcg_batch_solve
- * calls on the caller's batch for every persistent grid of 1, 2, 3 or 4
- * blocks per CU and every graph length K of 16, 32 or 64 passes (each
- * candidate twice, its faster host wall time counting), and writes the
- * fastest into opts[0].grid_blocks and opts[0].iters_per_launch; *best_ms
+ * calls on the caller's batch for the library's default shape (grid_blocks
+ * and iters_per_launch 0) and for every persistent grid of 1, 2, 3 or 4
+ * blocks per CU with every graph length K of 16, 32 or 64 passes (each
+ * candidate twice, its faster host wall time counting; a shape other than
+ * the default must beat it by 1%), and writes the winner into
+ * opts[0].grid_blocks and opts[0].iters_per_launch; *best_ms
  * (host, may be NULL) receives its solve time.  x0[k]: device initial guesses
  * (n_k binary64, read only), copied into x[k] before every candidate solve;
  * x[k]: device scratch, overwritten (it holds a solution on return).
