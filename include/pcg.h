@@ -234,7 +234,7 @@ pcg_status pcg_destroy(pcg_solver solver);
  * choice) on the caller's operator -- a solver is created on `workspace`
  * for each; an 8-pass probe sizes a run of about 3 ms of passes (24 to
  * 4096) from a zero initial guess, timed with HIP events -- and writes the
- * fastest into
+ * fastest (the built-in choice unless another shape is 1% faster) into
  * opt->variant (PCG_VAR_SET | unknowns-per-thread bits | PCG_VAR_NT),
  * opt->block_size and opt->grid_blocks; *best_us (host, may be NULL)
  * receives its time per pass.  b: device right-hand side (n binary64);
