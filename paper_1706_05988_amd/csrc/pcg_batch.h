@@ -9,9 +9,10 @@
 //   RESID   ||b - A x|| in binary64 (after the iteration ends)
 //   COPYOUT internal x -> caller x
 // The pass kernel works on a table of (system, tile) items; each tile is
-// 256 * kBatchEPT unknowns and writes one block partial into its
-// system's partial array.  At its head, every item block sums its system's
-// partials of the previous pass in tile order (so a system's results depend
+// 256 * kBatchEPT unknowns and writes one partial per wave into its
+// system's partial array (no block barrier between items).  At its head,
+// every item block sums its system's partials of the previous pass in
+// tile and wave order (so a system's results depend
 // only on that system, never on the rest of the batch), takes the stop /
 // breakdown / restart decisions and the scalar recurrences -- the same bits
 // in every block of the system -- and performs the next phase on its tile;
@@ -37,6 +38,7 @@ enum Phase : int32_t {
 
 constexpr int kBatchBlock = 256;      // threads of a pass block
 constexpr int kSpecAny = -1;          // pass kernels read operator kind and preconditioner per system
+constexpr int kBatchWaves = kBatchBlock / 64;  // partials per work tile (one per wave)
 #ifndef PCG_BATCH_EPT
 #define PCG_BATCH_EPT 4
 #endif
@@ -58,7 +60,7 @@ struct BatchSys {
     uint32_t tile_bytes;
     uint32_t off_slot[V_COUNT];
     uint32_t pad0;
-    double *part;       // 2 slots of ntiles * kFields
+    double *part;       // 2 slots of ntiles * kBatchWaves * kFields (one partial per wave)
     double *hist;       // history rows or nullptr
     int32_t hist_cap, replace_max, true_check, pad1;
 };

@@ -240,7 +240,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int 
             }
             double tot[3] = {0.0, 0.0, 0.0};
             if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT)
-                stage2<3>(D.part + (size_t)par * D.ntiles * kFields, D.ntiles, tot, lds_red);
+                stage2<3>(D.part + (size_t)par * D.ntiles * kBatchWaves * kFields, D.ntiles * kBatchWaves, tot, lds_red);
             S = batch_next(D, *Sin, tot, writer);
             if (writer) *Sout = S;
         } else {
@@ -249,9 +249,11 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int 
         double acc[3] = {0.0, 0.0, 0.0};
         if (S.phase >= PH_DONE) continue;
         batch_item<T, SPEC>(D, S, tile, acc);
-        block_sum<3>(acc, lds_red);
-        if (threadIdx.x == 0) {
-            double *pp = D.part + ((size_t)(1 - par) * D.ntiles + tile) * kFields;
+        // one partial per wave: no block barrier between items
+#pragma unroll
+        for (int f = 0; f < 3; ++f) acc[f] = wave_sum(acc[f]);
+        if ((threadIdx.x & 63) == 0) {
+            double *pp = D.part + (((size_t)(1 - par) * D.ntiles + tile) * kBatchWaves + (threadIdx.x >> 6)) * kFields;
             pp[0] = acc[0];
             pp[1] = acc[1];
             pp[2] = acc[2];
@@ -276,7 +278,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_trans(BatchTables tb, int
         }
         double tot[3] = {0.0, 0.0, 0.0};
         if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT)
-            stage2<3>(D.part + (size_t)par * D.ntiles * kFields, D.ntiles, tot, lds_red);
+            stage2<3>(D.part + (size_t)par * D.ntiles * kBatchWaves * kFields, D.ntiles * kBatchWaves, tot, lds_red);
         const BatchState S = batch_next(D, *Sin, tot, threadIdx.x == 0);
         if (threadIdx.x == 0) *Sout = S;
     }
@@ -348,7 +350,7 @@ pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options 
     l.blk = off;
     off += up256((size_t)l.ntiles * tb);
     l.part = off;
-    off += up256((size_t)2 * l.nwork * kFields * 8);  // two partial slots
+    off += up256((size_t)2 * l.nwork * kBatchWaves * kFields * 8);  // two partial slots, one per wave
     l.dinv = SIZE_MAX;
     if (op->kind == PCG_OP_CSR && jac) {
         l.dinv = off;
