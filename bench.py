@@ -481,7 +481,8 @@ def report_small(P, torch) -> dict:
     """Latency-bound cases: 2-D Poisson 100x100 (all three methods, to 1e-12)
     and the 1000x1000 Poisson problem of Section 5.2 (b = A*1, x0 = 0, to
     1e-6 and, as in the accuracy run, 2500 iterations) with CG, p-CG, p-CG-sh
-    and p-CG-rr."""
+    and p-CG-rr; then the fused pass on a 256 x 256 x 32 grid, one GPU's
+    share of the 256^3 problem split into 8 slabs."""
     import problems
     out = {}
     p = problems.poisson2d_manufactured(100)
@@ -507,6 +508,17 @@ def report_small(P, torch) -> dict:
                                             "true_residual_after_2500_or_breakdown": r2["rel_res_true"],
                                             "status_long_run": r2["status"], "iterations_long_run": r2["iterations"],
                                             "seconds_long_run": r2["wall_s"]}
+    # one GPU's share of the 256^3 problem split into 8 slabs along z: the
+    # fused pass on a 256 x 256 x 32 grid (Jacobi, FP64, p-CG-sh), 400 passes
+    p = problems.poisson3d(256, ny=256, nz=32, seed=0)
+    op = p.op
+    b = torch.from_numpy(p.b).cuda()
+    r = _timed_solve(P, torch, op, P.make_options(method="pipe_shift", jacobi=True, sigma=1.0, rtol=1e-300,
+                                                  max_iter=400, true_residual_check=False, timing=True), b)
+    us = r["iter_kernel_ms"] * 1e3 / max(1, r["iter_passes"])
+    out["slab_256x256x32_jacobi_fp64_pipe_shift"] = {
+        "unknowns": op.n, "us_per_pass": us, "TB_per_s_on_136B": 136.0 * op.n / (us * 1e-6) / 1e12,
+        "iters_per_s": r["iterations"] / r["wall_s"]}
     return out
 
 
@@ -573,6 +585,8 @@ def report_tune(P, torch) -> dict:
 
     out = {}
     cases = [("3d256_jacobi_fp64_pipe_shift", problems.poisson3d(256, seed=0), dict(jacobi=True, sigma=1.0)),
+             ("slab_256x256x32_jacobi_fp64_pipe_shift", problems.poisson3d(256, ny=256, nz=32, seed=0),
+              dict(jacobi=True, sigma=1.0)),
              ("3d256_jacobi_fp32_pipe_shift", problems.poisson3d(256, seed=0), dict(jacobi=True, fp32=True, sigma=1.0)),
              ("csr_aniso1024_fp64_pipe_shift", problems.anisotropic_csr(1024, seed=0), dict(jacobi=True, sigma=1.0)),
              ("csr_aniso1024_fp32_pipe_shift", problems.anisotropic_csr(1024, seed=0),

@@ -191,13 +191,16 @@ def lapl200() -> Problem:
                    rtol=1e-30, max_iter=500)
 
 
-def poisson3d(N: int = 256, seed: int = 0, jacobi: bool = True) -> Problem:
-    """3-D Poisson N^3, x_true ~ U(-1, 1), b = A x_true, x0 = 0, Jacobi,
-    sigma = 1 (midpoint of spec(A M^-1) for the constant diagonal 6)."""
-    op = stencil3d(N)
+def poisson3d(N: int = 256, seed: int = 0, jacobi: bool = True, ny: Optional[int] = None,
+              nz: Optional[int] = None) -> Problem:
+    """3-D Poisson N^3 (or N x ny x nz), x_true ~ U(-1, 1), b = A x_true,
+    x0 = 0, Jacobi, sigma = 1 (midpoint of spec(A M^-1) for the constant
+    diagonal 6)."""
+    op = stencil3d(N, ny, nz)
     rng = np.random.default_rng(seed)
     xt = rng.uniform(-1.0, 1.0, op.n)
-    return Problem(f"poisson3d_{N}", op, _matvec(op, xt), np.zeros(op.n), xt,
+    name = f"poisson3d_{N}" if ny is None and nz is None else f"poisson3d_{op.nx}x{op.ny}x{op.nz}"
+    return Problem(name, op, _matvec(op, xt), np.zeros(op.n), xt,
                    jacobi=jacobi, sigma=1.0 if jacobi else 6.0, rtol=1e-10,
                    max_iter=5000, seed=seed)
 
