@@ -81,3 +81,14 @@ def test_stencil_rhs_equals_kronecker_matvec():
     np.testing.assert_allclose(A @ p.x_true, p.b, rtol=1e-14, atol=1e-14)
     q = problems.batch_rectangles(3, seed=2, side_min=5, side_max=9)[0]
     assert isinstance(problems.to_scipy(q.op), sp.csr_matrix)
+
+
+def test_box_grid_rhs_equals_padded_stencil():
+    # a non-cubic box (the shape of one slab of a split grid): b = A x_true
+    # with A the 7-point stencil applied by explicit zero padding
+    p = problems.poisson3d(8, ny=6, nz=4, seed=2)
+    assert (p.op.nx, p.op.ny, p.op.nz, p.op.n) == (8, 6, 4, 192)
+    x = np.pad(p.x_true.reshape(4, 6, 8), 1)
+    ax = 6.0 * x[1:-1, 1:-1, 1:-1] - (x[:-2, 1:-1, 1:-1] + x[2:, 1:-1, 1:-1] + x[1:-1, :-2, 1:-1] +
+                                      x[1:-1, 2:, 1:-1] + x[1:-1, 1:-1, :-2] + x[1:-1, 1:-1, 2:])
+    np.testing.assert_allclose(ax.ravel(), p.b, rtol=0, atol=1e-14)
