@@ -49,6 +49,11 @@ struct CgZm {
     int32_t rows, seg, nchunks, nsegs;
 };
 
+// Points of a plane window each thread of the z-marching pass loads at once:
+// the launch keeps (rows + 2) * nx <= kZmBatch * threads per block, so one
+// batch covers the window.
+constexpr int kZmBatch = 8;
+
 template <typename T>
 struct PassArgs {
     OpDev<T> A;
@@ -907,9 +912,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_a(PassArgs<T> a)
 // at each of the seven points of every row (14 loads per unknown); this
 // one loads r and p_{i-1} about (rows + 2) / rows times per unknown.  Four
 // slots need one barrier per plane: filling plane z + 2 never overwrites a
-// plane that s of plane z still reads.  The values and the order of every
-// sum are those of k_cg_a (apply_row reads its operands through the LDS
-// window); only the partial sums are grouped differently.
+// plane that s of plane z still reads.  The loads of plane z + 2 are issued
+// into registers before s of plane z is evaluated, so they are in flight
+// during it.  The values and the order of every sum are those of k_cg_a
+// (apply_row reads its operands through the LDS window); only the partial
+// sums are grouped differently.
 template <typename T, bool JAC, bool NT>
 __global__ void __launch_bounds__(kMaxBlock) k_cg_a_zm(PassArgs<T> a, CgZm zm)
 {
@@ -929,41 +936,47 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_a_zm(PassArgs<T> a, CgZm zm)
         // window row w holds grid row r0 - 1 + w; rows outside the grid stay unfilled
         const uint32_t wr0 = r0 > 0 ? r0 - 1 : 0, wr1 = min(r1 + 1, ny);
         const uint32_t own0 = (r0 - wr0) * nx, own1 = (r1 - wr0) * nx;  // own rows, relative to wr0
-        // the loads of kZmBatch points per thread go out before any store
-        // (the stores could alias them as far as the compiler knows)
-        constexpr int kZmBatch = 8;
-        auto fill = [&](uint32_t zz) {
-            double *buf = zlds + (size_t)(zz & 3u) * slot + (size_t)(wr0 + 1 - r0) * nx;
-            const uint32_t cnt = (wr1 - wr0) * nx, g0 = zz * nxy + wr0 * nx;
-            const bool own = zz >= z0 && zz < z1;
-            for (uint32_t t0 = threadIdx.x; t0 < cnt; t0 += kZmBatch * blockDim.x) {
-                double rv[kZmBatch], pv[kZmBatch];
+        const uint32_t cnt = (wr1 - wr0) * nx;  // points of a plane window, <= kZmBatch * blockDim.x
+        // r and p_{i-1} of one plane window, kZmBatch points per thread
+        double rv[kZmBatch], pv[kZmBatch];
+        auto load = [&](uint32_t zz) {
+            const uint32_t g0 = zz * nxy + wr0 * nx;
 #pragma unroll
-                for (int j = 0; j < kZmBatch; ++j) {
-                    const uint32_t k = g0 + min(t0 + j * blockDim.x, cnt - 1);  // in bounds
-                    rv[j] = ld(vp<T>(a, a.off_r, k), 0);
-                    pv[j] = ld(vp<T>(a, a.off_win, k), 0);
-                }
-#pragma unroll
-                for (int j = 0; j < kZmBatch; ++j) {
-                    const uint32_t t = t0 + j * blockDim.x;
-                    if (t >= cnt) continue;
-                    const double p = cg_pnew_of<T, JAC, OP_3D7>(a, g0 + t, rv[j], pv[j], beta);
-                    buf[t] = p;
-                    if (own && t >= own0 && t < own1) sts<NT>(vp<T>(a, a.off_wout, g0 + t), p);
-                }
+            for (int j = 0; j < kZmBatch; ++j) {
+                const uint32_t k = g0 + min(threadIdx.x + j * blockDim.x, cnt - 1);  // in bounds
+                rv[j] = ld(vp<T>(a, a.off_r, k), 0);
+                pv[j] = ld(vp<T>(a, a.off_win, k), 0);
             }
         };
-        if (z0 > 0) fill(z0 - 1);
-        fill(z0);
+        // p_i of the loaded plane into its LDS slot (and, on own rows of own
+        // planes, to w_out)
+        auto commit = [&](uint32_t zz) {
+            double *buf = zlds + (size_t)(zz & 3u) * slot + (size_t)(wr0 + 1 - r0) * nx;
+            const uint32_t g0 = zz * nxy + wr0 * nx;
+            const bool own = zz >= z0 && zz < z1;
+#pragma unroll
+            for (int j = 0; j < kZmBatch; ++j) {
+                const uint32_t t = threadIdx.x + j * blockDim.x;
+                if (t >= cnt) continue;
+                const double p = cg_pnew_of<T, JAC, OP_3D7>(a, g0 + t, rv[j], pv[j], beta);
+                buf[t] = p;
+                if (own && t >= own0 && t < own1) sts<NT>(vp<T>(a, a.off_wout, g0 + t), p);
+            }
+        };
+        if (z0 > 0) load(z0 - 1), commit(z0 - 1);
+        load(z0);
+        commit(z0);
+        if (z0 + 1 < nz) load(z0 + 1);
         for (uint32_t z = z0; z < z1; ++z) {
-            if (z + 1 < nz) fill(z + 1);
+            if (z + 1 < nz) commit(z + 1);
             __syncthreads();
+            // plane z + 2 is needed while z + 1 < z1 (as the upper neighbour of z1 - 1 at most)
+            if (z + 2 < nz && z + 2 <= z1) load(z + 2);
             const double *cur = zlds + (size_t)(z & 3u) * slot;
             const double *prv = zlds + (size_t)((z + 3u) & 3u) * slot;
             const double *nxt = zlds + (size_t)((z + 1u) & 3u) * slot;
-            const uint32_t cnt = (r1 - r0) * nx, g0 = z * nxy + r0 * nx;
-            for (uint32_t t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const uint32_t ocnt = (r1 - r0) * nx, g0 = z * nxy + r0 * nx;
+            for (uint32_t t = threadIdx.x; t < ocnt; t += blockDim.x) {
                 const uint32_t e = g0 + t, w = nx + t;  // grid row r0 sits in window row 1
                 // apply_row asks for e (also in place of a missing
                 // neighbour), e -+ 1, e -+ nx and e -+ nx*ny

@@ -188,14 +188,16 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
     s.xcd_map = (want_xcd && g >= 64 && (g % 8) == 0) ? 1 : 0;
     s.K = o->iters_per_launch ? o->iters_per_launch : (op->n >= (1 << 20) ? 16 : 64);
     // classic CG on a 3-D grid: pass A marches along z with the p_i planes in
-    // LDS when its window fits (4 planes of rows + 2 grid rows in 48 KB) and
-    // the grid is large enough (or the variant asks for it); segments of at
-    // least 8 planes keep the refill of the first two planes of a segment
-    // small
+    // LDS when its window fits (4 planes of rows + 2 grid rows in 48 KB, and
+    // one plane window in kZmBatch points per thread) and the grid is large
+    // enough (or the variant asks for it); segments of at least 8 planes keep
+    // the refill of the first two planes of a segment small
     s.zm_rows = 0;
     if (o->method == PCG_CG && op->kind == PCG_OP_STENCIL3D7) {
         const size_t budget = 48 * 1024;
+        const int zblock = o->block_size ? o->block_size : 256;  // its block size wherever it runs
         int rows = (int)(budget / (4 * sizeof(double) * (size_t)op->nx)) - 2;
+        rows = std::min(rows, (int)((int64_t)kZmBatch * zblock / op->nx) - 2);
         rows = std::min(std::min(rows, 8), (int)op->ny);
         if (rows >= 1) {
             const int nchunks = (op->ny + rows - 1) / rows;
@@ -209,9 +211,10 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
             split(kZmBlocksPerCU * kNumCU, &seg, &nsegs);
             // built in where it measured faster: at least 4 rows per item (the
             // two halo rows are formed again by the neighbouring items: 320^3
-            // with 2 rows was slower, 693 vs 620 us per iteration) and an item
-            // for every resident block (128^3 with 256 items: 62 vs 53 us)
-            const bool pays = rows >= 4 && nchunks * nsegs >= kZmBlocksPerCU * kNumCU;
+            // with 2 rows was slower, 693 vs 620 us per iteration) and at
+            // least 1.5 items per CU (160^3 with 460 items: 82.7 vs 88.6 us;
+            // 128^3 with 256 items: 56.6 vs 53.1 us)
+            const bool pays = rows >= 4 && 2 * nchunks * nsegs >= 3 * kNumCU;
             if (!set && pays) {
                 // the built-in shape of this case: 256 threads, as many
                 // blocks as the 48 KB plane window lets reside (3 per CU)
@@ -633,6 +636,8 @@ extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const 
     if ((st = validate_operator(op, opt->prec))) return st;
     if (!workspace || !aligned(workspace, 256)) return invalid("workspace must be non-null and 256-byte aligned");
     const LaunchShape sh = choose_shape(op, opt);
+    if (sh.zm_rows > 0 && (int64_t)(sh.zm_rows + 2) * op->nx > (int64_t)kZmBatch * sh.block)
+        return invalid("z-marching pass: plane window larger than one load batch per thread");
     Layout L;
     const size_t need = layout(op, opt, sh, &L);
     if (bytes < need) return invalid("workspace too small");

@@ -123,11 +123,12 @@ def test_3d_ragged_grid(torch, method, jacobi):
 
 
 @pytest.mark.parametrize("dims,jacobi", [((37, 41, 43), True), ((24, 17, 30), False), ((5, 3, 11), True),
-                                         ((64, 64, 40), True)])
+                                         ((64, 64, 40), True), ((16, 12, 9), True)])
 def test_cg_zmarch_pass_matches_oracle(torch, dims, jacobi):
     """Classic CG with pass A marching along z through LDS (forced here on
     grids where the built-in rule would run the plain pass; 64x64x40 spans
-    several row chunks and segments): the oracle's history to 1e-10 over 50
+    several row chunks and segments, 16x12x9 ends in a one-plane segment):
+    the oracle's history to 1e-10 over 50
     iterations and its final explicit residual to 1e-12, and the plain
     pass's history to rounding."""
     from paper_1706_05988_amd import pcg as P
