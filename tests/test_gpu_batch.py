@@ -188,3 +188,36 @@ def test_batch_tune_picks_a_candidate_caches_it_and_keeps_the_bits(torch, tmp_pa
         assert tuned[k]["status"] == default[k]["status"] == "converged"
         assert tuned[k]["iterations"] == default[k]["iterations"]
         assert torch.equal(ys[k], zs[k])
+
+
+def test_batch_failures_stay_in_their_system(torch):
+    """Systems that end in a breakdown (indefinite operator) or on a
+    non-finite right-hand side, or that need no iteration (b = 0, an exact
+    start), end with their own status, and the other systems of the batch
+    keep the bits they get in a batch without them."""
+    good = mixed_set()[:2]
+    n = 40
+    vals = np.linspace(-1.0, 3.0, n)
+    vals[np.abs(vals) < 1e-3] = 0.5
+    indef = problems.Problem("indef", problems.csr_operator(np.arange(n + 1), np.arange(n, dtype=np.int32), vals),
+                             np.ones(n), np.zeros(n), None, sigma=1.0, rtol=1e-12, max_iter=100)
+    nanb = good[0].b.copy()
+    nanb[5] = np.nan
+    bad_rhs = problems.Problem("nan_rhs", good[0].op, nanb, np.zeros(good[0].op.n), None, sigma=good[0].sigma,
+                               rtol=1e-10, max_iter=3000)
+    zero = problems.Problem("zero_rhs", good[1].op, np.zeros(good[1].op.n), np.zeros(good[1].op.n), None,
+                            sigma=good[1].sigma, rtol=1e-10, max_iter=3000)
+    man = problems.poisson2d_manufactured(20)
+    exact = problems.Problem("exact_start", man.op, man.b, man.x_true.copy(), man.x_true, sigma=man.sigma,
+                             rtol=1e-10, max_iter=3000)
+    res = run_batch(torch, [good[0], indef, bad_rhs, good[1], zero, exact])
+    alone = run_batch(torch, good)
+    assert res[1]["status"] == "breakdown"
+    assert res[2]["status"] == "nonfinite"
+    assert res[4]["status"] == "converged" and res[4]["iterations"] == 0 and not np.any(res[4]["x"])
+    assert res[5]["status"] == "converged" and res[5]["iterations"] == 0
+    np.testing.assert_array_equal(res[5]["x"], man.x_true)
+    for g, a in zip((res[0], res[3]), alone):
+        assert g["status"] == a["status"] == "converged"
+        assert g["iterations"] == a["iterations"]
+        np.testing.assert_array_equal(g["x"], a["x"])
