@@ -311,7 +311,15 @@ typedef struct pcg_server_ *pcg_server;
 pcg_status pcg_server_create(pcg_server *server, void *arena, size_t arena_bytes, int32_t max_slots,
                              void *hip_stream);
 /* Enqueue a solve; op, b, x device data stay borrowed until the ticket is
- * done.  opt->method/pc/prec must match the server's first request's. */
+ * done.  opt->prec must be the first request's; opt->method must be PCG_PIPE
+ * or PCG_PIPE_SHIFT; operator kind and preconditioner may differ between
+ * requests.  Errors: PCG_ERR_INVALID (bad arguments, another precision or
+ * method), PCG_ERR_BUDGET (the request alone exceeds the arena),
+ * PCG_ERR_STATE (null or closing server).  A request that fails while it
+ * runs (non-finite right-hand side, breakdown) reports that in its result's
+ * status and pcg_wait / pcg_poll return PCG_OK; the other requests are
+ * unaffected.  A HIP error during a launch fails every running request:
+ * their pcg_wait / pcg_poll return that error. */
 pcg_status pcg_submit(pcg_server server, const pcg_operator *op, const pcg_options *opt,
                       const double *b, double *x, uint64_t *ticket);
 pcg_status pcg_poll(pcg_server server, uint64_t ticket, pcg_result *result);   /* PCG_PENDING until done */

@@ -117,3 +117,34 @@ def test_server_budget_error_and_poll(torch):
         time.sleep(0.001)
     assert r is not None and r["status"] == "converged"
     srv.close()
+
+
+def test_server_failed_request_leaves_the_others_alone(torch):
+    """A request with a non-finite right-hand side and one on an indefinite
+    operator end with their own status; the requests served beside them get
+    the bits they get alone."""
+    from paper_1706_05988_amd import pcg as P
+    good = request_set()[:2]
+    nanb = good[0].b.copy()
+    nanb[3] = np.inf
+    bad_rhs = problems.Problem("inf_rhs", good[0].op, nanb, np.zeros(good[0].op.n), None, sigma=good[0].sigma,
+                               rtol=1e-8, max_iter=4000)
+    n = 40
+    vals = np.linspace(-1.0, 3.0, n)
+    vals[np.abs(vals) < 1e-3] = 0.5
+    indef = problems.Problem("indef", problems.csr_operator(np.arange(n + 1), np.arange(n, dtype=np.int32), vals),
+                             np.ones(n), np.zeros(n), None, sigma=1.0, rtol=1e-8, max_iter=100)
+    ps = [good[0], bad_rhs, indef, good[1]]
+    srv = P.Server(64 << 20, max_slots=8)
+    bs = [torch.from_numpy(p.b).cuda() for p in ps]
+    xs = [torch.zeros_like(b) for b in bs]
+    tickets = [srv.submit(p.op, opts(P, p), b, x) for p, b, x in zip(ps, bs, xs)]
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    assert res[1]["status"] == "nonfinite"
+    assert res[2]["status"] == "breakdown"
+    for k in (0, 3):
+        alone = solve_alone(torch, P, ps[k])
+        assert res[k]["status"] == alone["status"] == "converged"
+        assert res[k]["iterations"] == alone["iterations"]
+        assert np.array_equal(alone["x"], xs[k].cpu().numpy())
