@@ -297,6 +297,22 @@ def test_zero_iterations_and_exact_start(torch):
     assert g["status"] == "converged" and g["iterations"] == 0
 
 
+@pytest.mark.parametrize("method", METHODS + ["pipe_rr", "pipe_var"])
+@pytest.mark.parametrize("fp32,jacobi", [(False, False), (True, True)])
+def test_zero_rhs_converges_at_once(torch, method, fp32, jacobi):
+    """b = 0 with x0 = 0: r_0 = 0 meets the stop test before any iteration
+    (||r_0|| <= rtol ||b|| = 0), x stays 0 and the residuals are reported
+    unnormalised (0, not 0/0)."""
+    op = problems.stencil3d(9, 7, 5)
+    p = problems.Problem("zero_rhs", op, np.zeros(op.n), np.zeros(op.n), np.zeros(op.n), jacobi=jacobi,
+                         sigma=1.0 if jacobi else 6.0, rtol=1e-10, max_iter=100)
+    kw = dict(sigma_schedule=[p.sigma, p.sigma]) if method == "pipe_var" else {}
+    g = gpu_solve(torch, p, method, fp32=fp32, sigma=p.sigma if method != "cg" else 0.0, **kw)
+    assert g["status"] == "converged" and g["iterations"] == 0
+    assert g["rel_res_true"] == 0.0 and g["rel_res_recursive"] == 0.0
+    assert not np.any(g["x"])
+
+
 def test_nonfinite_rhs_is_an_error(torch):
     from paper_1706_05988_amd import pcg as P
     p = problems.poisson2d_manufactured(20)
