@@ -108,6 +108,12 @@ def test_batch_rejects_cg_and_mixed_precision():
     assert n2 > n1
 
 
+def test_batch_rejects_an_empty_batch():
+    with pytest.raises(P.PcgError) as ei:
+        P.pcg_batch_workspace_size([], [])
+    assert ei.value.status == P.PCG_ERR_INVALID
+
+
 def test_server_argument_checks():
     lib = P.lib()
     h = C.c_void_p()
