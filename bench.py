@@ -439,11 +439,12 @@ def report_c3(P, torch, N: int, max_iter: int) -> dict:
 
 def report_c2(P, torch, N: int = 256) -> dict:
     """The 3-D Poisson problem (N^3, Jacobi, x_true ~ U(-1, 1), x0 = 0):
-    classic CG, p-CG and p-CG-sh in binary64, and p-CG-sh in the FP32-stream
-    form, each to the recursive tolerance 1e-10 with the binary64 explicit
-    check (restarts from x until it holds): iterations, time, iterations/s,
-    time per iteration, algorithmic GB/s and the fraction of 8 TB/s, explicit
-    residual.  Then the attainable accuracy of p-CG and p-CG-sh in both forms:
+    classic CG, p-CG and p-CG-sh in binary64, p-CG-sh in the FP32-stream
+    form, p-CG with a variable shift (Alg. 4) and p-CG-rr in binary64, each
+    to the recursive tolerance 1e-10 with the binary64 explicit check
+    (restarts from x until it holds): iterations, time, iterations/s, time
+    per iteration, algorithmic GB/s and the fraction of 8 TB/s (p-CG-rr's
+    gap-check passes are in its time, not in its bytes), explicit residual.  Then the attainable accuracy of p-CG and p-CG-sh in both forms:
     the explicit residual after 1500 iterations with no stop."""
     import problems
     p = problems.poisson3d(N, seed=0)
@@ -451,15 +452,21 @@ def report_c2(P, torch, N: int = 256) -> dict:
     b = torch.from_numpy(p.b).cuda()
     out = {"workload": f"3-D Poisson 7-point {N}^3 (n={n}), Jacobi, x_true ~ U(-1, 1), x0 = 0", "runs": [],
            "attainable_after_1500": []}
-    for method, fp32 in (("cg", False), ("pipe", False), ("pipe_shift", False), ("pipe_shift", True)):
-        sig = p.sigma if method == "pipe_shift" else 0.0
+    # Alg. 4's schedule here: sigma_{-1} = sigma_0 = 1.5, falling linearly to 1
+    # (the spectrum midpoint) at iteration 100 and constant after it
+    sched = [1.5] + [1.5 - 0.005 * i for i in range(101)]
+    for method, fp32 in (("cg", False), ("pipe", False), ("pipe_shift", False), ("pipe_shift", True),
+                         ("pipe_var", False), ("pipe_rr", False)):
+        sig = p.sigma if method in ("pipe_shift", "pipe_var") else 0.0
+        kw = dict(sigma_schedule=sched) if method == "pipe_var" else {}
         r = _timed_solve(P, torch, p.op, P.make_options(method=method, jacobi=True, fp32=fp32, sigma=sig, rtol=1e-10,
-                                                        max_iter=5000, replace_max=8, timing=True), b)
+                                                        max_iter=5000, replace_max=8, timing=True, **kw), b)
         its = r["iterations"]
         bytes_it = bytes_per_unknown(method, True, fp32) * n
         kern_s = r["iter_kernel_ms"] * 1e-3
         gbs = bytes_it * its / kern_s / 1e9 if kern_s > 0 else float("nan")
-        out["runs"].append({"method": method, "form": "fp32-stream" if fp32 else "fp64", "sigma": sig,
+        out["runs"].append({"method": method, "form": "fp32-stream" if fp32 else "fp64",
+                            "sigma": "schedule 1.5 -> 1 over 100 iterations" if method == "pipe_var" else sig,
                             "status": r["status"], "iterations": its, "restarts": r["replacements"],
                             "true_residual": r["rel_res_true"], "seconds": r["wall_s"],
                             "iters_per_s": its / r["wall_s"], "us_per_iteration": kern_s * 1e6 / max(1, its),
