@@ -99,6 +99,25 @@ def cpu_baseline(p, iters: int) -> dict:
                       f"(timing includes the oracle's init and final explicit residual), {dt:.1f} s"}
 
 
+def copy_probe(torch, dev, nbytes: int = 1 << 31, reps: int = 5) -> float:
+    """Bytes read plus bytes written per second (GB/s) of torch's device copy
+    of `nbytes` into another buffer, averaged over `reps` copies timed with
+    events on the current stream, after one untimed copy."""
+    a = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) * 1e-3 / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / sec / 1e9
+
+
 def _csv(path_glob):
     import csv
     import glob
@@ -729,6 +748,8 @@ def main():
     achieved = per_pass_bytes / avg_pass_s / 1e9
     traffic = traffic_entry() if (args.N == 256 and args.method == "pipe_shift" and not args.fp32
                                   and not args.block and not args.grid and not args.variant) else None
+    # (not in the counter runs: their calibration takes the largest device copy)
+    copy_gbs = None if args.calib_copy else copy_probe(torch, dev)
     out = {
         "metric": METRIC,
         "value": iters / elapsed,
@@ -762,6 +783,9 @@ def main():
             "kernel": "k_pipe (fused p-CG-sh iteration pass)" if args.method != "cg" else "k_cg_a + k_cg_b",
             "avg_pass_us": avg_pass_s * 1e6,
             "bytes_per_pass": per_pass_bytes,
+            # the same run's plain device copy (bytes read + written per second):
+            # what a kernel with a read / write mix reaches on this HBM
+            "copy_probe_gbs": copy_gbs,
         },
         "cpu_baseline": None,
     }
