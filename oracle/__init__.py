@@ -57,16 +57,19 @@ class _Opts(C.Structure):
                 ("replace_max", C.c_int32), ("ignore_breakdown", C.c_int32),
                 ("sigma_sched", C.c_void_p), ("sigma_sched_len", C.c_int32),
                 ("w0_perturb", C.c_void_p), ("rr_tau", C.c_double), ("rr_period", C.c_int32),
-                ("rr_floor", C.c_double)]
+                ("rr_floor", C.c_double), ("snap_iter", C.c_int32)]
 
 
 _HIST = ["h_res", "h_true", "h_alpha", "h_beta", "h_gamma", "h_delta", "h_f", "h_g", "h_h", "h_j"]
+# the stored vectors of a solve, in the oracle's slot order (absent ones come back as None)
+VECTORS = ["r", "u", "w", "z", "q", "s", "t", "p", "dinv"]
 
 
 class _Res(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("replacements", C.c_int32),
                 ("pad_", C.c_int32), ("bnorm", C.c_double), ("rel_res_recursive", C.c_double),
-                ("rel_res_true", C.c_double)] + [(h, C.c_void_p) for h in _HIST]
+                ("rel_res_true", C.c_double)] + [(h, C.c_void_p) for h in _HIST] + \
+               [("snap", C.c_void_p), ("final_vecs", C.c_void_p)]
 
 
 _lib = None
@@ -137,9 +140,15 @@ def solve(op, b: np.ndarray, x0: Optional[np.ndarray] = None, method: str = "pip
           fp32_storage: bool = False, record: bool = True, record_true: bool = False,
           record_gaps: bool = False, threads: int = 1, replace_max: int = 0,
           ignore_breakdown: bool = False, sigma_schedule=None, w0_perturb=None,
-          rr_tau: Optional[float] = None, rr_period: int = 8, rr_floor: float = 100.0) -> dict:
+          rr_tau: Optional[float] = None, rr_period: int = 8, rr_floor: float = 100.0,
+          snap_iter: Optional[int] = None, return_vectors: bool = False) -> dict:
     """Run the oracle.  Returns a dict with x, status, iterations, norms and
-    (if ``record``) histories indexed by iteration (NaN where not reached)."""
+    (if ``record``) histories indexed by iteration (NaN where not reached).
+    ``return_vectors``: also the stored vectors when the solve returns
+    (``final``: name -> array, None for a vector the method does not keep);
+    ``snap_iter``: the stored vectors as the body of that iteration finds
+    them, after any restart or replacement at its top (``snap``, None if the
+    solve never ran that body)."""
     lib = _load()
     o, keep = _make_op(op)
     opts = _Opts(METHODS[method], int(max_iter), float(sigma), float(rtol), int(bool(jacobi)),
@@ -173,6 +182,11 @@ def solve(op, b: np.ndarray, x0: Optional[np.ndarray] = None, method: str = "pip
             continue
         hist[h] = np.full(L, np.nan)
         setattr(res, h, _ptr(hist[h]))
+    nv = len(VECTORS)
+    opts.snap_iter = -1 if snap_iter is None else int(snap_iter)
+    snap = np.full(nv * op.n, np.inf) if snap_iter is not None else None
+    fin = np.empty(nv * op.n) if return_vectors else None
+    res.snap, res.final_vecs = _ptr(snap), _ptr(fin)
     rc = lib.orc_solve(C.byref(o), C.byref(opts), _ptr(b), _ptr(x), C.byref(res))
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
@@ -182,6 +196,15 @@ def solve(op, b: np.ndarray, x0: Optional[np.ndarray] = None, method: str = "pip
                rel_res_recursive=res.rel_res_recursive, rel_res_true=res.rel_res_true)
     for h, arr in hist.items():
         out[h[2:]] = arr[: res.iterations + 1]
+
+    def unpack(buf):
+        vs = buf.reshape(nv, op.n)
+        return {name: (None if np.isnan(v).all() else v.copy()) for name, v in zip(VECTORS, vs)}
+
+    if fin is not None:
+        out["final"] = unpack(fin)
+    if snap is not None:
+        out["snap"] = None if np.isinf(snap).all() else unpack(snap)
     return out
 
 

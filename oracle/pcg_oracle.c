@@ -59,7 +59,9 @@
  *     w := A u, s := A p_{i-1}, q := M^{-1} s, z := A q -- and iteration i
  *     starts again from its dot products, its beta continuing the old
  *     recurrence (gamma_{i-1}, alpha_{i-1} are kept).
- * Diagnostics: the explicit residual ||b - A x_i|| per iteration and the gap
+ * Diagnostics: the stored vectors (r, u, w, z, q, s, t, p and the Jacobi
+ * diagonal) when the solve returns and as the body of a chosen iteration
+ * finds them; the explicit residual ||b - A x_i|| per iteration and the gap
  * norms ||f||, ||g||, ||h||, ||j|| of Section 3.1 from their definitions; a
  * test hook adds a given vector to w_0, planting a known gap h_0 whose
  * propagation the tests follow through the propagation matrices.
@@ -108,6 +110,8 @@ typedef struct {
     double rr_tau;             /* p-CG-rr: replace when ||f_i|| > rr_tau ||r_i|| */
     int32_t rr_period;         /* p-CG-rr: measure the gap every rr_period iterations */
     double rr_floor;           /* p-CG-rr: ... and only when ||f_i|| > rr_floor * eps || |A||x| + |b| || */
+    int32_t snap_iter;         /* record the stored vectors as the body of iteration snap_iter finds them
+                                  (after any restart or replacement at its top); < 0: never */
 } orc_opts;
 
 typedef struct {
@@ -126,6 +130,10 @@ typedef struct {
     double *h_gamma;
     double *h_delta;
     double *h_f, *h_g, *h_h, *h_j; /* gap norms, index as in Section 3.1 */
+    /* optional ORC_NVEC * n buffers of the stored vectors, slot order r, u, w,
+     * z, q, s, t, p, dinv; a vector the method does not keep is written as NaN */
+    double *snap;        /* at the top of iteration snap_iter's body (untouched if never reached) */
+    double *final_vecs;  /* when the solve returns */
 } orc_result;
 
 /* ---------------------------------------------------------------- helpers */
@@ -136,6 +144,20 @@ static int g_fp32 = 0;
 static inline double st(double v) { return g_fp32 ? (double)(float)v : v; }
 
 static double *vec(int64_t n) { return (double *)calloc((size_t)(n > 0 ? n : 1), sizeof(double)); }
+
+/* The stored vectors of a method, in the slot order of orc_result.snap. */
+enum { ORC_NVEC = 9 };
+
+static void dump_vecs(double *out, int64_t n, const double *const v[ORC_NVEC])
+{
+    for (int k = 0; k < ORC_NVEC; ++k) {
+        double *o = out + (size_t)k * (size_t)n;
+        if (v[k])
+            memcpy(o, v[k], (size_t)n * sizeof(double));
+        else
+            for (int64_t i = 0; i < n; ++i) o[i] = NAN;
+    }
+}
 
 /* out = A v.  Dirichlet stencil rows take neighbours that exist only. */
 static void apply_A(const orc_op *A, const double *v, double *out)
@@ -372,6 +394,10 @@ static int solve_cg(const orc_op *A, const double *dinv, const orc_opts *o, cons
         }
         if (i >= o->max_iter) { status = ORC_MAX_ITER; break; }
         if (!o->ignore_breakdown && !(gamma > 0.0)) { status = ORC_BREAKDOWN; break; }
+        if (res->snap && i == o->snap_iter) {
+            const double *v[ORC_NVEC] = {r, u, NULL, NULL, NULL, s, NULL, p, dinv};
+            dump_vecs(res->snap, n, v);
+        }
 
         apply_A(A, p, s);                          /* s_i := A p_i           */
         for (int64_t k = 0; k < n; ++k) s[k] = st(s[k]);
@@ -397,6 +423,10 @@ static int solve_cg(const orc_op *A, const double *dinv, const orc_opts *o, cons
     res->rel_res_recursive = sqrt(rho) / bnorm;
     true_residual(A, b, x, tmp, tr);
     res->rel_res_true = norm2(n, tr) / bnorm;
+    if (res->final_vecs) {
+        const double *v[ORC_NVEC] = {r, u, NULL, NULL, NULL, s, NULL, p, dinv};
+        dump_vecs(res->final_vecs, n, v);
+    }
     free(r); free(u); free(p); free(s); free(tmp); free(tr);
     return 0;
 }
@@ -508,6 +538,10 @@ static int solve_pipe(const orc_op *A, const double *dinv, const orc_opts *o, in
             }
         }
         if (!o->ignore_breakdown && (!(gamma > 0.0) || !(delta > 0.0))) { status = ORC_BREAKDOWN; break; }
+        if (res->snap && i == o->snap_iter) {
+            const double *v[ORC_NVEC] = {r, u, w, z, q, s, t, p, dinv};
+            dump_vecs(res->snap, n, v);
+        }
 
         apply_Minv(n, dinv, w, m);                 /* m_i := M^{-1} w_i   */
         apply_A(A, m, nn);                         /* n_i := A m_i        */
@@ -574,6 +608,10 @@ static int solve_pipe(const orc_op *A, const double *dinv, const orc_opts *o, in
     res->rel_res_recursive = sqrt(rho) / bnorm;
     true_residual(A, b, x, tmp, tr);
     res->rel_res_true = norm2(n, tr) / bnorm;
+    if (res->final_vecs) {
+        const double *v[ORC_NVEC] = {r, u, w, z, q, s, t, p, dinv};
+        dump_vecs(res->final_vecs, n, v);
+    }
     free(r); free(u); free(w); free(m); free(nn);
     free(z); free(q); free(s); free(t); free(p);
     free(tmp); free(tr); free(gap);
@@ -661,6 +699,10 @@ static int solve_pipe_var(const orc_op *A, const double *dinv, const orc_opts *o
         }
         if (i >= o->max_iter) { status = ORC_MAX_ITER; break; }
         if (!o->ignore_breakdown && (!(gamma > 0.0) || !(delta > 0.0))) { status = ORC_BREAKDOWN; break; }
+        if (res->snap && i == o->snap_iter) {
+            const double *v[ORC_NVEC] = {r, u, w, z, q, s, t, p, dinv};
+            dump_vecs(res->snap, n, v);
+        }
 
         apply_Minv(n, dinv, w, m);                 /* m_i := M^{-1} w_i   */
         apply_A(A, m, nn);                         /* n_i := A m_i        */
@@ -720,6 +762,10 @@ static int solve_pipe_var(const orc_op *A, const double *dinv, const orc_opts *o
     res->rel_res_recursive = sqrt(rho) / bnorm;
     true_residual(A, b, x, tmp, tr);
     res->rel_res_true = norm2(n, tr) / bnorm;
+    if (res->final_vecs) {
+        const double *v[ORC_NVEC] = {r, u, w, z, q, s, t, p, dinv};
+        dump_vecs(res->final_vecs, n, v);
+    }
     free(r); free(u); free(w); free(m); free(nn);
     free(z); free(q); free(s); free(t); free(p);
     free(tmp); free(tr); free(gap);

@@ -359,6 +359,137 @@ def test_fp32_storage_x_and_b_stay_binary64():
     assert np.any(r["x"] != r["x"].astype(np.float32).astype(np.float64))
 
 
+# ------------------------------------------------------------ FP32 storage emulation, by its definition
+
+# what each method keeps in memory between its steps (Alg. 1: r, u, p, s;
+# Algs. 2-4: r, u, w, z, q, s, t, p), plus the Jacobi diagonal when M = diag(A)
+KEPT = {"cg": ["r", "u", "p", "s"]}
+KEPT_PIPE = ["r", "u", "w", "z", "q", "s", "t", "p"]
+ALL_METHODS = ["cg", "pipe", "pipe_shift", "pipe_var", "pipe_rr"]
+
+
+def _fp32_exact(v):
+    return np.array_equal(v, v.astype(np.float32).astype(np.float64))
+
+
+def _storage_problem(kind):
+    # the banded random CSR is well conditioned with and without Jacobi, and its
+    # diagonal inverse is not binary32
+    return problems.poisson2d_manufactured(20) if kind == "2d5" else problems.banded_csr(400, seed=2)
+
+
+def _storage_kw(m, p, jacobi):
+    kw = dict(jacobi=jacobi, sigma=0.0)
+    if m == "pipe_shift":
+        kw["sigma"] = 1.0 if jacobi else 4.0
+    if m == "pipe_var":
+        mid = 1.0 if jacobi else 4.0
+        kw["sigma_schedule"] = [1.5 * mid] + [mid * (1.5 - 0.05 * k) for k in range(11)]
+    if p.op.kind == "csr" and not jacobi and m == "pipe_shift":
+        kw["sigma"] = float(np.max(p.op.val))  # inside the operator's spectrum
+    return kw
+
+
+def _check_storage(vecs, m, jacobi, csr, fp32):
+    """Every vector the method keeps (and the Jacobi diagonal) is binary32
+    representable in FP32-storage mode; in binary64 mode some is not (the
+    CSR diagonal inverse among them)."""
+    kept = KEPT.get(m, KEPT_PIPE) + (["dinv"] if jacobi else [])
+    for name in kept:
+        assert vecs[name] is not None, name
+    for name, v in vecs.items():
+        if name not in kept:
+            assert v is None, name
+    exact = {name: _fp32_exact(vecs[name]) for name in kept}
+    if fp32:
+        assert all(exact.values()), exact
+    else:
+        assert not all(exact.values()), exact
+        if jacobi and csr:
+            assert not exact["dinv"]
+    return exact
+
+
+@pytest.mark.parametrize("kind", ["2d5", "csr"])
+@pytest.mark.parametrize("jacobi", [False, True])
+@pytest.mark.parametrize("m", ALL_METHODS)
+def test_fp32_storage_every_kept_vector_is_binary32(m, jacobi, kind):
+    """FP32-storage form by its definition: each store of a kept vector is
+    rounded to binary32 -- at the initialisation (max_iter 0), in the
+    iteration (the vectors the solve returns with), and at a restart from x
+    (the vectors the next body finds) -- while x stays binary64 and carries
+    bits below binary32 resolution.  The same checks in binary64 storage
+    find vectors that are not binary32, so a dropped rounding at any of these
+    stores fails here."""
+    p = _storage_problem(kind)
+    csr = kind == "csr"
+    kw = _storage_kw(m, p, jacobi)
+    for fp32 in (True, False):
+        # the initialisation's stores
+        r0 = oracle.solve(p.op, p.b, method=m, rtol=1e-30, max_iter=0, fp32_storage=fp32, return_vectors=True, **kw)
+        assert r0["iterations"] == 0
+        init = {k: v for k, v in r0["final"].items()}
+        if m == "cg":
+            # s has not been stored before the first iteration (zero)
+            assert not np.any(init["s"])
+            init["s"] = init["s"] + 0.0
+        if fp32:
+            assert all(_fp32_exact(init[k]) for k in KEPT.get(m, KEPT_PIPE)[:3])
+        # the iteration's stores
+        r = oracle.solve(p.op, p.b, method=m, rtol=1e-30, max_iter=25, fp32_storage=fp32, return_vectors=True,
+                         ignore_breakdown=True, **kw)
+        assert r["iterations"] == 25
+        _check_storage(r["final"], m, jacobi, csr, fp32)
+        if fp32:
+            assert not _fp32_exact(r["x"])
+    if m == "pipe_rr":
+        # its own replacement keeps the explicit residual at the tolerance, so it
+        # claims no false convergence; its restart from x is p-CG's code
+        return
+    # a restart from x: the first tolerance whose claim of convergence the
+    # explicit residual misses in FP32 storage (unshifted p-CG stagnates and
+    # breaks down early, so its tolerance is larger), then the vectors that
+    # the body of that iteration finds after the restart
+    for rtol in (1e-9, 1e-7, 1e-6, 1e-5, 1e-4):
+        a = oracle.solve(p.op, p.b, method=m, rtol=rtol, max_iter=4000, fp32_storage=True, **kw)
+        if a["status"] == "converged" and a["rel_res_true"] > rtol:
+            break
+    assert a["status"] == "converged" and a["rel_res_true"] > rtol, (a["status"], a["rel_res_true"])
+    k = a["iterations"]
+    b = oracle.solve(p.op, p.b, method=m, rtol=rtol, max_iter=k + 1, fp32_storage=True, replace_max=1,
+                     snap_iter=k, **kw)
+    assert b["replacements"] == 1 and b["snap"] is not None
+    snap = b["snap"]
+    _check_storage(snap, m, jacobi, csr, True)
+    if m != "cg":
+        # a restart re-runs the initialisation: the beta-recurrence vectors start from zero
+        for name in ("z", "q", "s", "t", "p"):
+            assert not np.any(snap[name]), name
+
+
+@pytest.mark.parametrize("jacobi", [False, True])
+def test_fp32_storage_replacement_vectors_are_binary32(jacobi):
+    """p-CG-rr's replacement (r, u, w, s, q, z reset from x and p) stores in
+    binary32 too: the vectors the body of the first replaced iteration finds
+    are binary32, and they differ from the recurrences' values there."""
+    p = problems.poisson2d_manufactured(24)
+    kw = dict(method="pipe_rr", jacobi=jacobi, rtol=1e-12, fp32_storage=True, rr_period=8)
+    first = None
+    for k in range(8, 800, 8):
+        r = oracle.solve(p.op, p.b, max_iter=k + 1, **kw)
+        if r["replacements"] >= 1:
+            first = k
+            break
+    assert first is not None
+    got = oracle.solve(p.op, p.b, max_iter=first + 1, snap_iter=first, **kw)["snap"]
+    ref = oracle.solve(p.op, p.b, max_iter=first + 1, snap_iter=first, **dict(kw, method="pipe"))["snap"]
+    _check_storage(got, "pipe_rr", jacobi, False, True)
+    for name in ("r", "w", "s", "z"):
+        assert not np.array_equal(got[name], ref[name]), name
+    # t and p are not reset
+    assert np.array_equal(got["t"], ref["t"]) and np.array_equal(got["p"], ref["p"])
+
+
 # ------------------------------------------------------------ residual replacement
 
 def test_residual_replacement_restores_accuracy_fp32():
