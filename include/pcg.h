@@ -38,6 +38,7 @@
  *   - Device pointers are HIP device addresses (e.g. torch tensors' data_ptr).
  *     The library never allocates device memory: the caller provides a
  *     workspace of at least pcg_workspace_size() bytes (256-byte aligned).
+ *     The one exception is the fixed static scratch of pcg_solve_static.
  *   - All device work is issued on the caller's HIP stream (hipStream_t passed
  *     as void*, NULL = the legacy default stream), stream-ordered with the
  *     caller's own work.  pcg_solve() returns after the solve has completed.
@@ -221,6 +222,35 @@ pcg_status pcg_solve(pcg_solver solver, const double *b, double *x, pcg_result *
 pcg_status pcg_true_residual(pcg_solver solver, const double *b, const double *x, double *rel);
 
 pcg_status pcg_destroy(pcg_solver solver);
+
+/* ------------------------------------------------- solve without allocation */
+
+/* Size of the device scratch behind pcg_solve_static, per device. */
+#define PCG_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same solve as
+ * pcg_create + pcg_solve + pcg_destroy, with the workspace taken from a
+ * static device array of PCG_STATIC_SCRATCH_BYTES inside the library instead
+ * of caller memory.  It calls no hipMalloc, hipFree, hipHostMalloc, event or
+ * graph creation: the iteration passes are launched one by one on the
+ * caller's stream and the status is read back into ordinary host memory
+ * after each launch of K passes.  Same kernels, launch shape and results as
+ * pcg_solve with opt->use_graph = 0; opt->timing is ignored (iter_kernel_ms
+ * is 0).  op, opt, b, x, result: as for pcg_create and pcg_solve.  Blocks
+ * the calling thread until the solve is done.
+ * Limit: a solve whose pcg_workspace_size() exceeds PCG_STATIC_SCRATCH_BYTES
+ * is rejected with PCG_ERR_INVALID (pcg_last_error states both sizes); e.g.
+ * binary64 Jacobi p-CG-sh holds about 80 bytes per unknown, so n up to
+ * about 800,000.
+ * Sharing: each device has ONE scratch array, which keeps the contents of
+ * the last call.  Calls from threads of one process on the same device are
+ * serialised by a lock inside the library; anything else that overlapped
+ * two solves on one device's scratch would race.
+ */
+pcg_status pcg_solve_static(const pcg_operator *op, const pcg_options *opt, const double *b, double *x,
+                            pcg_result *result, void *hip_stream);
 
 /* -------------------------------------------------------------- autotuner */
 

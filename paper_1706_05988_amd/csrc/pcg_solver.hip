@@ -10,6 +10,7 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -398,6 +399,8 @@ struct pcg_solver_ {
     hipGraphExec_t gexec = nullptr;
     const double *graph_b = nullptr;  // b baked into the captured graph
     DevState *pinned = nullptr;       // 2 host slots for polled status
+    bool no_alloc = false;            // static-scratch solve: no pinned memory, events or graphs
+    DevState host_state[2] = {};      // its status slots (pageable host memory)
     hipEvent_t ev_begin[2] = {nullptr, nullptr};
     hipEvent_t ev_end[2] = {nullptr, nullptr};
     hipEvent_t ev_copy[2] = {nullptr, nullptr};
@@ -626,11 +629,12 @@ double pcg::default_sigma(const pcg_operator *op, const pcg_options *opt, const 
     return 0.5 * (gersh_host[0] + gersh_host[1]);
 }
 
-extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const pcg_options *opt, void *workspace,
-                                 size_t bytes, void *hip_stream)
+// Bind a solver object to (op, opt), a workspace and a stream: validation,
+// launch shape, workspace layout, kernel table, CSR set-up and the shift.
+// Allocates nothing; the caller has set s->pinned (status slots).
+static pcg_status init_solver(pcg_solver_ *s, const pcg_operator *op, const pcg_options *opt, void *workspace,
+                              size_t bytes, void *hip_stream)
 {
-    if (!out) return invalid("solver out-pointer is null");
-    *out = nullptr;
     pcg_status st = validate_options(opt);
     if (st) return st;
     if ((st = validate_operator(op, opt->prec))) return st;
@@ -642,7 +646,6 @@ extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const 
     const size_t need = layout(op, opt, sh, &L);
     if (bytes < need) return invalid("workspace too small");
 
-    pcg_solver_ *s = new pcg_solver_();
     s->op = *op;
     if (s->op.kind != PCG_OP_STENCIL3D7) s->op.nz = 1;
     s->opt = *opt;
@@ -657,6 +660,39 @@ extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const 
     if (opt->pc == PCG_PC_JACOBI && op->kind != PCG_OP_CSR)
         s->dinv_s = opt->prec == PCG_FP64 ? 1.0 / centre : (double)(float)(1.0 / centre);
 
+    double gersh[2] = {0.0, 0.0};
+    if (op->kind == PCG_OP_CSR) {
+        const int jac = opt->pc == PCG_PC_JACOBI;
+        if ((st = csr_setup(op, opt->prec, jac, jac ? s->ws + L.dinv : nullptr, reinterpret_cast<int *>(s->ws + L.flag),
+                            s->stream)))
+            return st;
+        if (opt->method == PCG_PIPE_SHIFT && std::isnan(opt->sigma) &&
+            (st = csr_gershgorin(op, opt->prec, jac, reinterpret_cast<double *>(s->ws + L.gersh), s->stream, &gersh[0],
+                                 &gersh[1])))
+            return st;
+    }
+    s->sigma = default_sigma(op, opt, gersh);
+    if (opt->method == PCG_PIPE_VAR_SHIFT) {
+        s->sched.assign(opt->sigma_schedule, opt->sigma_schedule + opt->sigma_schedule_len);
+        s->opt.sigma_schedule = nullptr;  // the caller's array is not kept
+        HIPCHK(hipMemcpyAsync(s->ws + L.sched, s->sched.data(), s->sched.size() * 8, hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
+    return PCG_OK;
+}
+
+extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const pcg_options *opt, void *workspace,
+                                 size_t bytes, void *hip_stream)
+{
+    if (!out) return invalid("solver out-pointer is null");
+    *out = nullptr;
+    pcg_status st = validate_options(opt);
+    if (st) return st;
+    if ((st = validate_operator(op, opt->prec))) return st;
+    if (!workspace || !aligned(workspace, 256)) return invalid("workspace must be non-null and 256-byte aligned");
+    if (bytes < layout(op, opt, choose_shape(op, opt), nullptr)) return invalid("workspace too small");
+
+    pcg_solver_ *s = new pcg_solver_();
     auto fail = [&](pcg_status e) {
         pcg_destroy(s);
         return e;
@@ -670,27 +706,7 @@ extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const 
         if ((he = hipEventCreateWithFlags(&s->ev_copy[k], hipEventDisableTiming)) != hipSuccess)
             return fail(hip_fail(he, "hipEventCreate"));
     }
-
-    double gersh[2] = {0.0, 0.0};
-    if (op->kind == PCG_OP_CSR) {
-        const int jac = opt->pc == PCG_PC_JACOBI;
-        if ((st = csr_setup(op, opt->prec, jac, jac ? s->ws + L.dinv : nullptr, reinterpret_cast<int *>(s->ws + L.flag),
-                            s->stream)))
-            return fail(st);
-        if (opt->method == PCG_PIPE_SHIFT && std::isnan(opt->sigma) &&
-            (st = csr_gershgorin(op, opt->prec, jac, reinterpret_cast<double *>(s->ws + L.gersh), s->stream, &gersh[0],
-                                 &gersh[1])))
-            return fail(st);
-    }
-    s->sigma = default_sigma(op, opt, gersh);
-    if (opt->method == PCG_PIPE_VAR_SHIFT) {
-        s->sched.assign(opt->sigma_schedule, opt->sigma_schedule + opt->sigma_schedule_len);
-        s->opt.sigma_schedule = nullptr;  // the caller's array is not kept
-        if ((he = hipMemcpyAsync(s->ws + L.sched, s->sched.data(), s->sched.size() * 8, hipMemcpyHostToDevice,
-                                 s->stream)) != hipSuccess)
-            return fail(hip_fail(he, "hipMemcpyAsync"));
-        if ((he = hipStreamSynchronize(s->stream)) != hipSuccess) return fail(hip_fail(he, "hipStreamSynchronize"));
-    }
+    if ((st = init_solver(s, op, opt, workspace, bytes, hip_stream))) return fail(st);
     *out = s;
     return PCG_OK;
 }
@@ -705,7 +721,7 @@ extern "C" pcg_status pcg_destroy(pcg_solver s)
         if (s->ev_end[k]) (void)hipEventDestroy(s->ev_end[k]);
         if (s->ev_copy[k]) (void)hipEventDestroy(s->ev_copy[k]);
     }
-    if (s->pinned) (void)hipHostFree(s->pinned);
+    if (s->pinned && !s->no_alloc) (void)hipHostFree(s->pinned);
     delete s;
     return PCG_OK;
 }
@@ -788,6 +804,17 @@ extern "C" pcg_status pcg_solve(pcg_solver s, const double *b, double *x, pcg_re
         bool done = false;
         for (int g = 0; !done; ++g) {
             const int slot = g & 1;
+            if (s->no_alloc) {
+                // one launch at a time, its status read back into pageable memory
+                if ((st = s->launch_iterations(b))) return st;
+                HIPCHK(hipMemcpyAsync(&s->pinned[slot], s->state(0), sizeof(DevState), hipMemcpyDeviceToHost,
+                                      s->stream));
+                HIPCHK(hipStreamSynchronize(s->stream));
+                ++launches;
+                done = s->pinned[slot].status != RUNNING;
+                if (done) S = s->pinned[slot];
+                continue;
+            }
             if (o.timing) HIPCHK(hipEventRecord(s->ev_begin[slot], s->stream));
             if ((st = s->launch_iterations(b))) return st;
             if (o.timing) HIPCHK(hipEventRecord(s->ev_end[slot], s->stream));
@@ -864,4 +891,54 @@ extern "C" pcg_status pcg_true_residual(pcg_solver s, const double *b, const dou
     if (st) return st;
     *rel = b2 > 0 ? std::sqrt(tr2) / std::sqrt(b2) : std::sqrt(tr2);
     return PCG_OK;
+}
+
+// ------------------------------------------------- static-scratch solve
+
+// Device scratch of pcg_solve_static: the workspace of one solver (state,
+// partials, Krylov vectors) lives here instead of in caller memory.  Each
+// device that runs the library holds its own copy until the process ends.
+// Host code never passes this array's name to a kernel or a copy: the name
+// is a host-side stand-in, and the device address comes from
+// hipGetSymbolAddress, per device.
+static __device__ __align__(256) char scratch[PCG_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu[kMaxDevices];       // one static solve per device at a time
+char *g_static_ptr[kMaxDevices] = {};      // device address of `scratch`, per device
+}  // namespace
+
+extern "C" pcg_status pcg_solve_static(const pcg_operator *op, const pcg_options *opt, const double *b, double *x,
+                                       pcg_result *result, void *hip_stream)
+{
+    if (!result) return invalid("result must be non-null");
+    pcg_status st = validate_options(opt);
+    if (st) return st;
+    if ((st = validate_operator(op, opt->prec))) return st;
+    if (!b || !x) return invalid("b and x must be non-null");
+    const size_t need = layout(op, opt, choose_shape(op, opt), nullptr);
+    if (need > PCG_STATIC_SCRATCH_BYTES) {
+        g_last_error = "invalid argument: the solve needs " + std::to_string(need) +
+                       " bytes of scratch; the static scratch holds " + std::to_string((size_t)PCG_STATIC_SCRATCH_BYTES);
+        return PCG_ERR_INVALID;
+    }
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return invalid("device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lk(g_static_mu[dev]);
+    if (!g_static_ptr[dev]) {
+        // once per device, with that device current
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_static_ptr[dev] = static_cast<char *>(p);
+    }
+    pcg_solver_ s;
+    s.no_alloc = true;
+    s.pinned = s.host_state;
+    pcg_options o = *opt;
+    o.use_graph = 0;  // passes are launched one by one: no graph instantiation
+    o.timing = 0;     // no events
+    if ((st = init_solver(&s, op, &o, g_static_ptr[dev], PCG_STATIC_SCRATCH_BYTES, hip_stream))) return st;
+    return pcg_solve(&s, b, x, result);
 }

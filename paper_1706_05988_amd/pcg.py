@@ -75,6 +75,8 @@ _SIGS = {
     "pcg_solve": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(pcg_result)]),
     "pcg_true_residual": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "pcg_destroy": (C.c_int32, [C.c_void_p]),
+    "pcg_solve_static": (C.c_int32, [C.POINTER(pcg_operator), C.POINTER(pcg_options), C.c_void_p, C.c_void_p,
+                                     C.POINTER(pcg_result), C.c_void_p]),
     "pcg_batch_workspace_size": (C.c_int32, [C.c_int32, C.POINTER(pcg_operator), C.POINTER(pcg_options),
                                              C.POINTER(C.c_size_t)]),
     "pcg_batch_solve": (C.c_int32, [C.c_int32, C.POINTER(pcg_operator), C.POINTER(pcg_options),
@@ -171,6 +173,29 @@ def pcg_true_residual(handle: int, b: int, x: int) -> float:
 
 def pcg_destroy(handle: int) -> None:
     _check(lib().pcg_destroy(handle), "pcg_destroy")
+
+
+PCG_STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def pcg_solve_static(op: pcg_operator, opt: pcg_options, b: int, x: int, stream: int) -> pcg_result:
+    r = pcg_result()
+    _check(lib().pcg_solve_static(C.byref(op), C.byref(opt), b, x, C.byref(r), stream), "pcg_solve_static")
+    return r
+
+
+def solve_static(op, options: pcg_options, b, x, device="cuda", stream: Optional[int] = None) -> dict:
+    """One solve through pcg_solve_static (the library's static device
+    scratch, no workspace): b, x device tensors (binary64)."""
+    import numpy as np
+    dev = _device_op(op, options.prec, device)
+    hist = None
+    if options.history_cap > 0:
+        hist = np.full((options.history_cap, PCG_HISTORY_FIELDS), np.nan)
+        options.history = hist.ctypes.data
+    st = current_stream_handle() if stream is None else stream
+    r = pcg_solve_static(dev.struct, options, b.data_ptr(), x.data_ptr(), st)
+    return result_dict(r, hist)
 
 
 def pcg_batch_workspace_size(ops: Sequence[pcg_operator], opts: Sequence[pcg_options]) -> int:

@@ -225,3 +225,32 @@ def test_batch_tune_rejects_bad_arguments_before_device_work():
     assert L.pcg_batch_tune(1, OA, PA, B, X, X, fake, 1 << 40, None, C.byref(ms)) == P.PCG_ERR_INVALID
     assert L.pcg_batch_tune(1, OA, PA, B, X0, X, fake, 16, None, C.byref(ms)) == P.PCG_ERR_INVALID
     assert PA[0].grid_blocks == 0 and PA[0].iters_per_launch == 0  # unchanged on error
+
+
+def test_static_solve_rejects_before_device_work():
+    """pcg_solve_static checks its arguments and the scratch limit before any
+    HIP call: a solve whose workspace exceeds the static scratch is refused
+    with a message that states both sizes."""
+    lib = P.lib()
+    r = P.pcg_result()
+    o = P.make_options(jacobi=True)
+    big = stencil_op(nx=256, ny=256, nz=256)
+    need = P.pcg_workspace_size(big, o)
+    assert need > P.PCG_STATIC_SCRATCH_BYTES
+    st = lib.pcg_solve_static(C.byref(big), C.byref(o), 0x100000, 0x200000, C.byref(r), None)
+    assert st == P.PCG_ERR_INVALID
+    msg = P.pcg_last_error()
+    assert str(need) in msg and str(P.PCG_STATIC_SCRATCH_BYTES) in msg
+    small = stencil_op()
+    assert lib.pcg_solve_static(C.byref(small), C.byref(o), 0x100000, 0x200000, None, None) == P.PCG_ERR_INVALID
+    assert lib.pcg_solve_static(C.byref(small), C.byref(o), None, 0x200000, C.byref(r), None) == P.PCG_ERR_INVALID
+    bad = P.make_options(rtol=-1.0)
+    assert lib.pcg_solve_static(C.byref(small), C.byref(bad), 0x100000, 0x200000, C.byref(r), None) == P.PCG_ERR_INVALID
+
+
+def test_static_scratch_size_matches_header():
+    import re
+    txt = open(P.HEADER).read()
+    m = re.search(r"#define PCG_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
+    assert m, "PCG_STATIC_SCRATCH_BYTES not found in pcg.h"
+    assert int(m.group(1)) << int(m.group(2)) == P.PCG_STATIC_SCRATCH_BYTES
