@@ -35,13 +35,13 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pipe_3d7_jacobi_fp64_256.json")
 # the rocprofv3 runs whose output --ingest-profile summarises (run from the repo root)
 PROFILE_COMMANDS = [
-    "rocprofv3 --kernel-trace --stats -d rocprof_out/prof_trace -o trace --output-format csv -- "
-    "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batched --no-serving",
-    "rocprofv3 --pmc FETCH_SIZE -d rocprof_out/prof_fetch -o fetch --output-format csv -- "
-    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-serving --max-iter 24 --calib-copy",
-    "rocprofv3 --pmc WRITE_SIZE -d rocprof_out/prof_write -o write --output-format csv -- "
-    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-serving --max-iter 24 --calib-copy",
-    "python3 bench.py --ingest-profile rocprof_out/prof_trace rocprof_out/prof_fetch rocprof_out/prof_write",
+    "rocprofv3 --kernel-trace --stats -d gpurun_out/prof_trace -o trace --output-format csv -- "
+    "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline --no-batched --no-serving --no-methods",
+    "rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof_fetch -o fetch --output-format csv -- "
+    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-serving --no-methods --max-iter 24 --calib-copy",
+    "rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof_write -o write --output-format csv -- "
+    "python3 bench.py --steps 1 --warmup 0 --no-cpu-baseline --no-batched --no-serving --no-methods --max-iter 24 --calib-copy",
+    "python3 bench.py --ingest-profile gpurun_out/prof_trace gpurun_out/prof_fetch gpurun_out/prof_write",
 ]
 KERNEL_SOURCES = ["paper_1706_05988_amd/csrc/pcg_kernels.h", "paper_1706_05988_amd/csrc/pcg_device.h"]
 
@@ -116,6 +116,34 @@ def copy_probe(torch, dev, nbytes: int = 1 << 31, reps: int = 5) -> float:
     del a, b
     torch.cuda.empty_cache()
     return 2 * nbytes / sec / 1e9
+
+
+def stream_ceiling(P, torch, n: int = 1 << 24, reps: int = 20) -> dict:
+    """Streaming bandwidth of plain probe kernels (pcg_stream_probe, the
+    fused passes' tiling) over buffers the size of the headline pass's
+    vectors (n binary64 values each): read only, copy, and 9 read + 9
+    written streams -- the fused p-CG-sh pass with Jacobi moves 8.5 + 8.5
+    vectors per iteration (x every other iteration), the 9 + 8 mix its
+    catch-up pass.  GB/s = bytes moved / average launch time."""
+    mixes = [("read", 16, 0, n, 0), ("copy", 1, 1, 9 * n, 0), ("r9w8", 9, 8, n, 0), ("r9w9", 9, 9, n, 0),
+             ("f32_r8w8", 8, 8, n, P.PCG_PROBE_FP32)]
+    need = max(P.stream_probe_bytes(i, o, m) for _, i, o, m, _ in mixes)
+    buf = torch.zeros(need + 256, dtype=torch.uint8, device="cuda")
+    ptr = (buf.data_ptr() + 255) & ~255
+    st = torch.cuda.current_stream().cuda_stream
+    out = {"vector_bytes": 8 * n}
+    for name, nin, nout, m, f32 in mixes:
+        for flags in (0, P.PCG_PROBE_NT, P.PCG_PROBE_NT | P.PCG_PROBE_BLOCKED):
+            if name == "copy" and flags & P.PCG_PROBE_BLOCKED:
+                continue
+            us = P.pcg_stream_probe(nin, nout, flags | f32, m, ptr, need, reps, st)
+            tag = ("_nt" if flags & P.PCG_PROBE_NT else "") + ("_blocked" if flags & P.PCG_PROBE_BLOCKED else "")
+            out[f"{name}{tag}_gbs"] = (nin + nout) * (4 if f32 else 8) * m / (us * 1e-6) / 1e9
+    del buf
+    torch.cuda.empty_cache()
+    out["best_read_write_gbs"] = max(v for k, v in out.items() if k.startswith(("copy", "r9")))
+    out["best_fp32_read_write_gbs"] = max(v for k, v in out.items() if k.startswith("f32_"))
+    return out
 
 
 def _csv(path_glob):
@@ -196,6 +224,143 @@ def ingest_profiles(trace_dir: str, fetch_dir: str, write_dir: str, kernel: str,
     return out
 
 
+# Passes profiled one at a time (--profile-pass NAME, then --ingest-pass NAME):
+# the workload, the kernel-name prefix rocprofv3 reports, and the storage form.
+PASS_PROFILES = {
+    "pipe_3d7_jacobi_fp32_256": dict(problem="poisson3d", N=256, fp32=True, kernel="k_pipe<float, 1, true"),
+    "pipe_csr_aniso1024_jacobi_fp64": dict(problem="aniso", N=1024, fp32=False, kernel="k_pipe<double, 2, true"),
+    "pipe_csr_aniso1024_jacobi_fp32": dict(problem="aniso", N=1024, fp32=True, kernel="k_pipe<float, 2, true"),
+    "batch_rect512_fp32_fullpass": dict(problem="batch", N=512, fp32=True, kernel="k_batch_step<float"),
+}
+
+
+def pass_commands(name: str) -> list:
+    d = f"gpurun_out/prof_{name}"
+    return [
+        f"rocprofv3 --kernel-trace --stats -d {d}_trace -o trace --output-format csv -- "
+        f"python3 bench.py --profile-pass {name} --passes 200",
+        f"rocprofv3 --pmc FETCH_SIZE -d {d}_fetch -o fetch --output-format csv -- "
+        f"python3 bench.py --profile-pass {name} --passes 24 --calib-copy",
+        f"rocprofv3 --pmc WRITE_SIZE -d {d}_write -o write --output-format csv -- "
+        f"python3 bench.py --profile-pass {name} --passes 24 --calib-copy",
+        f"python3 bench.py --ingest-pass {name} {d}_trace {d}_fetch {d}_write",
+    ]
+
+
+def pass_workload(name: str, seed: int = 0):
+    """(description, algorithmic bytes per working pass, builder) of a
+    profiled pass; the builder returns a callable that runs `passes` passes."""
+    import problems
+    cfg = PASS_PROFILES[name]
+    es = 4 if cfg["fp32"] else 8
+    if cfg["problem"] == "poisson3d":
+        p = problems.poisson3d(cfg["N"], seed=seed)
+        n = p.op.n
+        return (f"3-D Poisson 7-point {cfg['N']}^3 (n={n}), Jacobi, p-CG-sh sigma = 1, "
+                f"{'FP32-stream' if cfg['fp32'] else 'FP64'}",
+                bytes_per_unknown("pipe_shift", True, cfg["fp32"]) * n, p)
+    if cfg["problem"] == "aniso":
+        p = problems.anisotropic_csr(cfg["N"], seed=seed)
+        n, nnz = p.op.n, p.op.nnz
+        # streams: x rw every other pass, 7 vectors rw, w r + w' w; CSR values,
+        # indices, row_ptr, Jacobi diagonal
+        return (f"2-D anisotropic diffusion {cfg['N']}^2 CSR (n={n}, nnz={nnz}), Jacobi, p-CG-sh sigma = 1, "
+                f"{'FP32-stream' if cfg['fp32'] else 'FP64'}",
+                n * (8 + es * 16) + nnz * (4 + es) + 4 * (n + 1) + es * n, p)
+    ps = problems.batch_rectangles(cfg["N"], seed=seed)
+    tot = sum(q.op.n for q in ps)
+    # x rw (16 B) + r, z, s, t rw (8 es) + w r, w' w (2 es)
+    return (f"{cfg['N']} 2-D Poisson rectangles (sum n = {tot}), FP32-stream p-CG-sh sigma = 4 + c, "
+            f"every system iterating", tot * (16 + es * 10), ps)
+
+
+def run_pass_profile(P, torch, name: str, passes: int):
+    """Run `passes` iteration passes of the named workload twice (a warm-up
+    solve and the profiled one) with no stop test."""
+    cfg = PASS_PROFILES[name]
+    desc, bpp, prob = pass_workload(name)
+    if cfg["problem"] == "batch":
+        bs = [torch.from_numpy(q.b).cuda() for q in prob]
+        xs = [torch.zeros_like(b) for b in bs]
+        opts = [P.make_options(method="pipe_shift", fp32=True, sigma=q.sigma, rtol=1e-30, max_iter=passes,
+                               true_residual_check=False) for q in prob]
+        B = P.Batch([q.op for q in prob], opts)
+        for _ in range(2):
+            for x in xs:
+                x.zero_()
+            B.solve(bs, xs)
+    else:
+        opt = P.make_options(method="pipe_shift", jacobi=True, fp32=cfg["fp32"], sigma=1.0, rtol=1e-30,
+                             max_iter=passes, true_residual_check=False)
+        sv = P.Solver(prob.op, opt)
+        b = torch.from_numpy(prob.b).cuda()
+        x = torch.zeros_like(b)
+        for _ in range(2):
+            x.zero_()
+            sv.solve(b, x)
+        sv.close()
+    torch.cuda.synchronize()
+    print(f"[bench] profile pass {name}: {desc}, {passes} passes x 2, {bpp} algorithmic bytes per pass",
+          flush=True)
+
+
+def ingest_pass(name: str, trace_dir: str, fetch_dir: str, write_dir: str) -> dict:
+    """Summarise the rocprofv3 runs of pass_commands(name) into
+    profiles/<name>.md: the pass's duration (working dispatches: above half
+    the longest), HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE scaled
+    by the 1 GiB calibration copy, both against the algorithmic bytes."""
+    cfg = PASS_PROFILES[name]
+    kernel = cfg["kernel"]
+    desc, bpp, _ = pass_workload(name)
+    GiB_KiB = 2 ** 20
+    stats = _csv(os.path.join(trace_dir, "**", "*kernel_stats.csv"))
+    trace = _csv(os.path.join(trace_dir, "**", "*kernel_trace.csv"))
+    durs = [int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in trace if kernel in r["Kernel_Name"]]
+    work = [d for d in durs if d > 0.5 * max(durs)]
+    avg = sum(work) / len(work)
+
+    def counter(dirname, cname):
+        rows = _csv(os.path.join(dirname, "**", "*counter_collection.csv"))
+        copy = [float(r["Counter_Value"]) for r in rows
+                if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == cname]
+        kv = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"] and r["Counter_Name"] == cname]
+        kv = [v for v in kv if v > 0.5 * max(kv)]
+        calib = max(copy)
+        return sum(kv) / len(kv), calib, GiB_KiB / calib
+
+    f_kib, f_cal, f_scale = counter(fetch_dir, "FETCH_SIZE")
+    w_kib, w_cal, w_scale = counter(write_dir, "WRITE_SIZE")
+    traffic = (f_kib * f_scale + w_kib * w_scale) * 1024
+    out = {"pass": name, "kernel": kernel, "workload": desc, "kernel_source_hash": kernel_source_hash(),
+           "commands": pass_commands(name), "working_dispatches": len(work), "average_ns": avg,
+           "algorithmic_bytes_per_pass": bpp, "achieved_gbs": bpp / avg, "frac_of_8TBs": bpp / avg / HBM_PEAK_GBS,
+           "fetch_kib": f_kib, "write_kib": w_kib, "fetch_scale": f_scale, "write_scale": w_scale,
+           "traffic_bytes_per_pass": traffic, "traffic_over_algorithmic": traffic / bpp,
+           "traffic_gbs": traffic / avg}
+    top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:8]
+    lines = [f"# rocprofv3 summary: {name}", "", f"Workload: {desc}.", "",
+             "Commands (from the repository root, on the MI355X):", ""]
+    lines += [f"    {c}" for c in out["commands"]]
+    lines += ["", "## Kernel statistics of the trace run (--kernel-trace --stats)", "",
+              "| kernel | calls | average ns | % |", "|---|---|---|---|"]
+    lines += [f"| {r['Name'][:80]} | {r['Calls']} | {float(r['AverageNs']):.0f} | {float(r['Percentage']):.2f} |"
+              for r in top]
+    lines += ["", "## The pass", "",
+              f"- kernel `{kernel}...`: {len(work)} working dispatches, average {avg:.0f} ns",
+              f"- algorithmic bytes per pass {bpp} -> {bpp / avg:.0f} GB/s = "
+              f"{100 * bpp / avg / HBM_PEAK_GBS:.1f}% of 8 TB/s",
+              f"- calibration: a 1 GiB device copy reads as FETCH_SIZE {f_cal:.0f} KiB and WRITE_SIZE {w_cal:.0f} KiB "
+              f"-> scale factors {f_scale:.4f} (fetch), {w_scale:.4f} (write)",
+              f"- counters per working dispatch: FETCH_SIZE {f_kib:.0f} KiB, WRITE_SIZE {w_kib:.0f} KiB -> "
+              f"{traffic:.4g} B of HBM traffic ({traffic / bpp:.3f} x the algorithmic bytes, {traffic / avg:.0f} GB/s)",
+              f"- kernel source hash: {out['kernel_source_hash']}", ""]
+    with open(os.path.join(ROOT, "profiles", f"{name}.md"), "w") as f:
+        f.write("\n".join(lines))
+    with open(os.path.join(ROOT, "profiles", f"traffic_{name}.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    return out
+
+
 def _pct(v, q):
     import numpy as np
     return float(np.percentile(np.asarray(v), q)) if len(v) else None
@@ -263,6 +428,53 @@ def bench_batched(P, torch, count: int = 512, seed: int = 0) -> dict:
     }
 
 
+def bench_methods(P, torch, p, b, repeats: int = 3) -> list:
+    """Config 2's comparison on the headline problem (256^3, Jacobi, x0 = 0,
+    to 1e-10 with the binary64 explicit check): classic CG and p-CG in
+    binary64 and p-CG-sh in the FP32-stream form, each solved `repeats`
+    times after one warm-up.  Per method: iterations, iterations/s over the
+    timed solves, explicit residual, and the roofline of its iteration
+    passes on its own algorithmic bytes (HIP-event time of the iteration
+    launches on the solver's stream)."""
+    n = p.op.n
+    out = []
+    for method, fp32 in (("cg", False), ("pipe", False), ("pipe_shift", True)):
+        sig = p.sigma if method == "pipe_shift" else 0.0
+        opt = P.make_options(method=method, jacobi=True, fp32=fp32, sigma=sig, rtol=1e-10, max_iter=5000,
+                             replace_max=8, timing=True)
+        sv = P.Solver(p.op, opt)
+        x = torch.zeros_like(b)
+        sv.solve(b, x)
+        torch.cuda.synchronize()
+        rs = []
+        t0 = time.perf_counter()
+        for _ in range(repeats):
+            x.zero_()
+            rs.append(sv.solve(b, x))
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sv.close()
+        its = sum(r["iterations"] for r in rs)
+        passes = sum(r["iter_passes"] for r in rs)
+        kern_s = sum(r["iter_kernel_ms"] for r in rs) * 1e-3
+        bpu = bytes_per_unknown(method, True, fp32)
+        per_pass = bpu * n / (2 if method == "cg" else 1)
+        achieved = per_pass * passes / kern_s / 1e9
+        out.append({
+            "method": method, "form": "fp32-stream" if fp32 else "fp64", "sigma": sig,
+            "status": rs[-1]["status"], "iterations": rs[-1]["iterations"], "restarts": rs[-1]["replacements"],
+            "true_residual_max": max(r["rel_res_true"] for r in rs),
+            "iterations_per_s": its / wall, "ms_per_solve": wall / repeats * 1e3,
+            "roofline": {"bound": "hbm", "bytes_per_unknown": bpu, "achieved": achieved, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "avg_pass_us": kern_s / passes * 1e6,
+                         "kernel": "k_cg_a + k_cg_b" if method == "cg" else "k_pipe"},
+        })
+        print(f"[bench] {method} {'fp32-stream' if fp32 else 'fp64'}: {rs[-1]['iterations']} it, "
+              f"{its / wall:.0f} it/s, true {out[-1]['true_residual_max']:.3e}, {achieved:.0f} GB/s", flush=True)
+    return out
+
+
 def _serving_pool(log10_max: float, seed: int):
     """Operators for the serving stream: sizes on a grid of quarter decades
     from 1e3 to 10^log10_max; per size a 3-D cube (side round(n^(1/3))) and a
@@ -321,28 +533,36 @@ def bench_serving(P, torch, count: int, log10_max: float, seed: int = 0) -> dict
     del tb, x0s
 
     def run(arrivals):
+        """Submit at the scheduled arrival times; each result's latency is
+        counted from its scheduled arrival (a late submit adds its lateness)."""
         srv = P.Server(arena, max_slots=512)
         xs = [torch.zeros_like(b) for _, b in reqs]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        tickets = []
+        tickets, late = [], []
         for (op, b), x, ta in zip(reqs, xs, arrivals):
             dt = t0 + ta - time.perf_counter()
             if dt > 0:
                 time.sleep(dt)
+            late.append(max(0.0, time.perf_counter() - (t0 + ta)))
             tickets.append(srv.submit(op, opts(), b, x))
         res = [srv.wait(t) for t in tickets]
         total = time.perf_counter() - t0
+        info = srv.info()
         srv.close()
-        return res, total
+        for r, lt in zip(res, late):
+            r["latency"] = r["seconds"] + lt
+        return res, total, info
 
     run([0.0] * min(8, count))  # warm-up
-    sat, t_sat = run([0.0] * count)
+    sat, t_sat, _ = run([0.0] * count)
     capacity = count / t_sat
     rate = 0.7 * capacity
     arrivals = np.cumsum(rng.exponential(1.0 / rate, count))
-    live, t_live = run(list(arrivals))
-    lat = [r["seconds"] for r in live]
+    live, t_live, info = run(list(arrivals))
+    lat = [r["latency"] for r in live]
+    print(f"[bench] serving: capacity {capacity:.1f} solves/s, live {count / t_live:.1f} solves/s, "
+          f"p99 {_pct(lat, 99):.4f} s", flush=True)
     # comparator: one request at a time, binary64 CG, service times measured alone
     service = []
     for key, (_, b) in zip(keys, reqs):
@@ -359,10 +579,14 @@ def bench_serving(P, torch, count: int, log10_max: float, seed: int = 0) -> dict
         start = max(done, ta)
         done = start + sv_t
         fifo_lat.append(done - ta)
+    sizes = [int(reqs[k][0].struct.n) for k in range(count)]
     return {
-        "workload": f"{count} requests, n log-uniform 1e3..1e{log10_max:g} (quarter-decade size classes), "
-                    f"half 3-D 7-point cubes, half banded CSR (7-27 nnz/row), Jacobi, sigma = 1, "
-                    f"FP32-stream shifted p-CG to 1e-8",
+        "workload": f"{count} requests, n log-uniform 1e3..1e{log10_max:g} (quarter-decade size classes, "
+                    f"largest drawn n = {max(sizes)}), half 3-D 7-point cubes, half banded CSR (7-27 nnz/row), "
+                    f"Jacobi, sigma = 1, FP32-stream shifted p-CG to 1e-8; arena {arena >> 30} GiB",
+        "requests": count,
+        "largest_n": max(sizes),
+        "requests_above_1e6": int(sum(n > 10 ** 6 for n in sizes)),
         "capacity_solves_per_s": capacity,
         "launch_shape": {"grid_blocks": shape["grid_blocks"] or "default", "passes_per_launch":
                          shape["iters_per_launch"] or "default",
@@ -371,8 +595,12 @@ def bench_serving(P, torch, count: int, log10_max: float, seed: int = 0) -> dict
         "solves_per_s": count / t_live,
         "p50_latency_s": _pct(lat, 50),
         "p99_latency_s": _pct(lat, 99),
+        "latency_from": "scheduled arrival",
         "converged": int(sum(r["status"] == "converged" for r in live)),
         "max_true_residual": float(max(r["rel_res_true"] for r in live)),
+        "max_resident_requests": info["max_running"],
+        "launches": info["launches"],
+        "joined_a_running_batch": int(sum(r["admitted_at"] > 0 for r in live)),
         "sequential_fp64_cg": {"solves_per_s": count / sum(service), "p50_latency_s": _pct(fifo_lat, 50),
                                "p99_latency_s": _pct(fifo_lat, 99)},
     }
@@ -654,13 +882,20 @@ def main():
                     help="iteration cap (profiling runs use a short fixed count)")
     ap.add_argument("--no-batched", action="store_true", help="skip the 512-system batch leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the serving-stream leg")
-    ap.add_argument("--serving-requests", type=int, default=200)
-    ap.add_argument("--serving-max-log10", type=float, default=6.0,
+    ap.add_argument("--no-methods", action="store_true",
+                    help="skip the CG / p-CG / FP32-stream p-CG-sh comparison on the headline problem")
+    ap.add_argument("--serving-requests", type=int, default=1000)
+    ap.add_argument("--serving-max-log10", type=float, default=7.0,
                     help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
-    ap.add_argument("--report", choices=["c2", "c3", "small", "tune", "psi", "batch"],
+    ap.add_argument("--report", choices=["c2", "c3", "small", "tune", "psi", "batch", "stream"],
                     help="print a measurement report (C3 accuracy per shift, or the latency-bound cases) and exit")
     ap.add_argument("--c3-N", type=int, default=1024)
     ap.add_argument("--c3-max-iter", type=int, default=12000)
+    ap.add_argument("--profile-pass", choices=sorted(PASS_PROFILES),
+                    help="run a fixed number of passes of one workload (for rocprofv3) and exit")
+    ap.add_argument("--passes", type=int, default=200)
+    ap.add_argument("--ingest-pass", nargs=4, metavar=("NAME", "TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="summarise the rocprofv3 runs of --profile-pass NAME into profiles/ and exit")
     ap.add_argument("--ingest-profile", nargs=3, metavar=("TRACE_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="summarise rocprofv3 output of this benchmark into profiles/ and exit")
     ap.add_argument("--calib-copy", action="store_true",
@@ -673,6 +908,10 @@ def main():
         res = ingest_profiles(t, fdir, wdir, "k_pipe<double, 1, true", "pipe_3d7_jacobi_fp64_256",
                               commands=PROFILE_COMMANDS)
         print(json.dumps(res, indent=1))
+        return
+
+    if args.ingest_pass:
+        print(json.dumps(ingest_pass(*args.ingest_pass), indent=1))
         return
 
     if args.gpus != 1:
@@ -693,6 +932,7 @@ def main():
                report_small(P, torch) if args.report == "small" else
                report_psi(P, torch) if args.report == "psi" else
                bench_batched(P, torch) if args.report == "batch" else
+               stream_ceiling(P, torch) if args.report == "stream" else
                report_c2(P, torch, args.N) if args.report == "c2" else report_tune(P, torch))
         print(json.dumps(rep), flush=True)
         return
@@ -704,6 +944,9 @@ def main():
         torch.cuda.synchronize()
         print("[bench] calibration: 3 copies of 1 GiB (2^27 doubles) done", flush=True)
         del src, dst
+    if args.profile_pass:
+        run_pass_profile(P, torch, args.profile_pass, args.passes)
+        return
     t_gen = time.perf_counter()
     p = problems.poisson3d(args.N, seed=0, jacobi=True)
     n = p.op.n
@@ -789,8 +1032,27 @@ def main():
         },
         "cpu_baseline": None,
     }
+    if args.N == 256 and args.method == "pipe_shift" and not args.fp32 and not fixed:
+        # the survey's accounting moves x every iteration (144 B per unknown);
+        # this pass moves it every other iteration (136 B)
+        svy = 144 * n / avg_pass_s / 1e9
+        out["roofline"]["at_144_bytes_per_unknown"] = {"achieved": svy, "frac": svy / HBM_PEAK_GBS}
+    if not args.calib_copy:
+        # plain streaming kernels over the same vector sizes, same run
+        sp = stream_ceiling(P, torch, n)
+        out["roofline"]["stream_probe"] = sp
+        out["roofline"]["frac_of_best_stream_probe"] = achieved / sp["best_read_write_gbs"]
+        print(f"[bench] stream probe: read {sp['read_nt_gbs']:.0f}, copy {sp['copy_nt_gbs']:.0f}, "
+              f"9r/8w {sp['r9w8_nt_gbs']:.0f} (blocked {sp['r9w8_nt_blocked_gbs']:.0f}), "
+              f"9r/9w {sp['r9w9_nt_gbs']:.0f} (blocked {sp['r9w9_nt_blocked_gbs']:.0f}) GB/s (non-temporal)",
+              flush=True)
     solver.close()
-    del solver, b, x
+    del solver, x
+    torch.cuda.empty_cache()
+    if not args.no_methods and args.N == 256 and not fixed:
+        print("[bench] methods leg", flush=True)
+        out["methods"] = bench_methods(P, torch, p, b)
+    del b
     torch.cuda.empty_cache()
     if not args.no_batched:
         print("[bench] batched leg", flush=True)

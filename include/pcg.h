@@ -184,7 +184,9 @@ typedef struct {
     double iter_kernel_ms;      /* HIP-event time of the iteration launches (timing = 1)  */
     int32_t iter_passes;        /* iteration passes that did work (iterations of all methods;
                                    CG counts 2 passes per iteration)                       */
-    int32_t reserved;
+    int32_t admitted_at;        /* server: launches the server had issued when the request
+                                   joined the batch (it was resident for `launches`
+                                   launches from there); 0 for the other entry points      */
     double sigma;               /* the shift actually used                                */
 } pcg_result;
 
@@ -349,11 +351,34 @@ pcg_status pcg_server_create(pcg_server *server, void *arena, size_t arena_bytes
  * runs (non-finite right-hand side, breakdown) reports that in its result's
  * status and pcg_wait / pcg_poll return PCG_OK; the other requests are
  * unaffected.  A HIP error during a launch fails every running request:
- * their pcg_wait / pcg_poll return that error. */
+ * their pcg_wait / pcg_poll return that error; the server drains its stream,
+ * takes back their slots and arena ranges and goes on with the queue. */
 pcg_status pcg_submit(pcg_server server, const pcg_operator *op, const pcg_options *opt,
                       const double *b, double *x, uint64_t *ticket);
 pcg_status pcg_poll(pcg_server server, uint64_t ticket, pcg_result *result);   /* PCG_PENDING until done */
 pcg_status pcg_wait(pcg_server server, uint64_t ticket, pcg_result *result);
+
+/* Counters of a server (a snapshot under the server's lock). */
+typedef struct {
+    int64_t submitted;          /* tickets issued                                          */
+    int64_t completed;          /* requests finished (PCG_OK from pcg_wait / pcg_poll)      */
+    int64_t failed;             /* requests that failed (admission or launch errors)        */
+    int32_t queued;             /* waiting for a slot or arena space                        */
+    int32_t running;            /* resident on the device now                               */
+    int32_t max_running;        /* most requests resident in one launch so far              */
+    int32_t launches;           /* launches of K passes issued                              */
+    size_t arena_bytes;         /* arena bytes available to requests (after the tables)     */
+    size_t arena_free;          /* of which free now                                        */
+    size_t arena_largest_free;  /* largest free contiguous range                            */
+} pcg_server_stats;
+
+pcg_status pcg_server_info(pcg_server server, pcg_server_stats *stats);
+
+/* A server whose process environment sets PCG_SERVER_FAIL_AT_LAUNCH=k at
+ * pcg_server_create fails its k-th launch (counted from 0) without issuing
+ * any device work, as a HIP error would: a test hook for the failure path,
+ * whose requests get PCG_ERR_HIP while their slots and arena ranges return
+ * to the server. */
 pcg_status pcg_server_destroy(pcg_server server);
 
 /* ------------------------------------------------------- shift selection */
@@ -391,6 +416,36 @@ pcg_status pcg_psi_variable(const double *alpha, const double *beta, int32_t i, 
  * slack = 1 is the plain argmin (ties to the smaller shift). */
 pcg_status pcg_select_shift(const double *alpha, const double *beta, int32_t i, const double *grid,
                             int32_t grid_len, double slack, double *psi_out, double *sigma_best);
+
+/* --------------------------------------------------------- measurement */
+
+/*
+ * Streaming-bandwidth probe: the ceiling the fused iteration passes, whose
+ * bound is HBM bandwidth, are compared with.  One launch streams nin input
+ * and nout output vectors of n binary64 values with the fused passes'
+ * tiling (a persistent grid of four 256-thread blocks per CU, 4 values per
+ * thread per tile, every load of a tile issued before its stores); output j
+ * receives in_j + c_j * (sum of the inputs).  flags: PCG_PROBE_NT puts the
+ * non-temporal hint on every access; PCG_PROBE_BLOCKED lays the streams out
+ * as the solver's workspace does (512-value tiles of every stream one after
+ * another) instead of one vector after another; PCG_PROBE_FP32 streams
+ * binary32 values instead of binary64 (bytes moved per launch then
+ * (nin + nout) * 4 n).
+ * Supported mixes: nout = 0 with nin in {1, 2, 4, 8, 9, 16} (read only; each
+ * block writes one sum to a sink), and (nin, nout) in {(1, 1), (2, 1),
+ * (4, 4), (5, 4), (8, 8), (9, 8), (9, 9)}.
+ * buffer: device, 256-byte aligned, at least (nin + nout) * round_up(8 n,
+ * 4096) + 65536 bytes (the streams, then the sink); its contents are read
+ * and overwritten.  One warm-up launch, then `reps` launches between two HIP
+ * events on hip_stream; *us_per_launch (host) receives their average
+ * duration.  Bytes moved per launch: (nin + nout) * 8 n (binary64).  Errors:
+ * PCG_ERR_INVALID (sizes, mix, flags, buffer), PCG_ERR_HIP.
+ */
+#define PCG_PROBE_NT      1
+#define PCG_PROBE_BLOCKED 2
+#define PCG_PROBE_FP32    4
+pcg_status pcg_stream_probe(int32_t nin, int32_t nout, int32_t flags, int64_t n, void *buffer, size_t bytes,
+                            int32_t reps, void *hip_stream, double *us_per_launch);
 
 /* ------------------------------------------------------------------ misc */
 

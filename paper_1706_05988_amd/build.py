@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libpcg.so")
 ARCH = os.environ.get("PCG_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["pcg_solver.hip", "pcg_batch.hip", "pcg_server.hip", "pcg_tune.hip", "pcg_shift.cpp"]
+SOURCES = ["pcg_solver.hip", "pcg_batch.hip", "pcg_server.hip", "pcg_tune.hip", "pcg_stream.hip", "pcg_shift.cpp"]
 
 # -Xclang -target-feature -Xclang -packed-fp32-ops keeps the compiler from
 # emitting packed FP32 VALU instructions on gfx950.
@@ -60,7 +60,7 @@ def build(verbose: bool = False) -> str:
         subprocess.run(cmd, check=True)
         return obj
 
-    with ThreadPoolExecutor(max_workers=min(4, len(srcs))) as ex:
+    with ThreadPoolExecutor(max_workers=min(6, len(srcs))) as ex:
         objs = list(ex.map(compile_one, srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs + ["-lpthread"]

@@ -524,12 +524,13 @@ pcg_status BatchEngine::upload_tables()
     uint32_t *act = reinterpret_cast<uint32_t *>(h_list_ + 16);
     uint32_t *items = reinterpret_cast<uint32_t *>(h_list_ + list_items_off(max_sys_));
     int64_t ni = 0;
-    int na = 0;
+    int na = 0, most = 0;
     for (int s = 0; s < max_sys_; ++s) {
         listed_[s] = 0;
         if (!in_use_[s] || h_st_[s].phase >= PH_DONE) continue;
         listed_[s] = 1;
         act[na++] = (uint32_t)s;
+        most = std::max(most, (int)sys_[s].ntiles);
         for (int t = 0; t < sys_[s].ntiles; ++t) {
             if (ni >= max_items_) return PCG_ERR_BUDGET;
             items[2 * ni] = (uint32_t)s;
@@ -557,6 +558,7 @@ pcg_status BatchEngine::upload_tables()
     tables_dirty_ = false;
     items_ = ni;
     active_ = na;
+    max_sys_items_ = most;
     return PCG_OK;
 }
 
@@ -636,7 +638,9 @@ pcg_status BatchEngine::step(double *gpu_ms)
     pcg_status st;
     if (tables_dirty_ && (st = upload_tables())) return st;
     if (active_ == 0) return PCG_OK;
-    const int split = items_ > split_items_ ? 1 : 0;
+    // split when the batch is large, or when one system is: in a fused pass
+    // each of a system's items sums all of that system's partials
+    const int split = (items_ > split_items_ || max_sys_items_ > fused_sys_items_) ? 1 : 0;
     if ((st = ensure_graph(split))) return st;
     BCHK(hipEventRecord(ev0_, stream_));
     BCHK(hipGraphLaunch(gexec_[split], stream_));

@@ -70,6 +70,12 @@ private:
     // above this many items a launch runs split (measured: the fused head
     // costs ~100 us per pass on a full 512-system batch, the extra kernel ~5 us)
     int64_t split_items_ = 4096;
+    // ... and when a listed system has more items than this: in a fused pass
+    // every item block of a system runs stage 2 over all of that system's
+    // partials, so that head's reads grow with the square of its item count
+    // (a 4M-unknown system: ~3900 items, ~1.5 GB of partial reads per pass)
+    int fused_sys_items_ = 64;
+    int max_sys_items_ = 0;  // most items of one listed system
     hipStream_t stream_ = nullptr;
     BatchSys *d_sys_ = nullptr;
     BatchState *d_st_ = nullptr;

@@ -12,6 +12,7 @@
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -74,6 +75,12 @@ public:
         for (auto &f : free_) m = std::max(m, f.second);
         return m;
     }
+    size_t total_free() const
+    {
+        size_t t = 0;
+        for (auto &f : free_) t += f.second;
+        return t;
+    }
 
 private:
     std::map<size_t, size_t> free_;  // offset -> length
@@ -90,6 +97,7 @@ struct Request {
     Clock::time_point t_submit;
     ReqState state = Q_QUEUED;
     int slot = -1;
+    int admitted_at = 0;  // server launches issued before the request joined the batch
     size_t off = 0, bytes = 0;
     pcg_result res{};
     pcg_status err = PCG_OK;
@@ -115,10 +123,35 @@ struct pcg_server_ {
     bool stop = false;
     std::string error;
     std::thread sched;
+    int64_t n_submitted = 0, n_completed = 0, n_failed = 0;
+    int max_running = 0;       // most systems resident in one launch
+    int launches = 0;          // launches issued by the scheduler
+    int fail_at_launch = -1;   // fault injection (PCG_SERVER_FAIL_AT_LAUNCH): that launch fails
 
     void loop();
     bool admit_head();
+    void fail_running(pcg_status st);
 };
+
+// A launch failed: every running request fails with `st`.  The stream is
+// drained first, so no pass of the failed launch still touches their memory,
+// then their batch slots and arena ranges are returned, so the server keeps
+// serving the requests that follow.  Called with mu held.
+void pcg_server_::fail_running(pcg_status st)
+{
+    error = g_last_error;
+    (void)hipStreamSynchronize(stream);
+    for (auto &kv : running) {
+        Request *r = kv.second;
+        eng->release(kv.first);
+        heap.release(r->off, r->bytes);
+        r->state = Q_FAILED;
+        r->err = st;
+        ++n_failed;
+    }
+    running.clear();
+    cv_done.notify_all();
+}
 
 bool pcg_server_::admit_head()
 {
@@ -134,11 +167,13 @@ bool pcg_server_::admit_head()
         heap.release(off, r->bytes);
         r->state = Q_FAILED;
         r->err = st;
+        ++n_failed;
         cv_done.notify_all();
         return true;
     }
     r->off = off;
     r->slot = slot;
+    r->admitted_at = launches;
     r->state = Q_RUNNING;
     running[slot] = r;
     return true;
@@ -155,18 +190,21 @@ void pcg_server_::loop()
             cv_work.wait(lk, [&] { return stop || !queue.empty(); });
             continue;
         }
+        max_running = std::max(max_running, (int)running.size());
+        const bool inject = launches == fail_at_launch;
         lk.unlock();
-        const pcg_status st = eng->step(nullptr);
+        pcg_status st;
+        if (inject) {
+            g_last_error = "injected failure of server launch " + std::to_string(fail_at_launch);
+            st = PCG_ERR_HIP;
+        } else {
+            st = eng->step(nullptr);
+        }
         lk.lock();
+        ++launches;
         if (st != PCG_OK) {
             // a device error ends every running request
-            error = g_last_error;
-            for (auto &kv : running) {
-                kv.second->state = Q_FAILED;
-                kv.second->err = st;
-            }
-            running.clear();
-            cv_done.notify_all();
+            fail_running(st);
             continue;
         }
         for (auto it = running.begin(); it != running.end();) {
@@ -179,9 +217,12 @@ void pcg_server_::loop()
             eng->result(slot, &r->res);
             if (r->opt.history_cap > 0) eng->copy_history(slot, r->opt.history, r->opt.history_cap);
             r->res.seconds = std::chrono::duration<double>(Clock::now() - r->t_submit).count();
+            r->res.admitted_at = r->admitted_at;
+            r->res.launches = launches - r->admitted_at;
             eng->release(slot);
             heap.release(r->off, r->bytes);
             r->state = Q_DONE;
+            ++n_completed;
             it = running.erase(it);
         }
         cv_done.notify_all();
@@ -208,6 +249,7 @@ extern "C" pcg_status pcg_server_create(pcg_server *out, void *arena, size_t are
     s->tables_bytes = tb;
     s->heap.init(arena_bytes - tb);
     s->prec = -1;  // the engine is set up for the first request's precision
+    if (const char *f = std::getenv("PCG_SERVER_FAIL_AT_LAUNCH")) s->fail_at_launch = std::atoi(f);
     s->sched = std::thread([s] { s->loop(); });
     *out = s;
     return PCG_OK;
@@ -250,6 +292,7 @@ extern "C" pcg_status pcg_submit(pcg_server s, const pcg_operator *op, const pcg
     }
     if (((L.bytes + 255) & ~size_t(255)) > s->arena_bytes - s->tables_bytes) return PCG_ERR_BUDGET;
     r->ticket = s->next_ticket++;
+    ++s->n_submitted;
     *ticket = r->ticket;
     s->queue.push_back(r.get());
     s->reqs[r->ticket] = std::move(r);
@@ -281,6 +324,25 @@ extern "C" pcg_status pcg_wait(pcg_server s, uint64_t ticket, pcg_result *res)
 {
     if (!s) return PCG_ERR_STATE;
     return take_result(s, ticket, res, true);
+}
+
+extern "C" pcg_status pcg_server_info(pcg_server s, pcg_server_stats *out)
+{
+    if (!s) return PCG_ERR_STATE;
+    if (!out) return invalid("stats is null");
+    std::lock_guard<std::mutex> lk(s->mu);
+    std::memset(out, 0, sizeof(*out));
+    out->submitted = s->n_submitted;
+    out->completed = s->n_completed;
+    out->failed = s->n_failed;
+    out->queued = (int32_t)s->queue.size();
+    out->running = (int32_t)s->running.size();
+    out->max_running = s->max_running;
+    out->launches = s->launches;
+    out->arena_bytes = s->arena_bytes - s->tables_bytes;
+    out->arena_free = s->heap.total_free();
+    out->arena_largest_free = s->heap.largest();
+    return PCG_OK;
 }
 
 extern "C" pcg_status pcg_server_destroy(pcg_server s)

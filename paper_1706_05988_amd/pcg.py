@@ -56,7 +56,14 @@ class pcg_result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("replacements", C.c_int32),
                 ("launches", C.c_int32), ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double),
                 ("seconds", C.c_double), ("iter_kernel_ms", C.c_double), ("iter_passes", C.c_int32),
-                ("reserved", C.c_int32), ("sigma", C.c_double)]
+                ("admitted_at", C.c_int32), ("sigma", C.c_double)]
+
+
+class pcg_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("queued", C.c_int32), ("running", C.c_int32), ("max_running", C.c_int32),
+                ("launches", C.c_int32), ("arena_bytes", C.c_size_t), ("arena_free", C.c_size_t),
+                ("arena_largest_free", C.c_size_t)]
 
 
 class PcgError(RuntimeError):
@@ -91,6 +98,7 @@ _SIGS = {
     "pcg_poll": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(pcg_result)]),
     "pcg_wait": (C.c_int32, [C.c_void_p, C.c_uint64, C.POINTER(pcg_result)]),
     "pcg_server_destroy": (C.c_int32, [C.c_void_p]),
+    "pcg_server_info": (C.c_int32, [C.c_void_p, C.POINTER(pcg_server_stats)]),
     "pcg_status_str": (C.c_char_p, [C.c_int32]),
     "pcg_tune_workspace_size": (C.c_int32, [C.POINTER(pcg_operator), C.POINTER(pcg_options), C.POINTER(C.c_size_t)]),
     "pcg_tune": (C.c_int32, [C.POINTER(pcg_operator), C.POINTER(pcg_options), C.c_void_p, C.c_size_t, C.c_void_p,
@@ -101,6 +109,8 @@ _SIGS = {
     "pcg_select_shift": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
                                      C.c_void_p, C.POINTER(C.c_double)]),
     "pcg_last_error": (C.c_char_p, []),
+    "pcg_stream_probe": (C.c_int32, [C.c_int32, C.c_int32, C.c_int32, C.c_int64, C.c_void_p, C.c_size_t,
+                                     C.c_int32, C.c_void_p, C.POINTER(C.c_double)]),
 }
 
 
@@ -256,6 +266,12 @@ def pcg_wait(server: int, ticket: int) -> pcg_result:
     return r
 
 
+def pcg_server_info(server: int) -> dict:
+    st = pcg_server_stats()
+    _check(lib().pcg_server_info(server, C.byref(st)), "pcg_server_info")
+    return {name: getattr(st, name) for name, _ in pcg_server_stats._fields_}
+
+
 def pcg_server_destroy(server: int) -> None:
     _check(lib().pcg_server_destroy(server), "pcg_server_destroy")
 
@@ -348,6 +364,23 @@ def tune(op, options: pcg_options, b=None, device="cuda", stream: Optional[int] 
     us = pcg_tune(dev.struct, out, ptr, nbytes, b.data_ptr(), x.data_ptr(), st)
     torch.cuda.synchronize()
     return out, us
+
+
+PCG_PROBE_NT, PCG_PROBE_BLOCKED, PCG_PROBE_FP32 = 1, 2, 4
+
+
+def pcg_stream_probe(nin: int, nout: int, flags: int, n: int, buffer: int, nbytes: int, reps: int,
+                     stream: int) -> float:
+    """Average microseconds of one streaming launch (nin read, nout written
+    streams of n binary64 values)."""
+    us = C.c_double()
+    _check(lib().pcg_stream_probe(int(nin), int(nout), int(flags), int(n), buffer, int(nbytes), int(reps),
+                                  stream, C.byref(us)), "pcg_stream_probe")
+    return us.value
+
+
+def stream_probe_bytes(nin: int, nout: int, n: int) -> int:
+    return (nin + nout) * ((8 * n + 4095) // 4096 * 4096) + 65536
 
 
 def _f64(a):
@@ -467,7 +500,7 @@ def result_dict(r: pcg_result, hist=None) -> dict:
     d = dict(status=OUTCOME.get(r.status, str(r.status)), iterations=r.iterations,
              replacements=r.replacements, launches=r.launches, rel_res_recursive=r.rel_res_recursive,
              rel_res_true=r.rel_res_true, seconds=r.seconds, iter_kernel_ms=r.iter_kernel_ms,
-             iter_passes=r.iter_passes, sigma=r.sigma)
+             iter_passes=r.iter_passes, admitted_at=r.admitted_at, sigma=r.sigma)
     if hist is not None:
         k = r.iterations + 1
         d.update(res=hist[:k, 0].copy(), alpha=hist[:k, 1].copy(), beta=hist[:k, 2].copy(),
@@ -544,8 +577,15 @@ class Server:
         return result_dict(r, self._keep.pop(ticket)[4])
 
     def wait(self, ticket: int) -> dict:
-        r = pcg_wait(self.handle, ticket)
+        try:
+            r = pcg_wait(self.handle, ticket)
+        except PcgError:
+            self._keep.pop(ticket, None)
+            raise
         return result_dict(r, self._keep.pop(ticket)[4])
+
+    def info(self) -> dict:
+        return pcg_server_info(self.handle)
 
     def close(self):
         if self.handle:

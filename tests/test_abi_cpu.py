@@ -163,7 +163,8 @@ def test_option_struct_layout_matches_header():
     import tempfile
     fields = {"pcg_options": [f for f, _ in P.pcg_options._fields_],
               "pcg_operator": [f for f, _ in P.pcg_operator._fields_],
-              "pcg_result": [f for f, _ in P.pcg_result._fields_]}
+              "pcg_result": [f for f, _ in P.pcg_result._fields_],
+              "pcg_server_stats": [f for f, _ in P.pcg_server_stats._fields_]}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "pcg.h"', "int main(void) {"]
     for st, fs in fields.items():
         src.append(f'printf("{st} %zu\\n", sizeof({st}));')
@@ -254,3 +255,20 @@ def test_static_scratch_size_matches_header():
     m = re.search(r"#define PCG_STATIC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", txt)
     assert m, "PCG_STATIC_SCRATCH_BYTES not found in pcg.h"
     assert int(m.group(1)) << int(m.group(2)) == P.PCG_STATIC_SCRATCH_BYTES
+
+
+def test_stream_probe_rejects_before_device_work():
+    lib = P.lib()
+    us = C.c_double()
+    n = 1 << 20
+    need = P.stream_probe_bytes(9, 9, n)
+    assert need == 18 * 8 * n + 65536
+    assert P.stream_probe_bytes(1, 1, 513) == 2 * 8192 + 65536
+    assert lib.pcg_stream_probe(9, 9, 8, n, 0x100000, need, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
+    # an unsupported mix, a short buffer, a misaligned buffer, bad sizes
+    assert lib.pcg_stream_probe(3, 3, 1, n, 0x100000, need, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
+    assert lib.pcg_stream_probe(9, 9, 1, n, 0x100000, need - 8, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
+    assert lib.pcg_stream_probe(9, 9, 1, n, 0x100008, need, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
+    assert lib.pcg_stream_probe(9, 9, 1, 0, 0x100000, need, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
+    assert lib.pcg_stream_probe(9, 9, 1, n, 0x100000, need, 0, None, C.byref(us)) == P.PCG_ERR_INVALID
+    assert lib.pcg_stream_probe(9, 9, 1, n, 0x100000, need, 10, None, None) == P.PCG_ERR_INVALID

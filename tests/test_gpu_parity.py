@@ -47,12 +47,12 @@ def gpu_solve(torch, p, method, jacobi=None, fp32=False, sigma=None, rtol=None, 
     return r
 
 
-def oracle_solve(p, method, jacobi=None, fp32=False, sigma=None, rtol=None, max_iter=None, **kw):
+def oracle_solve(p, method, jacobi=None, fp32=False, sigma=None, rtol=None, max_iter=None, threads=8, **kw):
     return oracle.solve(p.op, p.b, p.x0, method=method,
                         sigma=(p.sigma if method == "pipe_shift" else 0.0) if sigma is None else sigma,
                         rtol=p.rtol if rtol is None else rtol,
                         max_iter=p.max_iter if max_iter is None else max_iter,
-                        jacobi=p.jacobi if jacobi is None else jacobi, fp32_storage=fp32, threads=8, **kw)
+                        jacobi=p.jacobi if jacobi is None else jacobi, fp32_storage=fp32, threads=threads, **kw)
 
 
 def check_history(g, o, upto=50, rtol=1e-10):
@@ -359,23 +359,51 @@ def test_workspace_too_small_rejected(torch):
 
 # ---------------------------------------------------------------- full size (configs 2, 3)
 
-def test_config2_full_size_sampled(torch):
-    """3-D Poisson 256^3, Jacobi, sigma = 1, FP64, in the benchmark's launch
-    configuration: the first iterations' residual history matches the oracle
-    on the same input, and the solve reaches a true residual <= 1e-10."""
+def sample_index(n, nxy, nx, seed):
+    """Sampled unknowns plus the first and last tiles and the first and last
+    grid planes' opening rows."""
+    return np.unique(np.concatenate([
+        np.random.default_rng(seed).integers(0, n, 4000), np.arange(0, 1024), np.arange(n - 1024, n),
+        np.arange(nxy, nxy + nx), np.arange(n - nxy, n - nxy + nx)]))
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_config2_full_size_fifty_iterations(torch, method):
+    """3-D Poisson 256^3 (16.8M unknowns), Jacobi, sigma = 1, FP64, in the
+    benchmark's launch configuration: sqrt(rho_i)/||b||, alpha_i and beta_i
+    match the oracle's to 1e-10 over the first 50 iterations, and x after
+    them matches at sampled unknowns, the first and last tiles and planes
+    included."""
     p = problems.poisson3d(256, seed=0)
-    o = oracle_solve(p, "pipe_shift", max_iter=3, rtol=1e-30)
-    g3 = gpu_solve(torch, p, "pipe_shift", max_iter=3, rtol=1e-30, true_residual_check=False)
-    np.testing.assert_allclose(g3["res"][:4], o["res"][:4], rtol=1e-12)
-    np.testing.assert_allclose(g3["alpha"][:3], o["alpha"][:3], rtol=1e-12)
-    # x after 3 iterations at sampled unknowns
-    idx = np.random.default_rng(0).integers(0, p.op.n, 1000)
-    np.testing.assert_allclose(g3["x"][idx], o["x"][idx], rtol=1e-11, atol=1e-14)
-    g = gpu_solve(torch, p, "pipe_shift", hist=False)
-    assert g["status"] == "converged"
+    o = oracle_solve(p, method, max_iter=50, rtol=1e-30, threads=oracle.max_threads())
+    print(f"[parity] 256^3 {method}: oracle 50 iterations done", flush=True)
+    g = gpu_solve(torch, p, method, max_iter=50, rtol=1e-30, true_residual_check=False)
+    assert g["iterations"] == o["iterations"] == 50
+    check_history(g, o, upto=50)
+    idx = sample_index(p.op.n, 256 * 256, 256, 2)
+    np.testing.assert_allclose(g["x"][idx], o["x"][idx], rtol=1e-10, atol=1e-12 * np.abs(o["x"]).max())
+
+
+@pytest.mark.parametrize("method", METHODS)
+def test_config2_full_solve_final_residual(torch, method):
+    """The complete 256^3 solve to 1e-10 with the explicit-residual check and
+    restarts from x (the benchmark's options), GPU against the oracle with the
+    same restart rule: the same iteration count (within one), and final
+    explicit residuals ||b - A x||/||b|| within 1e-12 (p-CG: within a 10x
+    band, its attainable level being rounding-determined)."""
+    p = problems.poisson3d(256, seed=0)
+    o = oracle_solve(p, method, replace_max=4, record=False, threads=oracle.max_threads())
+    print(f"[parity] 256^3 {method}: oracle full solve {o['iterations']} iterations, "
+          f"true residual {o['rel_res_true']:.3e}", flush=True)
+    g = gpu_solve(torch, p, method, hist=False, replace_max=4)
+    assert g["status"] == o["status"] == "converged", (g["status"], o["status"])
+    assert abs(g["iterations"] - o["iterations"]) <= 1
     assert g["rel_res_true"] <= 1e-10
-    err = np.abs(g["x"] - p.x_true).max()
-    assert err < 1e-6
+    if method == "pipe":
+        assert g["rel_res_true"] <= 10 * o["rel_res_true"] and o["rel_res_true"] <= 10 * g["rel_res_true"]
+    else:
+        assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-12
+    assert np.abs(g["x"] - p.x_true).max() < 1e-6
 
 
 def test_largest_grid_sampled(torch):
@@ -410,16 +438,25 @@ def test_largest_grid_sampled(torch):
 @pytest.mark.parametrize("fp32", [False, True])
 def test_config3_full_size_sampled(torch, fp32):
     """2-D anisotropic diffusion 1024^2 CSR (5.24M nonzeros), Jacobi, sigma = 1,
-    in the report's launch configuration: the first 10 iterations' residual
-    history and x at sampled unknowns match the oracle (in the same storage
-    form) on the same input."""
+    in the report's launch configuration, against the oracle in the same
+    storage form on the same input.  Binary64: the residual history, alpha
+    and beta to 1e-10 over the first 50 iterations and x after them at
+    sampled unknowns (the last rows included).  FP32-stream: the first 10
+    iterations at binary32 resolution (1e-4; later iterates of the two sides
+    part at the binary32 rounding of the stored vectors)."""
     p = problems.anisotropic_csr(1024, seed=0)
-    kw = dict(fp32=fp32, sigma=1.0, max_iter=10, rtol=1e-30)
-    o = oracle_solve(p, "pipe_shift", **kw)
+    its = 10 if fp32 else 50
+    kw = dict(fp32=fp32, sigma=1.0, max_iter=its, rtol=1e-30)
+    o = oracle_solve(p, "pipe_shift", threads=oracle.max_threads(), **kw)
     g = gpu_solve(torch, p, "pipe_shift", true_residual_check=False, **kw)
     tol = 1e-4 if fp32 else 1e-10
-    np.testing.assert_allclose(g["res"][:11], o["res"][:11], rtol=tol)
-    idx = np.random.default_rng(1).integers(0, p.op.n, 2000)
+    if fp32:
+        np.testing.assert_allclose(g["res"][: its + 1], o["res"][: its + 1], rtol=tol)
+    else:
+        assert g["iterations"] == o["iterations"] == its
+        check_history(g, o, upto=its)
+    n = p.op.n
+    idx = np.unique(np.concatenate([np.random.default_rng(1).integers(0, n, 4000), np.arange(n - 2048, n)]))
     np.testing.assert_allclose(g["x"][idx], o["x"][idx], rtol=10 * tol, atol=10 * tol * np.abs(o["x"]).max())
 
 

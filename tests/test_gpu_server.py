@@ -85,10 +85,14 @@ def test_server_admits_while_running_and_respects_budget(torch):
     th.start()
     th.join()
     res = [srv.wait(t) for t in tickets]
+    info = srv.info()
     srv.close()
     for p, r in zip(ps, res):
         assert r["status"] == "converged", p.name
         assert r["rel_res_true"] <= 1e-8
+    assert info["completed"] == len(ps) and info["failed"] == 0
+    assert info["running"] == 0 and info["queued"] == 0
+    assert info["arena_free"] == info["arena_bytes"]  # every range returned
     # identical requests give identical bits whenever they ran
     n = len(request_set())
     for k in range(n):
@@ -148,3 +152,110 @@ def test_server_failed_request_leaves_the_others_alone(torch):
         assert res[k]["status"] == alone["status"] == "converged"
         assert res[k]["iterations"] == alone["iterations"]
         assert np.array_equal(alone["x"], xs[k].cpu().numpy())
+
+
+def test_server_fp64_requests_match_the_oracle_in_a_mixed_stream(torch):
+    """Binary64 requests of every operator kind, submitted one by one while
+    the others run: each result follows the oracle on the same system --
+    sqrt(rho_i)/||b||, alpha_i and beta_i to 1e-10 over the first 50
+    iterations and the final explicit residual to 1e-12."""
+    import oracle
+    from paper_1706_05988_amd import pcg as P
+    ps = request_set()
+    for p in ps:
+        p.rtol = 1e-10
+    srv = P.Server(256 << 20, max_slots=16)
+    bs = [torch.from_numpy(p.b).cuda() for p in ps]
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    tickets = []
+    for p, b, x in zip(ps, bs, xs):
+        o = P.make_options(method="pipe_shift", jacobi=p.jacobi, sigma=p.sigma, rtol=p.rtol, max_iter=p.max_iter,
+                           true_residual_check=False, history_cap=p.max_iter + 2)
+        tickets.append(srv.submit(p.op, o, b, x))
+        time.sleep(0.003)
+    res = [srv.wait(t) for t in tickets]
+    srv.close()
+    assert any(r["admitted_at"] > 0 for r in res)  # some joined a running batch
+    for p, r, x in zip(ps, res, xs):
+        o = oracle.solve(p.op, p.b, p.x0, method="pipe_shift", sigma=p.sigma, rtol=p.rtol, max_iter=p.max_iter,
+                         jacobi=p.jacobi, threads=8)
+        assert r["status"] == o["status"] == "converged", p.name
+        assert abs(r["iterations"] - o["iterations"]) <= 1, p.name
+        k = min(50, o["iterations"], r["iterations"])
+        np.testing.assert_allclose(r["res"][: k + 1], o["res"][: k + 1], rtol=1e-10, err_msg=p.name)
+        np.testing.assert_allclose(r["alpha"][:k], o["alpha"][:k], rtol=1e-10, err_msg=p.name)
+        np.testing.assert_allclose(r["beta"][1:k], o["beta"][1:k], rtol=1e-10, err_msg=p.name)
+        assert abs(r["rel_res_true"] - o["rel_res_true"]) <= 1e-12, (p.name, r["rel_res_true"], o["rel_res_true"])
+
+
+def test_server_launch_failure_returns_slots_and_memory(torch, monkeypatch):
+    """A launch that fails (injected from the host: the server issues no
+    device work for it) fails the requests then running with PCG_ERR_HIP;
+    their slots and arena ranges come back, and the same requests submitted
+    afterwards get the bits they get alone."""
+    from paper_1706_05988_amd import pcg as P
+    ps = request_set()[:4]
+    monkeypatch.setenv("PCG_SERVER_FAIL_AT_LAUNCH", "1")
+    srv = P.Server(16 << 20, max_slots=4)
+    monkeypatch.delenv("PCG_SERVER_FAIL_AT_LAUNCH")
+    bs = [torch.from_numpy(p.b).cuda() for p in ps]
+    xs = [torch.zeros_like(b) for b in bs]
+    tickets = [srv.submit(p.op, opts(P, p), b, x) for p, b, x in zip(ps, bs, xs)]
+    outcome = []
+    for t in tickets:
+        try:
+            outcome.append(srv.wait(t)["status"])
+        except P.PcgError as e:
+            outcome.append(e.status)
+    failed = [o for o in outcome if o == P.PCG_ERR_HIP]
+    assert failed, outcome  # the slow ones were still running at launch 1
+    info = srv.info()
+    assert info["failed"] == len(failed)
+    assert info["running"] == 0 and info["arena_free"] == info["arena_bytes"]
+    # the server goes on: every slot and the whole arena are usable again
+    xs2 = [torch.zeros_like(b) for b in bs]
+    res = [srv.wait(srv.submit(p.op, opts(P, p), b, x)) for p, b, x in zip(ps, bs, xs2)]
+    info = srv.info()
+    srv.close()
+    assert info["arena_free"] == info["arena_bytes"] and info["running"] == 0
+    for p, r, x in zip(ps, res, xs2):
+        assert r["status"] == "converged", p.name
+        alone = solve_alone(torch, P, p)
+        assert np.array_equal(alone["x"], x.cpu().numpy()), p.name
+
+
+def test_server_joins_requests_into_a_running_batch(torch):
+    """Continuous batching: requests submitted while a long solve is on the
+    device join its batch at a later launch (the long one still iterating),
+    run beside it, and give the bits they give alone."""
+    from paper_1706_05988_amd import pcg as P
+    op = problems.stencil2d(300, 280)  # no preconditioner: ~1000 iterations, many launches
+    b_long = np.random.default_rng(5).uniform(-1, 1, op.n)
+    long_p = problems.Problem("long", op, b_long, np.zeros(op.n), None, sigma=4.0, rtol=1e-8, max_iter=20000)
+    short = request_set()[:3]
+    srv = P.Server(256 << 20, max_slots=8)
+    bl = torch.from_numpy(long_p.b).cuda()
+    xl = torch.zeros_like(bl)
+    bs = [torch.from_numpy(p.b).cuda() for p in short]
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    t_long = srv.submit(long_p.op, opts(P, long_p), bl, xl)
+    for _ in range(20000):  # until the long solve has run two launches
+        if srv.info()["launches"] >= 2:
+            break
+        time.sleep(0.0005)
+    tickets = [srv.submit(p.op, opts(P, p), b, x) for p, b, x in zip(short, bs, xs)]
+    res = [srv.wait(t) for t in tickets]
+    r_long = srv.wait(t_long)
+    info = srv.info()
+    srv.close()
+    assert r_long["status"] == "converged" and r_long["admitted_at"] == 0
+    end_long = r_long["admitted_at"] + r_long["launches"]
+    for p, r, x in zip(short, res, xs):
+        assert r["status"] == "converged", p.name
+        assert 2 <= r["admitted_at"] < end_long, (r["admitted_at"], end_long)
+        alone = solve_alone(torch, P, p)
+        assert np.array_equal(alone["x"], x.cpu().numpy()), p.name
+    assert info["max_running"] >= 2
+    assert np.array_equal(solve_alone(torch, P, long_p)["x"], xl.cpu().numpy())
