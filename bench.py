@@ -121,10 +121,12 @@ def copy_probe(torch, dev, nbytes: int = 1 << 31, reps: int = 5) -> float:
 def stream_ceiling(P, torch, n: int = 1 << 24, reps: int = 20) -> dict:
     """Streaming bandwidth of plain probe kernels (pcg_stream_probe, the
     fused passes' tiling) over buffers the size of the headline pass's
-    vectors (n binary64 values each): read only, copy, and 9 read + 9
-    written streams -- the fused p-CG-sh pass with Jacobi moves 8.5 + 8.5
+    vectors (n values each): read only, copy, and 9 read + 9 written
+    binary64 streams -- the fused p-CG-sh pass with Jacobi moves 8.5 + 8.5
     vectors per iteration (x every other iteration), the 9 + 8 mix its
-    catch-up pass.  GB/s = bytes moved / average launch time."""
+    catch-up pass -- and 8 + 8 binary32 streams (the FP32-stream passes'
+    balance of reads and writes); each the fastest of 1, 2 and 4 blocks per
+    CU.  GB/s = bytes moved / average launch time."""
     mixes = [("read", 16, 0, n, 0), ("copy", 1, 1, 9 * n, 0), ("r9w8", 9, 8, n, 0), ("r9w9", 9, 9, n, 0),
              ("f32_r8w8", 8, 8, n, P.PCG_PROBE_FP32)]
     need = max(P.stream_probe_bytes(i, o, m) for _, i, o, m, _ in mixes)
@@ -133,12 +135,17 @@ def stream_ceiling(P, torch, n: int = 1 << 24, reps: int = 20) -> dict:
     st = torch.cuda.current_stream().cuda_stream
     out = {"vector_bytes": 8 * n}
     for name, nin, nout, m, f32 in mixes:
-        for flags in (0, P.PCG_PROBE_NT, P.PCG_PROBE_NT | P.PCG_PROBE_BLOCKED):
+        for flags in (0, P.PCG_PROBE_NT, P.PCG_PROBE_NT | P.PCG_PROBE_BLOCKED, P.PCG_PROBE_NT | P.PCG_PROBE_WIDE):
             if name == "copy" and flags & P.PCG_PROBE_BLOCKED:
                 continue
-            us = P.pcg_stream_probe(nin, nout, flags | f32, m, ptr, need, reps, st)
-            tag = ("_nt" if flags & P.PCG_PROBE_NT else "") + ("_blocked" if flags & P.PCG_PROBE_BLOCKED else "")
-            out[f"{name}{tag}_gbs"] = (nin + nout) * (4 if f32 else 8) * m / (us * 1e-6) / 1e9
+            # the persistent grid at 1, 2 and 4 blocks per CU; the fastest counts
+            best = 0.0
+            for per_cu in (1, 2, 4):
+                us = P.pcg_stream_probe(nin, nout, flags | f32 | (per_cu << 8), m, ptr, need, reps, st)
+                best = max(best, (nin + nout) * (4 if f32 else 8) * m / (us * 1e-6) / 1e9)
+            tag = (("_nt" if flags & P.PCG_PROBE_NT else "") + ("_blocked" if flags & P.PCG_PROBE_BLOCKED else "")
+                   + ("_wide" if flags & P.PCG_PROBE_WIDE else ""))
+            out[f"{name}{tag}_gbs"] = best
     del buf
     torch.cuda.empty_cache()
     out["best_read_write_gbs"] = max(v for k, v in out.items() if k.startswith(("copy", "r9")))
@@ -231,6 +238,12 @@ PASS_PROFILES = {
     "pipe_csr_aniso1024_jacobi_fp64": dict(problem="aniso", N=1024, fp32=False, kernel="k_pipe<double, 2, true"),
     "pipe_csr_aniso1024_jacobi_fp32": dict(problem="aniso", N=1024, fp32=True, kernel="k_pipe<float, 2, true"),
     "batch_rect512_fp32_fullpass": dict(problem="batch", N=512, fp32=True, kernel="k_batch_step<float"),
+    # classic CG's two passes (bytes per unknown: A reads r and p, writes p' and s;
+    # B reads x, r, p', s and writes x and r)
+    "cg_a_3d7_jacobi_fp64_256": dict(problem="poisson3d", N=256, fp32=False, method="cg",
+                                     kernel="k_cg_a_zm<double", bytes_per_unknown=32),
+    "cg_b_3d7_jacobi_fp64_256": dict(problem="poisson3d", N=256, fp32=False, method="cg",
+                                     kernel="k_cg_b<double, 1, true", bytes_per_unknown=48),
 }
 
 
@@ -256,6 +269,9 @@ def pass_workload(name: str, seed: int = 0):
     if cfg["problem"] == "poisson3d":
         p = problems.poisson3d(cfg["N"], seed=seed)
         n = p.op.n
+        if cfg.get("method") == "cg":
+            return (f"3-D Poisson 7-point {cfg['N']}^3 (n={n}), Jacobi, classic CG, FP64",
+                    cfg["bytes_per_unknown"] * n, p)
         return (f"3-D Poisson 7-point {cfg['N']}^3 (n={n}), Jacobi, p-CG-sh sigma = 1, "
                 f"{'FP32-stream' if cfg['fp32'] else 'FP64'}",
                 bytes_per_unknown("pipe_shift", True, cfg["fp32"]) * n, p)
@@ -290,8 +306,9 @@ def run_pass_profile(P, torch, name: str, passes: int):
                 x.zero_()
             B.solve(bs, xs)
     else:
-        opt = P.make_options(method="pipe_shift", jacobi=True, fp32=cfg["fp32"], sigma=1.0, rtol=1e-30,
-                             max_iter=passes, true_residual_check=False)
+        method = cfg.get("method", "pipe_shift")
+        opt = P.make_options(method=method, jacobi=True, fp32=cfg["fp32"], sigma=1.0 if method == "pipe_shift" else 0.0,
+                             rtol=1e-30, max_iter=passes, true_residual_check=False)
         sv = P.Solver(prob.op, opt)
         b = torch.from_numpy(prob.b).cuda()
         x = torch.zeros_like(b)
@@ -684,6 +701,112 @@ def report_c3(P, torch, N: int, max_iter: int) -> dict:
     return out
 
 
+def report_csr_sizes(P, torch, sizes=(512, 1024, 2048, 4096), passes: int = 200) -> dict:
+    """The fused CSR pass (2-D anisotropic diffusion N^2, Jacobi, p-CG-sh
+    sigma = 1) over grid sizes, both storage forms, reading the operator as
+    CSR or as its sliced-ELL copy, at the built-in launch shape: average
+    microseconds per pass (HIP events over `passes` passes) and algorithmic
+    GB/s.  A fit t = t0 + bytes / BW over the sizes separates the per-pass
+    fixed cost from the streaming rate."""
+    import numpy as np
+    import problems
+    out = {"workload": "2-D anisotropic diffusion N^2 CSR, Jacobi, p-CG-sh sigma = 1, " f"{passes} passes", "runs": []}
+    for N in sizes:
+        p = problems.anisotropic_csr(N, seed=0)
+        n, nnz = p.op.n, p.op.nnz
+        b = torch.from_numpy(p.b).cuda()
+        for fp32 in (False, True):
+            es = 4 if fp32 else 8
+            bpp = n * (8 + es * 16) + nnz * (4 + es) + 4 * (n + 1) + es * n
+            dev = P.DeviceOperator(p.op, P.PCG_FP32_STREAM if fp32 else P.PCG_FP64)
+            for sell in (False, True):
+                # the built-in CSR shapes: binary64 1 row per thread, 128 threads;
+                # FP32-stream 2 rows per thread, 256 threads; 4 blocks per CU
+                var = P.PCG_VAR_SET | P.PCG_VAR_NT | (0 if fp32 else P.PCG_VAR_EPT1) | (P.PCG_VAR_CSR_SELL if sell else 0)
+                opt = P.make_options(method="pipe_shift", jacobi=True, fp32=fp32, sigma=1.0, rtol=1e-30,
+                                     max_iter=passes, true_residual_check=False, timing=True, variant=var,
+                                     block_size=256 if fp32 else 128, grid_blocks=1024)
+                sv = P.Solver(dev, opt)
+                x = torch.zeros_like(b)
+                sv.solve(b, x)
+                x.zero_()
+                r = sv.solve(b, x)
+                sv.close()
+                us = r["iter_kernel_ms"] * 1e3 / max(1, r["iter_passes"])
+                out["runs"].append({"N": N, "n": n, "nnz": nnz, "form": "fp32-stream" if fp32 else "fp64",
+                                    "operand": "sliced-ELL" if sell else "CSR", "us_per_pass": us,
+                                    "bytes_per_pass": bpp, "gbs": bpp / (us * 1e-6) / 1e9})
+                print(out["runs"][-1], flush=True)
+            del dev
+        del b
+        torch.cuda.empty_cache()
+    for form in ("fp64", "fp32-stream"):
+        for operand in ("CSR", "sliced-ELL"):
+            rs = [r for r in out["runs"] if r["form"] == form and r["operand"] == operand]
+            A = np.array([[1.0, r["bytes_per_pass"]] for r in rs])
+            t = np.array([r["us_per_pass"] * 1e-6 for r in rs])
+            (t0, inv_bw), *_ = np.linalg.lstsq(A, t, rcond=None)
+            out[f"fit_{form}_{operand}"] = {"fixed_us": t0 * 1e6, "streaming_gbs": 1.0 / inv_bw / 1e9}
+    return out
+
+
+def report_csr_shapes(P, torch, sizes=(1024, 2048), passes: int = 200) -> dict:
+    """Launch shapes of the fused CSR pass (2-D anisotropic diffusion N^2,
+    Jacobi, p-CG-sh sigma = 1), both storage forms, CSR rows or the
+    sliced-ELL copy: 1, 2 or 4 rows per thread x 128 or 256 threads x 1, 2,
+    4 (and for 128 threads 8) blocks per CU; microseconds per pass over
+    `passes` passes (HIP events), then the built-in shape for reference."""
+    import problems
+    out = {"workload": f"2-D anisotropic diffusion N^2 CSR, Jacobi, p-CG-sh sigma = 1, {passes} passes",
+           "runs": []}
+    ept_bits = {1: P.PCG_VAR_EPT1, 2: 0, 4: P.PCG_VAR_EPT4}
+    for N in sizes:
+        p = problems.anisotropic_csr(N, seed=0)
+        n, nnz = p.op.n, p.op.nnz
+        b = torch.from_numpy(p.b).cuda()
+        for fp32 in (False, True):
+            es = 4 if fp32 else 8
+            bpp = n * (8 + es * 16) + nnz * (4 + es) + 4 * (n + 1) + es * n
+            dev = P.DeviceOperator(p.op, P.PCG_FP32_STREAM if fp32 else P.PCG_FP64)
+            shapes = [(None, None, None, None)]
+            for sell in (False, True):
+                for ept in (1, 2, 4):
+                    for block in (128, 256):
+                        for per_cu in (1, 2, 4, 8):
+                            if per_cu == 8 and block != 128:
+                                continue
+                            shapes.append((sell, ept, block, per_cu))
+            best = None
+            for sell, ept, block, per_cu in shapes:
+                if sell is None:
+                    kw = {}
+                else:
+                    kw = dict(variant=P.PCG_VAR_SET | P.PCG_VAR_NT | ept_bits[ept] | (P.PCG_VAR_CSR_SELL if sell else 0),
+                              block_size=block, grid_blocks=per_cu * 256)
+                opt = P.make_options(method="pipe_shift", jacobi=True, fp32=fp32, sigma=1.0, rtol=1e-30,
+                                     max_iter=passes, true_residual_check=False, timing=True, **kw)
+                sv = P.Solver(dev, opt)
+                x = torch.zeros_like(b)
+                sv.solve(b, x)
+                x.zero_()
+                r = sv.solve(b, x)
+                sv.close()
+                us = r["iter_kernel_ms"] * 1e3 / max(1, r["iter_passes"])
+                row = {"N": N, "form": "fp32-stream" if fp32 else "fp64",
+                       "shape": "built-in" if sell is None else
+                       f"{'sell' if sell else 'csr'} ept{ept} b{block} x{per_cu}/CU",
+                       "us_per_pass": round(us, 2), "gbs": round(bpp / (us * 1e-6) / 1e9)}
+                out["runs"].append(row)
+                if best is None or us < best["us_per_pass"]:
+                    best = row
+            out[f"best_{N}_{'fp32' if fp32 else 'fp64'}"] = best
+            print(best, [r for r in out["runs"] if r["shape"] == "built-in"][-1], flush=True)
+            del dev
+        del b
+        torch.cuda.empty_cache()
+    return out
+
+
 def report_c2(P, torch, N: int = 256) -> dict:
     """The 3-D Poisson problem (N^3, Jacobi, x_true ~ U(-1, 1), x0 = 0):
     classic CG, p-CG and p-CG-sh in binary64, p-CG-sh in the FP32-stream
@@ -887,7 +1010,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=1000)
     ap.add_argument("--serving-max-log10", type=float, default=7.0,
                     help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
-    ap.add_argument("--report", choices=["c2", "c3", "small", "tune", "psi", "batch", "stream"],
+    ap.add_argument("--report", choices=["c2", "c3", "small", "tune", "psi", "batch", "stream", "csr_sizes",
+                                         "csr_shapes"],
                     help="print a measurement report (C3 accuracy per shift, or the latency-bound cases) and exit")
     ap.add_argument("--c3-N", type=int, default=1024)
     ap.add_argument("--c3-max-iter", type=int, default=12000)
@@ -933,6 +1057,8 @@ def main():
                report_psi(P, torch) if args.report == "psi" else
                bench_batched(P, torch) if args.report == "batch" else
                stream_ceiling(P, torch) if args.report == "stream" else
+               report_csr_sizes(P, torch) if args.report == "csr_sizes" else
+               report_csr_shapes(P, torch) if args.report == "csr_shapes" else
                report_c2(P, torch, args.N) if args.report == "c2" else report_tune(P, torch))
         print(json.dumps(rep), flush=True)
         return

@@ -144,7 +144,7 @@ typedef struct {
     int32_t variant;            /* 0: the tuned kernel variant; else PCG_VAR_SET | bits below */
     int32_t sigma_schedule_len; /* PCG_PIPE_VAR_SHIFT: entries of sigma_schedule, 1 .. 2^24    */
     int32_t rr_period;          /* PCG_PIPE_RR: gap check every rr_period iterations (0: 8)  */
-    int32_t reserved;
+    int32_t flags;              /* PCG_FLAG_* bits below (0: none)                          */
     const double *sigma_schedule; /* PCG_PIPE_VAR_SHIFT: HOST array sigma_{-1}, sigma_0,
                                    sigma_1, ... (each finite, >= 0); entry k + 1 is the shift
                                    of iteration k and the last entry repeats past the end.
@@ -159,6 +159,15 @@ typedef struct {
                                    rounding scale of b - A x; NaN or <= 0: 100               */
 } pcg_options;
 
+/* Option flags (pcg_options.flags).
+ * PCG_FLAG_RUN_THROUGH_BREAKDOWN: pcg_solve and pcg_solve_static do not stop
+ * at a breakdown (gamma <= 0, delta <= 0, (s, p) <= 0, or an alpha that is
+ * not finite and positive) but run on to the stop test or the iteration
+ * cap, as the accuracy runs of Section 5.1 do (Table 1 reports p-CG after a
+ * fixed number of iterations); non-finite dot products still end the solve.
+ * The batch and server entry points reject the flag. */
+#define PCG_FLAG_RUN_THROUGH_BREAKDOWN 0x01
+
 /* Kernel variant bits (pcg_options.variant).  Every variant performs the same
  * per-unknown arithmetic; they differ in how unknowns map to threads, so the
  * order in which dot-product partials are accumulated (and hence the last
@@ -172,6 +181,10 @@ typedef struct {
 #define PCG_VAR_CG_ZMARCH 0x40  /* PCG_CG, 3-D stencil: pass A marches along z through
                                    LDS also where the built-in rule would not (grids
                                    with fewer work items than CUs)                      */
+#define PCG_VAR_CSR_SELL 0x80   /* CSR, PCG_PIPE / PCG_PIPE_SHIFT: the fused pass reads a
+                                   sliced-ELL copy of the operator (64-row slices, built
+                                   at pcg_create when its padding stays within a quarter
+                                   of nnz; the same sums in the same order)             */
 
 typedef struct {
     int32_t status;             /* PCG_CONVERGED .. PCG_NONFINITE                         */
@@ -260,14 +273,17 @@ pcg_status pcg_solve_static(const pcg_operator *op, const pcg_options *opt, cons
  * Launch-shape autotuner.  The fused pass is bound by memory latency and
  * bandwidth, and how many unknowns each thread handles (1, 2 or 4), the
  * block size (128 or 256) and the number of resident blocks per CU (1, 2 or
- * 4) decide how many independent loads are in flight; the best choice
+ * 4; 8 for 128-thread blocks) decide how many independent loads are in
+ * flight; for a CSR operator of PCG_PIPE / PCG_PIPE_SHIFT each shape is
+ * also tried on the sliced-ELL copy (PCG_VAR_CSR_SELL).  The best choice
  * depends on the operator, the method, the preconditioner and the storage
  * form.  pcg_tune measures every candidate (and the library's built-in
  * choice) on the caller's operator -- a solver is created on `workspace`
  * for each; an 8-pass probe sizes a run of about 3 ms of passes (24 to
  * 4096) from a zero initial guess, timed with HIP events -- and writes the
  * fastest (the built-in choice unless another shape is 1% faster) into
- * opt->variant (PCG_VAR_SET | unknowns-per-thread bits | PCG_VAR_NT),
+ * opt->variant (PCG_VAR_SET | unknowns-per-thread bits | PCG_VAR_NT
+ * [| PCG_VAR_CSR_SELL]),
  * opt->block_size and opt->grid_blocks; *best_us (host, may be NULL)
  * receives its time per pass.  b: device right-hand side (n binary64);
  * x: device scratch of n binary64, overwritten.  workspace: at least
@@ -430,7 +446,10 @@ pcg_status pcg_select_shift(const double *alpha, const double *beta, int32_t i, 
  * as the solver's workspace does (512-value tiles of every stream one after
  * another) instead of one vector after another; PCG_PROBE_FP32 streams
  * binary32 values instead of binary64 (bytes moved per launch then
- * (nin + nout) * 4 n).
+ * (nin + nout) * 4 n); PCG_PROBE_WIDE gives each lane 16-byte accesses
+ * (4 binary32 or 2 binary64 consecutive values; plain vectors only, n a
+ * multiple of that count); PCG_PROBE_BLOCKS_PER_CU(k), k in 1..15, sets the
+ * persistent grid to k blocks per CU instead of 4.
  * Supported mixes: nout = 0 with nin in {1, 2, 4, 8, 9, 16} (read only; each
  * block writes one sum to a sink), and (nin, nout) in {(1, 1), (2, 1),
  * (4, 4), (5, 4), (8, 8), (9, 8), (9, 9)}.
@@ -444,6 +463,8 @@ pcg_status pcg_select_shift(const double *alpha, const double *beta, int32_t i, 
 #define PCG_PROBE_NT      1
 #define PCG_PROBE_BLOCKED 2
 #define PCG_PROBE_FP32    4
+#define PCG_PROBE_WIDE    8
+#define PCG_PROBE_BLOCKS_PER_CU(k) ((int32_t)(k) << 8)
 pcg_status pcg_stream_probe(int32_t nin, int32_t nout, int32_t flags, int64_t n, void *buffer, size_t bytes,
                             int32_t reps, void *hip_stream, double *us_per_launch);
 

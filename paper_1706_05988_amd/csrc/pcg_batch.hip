@@ -224,8 +224,12 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int 
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     const int nitems = tb.counts[0];
-    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
-        const uint2 si = tb.items[it];
+    const int G = gridDim.x;
+    uint2 next = (int)blockIdx.x < nitems ? tb.items[blockIdx.x] : make_uint2(0u, 0u);
+    for (int it = blockIdx.x; it < nitems; it += G) {
+        const uint2 si = next;
+        // the next item's (system, tile) is fetched while this item streams
+        if (it + G < nitems) next = tb.items[it + G];
         const uint32_t s = si.x, tile = si.y;
         const BatchState *Sin = tb.st + (size_t)par * tb.max_sys + s;
         BatchState *Sout = tb.st + (size_t)(1 - par) * tb.max_sys + s;
@@ -377,6 +381,7 @@ pcg_status BatchEngine::validate(const pcg_operator *op, const pcg_options *opt)
     if ((st = validate_operator(op, opt->prec))) return st;
     if (opt->method == PCG_CG || opt->method == PCG_PIPE_VAR_SHIFT || opt->method == PCG_PIPE_RR)
         return invalid("the batched pass runs the constant-shift pipelined methods (PCG_PIPE, PCG_PIPE_SHIFT)");
+    if (opt->flags) return invalid("the batched pass takes no option flags");
     if (opt->prec != prec_) return invalid("every system of a batch must use the batch's precision");
     return PCG_OK;
 }
@@ -703,6 +708,7 @@ static pcg_status batch_plan(int32_t count, const pcg_operator *ops, const pcg_o
         if (opts[k].prec != opts[0].prec) return invalid("every system of a batch must use the same precision");
         if (opts[k].method == PCG_CG || opts[k].method == PCG_PIPE_VAR_SHIFT || opts[k].method == PCG_PIPE_RR)
             return invalid("the batched pass runs the constant-shift pipelined methods");
+        if (opts[k].flags) return invalid("the batched pass takes no option flags");
         BatchEngine::SysLayout L;
         BatchEngine::system_layout(&ops[k], &opts[k], &L);
         sys_off[k] = off;

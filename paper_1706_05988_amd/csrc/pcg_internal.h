@@ -29,6 +29,7 @@ struct LaunchShape {
     int nt;       // non-temporal streams on/off
     int K;        // iterations per graph launch
     int zm_rows, zm_seg, zm_nchunks, zm_nsegs;  // CG pass A z-marching split (zm_rows = 0: plain)
+    int sell;     // CSR operand of the fused pipelined pass in sliced-ELL form (where it fits)
 };
 
 // byte offsets into the caller's workspace (SIZE_MAX: absent)
@@ -36,6 +37,11 @@ struct Layout {
     size_t state, part[2], gersh, flag, hist, dinv;
     size_t sched;                // variable-shift schedule (SIZE_MAX: none)
     size_t blk;                  // blocked vectors: ceil(n / 512) tiles of tile_bytes
+    // sliced-ELL copy of a CSR operator for the fused pipelined pass
+    // (SIZE_MAX: none): slice offsets, columns and values of up to sell_cap entries
+    size_t sell_ptr, sell_col, sell_val;
+    int64_t sell_cap;
+    int32_t nslices;
     uint32_t tile_bytes;
     uint32_t slot_off[V_COUNT];  // byte offset of each slot in a tile (kNoSlot: absent)
     size_t total;
@@ -43,7 +49,7 @@ struct Layout {
 
 // Type-erased kernel arguments (PassArgs<double> or PassArgs<float>).
 struct PassArgsAny {
-    alignas(16) unsigned char bytes[320];
+    alignas(16) unsigned char bytes[352];
 };
 
 template <typename T>

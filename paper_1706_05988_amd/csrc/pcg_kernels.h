@@ -88,6 +88,12 @@ struct PassArgs {
     double rr_tau;        // ... replace when ||f|| > rr_tau ||r||
     double rr_floor;      // ... and ||f|| > rr_floor * 2^-53 || |A||x| + |b| ||
     CgZm zm;              // CG pass A on a 3-D grid: z-marching split (rows = 0: plain)
+    // CSR operand of the fused pipelined pass in sliced-ELL form (nullptr:
+    // the pass reads the CSR arrays): see sell_row
+    const int32_t *sell_ptr;
+    const int32_t *sell_col;
+    const T *sell_val;
+    int32_t run_through;  // 1: no breakdown stop (PCG_FLAG_RUN_THROUGH_BREAKDOWN)
 };
 
 template <typename V, typename T>
@@ -227,7 +233,7 @@ __device__ __forceinline__ bool pipe_head(const PassArgs<T> &a, double *lds_red,
         status = ST_CONVERGED;
     } else if (i >= a.max_iter) {
         status = ST_MAX_ITER;
-    } else if (!(gamma > 0.0) || !(delta > 0.0)) {
+    } else if (!a.run_through && (!(gamma > 0.0) || !(delta > 0.0))) {
         status = ST_BREAKDOWN;
     } else {
         if (i > S->i_start) {
@@ -237,7 +243,7 @@ __device__ __forceinline__ bool pipe_head(const PassArgs<T> &a, double *lds_red,
             beta = 0.0;
             alpha = gamma / delta;
         }
-        if (!(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
+        if (!a.run_through && !(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
     }
     if (state_writer()) {
         DevState *o = a.st_out;
@@ -408,7 +414,44 @@ struct PipeTile {
     double ne[EPT], we[EPT], re[EPT], ue[EPT], zo[EPT], so[EPT], to[EPT], qo[EPT], po[EPT], xo[EPT];
 };
 
-template <typename T, int OP, bool JAC, int EPT, bool NT, int XM = X_EACH>
+// The CSR operand in sliced-ELL form.  Rows are grouped in slices of 64
+// consecutive rows (one wave's rows of a tile); slice s holds its rows'
+// entries column-major, entry k of row r at sell_ptr[s] + 64 k + (r mod 64),
+// with (sell_ptr[s + 1] - sell_ptr[s]) / 64 = the longest row of the slice
+// (shorter rows padded with their own column and a zero value).  A wave's
+// load of entry k of its 64 rows is one contiguous 256-byte access, and its
+// address does not depend on the row pointers, so the gathers of a row wait
+// for one load instead of two.  Entries are summed in the row's CSR storage
+// order and padding is skipped by the row's length, so (A v)_e has the bits
+// of apply_row.
+template <typename T, typename F>
+__device__ __forceinline__ double sell_row(const PassArgs<T> &a, uint32_t e, F v)
+{
+    const uint32_t s = e >> 6, lane = e & 63;
+    const int32_t p0 = a.sell_ptr[s], w = (a.sell_ptr[s + 1] - p0) >> 6;
+    const int32_t len = a.A.row_ptr[e + 1] - a.A.row_ptr[e];
+    double acc = 0.0;
+    for (int32_t k = 0; k < w; k += kCsrChunk) {
+        int32_t c[kCsrChunk];
+        T wv[kCsrChunk];
+        double g[kCsrChunk];
+#pragma unroll
+        for (int u = 0; u < kCsrChunk; ++u) {
+            const int32_t kk = k + u < w ? k + u : k;
+            const int32_t idx = p0 + (kk << 6) + (int32_t)lane;
+            c[u] = a.sell_col[idx];
+            wv[u] = a.sell_val[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < kCsrChunk; ++u) g[u] = v((uint32_t)c[u]);
+#pragma unroll
+        for (int u = 0; u < kCsrChunk; ++u)
+            if (k + u < len) acc += (double)wv[u] * g[u];
+    }
+    return acc;
+}
+
+template <typename T, int OP, bool JAC, int EPT, bool NT, int XM = X_EACH, bool SELL = false>
 __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, PipeTile<EPT> &d)
 {
     const uint32_t off_u = JAC ? a.off_u : a.off_r;
@@ -423,9 +466,9 @@ __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, P
     for (int j = 0; j < EPT; ++j) {
         const uint32_t e = ti.e[j];
         we[j] = ld(vp<T>(a, a.off_win, e), 0);
-        ne[j] = apply_row<OP>(a.A, e, [&](uint32_t k) {
-            return minv<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_win, k), 0));
-        });
+        auto operand = [&](uint32_t k) { return minv<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_win, k), 0)); };
+        if constexpr (OP == OP_CSR && SELL) ne[j] = sell_row(a, e, operand);
+        else ne[j] = apply_row<OP>(a.A, e, operand);
         re[j] = lds<NT>(vp<T>(a, a.off_r, e));
         zo[j] = lds<NT>(vp<T>(a, a.off_z, e));
         so[j] = lds<NT>(vp<T>(a, a.off_s, e));
@@ -521,23 +564,24 @@ __device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const 
 
 // One pass with x's update mode fixed at compile time, so that the skipping
 // pass has no x loads or stores in its code at all.
-template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR, int XM>
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR, int XM, bool SELL>
 __device__ __forceinline__ void pipe_pass(const PassArgs<T> &a, const TileRange &tr, double *lds_red)
 {
     PipeTile<EPT> d;
-    if (tr.first < tr.end) tile_pipe_load<T, OP, JAC, EPT, NT, XM>(a, tr.first, d);
+    if (tr.first < tr.end) tile_pipe_load<T, OP, JAC, EPT, NT, XM, SELL>(a, tr.first, d);
     PipeScalars sc;
     if (!pipe_head<T, VAR>(a, lds_red, sc)) return;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-        if (tile != tr.first) tile_pipe_load<T, OP, JAC, EPT, NT, XM>(a, tile, d);
+        if (tile != tr.first) tile_pipe_load<T, OP, JAC, EPT, NT, XM, SELL>(a, tile, d);
         tile_pipe_update<T, OP, JAC, EPT, NT, VAR, XM>(a, d, sc, acc);
     }
     block_sum<3>(acc, lds_red);
     store_partial<3>(a.part_out, acc);
 }
 
-template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
+// SELL: a CSR operand read in sliced-ELL form (sell_row).
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false, bool SELL = false>
 __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
@@ -546,9 +590,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
     // point of the pipelined method (Section 1), inside one pass.
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
     if (lag_mode(a.st_in->iter, a.st_in->i_start) == X_SKIP)
-        pipe_pass<T, OP, JAC, EPT, NT, VAR, X_SKIP>(a, tr, lds_red);
+        pipe_pass<T, OP, JAC, EPT, NT, VAR, X_SKIP, SELL>(a, tr, lds_red);
     else
-        pipe_pass<T, OP, JAC, EPT, NT, VAR, X_CATCHUP>(a, tr, lds_red);
+        pipe_pass<T, OP, JAC, EPT, NT, VAR, X_CATCHUP, SELL>(a, tr, lds_red);
 }
 
 // x := x + alpha p: completes x after a solve that stopped after a pass that
@@ -699,7 +743,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
         if (status != RUNNING) {
             role = ROLE_STOP;
         } else if (role == ROLE_ITER) {
-            if (!(gamma > 0.0) || !(delta > 0.0)) {
+            if (!a.run_through && (!(gamma > 0.0) || !(delta > 0.0))) {
                 status = ST_BREAKDOWN;
             } else {
                 if (i > S->i_start) {
@@ -709,7 +753,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
                     beta = 0.0;
                     alpha = gamma / delta;
                 }
-                if (!(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
+                if (!a.run_through && !(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
             }
             if (status != RUNNING) role = ROLE_STOP;
         }
@@ -837,7 +881,7 @@ __device__ __forceinline__ bool cg_a_head(const PassArgs<T> &a, double *lds_red,
         status = ST_CONVERGED;
     } else if (i >= a.max_iter) {
         status = ST_MAX_ITER;
-    } else if (!(gamma > 0.0)) {
+    } else if (!a.run_through && !(gamma > 0.0)) {
         status = ST_BREAKDOWN;
     } else if (i > S->i_start) {
         beta = gamma / S->gamma_prev;  // beta_i = (r_i, u_i) / (r_{i-1}, u_{i-1})
@@ -1016,11 +1060,11 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_b(PassArgs<T> a)
     double alpha = __builtin_nan("");
     if (!isfinite(sp)) {
         status = ST_NONFINITE;
-    } else if (!(sp > 0.0)) {
+    } else if (!a.run_through && !(sp > 0.0)) {
         status = ST_BREAKDOWN;
     } else {
         alpha = gamma_i / sp;  // alpha_i = (r_i, u_i) / (s_i, p_i)
-        if (!(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
+        if (!a.run_through && !(isfinite(alpha) && alpha > 0.0)) status = ST_BREAKDOWN;
     }
     if (state_writer()) {
         DevState *o = a.st_out;
@@ -1128,6 +1172,63 @@ __global__ void k_jacobi(OpDev<T> A, T *dinv)
     for (int32_t k = A.row_ptr[e]; k < A.row_ptr[e + 1]; ++k)
         if ((uint32_t)A.col[k] == e) d += (double)A.val[k];
     dinv[e] = (T)(1.0 / d);
+}
+
+// Sliced-ELL copy of a CSR operator (see sell_row), built once per solver.
+// Step 1: the longest row of each 64-row slice, into sell_ptr[s].
+static __global__ void __launch_bounds__(256) k_sell_width(const int32_t *row_ptr, int32_t n, int32_t *sell_ptr)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one wave per slice
+    int32_t len = r < n ? row_ptr[r + 1] - row_ptr[r] : 0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) len = max(len, __shfl_xor(len, o, 64));
+    if ((threadIdx.x & 63) == 0 && r < n) sell_ptr[r >> 6] = len;
+}
+
+// Step 2 (one block): exclusive prefix sum of 64 x width over the slices,
+// in place; sell_ptr[nslices] = the total, or -1 when it exceeds cap.
+static __global__ void __launch_bounds__(1024) k_sell_scan(int32_t *sell_ptr, int32_t nslices, int64_t cap)
+{
+    __shared__ int64_t part[1024];
+    const int per = (nslices + 1023) / 1024;
+    const int s0 = min(nslices, (int)threadIdx.x * per), s1 = min(nslices, s0 + per);
+    int64_t mine = 0;
+    for (int s = s0; s < s1; ++s) mine += 64 * (int64_t)sell_ptr[s];
+    part[threadIdx.x] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int t = 0; t < 1024; ++t) {
+            const int64_t v = part[t];
+            part[t] = run;
+            run += v;
+        }
+        sell_ptr[nslices] = run <= cap ? (int32_t)run : -1;
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int s = s0; s < s1; ++s) {
+        const int64_t w = 64 * (int64_t)sell_ptr[s];
+        sell_ptr[s] = (int32_t)min(run, cap);
+        run += w;
+    }
+}
+
+// Step 3: each row's entries into its slice column, padding with the row's
+// own column and a zero value.
+template <typename T>
+__global__ void __launch_bounds__(256) k_sell_fill(OpDev<T> A, const int32_t *sell_ptr, int32_t *sell_col, T *sell_val)
+{
+    const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= (uint32_t)A.n) return;
+    const uint32_t s = r >> 6, lane = r & 63;
+    const int32_t p0 = sell_ptr[s], w = (sell_ptr[s + 1] - p0) >> 6;
+    const int32_t k0 = A.row_ptr[r], len = A.row_ptr[r + 1] - k0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int32_t idx = p0 + (k << 6) + (int32_t)lane;
+        sell_col[idx] = k < len ? A.col[k0 + k] : (int32_t)r;
+        sell_val[idx] = k < len ? A.val[k0 + k] : (T)0;
+    }
 }
 
 // Gershgorin bounds of spec(M^-1 A) for a CSR operator: per block

@@ -265,6 +265,7 @@ extern "C" pcg_status pcg_submit(pcg_server s, const pcg_operator *op, const pcg
     if ((st = validate_operator(op, opt->prec))) return st;
     if (opt->method == PCG_CG || opt->method == PCG_PIPE_VAR_SHIFT || opt->method == PCG_PIPE_RR)
         return invalid("the server runs the constant-shift pipelined methods (PCG_PIPE, PCG_PIPE_SHIFT)");
+    if (opt->flags) return invalid("the server takes no option flags");
     if (!b || !x || b == x) return invalid("b and x must be non-null and distinct");
     BatchEngine::SysLayout L;
     BatchEngine::system_layout(op, opt, &L);

@@ -133,6 +133,7 @@ pcg_status validate_options(const pcg_options *o)
     if (o->history_cap < 0) return invalid("history_cap must be >= 0");
     if (o->history_cap > 0 && !o->history) return invalid("history buffer is null");
     if (o->replace_max < 0) return invalid("replace_max must be >= 0");
+    if (o->flags & ~PCG_FLAG_RUN_THROUGH_BREAKDOWN) return invalid("unknown option flags");
     return PCG_OK;
 }
 
@@ -161,9 +162,15 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
         s.nt = 1;
         const bool pipe = o->method != PCG_CG, jac = o->pc == PCG_PC_JACOBI, fp64 = o->prec == PCG_FP64;
         if (pipe && op->kind == PCG_OP_CSR) {
-            // gathers need more waves in flight than the stencil streams
-            if (fp64) s.ept = 1, s.block = 128, blocks_per_cu = 4;
-            else s.ept = 2, s.block = 256, blocks_per_cu = 4;
+            // gathers need more waves in flight than the stencil streams:
+            // four blocks of 256 per CU on the sliced-ELL copy (measured on
+            // the anisotropic 1024^2 / 2048^2 operators: binary64 44.4 /
+            // 172.7 us per pass against 47.3 / 185.9 for 128-thread blocks on
+            // CSR rows); the FP32-stream form takes 4 rows per thread while
+            // that leaves about one tile per block (28.5 against 30.4 us at
+            // 1024^2), 2 beyond (88.9 against 91.6 us at 2048^2)
+            if (fp64) s.ept = 1, s.block = 256, blocks_per_cu = 4;
+            else s.ept = op->n <= int64_t(kNumCU) * 4 * 256 * 4 ? 4 : 2, s.block = 256, blocks_per_cu = 4;
         } else if (pipe && jac) {
             // 4 unknowns per thread keep ~70 independent loads in flight per
             // thread; binary64 runs best as one block per CU, the lighter
@@ -177,6 +184,8 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
             s.ept = 4, s.block = 256, blocks_per_cu = 4;
         }
     }
+    // sliced-ELL CSR copy: built in for both forms (where its padding fits)
+    s.sell = set ? ((var & PCG_VAR_CSR_SELL) != 0) : 1;
     if (o->block_size) s.block = o->block_size;
     const int64_t tile = int64_t(s.block) * s.ept;
     s.ntiles = (int)((op->n + tile - 1) / tile);
@@ -256,6 +265,21 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
     l.hist = take(size_t(o->history_cap) * PCG_HISTORY_FIELDS * 8);
     l.dinv = (op->kind == PCG_OP_CSR && jac) ? take(n * es) : SIZE_MAX;
     l.sched = o->method == PCG_PIPE_VAR_SHIFT ? take(size_t(o->sigma_schedule_len) * 8) : SIZE_MAX;
+    // the fused pass of p-CG / p-CG-sh reads a CSR operator in sliced-ELL
+    // form when its padding stays within a quarter of nnz (decided at set-up)
+    l.sell_ptr = l.sell_col = l.sell_val = SIZE_MAX;
+    l.sell_cap = 0;
+    l.nslices = 0;
+    if (op->kind == PCG_OP_CSR && (o->method == PCG_PIPE || o->method == PCG_PIPE_SHIFT) && sh.sell) {
+        const int64_t cap = op->nnz + op->nnz / 4 + 4096;
+        if (cap < (int64_t(1) << 31) - 64) {
+            l.nslices = (int32_t)((n + 63) / 64);
+            l.sell_cap = cap;
+            l.sell_ptr = take(size_t(l.nslices + 1) * 4);
+            l.sell_col = take(size_t(cap) * 4);
+            l.sell_val = take(size_t(cap) * es);
+        }
+    }
     // slots of a 512-unknown tile: x (binary64) first, then the stored vectors
     for (int k = 0; k < V_COUNT; ++k) l.slot_off[k] = kNoSlot;
     uint32_t tb = 0;
@@ -313,7 +337,15 @@ struct KernelSet {
     static void init1(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_init1<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void pipe(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    {
+        if constexpr (OP == OP_CSR) {
+            if (A(a).sell_ptr) {
+                hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, false, true>), dim3(g), dim3(b), 0, s, A(a));
+                return;
+            }
+        }
+        hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a));
+    }
     static void pipe_var(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, true>), dim3(g), dim3(b), 0, s, A(a)); }
     static void pipe_rr(PassArgsAny a, int g, int b, hipStream_t s)
@@ -395,6 +427,7 @@ struct pcg_solver_ {
     double sigma;            // shift in use (0 for CG / p-CG)
     std::vector<double> sched;  // variable shift: sigma_{-1}, sigma_0, ... (host copy)
     double dinv_s;           // stencil Jacobi scalar
+    bool sell = false;       // the fused pass reads the CSR operator's sliced-ELL copy
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     const double *graph_b = nullptr;  // b baked into the captured graph
@@ -463,6 +496,10 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
         a.rr_tau = opt.rr_tau > 0.0 ? opt.rr_tau : std::cbrt(opt.prec == PCG_FP64 ? 0x1p-53 : 0x1p-24);
         a.rr_floor = opt.rr_floor > 0.0 ? opt.rr_floor : 100.0;
         a.zm = CgZm{sh.zm_rows, sh.zm_seg, sh.zm_nchunks, sh.zm_nsegs};
+        a.sell_ptr = sell ? reinterpret_cast<const int32_t *>(ws + L.sell_ptr) : nullptr;
+        a.sell_col = sell ? reinterpret_cast<const int32_t *>(ws + L.sell_col) : nullptr;
+        a.sell_val = sell ? reinterpret_cast<const T *>(ws + L.sell_val) : nullptr;
+        a.run_through = (opt.flags & PCG_FLAG_RUN_THROUGH_BREAKDOWN) ? 1 : 0;
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
     else fill((float *)nullptr);
@@ -578,6 +615,35 @@ pcg_status csr_setup(const pcg_operator *op, int prec, int jac, void *dinv, int 
     return PCG_OK;
 }
 
+// Sliced-ELL copy of a CSR operator into the workspace (synchronous).
+// *built: 0 when the padded copy would exceed the reserved capacity (the
+// fused pass then reads the CSR arrays).
+pcg_status sell_setup(const pcg_operator *op, int prec, const Layout &L, char *ws, hipStream_t stream, int *built)
+{
+    *built = 0;
+    if (L.sell_col == SIZE_MAX || L.nslices < 1) return PCG_OK;
+    int32_t *sp = reinterpret_cast<int32_t *>(ws + L.sell_ptr);
+    const int32_t n = (int32_t)op->n;
+    const int g = (int)((op->n + 255) / 256);
+    hipLaunchKernelGGL(k_sell_width, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sp);
+    hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, stream, sp, L.nslices, L.sell_cap);
+    HIPCHK(hipGetLastError());
+    int32_t total = -1;
+    HIPCHK(hipMemcpyAsync(&total, sp + L.nslices, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    HIPCHK(hipStreamSynchronize(stream));
+    if (total < 0) return PCG_OK;
+    int32_t *sc = reinterpret_cast<int32_t *>(ws + L.sell_col);
+    if (prec == PCG_FP64)
+        hipLaunchKernelGGL(k_sell_fill<double>, dim3(g), dim3(256), 0, stream, make_opdev<double>(op), sp, sc,
+                           reinterpret_cast<double *>(ws + L.sell_val));
+    else
+        hipLaunchKernelGGL(k_sell_fill<float>, dim3(g), dim3(256), 0, stream, make_opdev<float>(op), sp, sc,
+                           reinterpret_cast<float *>(ws + L.sell_val));
+    HIPCHK(hipGetLastError());
+    *built = 1;
+    return PCG_OK;
+}
+
 pcg_status csr_gershgorin(const pcg_operator *op, int prec, int jac, double *gb, hipStream_t stream, double *lo,
                           double *hi)
 {
@@ -670,6 +736,9 @@ static pcg_status init_solver(pcg_solver_ *s, const pcg_operator *op, const pcg_
             (st = csr_gershgorin(op, opt->prec, jac, reinterpret_cast<double *>(s->ws + L.gersh), s->stream, &gersh[0],
                                  &gersh[1])))
             return st;
+        int built = 0;
+        if ((st = sell_setup(op, opt->prec, L, s->ws, s->stream, &built))) return st;
+        s->sell = built != 0;
     }
     s->sigma = default_sigma(op, opt, gersh);
     if (opt->method == PCG_PIPE_VAR_SHIFT) {

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "pcg.h"
 #include "pcg_internal.h"
@@ -34,6 +35,7 @@ struct Streams {
     double *sink;
     int nin, nout;
     uint32_t tile_bytes;  // blocked layout: bytes of one 512-value tile of all streams (0: plain vectors)
+    int wide;             // 16-byte accesses per lane (k_stream16)
 };
 
 // Element e of a stream that starts at p: plain vectors, or the blocked
@@ -58,6 +60,75 @@ __device__ __forceinline__ void stp(V *p, double v)
 {
     if constexpr (NT) __builtin_nontemporal_store((V)v, p);
     else *p = (V)v;
+}
+
+// The same streams with 16-byte accesses: each lane moves 16 / sizeof(V)
+// consecutive values of a stream per access (plain vectors only).
+typedef float ProbeF4 __attribute__((ext_vector_type(4)));
+typedef double ProbeD2 __attribute__((ext_vector_type(2)));
+template <typename V, int NIN, int NOUT, bool NT>
+__global__ void __launch_bounds__(kProbeBlock) k_stream16(Streams s, int64_t n)
+{
+    using W = typename std::conditional<sizeof(V) == 4, ProbeF4, ProbeD2>::type;
+    constexpr int VB = 16 / sizeof(V);
+    const int64_t groups = n / VB;  // n is a multiple of VB
+    const int64_t tile_g = (int64_t)kProbeBlock * kProbeEPT;
+    const int64_t ntiles = (groups + tile_g - 1) / tile_g;
+    double keep = 0.0;
+    for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        W v[NIN][kProbeEPT];
+        int64_t g[kProbeEPT];
+#pragma unroll
+        for (int j = 0; j < kProbeEPT; ++j) {
+            const int64_t k = t * tile_g + (int64_t)j * kProbeBlock + threadIdx.x;
+            g[j] = k < groups ? k : groups - 1;
+        }
+#pragma unroll
+        for (int i = 0; i < NIN; ++i)
+#pragma unroll
+            for (int j = 0; j < kProbeEPT; ++j) {
+                const W *p = static_cast<const W *>(s.in[i]) + g[j];
+                v[i][j] = NT ? __builtin_nontemporal_load(p) : *p;
+            }
+#pragma unroll
+        for (int j = 0; j < kProbeEPT; ++j) {
+            const int64_t k = t * tile_g + (int64_t)j * kProbeBlock + threadIdx.x;
+            double sum = 0.0;
+#pragma unroll
+            for (int i = 0; i < NIN; ++i) {
+                if constexpr (VB == 4) sum += (double)v[i][j].x + v[i][j].y + v[i][j].z + v[i][j].w;
+                else sum += v[i][j].x + v[i][j].y;
+            }
+            if constexpr (NOUT == 0) {
+                keep += sum;
+            } else if (k < groups) {
+#pragma unroll
+                for (int o = 0; o < NOUT; ++o) {
+                    W w = v[o % NIN][j];
+                    const V c = (V)((0.5 + o) * 1e-3 * sum);
+                    w.x += c;
+                    w.y += c;
+                    if constexpr (VB == 4) {
+                        w.z += c;
+                        w.w += c;
+                    }
+                    W *p = static_cast<W *>(s.out[o]) + k;
+                    if (NT) __builtin_nontemporal_store(w, p);
+                    else *p = w;
+                }
+            }
+        }
+    }
+    if constexpr (NOUT == 0) {
+        __shared__ double red[kProbeBlock];
+        red[threadIdx.x] = keep;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int k = 0; k < kProbeBlock; ++k) tot += red[k];
+            s.sink[blockIdx.x] = tot;
+        }
+    }
 }
 
 // NIN inputs and NOUT outputs fixed at compile time: all of a tile's loads
@@ -116,7 +187,8 @@ using ProbeFn = void (*)(const Streams &, int64_t, int, hipStream_t);
 template <typename V, int NIN, int NOUT, bool NT>
 void launch(const Streams &s, int64_t n, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_stream<V, NIN, NOUT, NT>), dim3(grid), dim3(kProbeBlock), 0, st, s, n);
+    if (s.wide) hipLaunchKernelGGL((k_stream16<V, NIN, NOUT, NT>), dim3(grid), dim3(kProbeBlock), 0, st, s, n);
+    else hipLaunchKernelGGL((k_stream<V, NIN, NOUT, NT>), dim3(grid), dim3(kProbeBlock), 0, st, s, n);
 }
 
 // The shapes the measurements use: read only, copy, and the fused passes'
@@ -155,7 +227,13 @@ extern "C" pcg_status pcg_stream_probe(int32_t nin, int32_t nout, int32_t flags,
     if (!us_per_launch) return invalid("us_per_launch is null");
     if (n < 1 || n > (int64_t(1) << 34)) return invalid("n must be in [1, 2^34]");
     if (reps < 1 || reps > 100000) return invalid("reps must be in [1, 100000]");
-    if (flags & ~(PCG_PROBE_NT | PCG_PROBE_BLOCKED | PCG_PROBE_FP32)) return invalid("unknown probe flags");
+    if (flags & ~(PCG_PROBE_NT | PCG_PROBE_BLOCKED | PCG_PROBE_FP32 | PCG_PROBE_WIDE | (0xf << 8)))
+        return invalid("unknown probe flags");
+    if ((flags & PCG_PROBE_WIDE) && (flags & PCG_PROBE_BLOCKED))
+        return invalid("PCG_PROBE_WIDE streams plain vectors only");
+    if ((flags & PCG_PROBE_WIDE) && (n % ((flags & PCG_PROBE_FP32) ? 4 : 2)))
+        return invalid("PCG_PROBE_WIDE needs n a multiple of the values per 16 bytes");
+    const int per_cu = (flags >> 8) & 0xf;  // blocks per CU of the persistent grid (0: 4)
     const bool nt = (flags & PCG_PROBE_NT) != 0, blocked = (flags & PCG_PROBE_BLOCKED) != 0;
     const bool f32 = (flags & PCG_PROBE_FP32) != 0;
     const ProbeFn fn = f32 ? (nt ? pick<float, true>(nin, nout) : pick<float, false>(nin, nout))
@@ -176,8 +254,10 @@ extern "C" pcg_status pcg_stream_probe(int32_t nin, int32_t nout, int32_t flags,
     s.nin = nin;
     s.nout = nout;
     s.tile_bytes = blocked ? (uint32_t)((nin + nout) * slice) : 0u;
-    const int64_t tiles = (n + kProbeBlock * kProbeEPT - 1) / (kProbeBlock * kProbeEPT);
-    const int grid = (int)std::min<int64_t>(kProbeGrid, tiles);
+    s.wide = (flags & PCG_PROBE_WIDE) != 0;
+    const int64_t per_tile = (int64_t)kProbeBlock * kProbeEPT * (s.wide ? 16 / (int64_t)es : 1);
+    const int64_t tiles = (n + per_tile - 1) / per_tile;
+    const int grid = (int)std::min<int64_t>(per_cu ? per_cu * kNumCU : kProbeGrid, tiles);
     hipStream_t st = (hipStream_t)hip_stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t he;

@@ -33,14 +33,25 @@ constexpr int kWarm = 8;               // passes of the probe that sizes the tim
 constexpr int kMinTimed = 24, kMaxTimed = 4096;
 constexpr double kTimedUs = 3000.0;     // ~3 ms of timed passes per candidate
 
-std::vector<Shape> candidates()
+// The built-in choice, then 1, 2 or 4 unknowns per thread x 128 or 256
+// threads x 1, 2 or 4 blocks per CU (128-thread blocks also 8); a CSR
+// operator of the fused pipelined pass adds each shape reading its
+// sliced-ELL copy.
+std::vector<Shape> candidates(const pcg_operator *op, const pcg_options *o)
 {
     std::vector<Shape> c;
-    c.push_back({0, 0, 0});  // the library's built-in choice
+    c.push_back({0, 0, 0});
     const int ept_bits[3] = {PCG_VAR_EPT1, 0, PCG_VAR_EPT4};
-    for (int eb : ept_bits)
-        for (int block : {128, 256})
-            for (int per_cu : {1, 2, 4}) c.push_back({PCG_VAR_SET | PCG_VAR_NT | eb, block, per_cu * kNumCU});
+    const bool sell = op->kind == PCG_OP_CSR && (o->method == PCG_PIPE || o->method == PCG_PIPE_SHIFT);
+    for (int sb : {0, PCG_VAR_CSR_SELL}) {
+        if (sb && !sell) continue;
+        for (int eb : ept_bits)
+            for (int block : {128, 256})
+                for (int per_cu : {1, 2, 4, 8}) {
+                    if (per_cu == 8 && block != 128) continue;
+                    c.push_back({PCG_VAR_SET | PCG_VAR_NT | eb | sb, block, per_cu * kNumCU});
+                }
+    }
     return c;
 }
 
@@ -108,7 +119,7 @@ extern "C" pcg_status pcg_tune_workspace_size(const pcg_operator *op, const pcg_
 {
     if (!op || !opt || !bytes) return invalid("operator, options and bytes must be non-null");
     size_t most = 0;
-    for (const Shape &s : candidates()) {
+    for (const Shape &s : candidates(op, opt)) {
         const pcg_options t = shaped(*opt, s, kMaxTimed);
         size_t b = 0;
         const pcg_status st = pcg_workspace_size(op, &t, &b);
@@ -154,7 +165,7 @@ extern "C" pcg_status pcg_tune(const pcg_operator *op, pcg_options *opt, void *w
         // beats it by 1%, more than the spread of repeated timings
         best_t = INFINITY;
         double builtin_t = INFINITY;
-        for (const Shape &sh : candidates()) {
+        for (const Shape &sh : candidates(op, opt)) {
             double probe = 0.0, us = 0.0;
             if ((st = run(sh, kWarm, &probe))) return st;
             if (!std::isfinite(probe)) continue;

@@ -28,6 +28,8 @@ PCG_FP64, PCG_FP32_STREAM = 0, 1
 PCG_HISTORY_FIELDS = 5
 PCG_VAR_SET, PCG_VAR_XCD_MAP, PCG_VAR_NT, PCG_VAR_EPT1, PCG_VAR_EPT4 = 0x01, 0x02, 0x04, 0x10, 0x20
 PCG_VAR_CG_ZMARCH = 0x40
+PCG_VAR_CSR_SELL = 0x80
+PCG_FLAG_RUN_THROUGH_BREAKDOWN = 0x01
 
 METHOD = {"cg": PCG_CG, "pipe": PCG_PIPE, "pipe_shift": PCG_PIPE_SHIFT, "pipe_var": PCG_PIPE_VAR_SHIFT, "pipe_rr": PCG_PIPE_RR}
 OUTCOME = {PCG_CONVERGED: "converged", PCG_MAX_ITER: "max_iter", PCG_BREAKDOWN: "breakdown",
@@ -48,7 +50,7 @@ class pcg_options(C.Structure):
                 ("replace_max", C.c_int32), ("iters_per_launch", C.c_int32), ("history_cap", C.c_int32),
                 ("history", C.c_void_p), ("block_size", C.c_int32), ("grid_blocks", C.c_int32),
                 ("timing", C.c_int32), ("use_graph", C.c_int32), ("variant", C.c_int32),
-                ("sigma_schedule_len", C.c_int32), ("rr_period", C.c_int32), ("reserved", C.c_int32),
+                ("sigma_schedule_len", C.c_int32), ("rr_period", C.c_int32), ("flags", C.c_int32),
                 ("sigma_schedule", C.c_void_p), ("rr_tau", C.c_double), ("rr_floor", C.c_double)]
 
 
@@ -366,7 +368,11 @@ def tune(op, options: pcg_options, b=None, device="cuda", stream: Optional[int] 
     return out, us
 
 
-PCG_PROBE_NT, PCG_PROBE_BLOCKED, PCG_PROBE_FP32 = 1, 2, 4
+PCG_PROBE_NT, PCG_PROBE_BLOCKED, PCG_PROBE_FP32, PCG_PROBE_WIDE = 1, 2, 4, 8
+
+
+def PCG_PROBE_BLOCKS_PER_CU(k: int) -> int:
+    return int(k) << 8
 
 
 def pcg_stream_probe(nin: int, nout: int, flags: int, n: int, buffer: int, nbytes: int, reps: int,
@@ -426,7 +432,7 @@ def make_options(method: str = "pipe_shift", jacobi: bool = False, fp32: bool = 
                  true_residual_check: bool = True, replace_max: int = 4, iters_per_launch: int = 0,
                  history_cap: int = 0, block_size: int = 0, grid_blocks: int = 0, timing: bool = False,
                  use_graph: bool = True, variant: int = 0, sigma_schedule=None, rr_tau: float = 0.0,
-                 rr_period: int = 0, rr_floor: float = 0.0) -> pcg_options:
+                 rr_period: int = 0, rr_floor: float = 0.0, run_through_breakdown: bool = False) -> pcg_options:
     """Options for pcg_create.  ``sigma_schedule`` (method "pipe_var") lists
     sigma_{-1}, sigma_0, sigma_1, ...; the returned struct keeps the array
     alive until the solver copies it at creation."""
@@ -449,6 +455,7 @@ def make_options(method: str = "pipe_shift", jacobi: bool = False, fp32: bool = 
     o.rr_tau = float(rr_tau)
     o.rr_period = int(rr_period)
     o.rr_floor = float(rr_floor)
+    o.flags = PCG_FLAG_RUN_THROUGH_BREAKDOWN if run_through_breakdown else 0
     if sigma_schedule is not None:
         import numpy as np
         sched = np.ascontiguousarray(sigma_schedule, dtype=np.float64)

@@ -108,6 +108,21 @@ def test_batch_rejects_cg_and_mixed_precision():
     assert n2 > n1
 
 
+def test_option_flags_validated():
+    op = stencil_op()
+    o = P.make_options(run_through_breakdown=True)
+    assert o.flags == P.PCG_FLAG_RUN_THROUGH_BREAKDOWN
+    assert P.pcg_workspace_size(op, o) > 0
+    bad = P.make_options()
+    bad.flags = 0x40
+    with pytest.raises(P.PcgError) as ei:
+        P.pcg_workspace_size(op, bad)
+    assert ei.value.status == P.PCG_ERR_INVALID
+    # the batched pass (and the server) take no flags
+    with pytest.raises(P.PcgError):
+        P.pcg_batch_workspace_size([op], [o])
+
+
 def test_batch_rejects_an_empty_batch():
     with pytest.raises(P.PcgError) as ei:
         P.pcg_batch_workspace_size([], [])
@@ -193,6 +208,18 @@ def test_tune_workspace_covers_every_candidate():
     n = C.c_size_t()
     assert P.lib().pcg_tune_workspace_size(C.byref(op), C.byref(o), C.byref(n)) == P.PCG_OK
     assert n.value >= P.pcg_workspace_size(op, o)
+    # a CSR operator: the candidates on its sliced-ELL copy need more room
+    csr = P.pcg_operator()
+    csr.kind, csr.n, csr.nnz = P.PCG_OP_CSR, 4096, 5 * 4096
+    csr.row_ptr, csr.col_idx, csr.vals = 0x100000, 0x200000, 0x300000
+    o32 = P.make_options(jacobi=True, fp32=True)
+    assert P.lib().pcg_tune_workspace_size(C.byref(csr), C.byref(o32), C.byref(n)) == P.PCG_OK
+    sell = P.make_options(jacobi=True, fp32=True, variant=P.PCG_VAR_SET | P.PCG_VAR_CSR_SELL | P.PCG_VAR_EPT1,
+                          block_size=128, grid_blocks=2048)
+    plain = P.make_options(jacobi=True, fp32=True, variant=P.PCG_VAR_SET | P.PCG_VAR_EPT1, block_size=128,
+                           grid_blocks=2048)
+    assert P.pcg_workspace_size(csr, sell) > P.pcg_workspace_size(csr, plain)
+    assert n.value >= P.pcg_workspace_size(csr, sell)
 
 
 def test_tune_rejects_bad_arguments_before_device_work():
@@ -264,7 +291,9 @@ def test_stream_probe_rejects_before_device_work():
     need = P.stream_probe_bytes(9, 9, n)
     assert need == 18 * 8 * n + 65536
     assert P.stream_probe_bytes(1, 1, 513) == 2 * 8192 + 65536
-    assert lib.pcg_stream_probe(9, 9, 8, n, 0x100000, need, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
+    assert lib.pcg_stream_probe(9, 9, 16, n, 0x100000, need, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
+    assert lib.pcg_stream_probe(9, 9, 8 | 2, n, 0x100000, need, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
+    assert lib.pcg_stream_probe(9, 9, 8 | 4, 1023, 0x100000, need, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
     # an unsupported mix, a short buffer, a misaligned buffer, bad sizes
     assert lib.pcg_stream_probe(3, 3, 1, n, 0x100000, need, 10, None, C.byref(us)) == P.PCG_ERR_INVALID
     assert lib.pcg_stream_probe(9, 9, 1, n, 0x100000, need - 8, 10, None, C.byref(us)) == P.PCG_ERR_INVALID

@@ -119,6 +119,53 @@ def test_config4_full_batch_sampled(torch):
         assert g["rel_res_true"] <= 10 * max(o["rel_res_true"], 1e-9), p.name
 
 
+def _oracle_all(ps, **kw):
+    """The oracle on every system, several at once (each single-threaded;
+    the library call releases the interpreter lock)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        return list(ex.map(lambda p: oracle.solve(p.op, p.b, p.x0, method="pipe_shift", sigma=p.sigma,
+                                                  threads=1, **kw), ps))
+
+
+def test_config4_every_system_binary64_matches_the_oracle(torch):
+    """The 512 rectangles of the benchmark batch solved in binary64 in one
+    batch, each system against the oracle at the parity bar: sqrt(rho_i)/||b||,
+    alpha_i and beta_i to 1e-10 over the first 50 iterations, the same
+    iteration count (within one) and the final explicit residual to 1e-12."""
+    from paper_1706_05988_amd import pcg as P
+    ps = problems.batch_rectangles(512, seed=0)
+    opts = [P.make_options(method="pipe_shift", sigma=p.sigma, rtol=1e-8, max_iter=3000,
+                           true_residual_check=False, history_cap=52) for p in ps]
+    B = P.Batch([p.op for p in ps], opts)
+    bs = [torch.from_numpy(p.b).cuda() for p in ps]
+    xs = [torch.zeros_like(b) for b in bs]
+    res = B.solve(bs, xs)
+    torch.cuda.synchronize()
+    orc = _oracle_all(ps, rtol=1e-8, max_iter=3000)
+    for p, g, o in zip(ps, res, orc):
+        assert g["status"] == o["status"] == "converged", p.name
+        assert abs(g["iterations"] - o["iterations"]) <= 1, p.name
+        k = min(50, g["iterations"], o["iterations"])
+        np.testing.assert_allclose(g["res"][: k + 1], o["res"][: k + 1], rtol=1e-10, err_msg=p.name)
+        np.testing.assert_allclose(g["alpha"][:k], o["alpha"][:k], rtol=1e-10, err_msg=p.name)
+        np.testing.assert_allclose(g["beta"][1:k], o["beta"][1:k], rtol=1e-10, err_msg=p.name)
+        assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-12, p.name
+
+
+def test_config4_every_system_fp32_stream_within_the_oracle_level(torch):
+    """The benchmark's FP32-stream batch (to 1e-8, binary64 explicit check and
+    restarts): every one of the 512 systems converges, and ends within 10x of
+    the oracle's level in the same storage form with the same restart rule."""
+    ps = problems.batch_rectangles(512, seed=0)
+    res = run_batch(torch, ps, fp32=True, rtol=1e-8, max_iter=20000, replace_max=8, hist=False)
+    orc = _oracle_all(ps, rtol=1e-8, max_iter=20000, fp32_storage=True, replace_max=8)
+    for p, g, o in zip(ps, res, orc):
+        assert g["status"] == o["status"] == "converged", p.name
+        assert g["rel_res_true"] <= 1e-8, p.name
+        assert g["rel_res_true"] <= 10 * o["rel_res_true"], p.name
+
+
 def test_batch_fp32_stream_with_restarts(torch):
     """FP32-stream batch: every system reaches the tolerance through
     restarts from its binary64 x."""

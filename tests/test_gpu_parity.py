@@ -88,19 +88,36 @@ def test_config1_poisson2d_history_and_final_residual(torch, method):
 
 @pytest.mark.parametrize("method", METHODS)
 def test_lapl200_table1_on_gpu(torch, method):
-    """500 iterations of lapl200 (Table 1): CG and p-CG-sh reach ~6.8e-12;
-    p-CG stagnates orders of magnitude higher."""
+    """500 iterations of lapl200 (Table 1) run through any breakdown, as the
+    paper's accuracy runs do: CG and p-CG-sh reach ~6.8e-12; p-CG stagnates
+    orders of magnitude higher.  Its level is set by rounding (the oracle's
+    lands at ~4e-9), so it is held to the oracle's own pin: at least 100x
+    CG's printed level and at most 10x its own printed 3.1e-7."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "table1_lapl200.json")) as f:
+        printed = json.load(f)["true_residual"][method]  # ||b|| = 1: absolute = relative
     p = problems.lapl200()
-    g = gpu_solve(torch, p, method, true_residual_check=False, rtol=1e-30, max_iter=500)
+    g = gpu_solve(torch, p, method, true_residual_check=False, rtol=1e-30, max_iter=500,
+                  run_through_breakdown=True)
     o = oracle_solve(p, method, rtol=1e-30, max_iter=500, ignore_breakdown=True)
     check_history(g, o)
+    assert g["iterations"] == 500
     if method == "pipe":
-        # the GPU stops at the first non-positive alpha, as the library must
-        assert g["rel_res_true"] > 1e-10
+        with open(os.path.join(os.path.dirname(__file__), "golden", "table1_lapl200.json")) as f:
+            cg_printed = json.load(f)["true_residual"]["cg"]
+        assert 100 * cg_printed <= g["rel_res_true"] <= 10 * printed
     else:
-        assert g["iterations"] == 500
-        assert g["rel_res_true"] <= 3 * 6.8e-12
+        assert g["rel_res_true"] <= 3 * printed
         assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-11
+
+
+def test_breakdown_stops_without_the_flag(torch):
+    """Without the run-through flag the library stops p-CG on lapl200 at the
+    first non-positive alpha or delta, with status breakdown."""
+    p = problems.lapl200()
+    g = gpu_solve(torch, p, "pipe", true_residual_check=False, rtol=1e-30, max_iter=500)
+    assert g["status"] == "breakdown" and g["iterations"] < 500
 
 
 # ---------------------------------------------------------------- 3-D, Jacobi, ragged

@@ -259,3 +259,40 @@ def test_server_joins_requests_into_a_running_batch(torch):
         assert np.array_equal(alone["x"], x.cpu().numpy()), p.name
     assert info["max_running"] >= 2
     assert np.array_equal(solve_alone(torch, P, long_p)["x"], xl.cpu().numpy())
+
+
+def test_server_admission_is_first_in_first_out_under_a_full_arena(torch):
+    """A queue far larger than the arena for a long time: the arena holds the
+    large request alone, or small ones, never the large one beside a small
+    one.  Requests are admitted in submission order (the queue head is never
+    skipped, so the large request does not starve behind small ones submitted
+    after it, and those wait until it is done), every request finishes with
+    the bits it gets alone, and all memory comes back."""
+    from paper_1706_05988_amd import pcg as P
+    op = problems.stencil2d(200, 160)
+    big = problems.Problem("big", op, np.random.default_rng(1).uniform(-1, 1, op.n), np.zeros(op.n), None,
+                           sigma=4.0, rtol=1e-8, max_iter=20000)
+    small = request_set()[:2]
+    order = [small[0], small[1], big] + [small[k % 2] for k in range(12)]
+    k_big = 2
+    ob = opts(P, big)
+    hb = np.zeros((ob.history_cap, P.PCG_HISTORY_FIELDS))  # the size query checks the history buffer
+    ob.history = hb.ctypes.data
+    foot_big = P.pcg_batch_workspace_size([P.DeviceOperator(big.op, ob.prec).struct], [ob])
+    srv = P.Server(foot_big + (16 << 10), max_slots=16)  # no small request fits beside the big one
+    bs = [torch.from_numpy(p.b).cuda() for p in order]
+    xs = [torch.zeros_like(b) for b in bs]
+    torch.cuda.synchronize()
+    tickets = [srv.submit(p.op, opts(P, p), b, x) for p, b, x in zip(order, bs, xs)]
+    res = [srv.wait(t) for t in tickets]
+    info = srv.info()
+    srv.close()
+    adm = [r["admitted_at"] for r in res]
+    assert adm == sorted(adm), adm  # first in, first admitted
+    end_big = adm[k_big] + res[k_big]["launches"]
+    assert adm[k_big] >= max(adm[j] + res[j]["launches"] for j in range(k_big)) - 1  # waited for memory
+    assert all(a >= end_big for a in adm[k_big + 1:]), (adm, end_big)
+    assert all(r["status"] == "converged" for r in res)
+    assert info["completed"] == len(order) and info["arena_free"] == info["arena_bytes"]
+    assert np.array_equal(solve_alone(torch, P, big)["x"], xs[k_big].cpu().numpy())
+    assert np.array_equal(solve_alone(torch, P, small[1])["x"], xs[-1].cpu().numpy())
