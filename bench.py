@@ -285,9 +285,9 @@ def pass_workload(name: str, seed: int = 0):
                 n * (8 + es * 16) + nnz * (4 + es) + 4 * (n + 1) + es * n, p)
     ps = problems.batch_rectangles(cfg["N"], seed=seed)
     tot = sum(q.op.n for q in ps)
-    # x rw (16 B) + r, z, s, t rw (8 es) + w r, w' w (2 es)
+    # x rw every other pass (8 B on average) + r, z, s, t rw (8 es) + w r, w' w (2 es)
     return (f"{cfg['N']} 2-D Poisson rectangles (sum n = {tot}), FP32-stream p-CG-sh sigma = 4 + c, "
-            f"every system iterating", tot * (16 + es * 10), ps)
+            f"every system iterating", tot * (8 + es * 10), ps)
 
 
 def run_pass_profile(P, torch, name: str, passes: int):

@@ -5,7 +5,10 @@
 //   COPYIN  caller x -> internal (blocked) x
 //   INIT0   r_0 := b - A x_0, u_0 := M^-1 r_0, z = q = s = t = p := 0; (b, b)
 //   INIT1   w_0 := A u_0 - sigma r_0; gamma_0, delta_0, rho_0
-//   ITER    one iteration of shifted pipelined CG (Alg. 3)
+//   ITER    one iteration of shifted pipelined CG (Alg. 3); x is written
+//           every other iteration (the pass of iteration i leaves it, that
+//           of i + 1 applies both updates in order)
+//   XFIX    x := x + alpha p when the last iteration pass left x
 //   RESID   ||b - A x|| in binary64 (after the iteration ends)
 //   COPYOUT internal x -> caller x
 // The pass kernel works on a table of (system, tile) items; each tile is
@@ -33,7 +36,7 @@ namespace pcg {
 
 // A state's phase is the one its system performed in the pass that wrote it.
 enum Phase : int32_t {
-    PH_ADMIT = 0, PH_COPYIN, PH_INIT0, PH_INIT1, PH_ITER, PH_RESID, PH_COPYOUT, PH_DONE, PH_FREE
+    PH_ADMIT = 0, PH_COPYIN, PH_INIT0, PH_INIT1, PH_ITER, PH_XFIX, PH_RESID, PH_COPYOUT, PH_DONE, PH_FREE
 };
 
 constexpr int kBatchBlock = 256;      // threads of a pass block
@@ -72,6 +75,8 @@ struct BatchState {
     double alpha, beta, gamma;  // alpha_i, beta_i, gamma_i of the iteration i the next ITER pass performs;
                                 // after it, alpha and gamma serve as alpha_{i-1}, gamma_{i-1}
     double bnorm2, rho, true_res2;
+    double alpha_prev;          // alpha_{i-1} while iterating (the catching-up pass's first x update)
+    double pad2;
 };
 
 struct BatchTables {

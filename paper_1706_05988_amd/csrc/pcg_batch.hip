@@ -76,9 +76,13 @@ __device__ __forceinline__ void batch_tile(const PassArgs<T> &a, const BatchStat
         sc.beta = S.beta;
         sc.sigma = a.sigma;
         sc.dsig = 0.0;
-        tile_pipe<T, OP, JAC, E, true>(a, tile, sc, acc);
+        sc.alpha_prev = S.alpha_prev;
+        // x every other iteration (the same two updates in the same order)
+        if (lag_mode(S.iter, S.i_start) == X_SKIP) tile_pipe<T, OP, JAC, E, true, false, X_SKIP>(a, tile, sc, acc);
+        else tile_pipe<T, OP, JAC, E, true, false, X_CATCHUP>(a, tile, sc, acc);
         break;
     }
+    case PH_XFIX: tile_x_fixup<T, JAC, E>(a, tile, S.alpha); break;
     case PH_RESID: {
         double r2[2] = {0.0, 0.0};
         tile_resid<T, OP, E>(a, tile, r2);
@@ -162,12 +166,15 @@ __device__ __forceinline__ BatchState batch_decide(const BatchSys &D, BatchState
     S.rho = rho;
     if (status == RUNNING) {
         S.phase = PH_ITER;
+        S.alpha_prev = S.alpha;
         S.alpha = alpha;
         S.beta = beta;
         S.gamma = gamma;
     } else {
         S.status = status;
-        S.phase = PH_RESID;
+        // the last iteration pass (i - 1) left x: complete it with
+        // alpha_{i-1} p_{i-1} (S.alpha, p as that pass stored it) first
+        S.phase = (i > S.i_start && ((i - 1 - S.i_start) & 1) == 0) ? PH_XFIX : PH_RESID;
     }
     return S;
 }
@@ -193,6 +200,7 @@ __device__ __forceinline__ BatchState batch_next(const BatchSys &D, BatchState S
         S.wcur ^= 1;
         S = batch_decide(D, S, tot[0], tot[1], tot[2], writer);
         break;
+    case PH_XFIX: S.phase = PH_RESID; break;
     case PH_RESID: {
         S.true_res2 = tot[0];
         const bool restart = S.status == ST_CONVERGED && D.true_check && S.restarts < D.replace_max &&
@@ -219,8 +227,11 @@ __device__ __forceinline__ BatchState batch_next(const BatchSys &D, BatchState S
 // partials are read from slot par and written to slot 1 - par.  HEAD: the
 // item block takes its system's transition itself; otherwise k_batch_trans
 // has already written the transitioned state into slot 1 - par.
+#ifndef PCG_BATCH_MIN_WAVES
+#define PCG_BATCH_MIN_WAVES 1
+#endif
 template <typename T, bool HEAD, int SPEC>
-__global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int par)
+__global__ void __launch_bounds__(kBatchBlock, PCG_BATCH_MIN_WAVES) k_batch_step(BatchTables tb, int par)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     const int nitems = tb.counts[0];
@@ -243,7 +254,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int 
                 continue;
             }
             double tot[3] = {0.0, 0.0, 0.0};
-            if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT)
+            if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT && phase != PH_XFIX)
                 stage2<3>(D.part + (size_t)par * D.ntiles * kBatchWaves * kFields, D.ntiles * kBatchWaves, tot, lds_red);
             S = batch_next(D, *Sin, tot, writer);
             if (writer) *Sout = S;
@@ -281,7 +292,7 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_trans(BatchTables tb, int
             continue;
         }
         double tot[3] = {0.0, 0.0, 0.0};
-        if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT)
+        if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT && phase != PH_XFIX)
             stage2<3>(D.part + (size_t)par * D.ntiles * kBatchWaves * kFields, D.ntiles * kBatchWaves, tot, lds_red);
         const BatchState S = batch_next(D, *Sin, tot, threadIdx.x == 0);
         if (threadIdx.x == 0) *Sout = S;

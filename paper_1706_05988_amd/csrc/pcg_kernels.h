@@ -554,12 +554,12 @@ __device__ __forceinline__ void tile_pipe_update(const PassArgs<T> &a, const Pip
     }
 }
 
-template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false>
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false, int XM = X_EACH>
 __device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const PipeScalars &sc, double (&acc)[3])
 {
     PipeTile<EPT> d;
-    tile_pipe_load<T, OP, JAC, EPT, NT>(a, tile, d);
-    tile_pipe_update<T, OP, JAC, EPT, NT, VAR>(a, d, sc, acc);
+    tile_pipe_load<T, OP, JAC, EPT, NT, XM>(a, tile, d);
+    tile_pipe_update<T, OP, JAC, EPT, NT, VAR, XM>(a, d, sc, acc);
 }
 
 // One pass with x's update mode fixed at compile time, so that the skipping
@@ -595,22 +595,26 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
         pipe_pass<T, OP, JAC, EPT, NT, VAR, X_CATCHUP, SELL>(a, tr, lds_red);
 }
 
-// x := x + alpha p: completes x after a solve that stopped after a pass that
-// skipped x (alpha = alpha_i and p = p_i of that pass's iteration).
+// x := x + alpha p on one tile: completes x after a solve that stopped after
+// a pass that skipped x (alpha = alpha_i and p = p_i of that pass's iteration).
+template <typename T, bool JAC, int EPT>
+__device__ __forceinline__ void tile_x_fixup(const PassArgs<T> &a, int tile, double alpha)
+{
+    const uint32_t off_p = JAC ? a.off_p : a.off_t;
+    const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        if (!ti.live[j]) continue;
+        double *xp = vp<double>(a, a.off_x, ti.e[j]);
+        *xp = *xp + alpha * ld(vp<T>(a, off_p, ti.e[j]), 0);
+    }
+}
+
 template <typename T, bool JAC, int EPT>
 __global__ void __launch_bounds__(kMaxBlock) k_x_fixup(PassArgs<T> a, double alpha)
 {
-    const uint32_t off_p = JAC ? a.off_p : a.off_t;
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) {
-        const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            if (!ti.live[j]) continue;
-            double *xp = vp<double>(a, a.off_x, ti.e[j]);
-            *xp = *xp + alpha * ld(vp<T>(a, off_p, ti.e[j]), 0);
-        }
-    }
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_x_fixup<T, JAC, EPT>(a, tile, alpha);
 }
 
 // ------------------------------------------------- p-CG with residual replacement

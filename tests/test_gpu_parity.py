@@ -764,3 +764,32 @@ def test_autotuner_shape_solves_like_the_oracle_and_caches(torch, tmp_path, monk
     s.close()
     o = oracle_solve(p, "pipe_shift", sigma=1.0, rtol=1e-30, max_iter=60)
     check_history(g, o)
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("method", ["pipe", "pipe_shift"])
+def test_csr_sliced_ell_operand_gives_the_csr_bits(torch, method, fp32):
+    """The fused pass on the sliced-ELL copy of a CSR operator forms every
+    row's products and sums in CSR storage order, so at one launch shape a
+    solve gives the same bits with either operand form -- on the
+    anisotropic operator (rows of 3 to 5 entries, a ragged last slice) and
+    on a 3-D 7-point Laplacian assembled as CSR (rows of 4 to 7 entries,
+    Jacobi from its diagonal, a last slice of 4 rows)."""
+    from paper_1706_05988_amd import pcg as P
+    A = problems.to_scipy(problems.stencil3d(20, 17, 13)).tocsr()
+    A.sort_indices()
+    op3 = problems.csr_operator(A.indptr, A.indices, A.data)
+    xt = np.random.default_rng(8).uniform(-1, 1, op3.n)
+    p3 = problems.Problem("lapl3d_csr", op3, A @ xt, np.zeros(op3.n), xt, jacobi=True, sigma=1.0)
+    for p in (problems.anisotropic_csr(90, seed=4), p3):
+        base = P.PCG_VAR_SET | P.PCG_VAR_NT | P.PCG_VAR_EPT1
+        out = []
+        for sell in (0, P.PCG_VAR_CSR_SELL):
+            g = gpu_solve(torch, p, method, fp32=fp32, sigma=1.0 if method == "pipe_shift" else 0.0, max_iter=300,
+                          rtol=1e-30, true_residual_check=False, variant=base | sell, block_size=256,
+                          grid_blocks=64)
+            out.append(g)
+        a, b = out
+        assert a["iterations"] == b["iterations"]
+        np.testing.assert_array_equal(a["res"], b["res"])
+        np.testing.assert_array_equal(a["x"], b["x"])
