@@ -807,6 +807,48 @@ def report_csr_shapes(P, torch, sizes=(1024, 2048), passes: int = 200) -> dict:
     return out
 
 
+def report_pipe_shapes(P, torch, passes: int = 200) -> dict:
+    """Launch shapes of the fused p-CG-sh pass without a preconditioner on
+    stencils (the Section 5.2 problem 1000^2, a 3300^2 grid and 256^3), both
+    storage forms: 1, 2 or 4 unknowns per thread x 128 or 256 threads x 1,
+    2, 4 (and for 128 threads 8) blocks per CU; microseconds per pass over
+    `passes` passes (HIP events), and the built-in shape."""
+    import problems
+    out = {"workload": f"p-CG-sh, M = I, {passes} passes", "runs": []}
+    ept_bits = {1: P.PCG_VAR_EPT1, 2: 0, 4: P.PCG_VAR_EPT4}
+    cases = [("2d 1000^2", problems.stencil2d(1000), 4.0), ("2d 3300^2", problems.stencil2d(3300), 4.0),
+             ("3d 256^3", problems.stencil3d(256), 6.0)]
+    for name, op, sig in cases:
+        b = torch.rand(op.n, dtype=torch.float64, device="cuda") * 2 - 1
+        for fp32 in (False, True):
+            bpp = op.n * bytes_per_unknown("pipe_shift", False, fp32)
+            shapes = [None] + [(e, bl, pc) for e in (1, 2, 4) for bl in (128, 256) for pc in (1, 2, 4, 8)
+                               if not (pc == 8 and bl != 128)]
+            best = None
+            for sh in shapes:
+                kw = {} if sh is None else dict(variant=P.PCG_VAR_SET | P.PCG_VAR_NT | ept_bits[sh[0]],
+                                                block_size=sh[1], grid_blocks=sh[2] * 256)
+                opt = P.make_options(method="pipe_shift", fp32=fp32, sigma=sig, rtol=1e-30, max_iter=passes,
+                                     true_residual_check=False, timing=True, **kw)
+                sv = P.Solver(op, opt)
+                x = torch.zeros_like(b)
+                sv.solve(b, x)
+                x.zero_()
+                r = sv.solve(b, x)
+                sv.close()
+                us = r["iter_kernel_ms"] * 1e3 / max(1, r["iter_passes"])
+                row = {"case": name, "form": "fp32-stream" if fp32 else "fp64",
+                       "shape": "built-in" if sh is None else f"ept{sh[0]} b{sh[1]} x{sh[2]}/CU",
+                       "us_per_pass": round(us, 2), "gbs": round(bpp / (us * 1e-6) / 1e9)}
+                out["runs"].append(row)
+                if best is None or us < best["us_per_pass"]:
+                    best = row
+            print(best, [r for r in out["runs"] if r["shape"] == "built-in"][-1], flush=True)
+        del b
+        torch.cuda.empty_cache()
+    return out
+
+
 def report_c2(P, torch, N: int = 256) -> dict:
     """The 3-D Poisson problem (N^3, Jacobi, x_true ~ U(-1, 1), x0 = 0):
     classic CG, p-CG and p-CG-sh in binary64, p-CG-sh in the FP32-stream
@@ -1011,7 +1053,7 @@ def main():
     ap.add_argument("--serving-max-log10", type=float, default=7.0,
                     help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
     ap.add_argument("--report", choices=["c2", "c3", "small", "tune", "psi", "batch", "stream", "csr_sizes",
-                                         "csr_shapes"],
+                                         "csr_shapes", "pipe_shapes"],
                     help="print a measurement report (C3 accuracy per shift, or the latency-bound cases) and exit")
     ap.add_argument("--c3-N", type=int, default=1024)
     ap.add_argument("--c3-max-iter", type=int, default=12000)
@@ -1059,6 +1101,7 @@ def main():
                stream_ceiling(P, torch) if args.report == "stream" else
                report_csr_sizes(P, torch) if args.report == "csr_sizes" else
                report_csr_shapes(P, torch) if args.report == "csr_shapes" else
+               report_pipe_shapes(P, torch) if args.report == "pipe_shapes" else
                report_c2(P, torch, args.N) if args.report == "c2" else report_tune(P, torch))
         print(json.dumps(rep), flush=True)
         return

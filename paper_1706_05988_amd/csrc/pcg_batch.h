@@ -46,6 +46,11 @@ constexpr int kBatchWaves = kBatchBlock / 64;  // partials per work tile (one pe
 #define PCG_BATCH_EPT 4
 #endif
 constexpr int kBatchEPT = PCG_BATCH_EPT;  // unknowns per thread: a work tile is 256 * kBatchEPT unknowns
+// A system with more partials than this has them summed in fixed chunks of
+// this many by the chunk pass (one block per chunk, the stage-2 order within
+// a chunk), and its transition adds the chunk sums in chunk order: the sum
+// of a large system no longer waits on one block reading all its partials.
+constexpr int kChunkParts = 1024;
 
 // Per-system descriptor, written once at admission.
 struct BatchSys {
@@ -65,7 +70,8 @@ struct BatchSys {
     uint32_t pad0;
     double *part;       // 2 slots of ntiles * kBatchWaves * kFields (one partial per wave)
     double *hist;       // history rows or nullptr
-    int32_t hist_cap, replace_max, true_check, pad1;
+    double *chunk;      // nchunks > 1: 2 slots of nchunks * kFields chunk sums
+    int32_t hist_cap, replace_max, true_check, nchunks;
 };
 
 // Per-system scalars, advanced by the finalize kernel.
@@ -82,9 +88,9 @@ struct BatchState {
 struct BatchTables {
     const BatchSys *sys;
     BatchState *st;          // 2 slots of max_sys states
-    const int32_t *counts;   // [0] = items, [1] = listed systems
+    const int32_t *counts;   // [0] = items, [1] = listed systems, [2] = chunks
     const uint32_t *active;  // listed systems (split mode)
-    const uint2 *items;      // (system, work tile) of each item
+    const uint2 *items;      // (system, work tile) of each item, then (system, chunk) of each chunk
     int32_t max_sys;
     int32_t pad;
 };

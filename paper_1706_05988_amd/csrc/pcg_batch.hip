@@ -227,11 +227,8 @@ __device__ __forceinline__ BatchState batch_next(const BatchSys &D, BatchState S
 // partials are read from slot par and written to slot 1 - par.  HEAD: the
 // item block takes its system's transition itself; otherwise k_batch_trans
 // has already written the transitioned state into slot 1 - par.
-#ifndef PCG_BATCH_MIN_WAVES
-#define PCG_BATCH_MIN_WAVES 1
-#endif
 template <typename T, bool HEAD, int SPEC>
-__global__ void __launch_bounds__(kBatchBlock, PCG_BATCH_MIN_WAVES) k_batch_step(BatchTables tb, int par)
+__global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int par)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     const int nitems = tb.counts[0];
@@ -292,10 +289,43 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_trans(BatchTables tb, int
             continue;
         }
         double tot[3] = {0.0, 0.0, 0.0};
-        if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT && phase != PH_XFIX)
-            stage2<3>(D.part + (size_t)par * D.ntiles * kBatchWaves * kFields, D.ntiles * kBatchWaves, tot, lds_red);
+        if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT && phase != PH_XFIX) {
+            if (D.nchunks > 1) {
+                // the chunk pass's sums, added in chunk order (the same bits in every thread)
+                const double *cs = D.chunk + (size_t)par * D.nchunks * kFields;
+                for (int c = 0; c < D.nchunks; ++c)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) tot[f] += cs[c * kFields + f];
+            } else {
+                stage2<3>(D.part + (size_t)par * D.ntiles * kBatchWaves * kFields, D.ntiles * kBatchWaves, tot,
+                          lds_red);
+            }
+        }
         const BatchState S = batch_next(D, *Sin, tot, threadIdx.x == 0);
         if (threadIdx.x == 0) *Sout = S;
+    }
+}
+
+// Split mode with large systems: each listed (system, chunk) sums its
+// kChunkParts partials of slot par in the stage-2 order into the system's
+// chunk array; k_batch_trans then adds the chunk sums.
+__global__ void __launch_bounds__(kBatchBlock) k_batch_chunk(BatchTables tb, int par)
+{
+    __shared__ double lds_red[kMaxWaves * kFields];
+    const int ni = tb.counts[0], nc = tb.counts[2];
+    for (int k = blockIdx.x; k < nc; k += gridDim.x) {
+        const uint2 sc = tb.items[ni + k];
+        const BatchSys &D = tb.sys[sc.x];
+        const int c = (int)sc.y, nparts = D.ntiles * kBatchWaves;
+        const int p0 = c * kChunkParts, np = min(kChunkParts, nparts - p0);
+        double tot[3];
+        stage2<3>(D.part + ((size_t)par * nparts + p0) * kFields, np, tot, lds_red);
+        if (threadIdx.x == 0) {
+            double *o = D.chunk + ((size_t)par * D.nchunks + c) * kFields;
+            o[0] = tot[0];
+            o[1] = tot[1];
+            o[2] = tot[2];
+        }
     }
 }
 
@@ -326,7 +356,12 @@ static size_t up256(size_t v) { return (v + 255) & ~size_t(255); }
 // The work list, one block uploaded in one copy: the two counts (16 bytes),
 // the listed systems (padded to 8 bytes), then the (system, tile) pairs.
 static size_t list_items_off(int max_sys) { return 16 + 8 * (size_t)((max_sys + 1) / 2); }
-static size_t list_bytes(int max_sys, int64_t max_items) { return list_items_off(max_sys) + 8 * (size_t)max_items; }
+// (system, chunk) entries: a system of t work tiles has ceil(4 t / 1024) <= t / 256 + 1 chunks
+static int64_t max_chunks(int max_sys, int64_t max_items) { return max_items / 256 + max_sys + 1; }
+static size_t list_bytes(int max_sys, int64_t max_items)
+{
+    return list_items_off(max_sys) + 8 * (size_t)(max_items + max_chunks(max_sys, max_items));
+}
 
 size_t BatchEngine::table_bytes(int max_sys, int64_t max_items)
 {
@@ -366,6 +401,12 @@ pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options 
     off += up256((size_t)l.ntiles * tb);
     l.part = off;
     off += up256((size_t)2 * l.nwork * kBatchWaves * kFields * 8);  // two partial slots, one per wave
+    l.nchunks = (int32_t)(((int64_t)l.nwork * kBatchWaves + kChunkParts - 1) / kChunkParts);
+    l.chunk = SIZE_MAX;
+    if (l.nchunks > 1) {
+        l.chunk = off;
+        off += up256((size_t)2 * l.nchunks * kFields * 8);
+    }
     l.dinv = SIZE_MAX;
     if (op->kind == PCG_OP_CSR && jac) {
         l.dinv = off;
@@ -435,7 +476,7 @@ pcg_status BatchEngine::init(char *tables, int max_sys, int64_t max_items, int p
 
 BatchEngine::~BatchEngine()
 {
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < 3; ++k) {
         if (gexec_[k]) (void)hipGraphExecDestroy(gexec_[k]);
         if (graph_[k]) (void)hipGraphDestroy(graph_[k]);
     }
@@ -502,6 +543,8 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
     D.tile_bytes = L.tile_bytes;
     for (int k = 0; k < V_COUNT; ++k) D.off_slot[k] = L.off_slot[k];
     D.part = (double *)(region + L.part);
+    D.nchunks = L.nchunks;
+    D.chunk = L.chunk == SIZE_MAX ? nullptr : (double *)(region + L.chunk);
     D.hist = L.hist == SIZE_MAX ? nullptr : (double *)(region + L.hist);
     D.hist_cap = opt->history_cap;
     D.replace_max = opt->replace_max;
@@ -554,8 +597,22 @@ pcg_status BatchEngine::upload_tables()
             ++ni;
         }
     }
+    // the chunk entries of the large systems follow the items
+    int64_t nc = 0;
+    const int64_t cap = max_items_ + max_chunks(max_sys_, max_items_);
+    for (int k = 0; k < na; ++k) {
+        const int s = (int)act[k];
+        if (sys_[s].nchunks <= 1) continue;
+        for (int c = 0; c < sys_[s].nchunks; ++c) {
+            if (ni + nc >= cap) return PCG_ERR_BUDGET;
+            items[2 * (ni + nc)] = (uint32_t)s;
+            items[2 * (ni + nc) + 1] = (uint32_t)c;
+            ++nc;
+        }
+    }
     cnt[0] = (int32_t)ni;
     cnt[1] = na;
+    cnt[2] = (int32_t)nc;
     // descriptors and states only when a slot was admitted or released:
     // between launches the host copy of a running system's state equals the
     // device one (it was just read back), and admitted or released slots
@@ -568,12 +625,13 @@ pcg_status BatchEngine::upload_tables()
     // the work list in one copy; stream order puts it before the next
     // launch, and the staging buffer is next written after the read-back
     // that follows that launch has been waited for
-    BCHK(hipMemcpyAsync(d_list_, h_list_, list_items_off(max_sys_) + 8 * (size_t)ni, hipMemcpyHostToDevice,
+    BCHK(hipMemcpyAsync(d_list_, h_list_, list_items_off(max_sys_) + 8 * (size_t)(ni + nc), hipMemcpyHostToDevice,
                         stream_));
     BCHK(hipEventRecord(ev_up_, stream_));
     tables_dirty_ = false;
     items_ = ni;
     active_ = na;
+    chunks_ = nc;
     max_sys_items_ = most;
     return PCG_OK;
 }
@@ -621,6 +679,7 @@ void BatchEngine::enqueue_passes(hipStream_t st, int split)
     for (int k = 0; k < K_; ++k) {
         const int par = k & 1;
         if (split) {
+            if (split == 2) hipLaunchKernelGGL(k_batch_chunk, dim3(chunk_grid_), bk, 0, st, tb, par);
             hipLaunchKernelGGL(k_batch_trans, dim3(trans_grid_), bk, 0, st, tb, par);
             if (prec_ == PCG_FP64) launch_step<double, false>(spec_, pg, bk, st, tb, par);
             else launch_step<float, false>(spec_, pg, bk, st, tb, par);
@@ -655,8 +714,9 @@ pcg_status BatchEngine::step(double *gpu_ms)
     if (tables_dirty_ && (st = upload_tables())) return st;
     if (active_ == 0) return PCG_OK;
     // split when the batch is large, or when one system is: in a fused pass
-    // each of a system's items sums all of that system's partials
-    const int split = (items_ > split_items_ || max_sys_items_ > fused_sys_items_) ? 1 : 0;
+    // each of a system's items sums all of that system's partials; with
+    // chunked systems the chunk pass runs first
+    const int split = chunks_ > 0 ? 2 : (items_ > split_items_ || max_sys_items_ > fused_sys_items_) ? 1 : 0;
     if ((st = ensure_graph(split))) return st;
     BCHK(hipEventRecord(ev0_, stream_));
     BCHK(hipGraphLaunch(gexec_[split], stream_));

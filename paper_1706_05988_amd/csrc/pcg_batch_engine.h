@@ -16,7 +16,8 @@ class BatchEngine {
 public:
     // Byte layout of one system's device region (offsets from its start).
     struct SysLayout {
-        size_t blk, part, dinv, hist, flag, gersh, bytes;
+        size_t blk, part, chunk, dinv, hist, flag, gersh, bytes;
+        int32_t nchunks;  // chunks of kChunkParts partials (1: summed whole)
         uint32_t tile_bytes;
         int32_t ntiles;   // layout tiles (kBlk unknowns)
         int32_t nwork;    // work tiles of the pass (kBatchBlock * kBatchEPT unknowns)
@@ -66,6 +67,7 @@ private:
     int K_ = 8;
     int pass_grid_ = 0;      // persistent blocks of the pass; 0: default_pass_grid()
     int trans_grid_ = 256;
+    int chunk_grid_ = 256;
     int spec_ = kSpecAny;
     // above this many items a launch runs split (measured: the fused head
     // costs ~100 us per pass on a full 512-system batch, the extra kernel ~5 us)
@@ -88,11 +90,13 @@ private:
     bool tables_dirty_ = true;
     bool slots_dirty_ = true;     // a slot was admitted or released since the last upload
     int64_t items_ = 0;
+    int64_t chunks_ = 0;          // (system, chunk) entries of the large systems
     int active_ = 0;
     int launches_ = 0;
-    // [0]: fused passes (few items), [1]: transition + pass (many items)
-    hipGraph_t graph_[2] = {nullptr, nullptr};
-    hipGraphExec_t gexec_[2] = {nullptr, nullptr};
+    // [0]: fused passes (few items), [1]: transition + pass (many items),
+    // [2]: chunk sums + transition + pass (a system above kChunkParts partials)
+    hipGraph_t graph_[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t gexec_[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
     hipEvent_t ev_up_ = nullptr;  // after the last upload from the staging buffers
 };

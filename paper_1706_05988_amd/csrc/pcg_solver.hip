@@ -177,7 +177,14 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
             // binary32 streams with four
             s.ept = 4, s.block = 256, blocks_per_cu = fp64 ? 1 : 4;
         } else if (pipe) {
-            s.ept = 1, s.block = 128, blocks_per_cu = 4;
+            // without a preconditioner (measured: FP32-stream 256^3 153.5
+            // against 224.4 us with 1 unknown per thread in 128-thread
+            // blocks, 3300^2 101.5 against 144.0; binary64 256^3 273.6 against
+            // 291.1, 3300^2 174.9 against 184.8; binary64 1000^2 keeps the
+            // lighter shape, 24.8 against 25.8 us)
+            if (!fp64) s.ept = 4, s.block = 256, blocks_per_cu = op->n <= (int64_t(1) << 21) ? 2 : 4;
+            else if (op->n >= (int64_t(1) << 22)) s.ept = 4, s.block = 256, blocks_per_cu = 4;
+            else s.ept = 1, s.block = 128, blocks_per_cu = 4;
         } else if (fp64) {
             s.ept = 1, s.block = 128, blocks_per_cu = 4;
         } else {

@@ -268,3 +268,27 @@ def test_batch_failures_stay_in_their_system(torch):
         assert g["status"] == a["status"] == "converged"
         assert g["iterations"] == a["iterations"]
         np.testing.assert_array_equal(g["x"], a["x"])
+
+
+def test_large_system_chunked_reduction_matches_oracle_and_alone(torch):
+    """A system with more than 1024 partials (here 700 x 600: 411 work tiles,
+    1644 partials, two chunks) has its partials summed in fixed chunks by
+    the chunk pass; beside small systems it gives the bits it gives alone,
+    and it follows the oracle at the parity bar (binary64)."""
+    op = problems.stencil2d(700, 600, shift=0.03)
+    b = np.random.default_rng(21).uniform(-1, 1, op.n)
+    big = problems.Problem("big700x600", op, b, np.zeros(op.n), None, sigma=4.03, rtol=1e-10, max_iter=4000)
+    ps = [big] + mixed_set()[:3]
+    together = run_batch(torch, ps, true_residual_check=False)
+    alone = run_batch(torch, [big], true_residual_check=False)[0]
+    assert np.array_equal(alone["x"], together[0]["x"])
+    assert alone["iterations"] == together[0]["iterations"]
+    np.testing.assert_array_equal(alone["res"], together[0]["res"])
+    o = oracle.solve(big.op, big.b, big.x0, method="pipe_shift", sigma=big.sigma, rtol=big.rtol,
+                     max_iter=big.max_iter, threads=8)
+    g = together[0]
+    assert g["status"] == o["status"] == "converged"
+    assert abs(g["iterations"] - o["iterations"]) <= 1
+    k = min(50, g["iterations"], o["iterations"])
+    np.testing.assert_allclose(g["res"][: k + 1], o["res"][: k + 1], rtol=1e-10)
+    assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-12
