@@ -807,6 +807,56 @@ def report_csr_shapes(P, torch, sizes=(1024, 2048), passes: int = 200) -> dict:
     return out
 
 
+def report_csr_banded(P, torch, sizes=(10 ** 6, 4 * 10 ** 6), passes: int = 200) -> dict:
+    """The fused CSR pass on banded random operators (rows of 4 to 40
+    entries, the serving mix's CSR half), Jacobi, p-CG-sh sigma = 1, both
+    storage forms: the built-in choice, CSR rows at their best shape, and
+    the sorted sliced-ELL copy at 4 rows per thread x 128 / 256 threads x 2,
+    4 or 6 / 2, 3 blocks per CU; microseconds per pass over `passes` passes
+    (HIP events) with the form, shape and copy size the solver reports."""
+    import problems
+    out = {"workload": f"banded random CSR (rows 4..40 entries), Jacobi, p-CG-sh sigma = 1, {passes} passes",
+           "runs": []}
+    for n in sizes:
+        p = problems.banded_csr(n, seed=1)
+        nnz = int(p.op.row_ptr[-1])
+        b = torch.rand(n, dtype=torch.float64, device="cuda") * 2 - 1
+        for fp32 in (False, True):
+            es = 4 if fp32 else 8
+            bpp = n * (8 + es * 16) + nnz * (4 + es) + 4 * (n + 1) + es * n
+            dev = P.DeviceOperator(p.op, P.PCG_FP32_STREAM if fp32 else P.PCG_FP64)
+            shapes = [("built-in", {})]
+            shapes.append(("csr ept1 b256 x4/CU", dict(variant=P.PCG_VAR_SET | P.PCG_VAR_NT | P.PCG_VAR_EPT1,
+                                                      block_size=256, grid_blocks=1024)))
+            shapes.append(("csr ept2 b256 x2/CU", dict(variant=P.PCG_VAR_SET | P.PCG_VAR_NT, block_size=256,
+                                                      grid_blocks=512)))
+            for block, per_cu in ((128, 2), (128, 4), (128, 6), (256, 2), (256, 3)):
+                shapes.append((f"sorted ept4 b{block} x{per_cu}/CU",
+                               dict(variant=P.PCG_VAR_SET | P.PCG_VAR_NT | P.PCG_VAR_EPT4 | P.PCG_VAR_CSR_SELL_SORTED,
+                                    block_size=block, grid_blocks=per_cu * 256)))
+            for name, kw in shapes:
+                opt = P.make_options(method="pipe_shift", jacobi=True, fp32=fp32, sigma=1.0, rtol=1e-30,
+                                     max_iter=passes, true_residual_check=False, timing=True, **kw)
+                sv = P.Solver(dev, opt)
+                x = torch.zeros_like(b)
+                sv.solve(b, x)
+                x.zero_()
+                r = sv.solve(b, x)
+                info = sv.info()
+                sv.close()
+                us = r["iter_kernel_ms"] * 1e3 / max(1, r["iter_passes"])
+                row = {"n": n, "form": "fp32-stream" if fp32 else "fp64", "shape": name,
+                       "us_per_pass": round(us, 2), "gbs_on_csr_bytes": round(bpp / (us * 1e-6) / 1e9),
+                       "operand": info["csr_form_name"], "ept": info["ept"], "block": info["block"],
+                       "grid": info["grid"], "copy_entries_per_nnz": round(info["csr_entries"] / nnz, 3)}
+                out["runs"].append(row)
+                print(row, flush=True)
+            del dev
+        del b
+        torch.cuda.empty_cache()
+    return out
+
+
 def report_pipe_shapes(P, torch, passes: int = 200) -> dict:
     """Launch shapes of the fused p-CG-sh pass without a preconditioner on
     stencils (the Section 5.2 problem 1000^2, a 3300^2 grid and 256^3), both
@@ -1053,7 +1103,7 @@ def main():
     ap.add_argument("--serving-max-log10", type=float, default=7.0,
                     help="largest request size 10^x (the full range is 7; larger sizes take longer to generate)")
     ap.add_argument("--report", choices=["c2", "c3", "small", "tune", "psi", "batch", "stream", "csr_sizes",
-                                         "csr_shapes", "pipe_shapes"],
+                                         "csr_shapes", "csr_banded", "pipe_shapes"],
                     help="print a measurement report (C3 accuracy per shift, or the latency-bound cases) and exit")
     ap.add_argument("--c3-N", type=int, default=1024)
     ap.add_argument("--c3-max-iter", type=int, default=12000)
@@ -1101,6 +1151,7 @@ def main():
                stream_ceiling(P, torch) if args.report == "stream" else
                report_csr_sizes(P, torch) if args.report == "csr_sizes" else
                report_csr_shapes(P, torch) if args.report == "csr_shapes" else
+               report_csr_banded(P, torch) if args.report == "csr_banded" else
                report_pipe_shapes(P, torch) if args.report == "pipe_shapes" else
                report_c2(P, torch, args.N) if args.report == "c2" else report_tune(P, torch))
         print(json.dumps(rep), flush=True)

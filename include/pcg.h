@@ -185,6 +185,13 @@ typedef struct {
                                    sliced-ELL copy of the operator (64-row slices, built
                                    at pcg_create when its padding stays within a quarter
                                    of nnz; the same sums in the same order)             */
+#define PCG_VAR_CSR_SELL_SORTED 0x100 /* as PCG_VAR_CSR_SELL, with the rows sorted by
+                                   length (longest first) within each wave's rows of a
+                                   tile (SELL-C-sigma, C = 64) so that rows of mixed
+                                   lengths pad little; each row's sum is unchanged.  With
+                                   both bits the smaller copy is kept.  Without
+                                   PCG_VAR_SET both are tried, the sorted copy with 4
+                                   unknowns per thread (the passes then take that shape) */
 
 typedef struct {
     int32_t status;             /* PCG_CONVERGED .. PCG_NONFINITE                         */
@@ -238,6 +245,22 @@ pcg_status pcg_true_residual(pcg_solver solver, const double *b, const double *x
 
 pcg_status pcg_destroy(pcg_solver solver);
 
+/* What a solver runs: its passes' launch shape and the form in which the
+ * fused pass reads a CSR operator (decided at pcg_create; a sorted
+ * sliced-ELL copy brings its own shape).  Errors: PCG_ERR_INVALID for a
+ * null argument. */
+typedef struct {
+    int32_t block;              /* threads per block                                      */
+    int32_t ept;                /* unknowns per thread per tile                            */
+    int32_t grid;               /* persistent blocks                                       */
+    int32_t ntiles;             /* tiles of block x ept unknowns                           */
+    int32_t iters_per_launch;   /* iterations per graph launch                            */
+    int32_t csr_form;           /* 0: CSR arrays (or a stencil), 1: sliced-ELL copy with
+                                   the rows in place, 2: sorted sliced-ELL copy           */
+    int64_t csr_entries;        /* entries of that copy, padding included (0 if none)     */
+} pcg_solver_shape;
+pcg_status pcg_solver_info(pcg_solver solver, pcg_solver_shape *shape);
+
 /* ------------------------------------------------- solve without allocation */
 
 /* Size of the device scratch behind pcg_solve_static, per device. */
@@ -275,7 +298,8 @@ pcg_status pcg_solve_static(const pcg_operator *op, const pcg_options *opt, cons
  * block size (128 or 256) and the number of resident blocks per CU (1, 2 or
  * 4; 8 for 128-thread blocks) decide how many independent loads are in
  * flight; for a CSR operator of PCG_PIPE / PCG_PIPE_SHIFT each shape is
- * also tried on the sliced-ELL copy (PCG_VAR_CSR_SELL).  The best choice
+ * also tried on the sliced-ELL copies (PCG_VAR_CSR_SELL, and with 2 or 4
+ * unknowns per thread PCG_VAR_CSR_SELL_SORTED).  The best choice
  * depends on the operator, the method, the preconditioner and the storage
  * form.  pcg_tune measures every candidate (and the library's built-in
  * choice) on the caller's operator -- a solver is created on `workspace`
@@ -283,7 +307,7 @@ pcg_status pcg_solve_static(const pcg_operator *op, const pcg_options *opt, cons
  * 4096) from a zero initial guess, timed with HIP events -- and writes the
  * fastest (the built-in choice unless another shape is 1% faster) into
  * opt->variant (PCG_VAR_SET | unknowns-per-thread bits | PCG_VAR_NT
- * [| PCG_VAR_CSR_SELL]),
+ * [| PCG_VAR_CSR_SELL | PCG_VAR_CSR_SELL_SORTED]),
  * opt->block_size and opt->grid_blocks; *best_us (host, may be NULL)
  * receives its time per pass.  b: device right-hand side (n binary64);
  * x: device scratch of n binary64, overwritten.  workspace: at least

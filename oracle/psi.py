@@ -12,6 +12,13 @@ is the quantity minimised over sigma to pick the shift a posteriori from the
 alpha/beta history of a p-CG run (Section 5.1).
 
 Section 4 gives the variable-shift analogue P_i(sigma_{i-1}, sigma_i).
+
+Parity status: psi itself is pinned (hand-computed one- and two-step
+products, the reduction at sigma = 0, and psi_500(sigma*) of Section 5.1 on
+lapl200).  The selection rule's ``slack`` (select_shift) is a reading of
+Section 5.1's warning against large shifts whose value 2 was chosen so the
+rule returns the published sigma* on lapl200: the slack rule is parity
+unpinned.
 """
 from __future__ import annotations
 

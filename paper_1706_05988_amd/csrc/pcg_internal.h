@@ -29,7 +29,13 @@ struct LaunchShape {
     int nt;       // non-temporal streams on/off
     int K;        // iterations per graph launch
     int zm_rows, zm_seg, zm_nchunks, zm_nsegs;  // CG pass A z-marching split (zm_rows = 0: plain)
-    int sell;     // CSR operand of the fused pipelined pass in sliced-ELL form (where it fits)
+    // CSR operand of the fused pipelined pass in sliced-ELL form (where it
+    // fits): bit 0 rows in place, bit 1 rows sorted by length within each
+    // wave's rows; with both, set-up keeps the smaller copy.  The sorted copy
+    // is laid out for the shape sort_*, which replaces the shape above when
+    // that copy is the one kept.
+    int sell;
+    int sort_block, sort_ept, sort_ntiles, sort_grid;
 };
 
 // byte offsets into the caller's workspace (SIZE_MAX: absent)
@@ -42,6 +48,9 @@ struct Layout {
     size_t sell_ptr, sell_col, sell_val;
     int64_t sell_cap;
     int32_t nslices;
+    // its sorted form: slice offsets and per-slot (length << 8) | position
+    size_t sort_ptr, sort_perm;
+    int32_t sort_nslices;
     uint32_t tile_bytes;
     uint32_t slot_off[V_COUNT];  // byte offset of each slot in a tile (kNoSlot: absent)
     size_t total;

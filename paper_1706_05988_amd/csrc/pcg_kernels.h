@@ -93,6 +93,9 @@ struct PassArgs {
     const int32_t *sell_ptr;
     const int32_t *sell_col;
     const T *sell_val;
+    // sorted form (nullptr: rows in place): per slice slot, (row length << 8)
+    // | the row's position among its wave's rows; see sell_sorted_rows
+    const int32_t *sell_perm;
     int32_t run_through;  // 1: no breakdown stop (PCG_FLAG_RUN_THROUGH_BREAKDOWN)
 };
 
@@ -424,12 +427,13 @@ struct PipeTile {
 // for one load instead of two.  Entries are summed in the row's CSR storage
 // order and padding is skipped by the row's length, so (A v)_e has the bits
 // of apply_row.
+// One row's product from slice s of a sliced-ELL copy: the row sits in
+// lane `lane` of the slice and has len entries (the rest of the slice's
+// width is padding, skipped).
 template <typename T, typename F>
-__device__ __forceinline__ double sell_row(const PassArgs<T> &a, uint32_t e, F v)
+__device__ __forceinline__ double sell_slice(const PassArgs<T> &a, uint32_t s, uint32_t lane, int32_t len, F v)
 {
-    const uint32_t s = e >> 6, lane = e & 63;
     const int32_t p0 = a.sell_ptr[s], w = (a.sell_ptr[s + 1] - p0) >> 6;
-    const int32_t len = a.A.row_ptr[e + 1] - a.A.row_ptr[e];
     double acc = 0.0;
     for (int32_t k = 0; k < w; k += kCsrChunk) {
         int32_t c[kCsrChunk];
@@ -451,7 +455,120 @@ __device__ __forceinline__ double sell_row(const PassArgs<T> &a, uint32_t e, F v
     return acc;
 }
 
-template <typename T, int OP, bool JAC, int EPT, bool NT, int XM = X_EACH, bool SELL = false>
+template <typename T, typename F>
+__device__ __forceinline__ double sell_row(const PassArgs<T> &a, uint32_t e, F v)
+{
+    return sell_slice(a, e >> 6, e & 63, a.A.row_ptr[e + 1] - a.A.row_ptr[e], v);
+}
+
+// The sorted sliced-ELL form (SELL-C-sigma of Kreutzer et al., SIAM J. Sci.
+// Comput. 36 (2014), with C = 64 and the sorting window = one wave's rows of
+// a tile).  A wave owns the EPT x 64 rows tile * B * EPT + j B + 64 w + l
+// (j < EPT, l < 64; B = blockDim.x, w = the wave); they are ordered by
+// length, longest first, and cut into EPT slices of 64 (slice g EPT + j' for
+// the wave's group g = tile * B / 64 + w), so that each slice is as wide as
+// its own longest row instead of the longest of 64 rows taken in place.  The
+// thread at (j', l) forms the product of the row in slot l of slice j'; the
+// products then return to their rows through the wave's own stretch of LDS
+// (EPT x 64 doubles; no block barrier).  Each row is still summed alone in
+// CSR storage order, so ne has the bits of apply_row.
+template <int EPT>
+__device__ __forceinline__ double *sell_exchange_lds()
+{
+    __shared__ double xch[kMaxBlock * EPT];
+    return xch;
+}
+
+// Two slices of one wave at once (s0 the wider, as sorted): their chunks'
+// loads go out together while both have entries left, the second slice's
+// part skipped (a wave-uniform branch) once it has none.
+template <typename T, typename F>
+__device__ __forceinline__ void sell_slice_pair(const PassArgs<T> &a, uint32_t s0, uint32_t lane, int32_t len0,
+                                                int32_t len1, F v, double &out0, double &out1)
+{
+    const int32_t p0 = a.sell_ptr[s0], q0 = a.sell_ptr[s0 + 1], q1 = a.sell_ptr[s0 + 2];
+    const int32_t w0 = (q0 - p0) >> 6, w1 = (q1 - q0) >> 6;
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int32_t k = 0; k < w0; k += kCsrChunk) {
+        const bool two = k < w1;
+        int32_t c0[kCsrChunk], c1[kCsrChunk];
+        T v0[kCsrChunk], v1[kCsrChunk];
+        double g0[kCsrChunk], g1[kCsrChunk];
+#pragma unroll
+        for (int u = 0; u < kCsrChunk; ++u) {
+            const int32_t kk = k + u < w0 ? k + u : k;
+            const int32_t idx = p0 + (kk << 6) + (int32_t)lane;
+            c0[u] = a.sell_col[idx];
+            v0[u] = a.sell_val[idx];
+        }
+        if (two) {
+#pragma unroll
+            for (int u = 0; u < kCsrChunk; ++u) {
+                const int32_t kk = k + u < w1 ? k + u : k;
+                const int32_t idx = q0 + (kk << 6) + (int32_t)lane;
+                c1[u] = a.sell_col[idx];
+                v1[u] = a.sell_val[idx];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kCsrChunk; ++u) g0[u] = v((uint32_t)c0[u]);
+        if (two) {
+#pragma unroll
+            for (int u = 0; u < kCsrChunk; ++u) g1[u] = v((uint32_t)c1[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < kCsrChunk; ++u)
+            if (k + u < len0) acc0 += (double)v0[u] * g0[u];
+        if (two) {
+#pragma unroll
+            for (int u = 0; u < kCsrChunk; ++u)
+                if (k + u < len1) acc1 += (double)v1[u] * g1[u];
+        }
+    }
+    out0 = acc0, out1 = acc1;
+}
+
+template <typename T, int EPT, typename F>
+__device__ __forceinline__ void sell_sorted_rows(const PassArgs<T> &a, int tile, double (&ne)[EPT], F v)
+{
+    static_assert(EPT * 64 <= 256, "a row's position in its wave's rows is kept in 8 bits");
+    double *xch = sell_exchange_lds<EPT>();
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t g = (uint32_t)tile * (blockDim.x >> 6) + wave;
+    double pr[EPT];
+    uint32_t at[EPT];
+    int32_t len[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int32_t info = a.sell_perm[(size_t)(g * EPT + j) * 64 + lane];
+        at[j] = (uint32_t)info & 255;
+        len[j] = info >> 8;
+    }
+    // binary64 slices go two at a time (measured on banded random operators
+    // of 1e6 / 4e6 rows: 94.5 / 382.9 against 99.3 / 402.6 us per pass; the
+    // FP32-stream form gained nothing, 75.5 / 251.6 against 73.5 / 253.8)
+    if constexpr (sizeof(T) == 8 && EPT % 2 == 0) {
+#pragma unroll
+        for (int j = 0; j < EPT; j += 2) sell_slice_pair(a, g * EPT + j, lane, len[j], len[j + 1], v, pr[j], pr[j + 1]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) pr[j] = sell_slice(a, g * EPT + j, lane, len[j], v);
+    }
+    double *xw = xch + wave * (EPT * 64);
+    // the previous tile's reads of xw are done before it is written again
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) xw[at[j]] = pr[j];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) ne[j] = xw[j * 64 + lane];
+}
+
+template <typename T, int OP, bool JAC, int EPT, bool NT, int XM = X_EACH, int SELL = 0>
 __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, PipeTile<EPT> &d)
 {
     const uint32_t off_u = JAC ? a.off_u : a.off_r;
@@ -462,13 +579,14 @@ __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, P
     double *ne = d.ne, *we = d.we, *re = d.re, *ue = d.ue, *zo = d.zo, *so = d.so, *to = d.to, *qo = d.qo,
            *po = d.po, *xo = d.xo;
     // loads: the stencil / CSR operand w_i (cached), then the streams
+    auto operand = [&](uint32_t k) { return minv<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_win, k), 0)); };
+    if constexpr (OP == OP_CSR && SELL == 2) sell_sorted_rows<T, EPT>(a, tile, d.ne, operand);
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const uint32_t e = ti.e[j];
         we[j] = ld(vp<T>(a, a.off_win, e), 0);
-        auto operand = [&](uint32_t k) { return minv<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_win, k), 0)); };
-        if constexpr (OP == OP_CSR && SELL) ne[j] = sell_row(a, e, operand);
-        else ne[j] = apply_row<OP>(a.A, e, operand);
+        if constexpr (OP == OP_CSR && SELL == 1) ne[j] = sell_row(a, e, operand);
+        else if constexpr (OP != OP_CSR || SELL == 0) ne[j] = apply_row<OP>(a.A, e, operand);
         re[j] = lds<NT>(vp<T>(a, a.off_r, e));
         zo[j] = lds<NT>(vp<T>(a, a.off_z, e));
         so[j] = lds<NT>(vp<T>(a, a.off_s, e));
@@ -564,7 +682,7 @@ __device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const 
 
 // One pass with x's update mode fixed at compile time, so that the skipping
 // pass has no x loads or stores in its code at all.
-template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR, int XM, bool SELL>
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR, int XM, int SELL>
 __device__ __forceinline__ void pipe_pass(const PassArgs<T> &a, const TileRange &tr, double *lds_red)
 {
     PipeTile<EPT> d;
@@ -580,8 +698,9 @@ __device__ __forceinline__ void pipe_pass(const PassArgs<T> &a, const TileRange 
     store_partial<3>(a.part_out, acc);
 }
 
-// SELL: a CSR operand read in sliced-ELL form (sell_row).
-template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false, bool SELL = false>
+// SELL: a CSR operand read in sliced-ELL form, 1 with the rows in place
+// (sell_row), 2 sorted (sell_sorted_rows).
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false, int SELL = 0>
 __global__ void __launch_bounds__(kMaxBlock) k_pipe(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
@@ -1231,6 +1350,73 @@ __global__ void __launch_bounds__(256) k_sell_fill(OpDev<T> A, const int32_t *se
     for (int32_t k = 0; k < w; ++k) {
         const int32_t idx = p0 + (k << 6) + (int32_t)lane;
         sell_col[idx] = k < len ? A.col[k0 + k] : (int32_t)r;
+        sell_val[idx] = k < len ? A.val[k0 + k] : (T)0;
+    }
+}
+
+// The sorted form (see sell_sorted_rows), step 1: one wave per group of EPT
+// x 64 rows (a wave's rows of a B-thread tile) ranks its rows by length,
+// longest first, ties by position in the group; writes slot rank of the
+// group as (length << 8) | position and each slice's width (the length of
+// its first slot) into sell_ptr[slice].  A row of 2^23 entries or more
+// gives its slice a width that no capacity admits, so the copy is not made.
+template <int EPT>
+static __global__ void __launch_bounds__(256) k_sell_sort(const int32_t *row_ptr, int32_t n, int32_t block,
+                                                         int32_t ngroups, int32_t *sell_ptr, int32_t *perm)
+{
+    constexpr int R = EPT * 64;
+    __shared__ int32_t len_s[4][R];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * 4 + wave;
+    if (g >= ngroups) return;  // the whole wave
+    const int wpb = block >> 6;
+    const int64_t first = (g / wpb) * (int64_t)block * EPT + (g % wpb) * 64 + lane;
+    int32_t L[EPT];
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int64_t r = first + (int64_t)j * block;
+        L[j] = r < n ? row_ptr[r + 1] - row_ptr[r] : 0;
+        len_s[wave][j * 64 + lane] = L[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+    for (int j = 0; j < EPT; ++j) {
+        const int o = j * 64 + lane;
+        int rank = 0;
+        for (int q = 0; q < R; ++q) {
+            const int32_t lq = len_s[wave][q];
+            rank += (lq > L[j]) || (lq == L[j] && q < o);
+        }
+        const bool fits = L[j] < (1 << 23);
+        perm[g * R + rank] = ((fits ? L[j] : 0) << 8) | o;
+        if ((rank & 63) == 0) sell_ptr[g * EPT + (rank >> 6)] = fits ? L[j] : (INT32_MAX >> 6);
+    }
+}
+
+// The sorted form, step 3 (after k_sell_scan over the slices): one thread
+// per slot copies its row's entries into the slot's column of its slice,
+// padding with the row's own column (column 0 for a slot past the last row)
+// and a zero value.
+template <typename T, int EPT>
+__global__ void __launch_bounds__(256) k_sell_fill_sorted(OpDev<T> A, int32_t block, int64_t slots,
+                                                           const int32_t *sell_ptr, const int32_t *perm,
+                                                           int32_t *sell_col, T *sell_val)
+{
+    const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (P >= slots) return;
+    const int64_t s = P >> 6, g = s / EPT;
+    const int32_t lane = (int32_t)(P & 63);
+    const int32_t info = perm[P], len = info >> 8, o = info & 255;
+    const int wpb = block >> 6;
+    const int64_t r = (g / wpb) * (int64_t)block * EPT + (int64_t)(o >> 6) * block + (g % wpb) * 64 + (o & 63);
+    const int32_t p0 = sell_ptr[s], w = (sell_ptr[s + 1] - p0) >> 6;
+    const int32_t k0 = len > 0 ? A.row_ptr[r] : 0;  // len > 0 only for r < n
+    const int32_t pad = r < A.n ? (int32_t)r : 0;
+    for (int32_t k = 0; k < w; ++k) {
+        const int64_t idx = p0 + ((int64_t)k << 6) + lane;
+        sell_col[idx] = k < len ? A.col[k0 + k] : pad;
         sell_val[idx] = k < len ? A.val[k0 + k] : (T)0;
     }
 }

@@ -191,18 +191,33 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
             s.ept = 4, s.block = 256, blocks_per_cu = 4;
         }
     }
-    // sliced-ELL CSR copy: built in for both forms (where its padding fits)
-    s.sell = set ? ((var & PCG_VAR_CSR_SELL) != 0) : 1;
+    // sliced-ELL CSR copy: built in for both forms, in place or sorted,
+    // whichever is smaller (where its padding fits)
+    s.sell = set ? ((var & PCG_VAR_CSR_SELL) ? 1 : 0) | ((var & PCG_VAR_CSR_SELL_SORTED) ? 2 : 0) : 3;
     if (o->block_size) s.block = o->block_size;
-    const int64_t tile = int64_t(s.block) * s.ept;
-    s.ntiles = (int)((op->n + tile - 1) / tile);
-    int g = o->grid_blocks ? o->grid_blocks : blocks_per_cu * kNumCU;
-    if (g > s.ntiles) g = s.ntiles;
-    if (g >= 64) g &= ~7;  // a multiple of the XCD count
-    if (g < 1) g = 1;
-    s.grid = g;
+    auto tiles_grid = [&](int block, int ept, int per_cu, int *ntiles, int *grid) {
+        const int64_t tile = int64_t(block) * ept;
+        *ntiles = (int)((op->n + tile - 1) / tile);
+        int g = o->grid_blocks ? o->grid_blocks : per_cu * kNumCU;
+        if (g > *ntiles) g = *ntiles;
+        if (g >= 64) g &= ~7;  // a multiple of the XCD count
+        if (g < 1) g = 1;
+        *grid = g;
+    };
+    tiles_grid(s.block, s.ept, blocks_per_cu, &s.ntiles, &s.grid);
+    // the sorted copy sorts within a wave's rows of a tile, so it takes 4
+    // rows per thread unless the shape is given: four blocks of 128 per CU
+    // (measured on banded random operators of 1e6 and 4e6 rows of 4 to 40
+    // entries: binary64 100.1 / 403.4 us per pass against 98.5 / 406.8 for
+    // two blocks of 256, FP32-stream 73.8 / 253.8 against 74.1 / 263.6)
+    s.sort_block = s.block, s.sort_ept = s.ept, s.sort_ntiles = s.ntiles, s.sort_grid = s.grid;
+    if (!set && op->kind == PCG_OP_CSR) {
+        s.sort_block = o->block_size ? o->block_size : 128;
+        s.sort_ept = 4;
+        tiles_grid(s.sort_block, s.sort_ept, 4, &s.sort_ntiles, &s.sort_grid);
+    }
     const bool want_xcd = set && (var & PCG_VAR_XCD_MAP) != 0;
-    s.xcd_map = (want_xcd && g >= 64 && (g % 8) == 0) ? 1 : 0;
+    s.xcd_map = (want_xcd && s.grid >= 64 && (s.grid % 8) == 0) ? 1 : 0;
     s.K = o->iters_per_launch ? o->iters_per_launch : (op->n >= (1 << 20) ? 16 : 64);
     // classic CG on a 3-D grid: pass A marches along z with the p_i planes in
     // LDS when its window fits (4 planes of rows + 2 grid rows in 48 KB, and
@@ -265,8 +280,11 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
     };
     Layout l{};
     l.state = take(2 * sizeof(DevState) + 128);
-    l.part[0] = take(size_t(sh.grid) * kFields * 8);
-    l.part[1] = take(size_t(sh.grid) * kFields * 8);
+    // partials for the larger of the two grids (a sorted sliced-ELL copy
+    // brings its own shape)
+    const size_t parts = size_t(std::max(sh.grid, sh.sort_grid)) * kFields * 8;
+    l.part[0] = take(parts);
+    l.part[1] = take(parts);
     l.gersh = take(size_t(kGershBlocks) * 2 * 8);
     l.flag = take(64);
     l.hist = take(size_t(o->history_cap) * PCG_HISTORY_FIELDS * 8);
@@ -274,17 +292,27 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
     l.sched = o->method == PCG_PIPE_VAR_SHIFT ? take(size_t(o->sigma_schedule_len) * 8) : SIZE_MAX;
     // the fused pass of p-CG / p-CG-sh reads a CSR operator in sliced-ELL
     // form when its padding stays within a quarter of nnz (decided at set-up)
-    l.sell_ptr = l.sell_col = l.sell_val = SIZE_MAX;
+    l.sell_ptr = l.sell_col = l.sell_val = l.sort_ptr = l.sort_perm = SIZE_MAX;
     l.sell_cap = 0;
-    l.nslices = 0;
+    l.nslices = l.sort_nslices = 0;
     if (op->kind == PCG_OP_CSR && (o->method == PCG_PIPE || o->method == PCG_PIPE_SHIFT) && sh.sell) {
         const int64_t cap = op->nnz + op->nnz / 4 + 4096;
+        const int64_t slots = int64_t(sh.sort_ntiles) * sh.sort_block * sh.sort_ept;
         if (cap < (int64_t(1) << 31) - 64) {
-            l.nslices = (int32_t)((n + 63) / 64);
             l.sell_cap = cap;
-            l.sell_ptr = take(size_t(l.nslices + 1) * 4);
-            l.sell_col = take(size_t(cap) * 4);
-            l.sell_val = take(size_t(cap) * es);
+            if (sh.sell & 1) {
+                l.nslices = (int32_t)((n + 63) / 64);
+                l.sell_ptr = take(size_t(l.nslices + 1) * 4);
+            }
+            if ((sh.sell & 2) && slots < (int64_t(1) << 31) - 1) {
+                l.sort_nslices = (int32_t)(slots / 64);
+                l.sort_ptr = take(size_t(l.sort_nslices + 1) * 4);
+                l.sort_perm = take(size_t(slots) * 4);
+            }
+            if (l.sell_ptr != SIZE_MAX || l.sort_ptr != SIZE_MAX) {
+                l.sell_col = take(size_t(cap) * 4);
+                l.sell_val = take(size_t(cap) * es);
+            }
         }
     }
     // slots of a 512-unknown tile: x (binary64) first, then the stored vectors
@@ -346,8 +374,12 @@ struct KernelSet {
     static void pipe(PassArgsAny a, int g, int b, hipStream_t s)
     {
         if constexpr (OP == OP_CSR) {
+            if (A(a).sell_perm) {
+                hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, false, 2>), dim3(g), dim3(b), 0, s, A(a));
+                return;
+            }
             if (A(a).sell_ptr) {
-                hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, false, true>), dim3(g), dim3(b), 0, s, A(a));
+                hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, false, 1>), dim3(g), dim3(b), 0, s, A(a));
                 return;
             }
         }
@@ -434,7 +466,9 @@ struct pcg_solver_ {
     double sigma;            // shift in use (0 for CG / p-CG)
     std::vector<double> sched;  // variable shift: sigma_{-1}, sigma_0, ... (host copy)
     double dinv_s;           // stencil Jacobi scalar
-    bool sell = false;       // the fused pass reads the CSR operator's sliced-ELL copy
+    int sell = 0;            // the fused pass reads the CSR operator's sliced-ELL copy: 1 rows
+                             // in place, 2 sorted (0: the CSR arrays)
+    int64_t sell_entries = 0;  // entries of that copy, padding included
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     const double *graph_b = nullptr;  // b baked into the captured graph
@@ -503,9 +537,10 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
         a.rr_tau = opt.rr_tau > 0.0 ? opt.rr_tau : std::cbrt(opt.prec == PCG_FP64 ? 0x1p-53 : 0x1p-24);
         a.rr_floor = opt.rr_floor > 0.0 ? opt.rr_floor : 100.0;
         a.zm = CgZm{sh.zm_rows, sh.zm_seg, sh.zm_nchunks, sh.zm_nsegs};
-        a.sell_ptr = sell ? reinterpret_cast<const int32_t *>(ws + L.sell_ptr) : nullptr;
+        a.sell_ptr = sell ? reinterpret_cast<const int32_t *>(ws + (sell == 2 ? L.sort_ptr : L.sell_ptr)) : nullptr;
         a.sell_col = sell ? reinterpret_cast<const int32_t *>(ws + L.sell_col) : nullptr;
         a.sell_val = sell ? reinterpret_cast<const T *>(ws + L.sell_val) : nullptr;
+        a.sell_perm = sell == 2 ? reinterpret_cast<const int32_t *>(ws + L.sort_perm) : nullptr;
         a.run_through = (opt.flags & PCG_FLAG_RUN_THROUGH_BREAKDOWN) ? 1 : 0;
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
@@ -622,32 +657,73 @@ pcg_status csr_setup(const pcg_operator *op, int prec, int jac, void *dinv, int 
     return PCG_OK;
 }
 
-// Sliced-ELL copy of a CSR operator into the workspace (synchronous).
-// *built: 0 when the padded copy would exceed the reserved capacity (the
-// fused pass then reads the CSR arrays).
-pcg_status sell_setup(const pcg_operator *op, int prec, const Layout &L, char *ws, hipStream_t stream, int *built)
+// Sliced-ELL copy of a CSR operator into the workspace (synchronous): the
+// rows in place and / or sorted within each wave's rows, as reserved; the
+// smaller of the two is kept (the sorted one only when at least 1/32
+// smaller, since it also routes the products through LDS).  *form: 0 when
+// neither fits the reserved capacity (the fused pass then reads the CSR
+// arrays), 1 in place, 2 sorted; *entries: the copy's entries.
+pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape &sh, const Layout &L, char *ws,
+                      hipStream_t stream, int *form, int64_t *entries)
 {
-    *built = 0;
-    if (L.sell_col == SIZE_MAX || L.nslices < 1) return PCG_OK;
-    int32_t *sp = reinterpret_cast<int32_t *>(ws + L.sell_ptr);
+    *form = 0;
+    *entries = 0;
+    if (L.sell_col == SIZE_MAX) return PCG_OK;
     const int32_t n = (int32_t)op->n;
-    const int g = (int)((op->n + 255) / 256);
-    hipLaunchKernelGGL(k_sell_width, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sp);
-    hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, stream, sp, L.nslices, L.sell_cap);
-    HIPCHK(hipGetLastError());
-    int32_t total = -1;
-    HIPCHK(hipMemcpyAsync(&total, sp + L.nslices, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    int32_t total[2] = {-1, -1};
+    int32_t *sp = L.sell_ptr == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(ws + L.sell_ptr);
+    int32_t *tp = L.sort_ptr == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(ws + L.sort_ptr);
+    int32_t *perm = L.sort_perm == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(ws + L.sort_perm);
+    if (sp) {
+        const int g = (int)((op->n + 255) / 256);
+        hipLaunchKernelGGL(k_sell_width, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sp);
+        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, stream, sp, L.nslices, L.sell_cap);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&total[0], sp + L.nslices, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    }
+    if (tp) {
+        const int32_t ngroups = L.sort_nslices / sh.sort_ept;
+        const int g = (ngroups + 3) / 4;
+        if (sh.sort_ept == 1)
+            hipLaunchKernelGGL(k_sell_sort<1>, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sh.sort_block, ngroups, tp, perm);
+        else if (sh.sort_ept == 2)
+            hipLaunchKernelGGL(k_sell_sort<2>, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sh.sort_block, ngroups, tp, perm);
+        else
+            hipLaunchKernelGGL(k_sell_sort<4>, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sh.sort_block, ngroups, tp, perm);
+        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, stream, tp, L.sort_nslices, L.sell_cap);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(&total[1], tp + L.sort_nslices, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    }
     HIPCHK(hipStreamSynchronize(stream));
-    if (total < 0) return PCG_OK;
+    int f = total[0] >= 0 ? 1 : 0;
+    if (total[1] >= 0 && (f == 0 || int64_t(total[1]) + total[1] / 32 < int64_t(total[0]))) f = 2;
+    if (f == 0) return PCG_OK;
     int32_t *sc = reinterpret_cast<int32_t *>(ws + L.sell_col);
-    if (prec == PCG_FP64)
-        hipLaunchKernelGGL(k_sell_fill<double>, dim3(g), dim3(256), 0, stream, make_opdev<double>(op), sp, sc,
-                           reinterpret_cast<double *>(ws + L.sell_val));
-    else
-        hipLaunchKernelGGL(k_sell_fill<float>, dim3(g), dim3(256), 0, stream, make_opdev<float>(op), sp, sc,
-                           reinterpret_cast<float *>(ws + L.sell_val));
+    auto fill = [&](auto *tag) {
+        using T = std::remove_pointer_t<decltype(tag)>;
+        T *sv = reinterpret_cast<T *>(ws + L.sell_val);
+        if (f == 1) {
+            const int g = (int)((op->n + 255) / 256);
+            hipLaunchKernelGGL(k_sell_fill<T>, dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sp, sc, sv);
+            return;
+        }
+        const int64_t slots = int64_t(L.sort_nslices) * 64;
+        const int g = (int)((slots + 255) / 256);
+        if (sh.sort_ept == 1)
+            hipLaunchKernelGGL((k_sell_fill_sorted<T, 1>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sh.sort_block,
+                               slots, tp, perm, sc, sv);
+        else if (sh.sort_ept == 2)
+            hipLaunchKernelGGL((k_sell_fill_sorted<T, 2>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sh.sort_block,
+                               slots, tp, perm, sc, sv);
+        else
+            hipLaunchKernelGGL((k_sell_fill_sorted<T, 4>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sh.sort_block,
+                               slots, tp, perm, sc, sv);
+    };
+    if (prec == PCG_FP64) fill((double *)nullptr);
+    else fill((float *)nullptr);
     HIPCHK(hipGetLastError());
-    *built = 1;
+    *form = f;
+    *entries = total[f - 1];
     return PCG_OK;
 }
 
@@ -743,9 +819,13 @@ static pcg_status init_solver(pcg_solver_ *s, const pcg_operator *op, const pcg_
             (st = csr_gershgorin(op, opt->prec, jac, reinterpret_cast<double *>(s->ws + L.gersh), s->stream, &gersh[0],
                                  &gersh[1])))
             return st;
-        int built = 0;
-        if ((st = sell_setup(op, opt->prec, L, s->ws, s->stream, &built))) return st;
-        s->sell = built != 0;
+        if ((st = sell_setup(op, opt->prec, sh, L, s->ws, s->stream, &s->sell, &s->sell_entries))) return st;
+        if (s->sell == 2 && (sh.sort_ept != sh.ept || sh.sort_block != sh.block)) {
+            // the sorted copy is laid out for its own shape: the passes take it
+            s->sh.ept = sh.sort_ept, s->sh.block = sh.sort_block;
+            s->sh.ntiles = sh.sort_ntiles, s->sh.grid = sh.sort_grid;
+            s->kern = pick(opt->prec, op->kind, opt->pc == PCG_PC_JACOBI, s->sh.ept, s->sh.nt != 0);
+        }
     }
     s->sigma = default_sigma(op, opt, gersh);
     if (opt->method == PCG_PIPE_VAR_SHIFT) {
@@ -784,6 +864,19 @@ extern "C" pcg_status pcg_create(pcg_solver *out, const pcg_operator *op, const 
     }
     if ((st = init_solver(s, op, opt, workspace, bytes, hip_stream))) return fail(st);
     *out = s;
+    return PCG_OK;
+}
+
+extern "C" pcg_status pcg_solver_info(pcg_solver s, pcg_solver_shape *out)
+{
+    if (!s || !out) return invalid("null argument");
+    out->block = s->sh.block;
+    out->ept = s->sh.ept;
+    out->grid = s->sh.grid;
+    out->ntiles = s->sh.ntiles;
+    out->iters_per_launch = s->sh.K;
+    out->csr_form = s->sell;
+    out->csr_entries = s->sell_entries;
     return PCG_OK;
 }
 

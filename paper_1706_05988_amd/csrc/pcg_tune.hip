@@ -36,21 +36,24 @@ constexpr double kTimedUs = 3000.0;     // ~3 ms of timed passes per candidate
 // The built-in choice, then 1, 2 or 4 unknowns per thread x 128 or 256
 // threads x 1, 2 or 4 blocks per CU (128-thread blocks also 8); a CSR
 // operator of the fused pipelined pass adds each shape reading its
-// sliced-ELL copy.
+// sliced-ELL copy, and those of 2 or 4 unknowns per thread its sorted copy
+// (with 1 the sorted copy is the other one).
 std::vector<Shape> candidates(const pcg_operator *op, const pcg_options *o)
 {
     std::vector<Shape> c;
     c.push_back({0, 0, 0});
     const int ept_bits[3] = {PCG_VAR_EPT1, 0, PCG_VAR_EPT4};
     const bool sell = op->kind == PCG_OP_CSR && (o->method == PCG_PIPE || o->method == PCG_PIPE_SHIFT);
-    for (int sb : {0, PCG_VAR_CSR_SELL}) {
+    for (int sb : {0, PCG_VAR_CSR_SELL, PCG_VAR_CSR_SELL_SORTED}) {
         if (sb && !sell) continue;
-        for (int eb : ept_bits)
+        for (int eb : ept_bits) {
+            if (sb == PCG_VAR_CSR_SELL_SORTED && eb == PCG_VAR_EPT1) continue;
             for (int block : {128, 256})
                 for (int per_cu : {1, 2, 4, 8}) {
                     if (per_cu == 8 && block != 128) continue;
                     c.push_back({PCG_VAR_SET | PCG_VAR_NT | eb | sb, block, per_cu * kNumCU});
                 }
+        }
     }
     return c;
 }

@@ -29,6 +29,7 @@ PCG_HISTORY_FIELDS = 5
 PCG_VAR_SET, PCG_VAR_XCD_MAP, PCG_VAR_NT, PCG_VAR_EPT1, PCG_VAR_EPT4 = 0x01, 0x02, 0x04, 0x10, 0x20
 PCG_VAR_CG_ZMARCH = 0x40
 PCG_VAR_CSR_SELL = 0x80
+PCG_VAR_CSR_SELL_SORTED = 0x100
 PCG_FLAG_RUN_THROUGH_BREAKDOWN = 0x01
 
 METHOD = {"cg": PCG_CG, "pipe": PCG_PIPE, "pipe_shift": PCG_PIPE_SHIFT, "pipe_var": PCG_PIPE_VAR_SHIFT, "pipe_rr": PCG_PIPE_RR}
@@ -61,6 +62,11 @@ class pcg_result(C.Structure):
                 ("admitted_at", C.c_int32), ("sigma", C.c_double)]
 
 
+class pcg_solver_shape(C.Structure):
+    _fields_ = [("block", C.c_int32), ("ept", C.c_int32), ("grid", C.c_int32), ("ntiles", C.c_int32),
+                ("iters_per_launch", C.c_int32), ("csr_form", C.c_int32), ("csr_entries", C.c_int64)]
+
+
 class pcg_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("queued", C.c_int32), ("running", C.c_int32), ("max_running", C.c_int32),
@@ -84,6 +90,7 @@ _SIGS = {
     "pcg_solve": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(pcg_result)]),
     "pcg_true_residual": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "pcg_destroy": (C.c_int32, [C.c_void_p]),
+    "pcg_solver_info": (C.c_int32, [C.c_void_p, C.POINTER(pcg_solver_shape)]),
     "pcg_solve_static": (C.c_int32, [C.POINTER(pcg_operator), C.POINTER(pcg_options), C.c_void_p, C.c_void_p,
                                      C.POINTER(pcg_result), C.c_void_p]),
     "pcg_batch_workspace_size": (C.c_int32, [C.c_int32, C.POINTER(pcg_operator), C.POINTER(pcg_options),
@@ -185,6 +192,17 @@ def pcg_true_residual(handle: int, b: int, x: int) -> float:
 
 def pcg_destroy(handle: int) -> None:
     _check(lib().pcg_destroy(handle), "pcg_destroy")
+
+
+CSR_FORMS = {0: "csr", 1: "sell", 2: "sell_sorted"}
+
+
+def pcg_solver_info(handle: int) -> dict:
+    sh = pcg_solver_shape()
+    _check(lib().pcg_solver_info(handle, C.byref(sh)), "pcg_solver_info")
+    d = {name: getattr(sh, name) for name, _ in pcg_solver_shape._fields_}
+    d["csr_form_name"] = CSR_FORMS.get(d["csr_form"], "?")
+    return d
 
 
 PCG_STATIC_SCRATCH_BYTES = 64 << 20
@@ -490,6 +508,9 @@ class Solver:
 
     def true_residual(self, b, x) -> float:
         return pcg_true_residual(self.handle, b.data_ptr(), x.data_ptr())
+
+    def info(self) -> dict:
+        return pcg_solver_info(self.handle)
 
     def close(self):
         if self.handle:

@@ -179,7 +179,8 @@ def test_option_struct_layout_matches_header():
     fields = {"pcg_options": [f for f, _ in P.pcg_options._fields_],
               "pcg_operator": [f for f, _ in P.pcg_operator._fields_],
               "pcg_result": [f for f, _ in P.pcg_result._fields_],
-              "pcg_server_stats": [f for f, _ in P.pcg_server_stats._fields_]}
+              "pcg_server_stats": [f for f, _ in P.pcg_server_stats._fields_],
+              "pcg_solver_shape": [f for f, _ in P.pcg_solver_shape._fields_]}
     src = ['#include <stdio.h>', '#include <stddef.h>', '#include "pcg.h"', "int main(void) {"]
     for st, fs in fields.items():
         src.append(f'printf("{st} %zu\\n", sizeof({st}));')
@@ -220,6 +221,21 @@ def test_tune_workspace_covers_every_candidate():
                            grid_blocks=2048)
     assert P.pcg_workspace_size(csr, sell) > P.pcg_workspace_size(csr, plain)
     assert n.value >= P.pcg_workspace_size(csr, sell)
+    # ... and the sorted copy also its per-slot (length, position) words
+    srt, sell4 = (P.make_options(jacobi=True, fp32=True, variant=P.PCG_VAR_SET | form | P.PCG_VAR_EPT4,
+                                 block_size=128, grid_blocks=2048)
+                  for form in (P.PCG_VAR_CSR_SELL_SORTED, P.PCG_VAR_CSR_SELL))
+    assert P.pcg_workspace_size(csr, srt) == P.pcg_workspace_size(csr, sell4) + 4 * 4096
+    assert n.value >= P.pcg_workspace_size(csr, srt)
+    # the built-in shape reserves both copies' offsets and one set of entries
+    assert P.pcg_workspace_size(csr, o32) >= P.pcg_workspace_size(csr, srt)
+
+
+def test_solver_info_rejects_null():
+    import ctypes as C
+    sh = P.pcg_solver_shape()
+    assert P.lib().pcg_solver_info(None, C.byref(sh)) == P.PCG_ERR_INVALID
+    assert P.lib().pcg_solver_info(C.c_void_p(4096), None) == P.PCG_ERR_INVALID
 
 
 def test_tune_rejects_bad_arguments_before_device_work():

@@ -43,6 +43,7 @@ def gpu_solve(torch, p, method, jacobi=None, fp32=False, sigma=None, rtol=None, 
     r = s.solve(b, x)
     torch.cuda.synchronize()
     r["x"] = x.cpu().numpy()
+    r["info"] = s.info()
     s.close()
     return r
 
@@ -199,6 +200,10 @@ def test_csr_banded(torch, method):
     assert g["status"] == o["status"] == "converged"
     check_history(g, o)
     assert abs(g["rel_res_true"] - o["rel_res_true"]) <= 1e-12
+    if method == "pipe_shift":
+        # rows of 4 to 40 entries: the built-in choice is the sorted copy,
+        # with its own shape of 4 unknowns per thread
+        assert g["info"]["csr_form_name"] == "sell_sorted" and g["info"]["ept"] == 4
 
 
 def test_csr_default_sigma_gershgorin(torch):
@@ -790,6 +795,54 @@ def test_csr_sliced_ell_operand_gives_the_csr_bits(torch, method, fp32):
                           grid_blocks=64)
             out.append(g)
         a, b = out
+        assert a["iterations"] == b["iterations"]
+        np.testing.assert_array_equal(a["res"], b["res"])
+        np.testing.assert_array_equal(a["x"], b["x"])
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("shape", [(256, 4), (128, 2), (64, 4)])
+def test_csr_sorted_sliced_ell_gives_the_csr_bits(torch, shape, fp32):
+    """The sorted sliced-ELL copy orders each wave's rows by length and
+    routes the products back to their rows through LDS; every row is still
+    summed alone in CSR storage order, so at one launch shape a p-CG-sh
+    solve gives the same bits as on the CSR arrays -- on banded random
+    operators (rows of 4 to 40 entries, ragged last tile), the anisotropic
+    operator and a 3-D Laplacian assembled as CSR."""
+    from paper_1706_05988_amd import pcg as P
+    block, ept = shape
+    A = problems.to_scipy(problems.stencil3d(19, 17, 13)).tocsr()
+    A.sort_indices()
+    op3 = problems.csr_operator(A.indptr, A.indices, A.data)
+    xt = np.random.default_rng(9).uniform(-1, 1, op3.n)
+    p3 = problems.Problem("lapl3d_csr", op3, A @ xt, np.zeros(op3.n), xt, jacobi=True, sigma=1.0)
+    for p in (problems.banded_csr(5003, seed=3), problems.banded_csr(20011, seed=5),
+              problems.anisotropic_csr(90, seed=4), p3):
+        base = P.PCG_VAR_SET | P.PCG_VAR_NT | (P.PCG_VAR_EPT4 if ept == 4 else 0)
+        out = []
+        for form in (0, P.PCG_VAR_CSR_SELL_SORTED):
+            g = gpu_solve(torch, p, "pipe_shift", fp32=fp32, sigma=1.0, max_iter=200, rtol=1e-30,
+                          true_residual_check=False, variant=base | form, block_size=block, grid_blocks=48)
+            out.append(g)
+        a, b = out
+        # the copy's size from the sorting rule: each wave's ept x 64 rows of a
+        # tile sorted by length cut into slices of 64 as wide as their longest
+        lens = np.diff(np.asarray(p.op.row_ptr, dtype=np.int64))
+        R = block * ept
+        padded = np.zeros(-(-p.op.n // R) * R, np.int64)
+        padded[:p.op.n] = lens
+        groups = padded.reshape(-1, ept, block // 64, 64).transpose(0, 2, 1, 3).reshape(-1, ept * 64)
+        want = 64 * int(np.sort(groups, axis=1)[:, ::-1].reshape(-1, 64).max(axis=1).sum())
+        nnz = int(p.op.row_ptr[-1])
+        fits = want <= nnz + nnz // 4 + 4096
+        print(f"[sorted-sell] {p.name} n={p.op.n} block={block} ept={ept} fp32={fp32}: "
+              f"{b['info']['csr_entries']} entries (rule: {want}) for nnz {nnz}", flush=True)
+        assert a["info"]["csr_form_name"] == "csr"
+        if not fits:  # beyond the reserved capacity: the CSR arrays
+            assert b["info"]["csr_form_name"] == "csr"
+            continue
+        assert b["info"]["csr_form_name"] == "sell_sorted" and b["info"]["csr_entries"] == want
+        assert (b["info"]["block"], b["info"]["ept"]) == (block, ept)
         assert a["iterations"] == b["iterations"]
         np.testing.assert_array_equal(a["res"], b["res"])
         np.testing.assert_array_equal(a["x"], b["x"])
