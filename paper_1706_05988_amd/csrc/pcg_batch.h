@@ -21,12 +21,14 @@
 // in every block of the system -- and performs the next phase on its tile;
 // the block of tile 0 writes the system's new state.  State and partials
 // ping-pong between two slots (pass k reads slot k%2), so one kernel per
-// iteration suffices and no atomics or fences are needed across the XCDs.
+// iteration suffices and the passes need no atomics or fences across the
+// XCDs (only the transition of a chunked system counts its chunk sums).
 // With many items that head (a chain of dependent loads and a block
 // reduction before the tile's own loads) costs more than a kernel launch,
-// so large batches run split: a transition kernel (one block per system)
-// followed by the pass without the head.  Both compute the same transition
-// with the same reduction, so the results do not depend on the mode.
+// so large batches run split: a transition kernel (one block per system,
+// or per chunk of a large system's partials) followed by the pass without
+// the head.  Both compute the same transition with the same reduction, so
+// the results do not depend on the mode.
 #pragma once
 
 #include "pcg_internal.h"
@@ -47,9 +49,11 @@ constexpr int kBatchWaves = kBatchBlock / 64;  // partials per work tile (one pe
 #endif
 constexpr int kBatchEPT = PCG_BATCH_EPT;  // unknowns per thread: a work tile is 256 * kBatchEPT unknowns
 // A system with more partials than this has them summed in fixed chunks of
-// this many by the chunk pass (one block per chunk, the stage-2 order within
-// a chunk), and its transition adds the chunk sums in chunk order: the sum
-// of a large system no longer waits on one block reading all its partials.
+// this many (one block per chunk, the stage-2 order within a chunk), and its
+// transition adds the chunk sums in chunk order: the sum of a large system
+// does not wait on one block reading all its partials.  The block that
+// writes a system's last chunk sum (counted with an atomic) takes the
+// transition, in the same kernel.
 constexpr int kChunkParts = 1024;
 
 // Per-system descriptor, written once at admission.
@@ -71,6 +75,7 @@ struct BatchSys {
     double *part;       // 2 slots of ntiles * kBatchWaves * kFields (one partial per wave)
     double *hist;       // history rows or nullptr
     double *chunk;      // nchunks > 1: 2 slots of nchunks * kFields chunk sums
+    int32_t *chunks_done;  // nchunks > 1: chunk sums of the current transition written so far
     int32_t hist_cap, replace_max, true_check, nchunks;
 };
 

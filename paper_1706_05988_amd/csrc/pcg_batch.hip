@@ -273,7 +273,8 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_step(BatchTables tb, int 
     }
 }
 
-// Split mode: the transition of every listed system, one block per system.
+// Split mode without large systems: the transition of every listed system,
+// one block per system.
 __global__ void __launch_bounds__(kBatchBlock) k_batch_trans(BatchTables tb, int par)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
@@ -289,43 +290,88 @@ __global__ void __launch_bounds__(kBatchBlock) k_batch_trans(BatchTables tb, int
             continue;
         }
         double tot[3] = {0.0, 0.0, 0.0};
-        if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT && phase != PH_XFIX) {
-            if (D.nchunks > 1) {
-                // the chunk pass's sums, added in chunk order (the same bits in every thread)
-                const double *cs = D.chunk + (size_t)par * D.nchunks * kFields;
-                for (int c = 0; c < D.nchunks; ++c)
-#pragma unroll
-                    for (int f = 0; f < 3; ++f) tot[f] += cs[c * kFields + f];
-            } else {
-                stage2<3>(D.part + (size_t)par * D.ntiles * kBatchWaves * kFields, D.ntiles * kBatchWaves, tot,
-                          lds_red);
-            }
-        }
+        if (phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT && phase != PH_XFIX)
+            stage2<3>(D.part + (size_t)par * D.ntiles * kBatchWaves * kFields, D.ntiles * kBatchWaves, tot, lds_red);
         const BatchState S = batch_next(D, *Sin, tot, threadIdx.x == 0);
         if (threadIdx.x == 0) *Sout = S;
     }
 }
 
-// Split mode with large systems: each listed (system, chunk) sums its
-// kChunkParts partials of slot par in the stage-2 order into the system's
-// chunk array; k_batch_trans then adds the chunk sums.
-__global__ void __launch_bounds__(kBatchBlock) k_batch_chunk(BatchTables tb, int par)
+// Split mode with large systems, in place of k_batch_trans: the listed
+// systems of one chunk are transitioned as there; each (system, chunk) entry
+// of a large system sums its kChunkParts partials of slot par in the stage-2
+// order into the system's chunk array, and the block that writes the last
+// chunk sum of its system (an agent-scope counter; release before, acquire
+// after) adds the chunk sums in chunk order and takes the transition.  The
+// counter returns to zero there, for the next pass's kernel.
+__global__ void __launch_bounds__(kBatchBlock) k_batch_trans_chunked(BatchTables tb, int par)
 {
+    constexpr int kStage = 1024;  // chunk sums staged in LDS at a time
     __shared__ double lds_red[kMaxWaves * kFields];
-    const int ni = tb.counts[0], nc = tb.counts[2];
-    for (int k = blockIdx.x; k < nc; k += gridDim.x) {
-        const uint2 sc = tb.items[ni + k];
-        const BatchSys &D = tb.sys[sc.x];
-        const int c = (int)sc.y, nparts = D.ntiles * kBatchWaves;
-        const int p0 = c * kChunkParts, np = min(kChunkParts, nparts - p0);
-        double tot[3];
-        stage2<3>(D.part + ((size_t)par * nparts + p0) * kFields, np, tot, lds_red);
-        if (threadIdx.x == 0) {
-            double *o = D.chunk + ((size_t)par * D.nchunks + c) * kFields;
-            o[0] = tot[0];
-            o[1] = tot[1];
-            o[2] = tot[2];
+    __shared__ double staged[kStage * 3];
+    __shared__ int last;
+    const int ni = tb.counts[0], nact = tb.counts[1], nc = tb.counts[2];
+    for (int k = blockIdx.x; k < nact + nc; k += gridDim.x) {
+        uint32_t s;
+        int c = 0;
+        if (k < nact) {
+            s = tb.active[k];
+            if (tb.sys[s].nchunks > 1) continue;  // its chunk entries take it
+        } else {
+            const uint2 sc = tb.items[ni + (k - nact)];
+            s = sc.x;
+            c = (int)sc.y;
         }
+        const BatchSys &D = tb.sys[s];
+        const BatchState *Sin = tb.st + (size_t)par * tb.max_sys + s;
+        BatchState *Sout = tb.st + (size_t)(1 - par) * tb.max_sys + s;
+        const int phase = Sin->phase;
+        if (phase >= PH_DONE) {
+            if (c == 0 && threadIdx.x == 0) *Sout = *Sin;
+            continue;
+        }
+        const bool sums = phase != PH_ADMIT && phase != PH_COPYIN && phase != PH_COPYOUT && phase != PH_XFIX;
+        const int nparts = D.ntiles * kBatchWaves;
+        double tot[3] = {0.0, 0.0, 0.0};
+        if (D.nchunks <= 1) {
+            if (sums) stage2<3>(D.part + (size_t)par * nparts * kFields, nparts, tot, lds_red);
+        } else {
+            double cs[3] = {0.0, 0.0, 0.0};
+            const int p0 = c * kChunkParts, np = min(kChunkParts, nparts - p0);
+            if (sums) stage2<3>(D.part + ((size_t)par * nparts + p0) * kFields, np, cs, lds_red);
+            if (threadIdx.x == 0) {
+                double *o = D.chunk + ((size_t)par * D.nchunks + c) * kFields;
+                o[0] = cs[0];
+                o[1] = cs[1];
+                o[2] = cs[2];
+                const int before =
+                    __hip_atomic_fetch_add(D.chunks_done, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+                last = before == D.nchunks - 1;
+                if (last) *D.chunks_done = 0;
+            }
+            __syncthreads();
+            const bool mine = last != 0;
+            __syncthreads();  // `last` is read before the next entry writes it
+            if (!mine) continue;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            // the chunk sums, added in chunk order (the same bits in every
+            // thread); loaded into LDS together, so the ordered sum waits on
+            // one memory latency per kStage chunks instead of one per chunk
+            const double *all = D.chunk + (size_t)par * D.nchunks * kFields;
+            for (int q0 = 0; q0 < D.nchunks; q0 += kStage) {
+                const int cnt = min(kStage, D.nchunks - q0);
+                for (int q = threadIdx.x; q < cnt; q += blockDim.x)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) staged[q * 3 + f] = all[(q0 + q) * kFields + f];
+                __syncthreads();
+                for (int q = 0; q < cnt; ++q)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) tot[f] += staged[q * 3 + f];
+                __syncthreads();
+            }
+        }
+        const BatchState S = batch_next(D, *Sin, tot, threadIdx.x == 0);
+        if (threadIdx.x == 0) *Sout = S;
     }
 }
 
@@ -402,10 +448,12 @@ pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options 
     l.part = off;
     off += up256((size_t)2 * l.nwork * kBatchWaves * kFields * 8);  // two partial slots, one per wave
     l.nchunks = (int32_t)(((int64_t)l.nwork * kBatchWaves + kChunkParts - 1) / kChunkParts);
-    l.chunk = SIZE_MAX;
+    l.chunk = l.chunks_done = SIZE_MAX;
     if (l.nchunks > 1) {
         l.chunk = off;
         off += up256((size_t)2 * l.nchunks * kFields * 8);
+        l.chunks_done = off;
+        off += 256;
     }
     l.dinv = SIZE_MAX;
     if (op->kind == PCG_OP_CSR && jac) {
@@ -545,6 +593,10 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
     D.part = (double *)(region + L.part);
     D.nchunks = L.nchunks;
     D.chunk = L.chunk == SIZE_MAX ? nullptr : (double *)(region + L.chunk);
+    D.chunks_done = L.chunks_done == SIZE_MAX ? nullptr : (int32_t *)(region + L.chunks_done);
+    // the counter of written chunk sums starts at zero (the transition that
+    // completes it sets it back)
+    if (D.chunks_done) BCHK(hipMemsetAsync(D.chunks_done, 0, sizeof(int32_t), stream_));
     D.hist = L.hist == SIZE_MAX ? nullptr : (double *)(region + L.hist);
     D.hist_cap = opt->history_cap;
     D.replace_max = opt->replace_max;
@@ -656,13 +708,15 @@ static int step_occupancy(int spec)
 }
 
 // Blocks of the persistent pass when the caller gave none: as many as the
-// pass kernels keep resident (at most four per CU), so that every block
-// starts at once and the items are shared out evenly.
-int BatchEngine::default_pass_grid() const
+// mode's pass kernel keeps resident (at most four per CU), so that every
+// block starts at once and the items are shared out evenly.  The kernel
+// without the head needs fewer registers, so the split modes can run more
+// blocks than the fused one.
+int BatchEngine::default_pass_grid(int split) const
 {
-    const int a = prec_ == PCG_FP64 ? step_occupancy<double, false>(spec_) : step_occupancy<float, false>(spec_);
-    const int b = prec_ == PCG_FP64 ? step_occupancy<double, true>(spec_) : step_occupancy<float, true>(spec_);
-    const int per_cu = std::min(4, std::max(1, std::min(a, b)));
+    const int a = split ? (prec_ == PCG_FP64 ? step_occupancy<double, false>(spec_) : step_occupancy<float, false>(spec_))
+                        : (prec_ == PCG_FP64 ? step_occupancy<double, true>(spec_) : step_occupancy<float, true>(spec_));
+    const int per_cu = std::min(4, std::max(1, a));
     return per_cu * kNumCU;
 }
 
@@ -675,12 +729,12 @@ void BatchEngine::enqueue_passes(hipStream_t st, int split)
                    reinterpret_cast<const uint2 *>(d_list_ + list_items_off(max_sys_)),
                    max_sys_,
                    0};
-    const dim3 pg(pass_grid_ > 0 ? pass_grid_ : default_pass_grid()), bk(kBatchBlock);
+    const dim3 pg(pass_grid_ > 0 ? pass_grid_ : default_pass_grid(split)), bk(kBatchBlock);
     for (int k = 0; k < K_; ++k) {
         const int par = k & 1;
         if (split) {
-            if (split == 2) hipLaunchKernelGGL(k_batch_chunk, dim3(chunk_grid_), bk, 0, st, tb, par);
-            hipLaunchKernelGGL(k_batch_trans, dim3(trans_grid_), bk, 0, st, tb, par);
+            if (split == 2) hipLaunchKernelGGL(k_batch_trans_chunked, dim3(chunk_grid_), bk, 0, st, tb, par);
+            else hipLaunchKernelGGL(k_batch_trans, dim3(trans_grid_), bk, 0, st, tb, par);
             if (prec_ == PCG_FP64) launch_step<double, false>(spec_, pg, bk, st, tb, par);
             else launch_step<float, false>(spec_, pg, bk, st, tb, par);
         } else {

@@ -16,7 +16,7 @@ class BatchEngine {
 public:
     // Byte layout of one system's device region (offsets from its start).
     struct SysLayout {
-        size_t blk, part, chunk, dinv, hist, flag, gersh, bytes;
+        size_t blk, part, chunk, chunks_done, dinv, hist, flag, gersh, bytes;
         int32_t nchunks;  // chunks of kChunkParts partials (1: summed whole)
         uint32_t tile_bytes;
         int32_t ntiles;   // layout tiles (kBlk unknowns)
@@ -59,7 +59,7 @@ private:
     pcg_status upload_tables();
     pcg_status ensure_graph(int split);
     void enqueue_passes(hipStream_t st, int split);
-    int default_pass_grid() const;
+    int default_pass_grid(int split) const;
 
     int max_sys_ = 0;
     int64_t max_items_ = 0;
@@ -94,7 +94,8 @@ private:
     int active_ = 0;
     int launches_ = 0;
     // [0]: fused passes (few items), [1]: transition + pass (many items),
-    // [2]: chunk sums + transition + pass (a system above kChunkParts partials)
+    // [2]: chunk sums with the transition + pass (a system above kChunkParts
+    // partials)
     hipGraph_t graph_[3] = {nullptr, nullptr, nullptr};
     hipGraphExec_t gexec_[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev0_ = nullptr, ev1_ = nullptr;
