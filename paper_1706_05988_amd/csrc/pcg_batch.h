@@ -76,6 +76,12 @@ struct BatchSys {
     double *hist;       // history rows or nullptr
     double *chunk;      // nchunks > 1: 2 slots of nchunks * kFields chunk sums
     int32_t *chunks_done;  // nchunks > 1: chunk sums of the current transition written so far
+    // CSR: the iteration pass's sliced-ELL copy (in place, or sorted for the
+    // pass's 256 x kBatchEPT-row tiles when sell_perm is set; nullptr: CSR rows)
+    const int32_t *sell_ptr;
+    const int32_t *sell_col;
+    const int32_t *sell_perm;
+    const void *sell_val;
     int32_t hist_cap, replace_max, true_check, nchunks;
 };
 

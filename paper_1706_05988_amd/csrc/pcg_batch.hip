@@ -52,6 +52,10 @@ __device__ __forceinline__ PassArgs<T> batch_args(const BatchSys &D, const Batch
     a.sigma = D.sigma;
     a.copy_out = S.phase == PH_COPYOUT;
     a.x_plain = 0;
+    a.sell_ptr = D.sell_ptr;
+    a.sell_col = D.sell_col;
+    a.sell_val = (const T *)D.sell_val;
+    a.sell_perm = D.sell_perm;
     return a;
 }
 
@@ -78,7 +82,21 @@ __device__ __forceinline__ void batch_tile(const PassArgs<T> &a, const BatchStat
         sc.dsig = 0.0;
         sc.alpha_prev = S.alpha_prev;
         // x every other iteration (the same two updates in the same order)
-        if (lag_mode(S.iter, S.i_start) == X_SKIP) tile_pipe<T, OP, JAC, E, true, false, X_SKIP>(a, tile, sc, acc);
+        const bool skip = lag_mode(S.iter, S.i_start) == X_SKIP;
+        if constexpr (OP == OP_CSR) {
+            // the CSR operand: sorted sliced-ELL copy, in-place copy, or rows
+            if (a.sell_perm) {
+                if (skip) tile_pipe<T, OP, JAC, E, true, false, X_SKIP, 2>(a, tile, sc, acc);
+                else tile_pipe<T, OP, JAC, E, true, false, X_CATCHUP, 2>(a, tile, sc, acc);
+                break;
+            }
+            if (a.sell_ptr) {
+                if (skip) tile_pipe<T, OP, JAC, E, true, false, X_SKIP, 1>(a, tile, sc, acc);
+                else tile_pipe<T, OP, JAC, E, true, false, X_CATCHUP, 1>(a, tile, sc, acc);
+                break;
+            }
+        }
+        if (skip) tile_pipe<T, OP, JAC, E, true, false, X_SKIP>(a, tile, sc, acc);
         else tile_pipe<T, OP, JAC, E, true, false, X_CATCHUP>(a, tile, sc, acc);
         break;
     }
@@ -469,6 +487,31 @@ pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options 
     off += 256;
     l.gersh = off;
     off += up256((size_t)kGershBlocks * 2 * 8);
+    // the iteration pass of a CSR system reads a sliced-ELL copy where its
+    // padding stays within a quarter of nnz: rows in place, or sorted within
+    // each wave's rows of a work tile (whichever is smaller)
+    l.sell_ptr = l.sort_ptr = l.sort_perm = l.sell_col = l.sell_val = SIZE_MAX;
+    l.nslices = l.sort_nslices = 0;
+    l.sell_cap = 0;
+    if (op->kind == PCG_OP_CSR) {
+        const int64_t cap = op->nnz + op->nnz / 4 + 4096;
+        const int64_t slots = (int64_t)l.nwork * kBatchBlock * kBatchEPT;
+        if (cap < (int64_t(1) << 31) - 64 && slots < (int64_t(1) << 31) - 1) {
+            l.sell_cap = cap;
+            l.nslices = (int32_t)((n + 63) / 64);
+            l.sell_ptr = off;
+            off += up256((size_t)(l.nslices + 1) * 4);
+            l.sort_nslices = (int32_t)(slots / 64);
+            l.sort_ptr = off;
+            off += up256((size_t)(l.sort_nslices + 1) * 4);
+            l.sort_perm = off;
+            off += up256((size_t)slots * 4);
+            l.sell_col = off;
+            off += up256((size_t)cap * 4);
+            l.sell_val = off;
+            off += up256((size_t)cap * es);
+        }
+    }
     l.bytes = off;
     *L = l;
     return PCG_OK;
@@ -561,6 +604,22 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
             (st = csr_gershgorin(op, opt->prec, jac, (double *)(region + L.gersh), stream_, &gersh[0], &gersh[1])))
             return st;
     }
+    int form = 0;
+    int64_t entries = 0;
+    if (op->kind == PCG_OP_CSR && L.sell_col != SIZE_MAX) {
+        SellPlan p;
+        p.sell_ptr = (int32_t *)(region + L.sell_ptr);
+        p.nslices = L.nslices;
+        p.sort_ptr = (int32_t *)(region + L.sort_ptr);
+        p.sort_perm = (int32_t *)(region + L.sort_perm);
+        p.sort_nslices = L.sort_nslices;
+        p.sort_block = kBatchBlock;
+        p.sort_ept = kBatchEPT;
+        p.cap = L.sell_cap;
+        p.col = (int32_t *)(region + L.sell_col);
+        p.val = region + L.sell_val;
+        if ((st = sell_build(op, opt->prec, p, stream_, &form, &entries))) return st;
+    }
     BatchSys D{};
     D.kind = op->kind;
     D.jac = jac;
@@ -594,6 +653,12 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
     D.nchunks = L.nchunks;
     D.chunk = L.chunk == SIZE_MAX ? nullptr : (double *)(region + L.chunk);
     D.chunks_done = L.chunks_done == SIZE_MAX ? nullptr : (int32_t *)(region + L.chunks_done);
+    D.sell_ptr = form == 1 ? (const int32_t *)(region + L.sell_ptr)
+                 : form == 2 ? (const int32_t *)(region + L.sort_ptr)
+                             : nullptr;
+    D.sell_col = form ? (const int32_t *)(region + L.sell_col) : nullptr;
+    D.sell_perm = form == 2 ? (const int32_t *)(region + L.sort_perm) : nullptr;
+    D.sell_val = form ? (const void *)(region + L.sell_val) : nullptr;
     // the counter of written chunk sums starts at zero (the transition that
     // completes it sets it back)
     if (D.chunks_done) BCHK(hipMemsetAsync(D.chunks_done, 0, sizeof(int32_t), stream_));

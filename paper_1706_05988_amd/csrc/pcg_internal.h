@@ -97,4 +97,25 @@ double default_sigma(const pcg_operator *op, const pcg_options *opt, const doubl
 pcg_status csr_gershgorin(const pcg_operator *op, int prec, int jac, double *scratch_dev, hipStream_t stream,
                           double *lo, double *hi);
 
+// Where the sliced-ELL copies of a CSR operator go (device memory; nullptr /
+// 0 for a form not reserved): the in-place form's nslices + 1 slice offsets,
+// the sorted form's sort_nslices + 1 offsets and per-slot words (laid out for
+// tiles of sort_block x sort_ept rows), and the shared entry arrays of cap
+// entries.
+struct SellPlan {
+    int32_t *sell_ptr = nullptr;
+    int32_t nslices = 0;
+    int32_t *sort_ptr = nullptr, *sort_perm = nullptr;
+    int32_t sort_nslices = 0;
+    int sort_block = 0, sort_ept = 0;
+    int64_t cap = 0;
+    int32_t *col = nullptr;
+    void *val = nullptr;  // cap values of the storage type
+};
+// Build the smaller of the reserved copies that fits cap (synchronous):
+// *form 0 (none fits), 1 (in place; slice offsets at sell_ptr) or 2 (sorted;
+// at sort_ptr / sort_perm); *entries its entries.
+pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipStream_t stream, int *form,
+                      int64_t *entries);
+
 }  // namespace pcg

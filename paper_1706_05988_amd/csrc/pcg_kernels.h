@@ -672,11 +672,11 @@ __device__ __forceinline__ void tile_pipe_update(const PassArgs<T> &a, const Pip
     }
 }
 
-template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false, int XM = X_EACH>
+template <typename T, int OP, bool JAC, int EPT, bool NT, bool VAR = false, int XM = X_EACH, int SELL = 0>
 __device__ __forceinline__ void tile_pipe(const PassArgs<T> &a, int tile, const PipeScalars &sc, double (&acc)[3])
 {
     PipeTile<EPT> d;
-    tile_pipe_load<T, OP, JAC, EPT, NT, XM>(a, tile, d);
+    tile_pipe_load<T, OP, JAC, EPT, NT, XM, SELL>(a, tile, d);
     tile_pipe_update<T, OP, JAC, EPT, NT, VAR, XM>(a, d, sc, acc);
 }
 

@@ -657,67 +657,62 @@ pcg_status csr_setup(const pcg_operator *op, int prec, int jac, void *dinv, int 
     return PCG_OK;
 }
 
-// Sliced-ELL copy of a CSR operator into the workspace (synchronous): the
-// rows in place and / or sorted within each wave's rows, as reserved; the
-// smaller of the two is kept (the sorted one only when at least 1/32
-// smaller, since it also routes the products through LDS).  *form: 0 when
-// neither fits the reserved capacity (the fused pass then reads the CSR
-// arrays), 1 in place, 2 sorted; *entries: the copy's entries.
-pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape &sh, const Layout &L, char *ws,
-                      hipStream_t stream, int *form, int64_t *entries)
+// Sliced-ELL copies of a CSR operator (synchronous): the rows in place
+// and / or sorted within each wave's rows, as reserved; the smaller of the
+// two is kept (the sorted one only when at least 1/32 smaller, since it
+// also routes the products through LDS).
+pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipStream_t stream, int *form,
+                      int64_t *entries)
 {
     *form = 0;
     *entries = 0;
-    if (L.sell_col == SIZE_MAX) return PCG_OK;
+    if (!p.col || (!p.sell_ptr && !p.sort_ptr)) return PCG_OK;
     const int32_t n = (int32_t)op->n;
     int32_t total[2] = {-1, -1};
-    int32_t *sp = L.sell_ptr == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(ws + L.sell_ptr);
-    int32_t *tp = L.sort_ptr == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(ws + L.sort_ptr);
-    int32_t *perm = L.sort_perm == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(ws + L.sort_perm);
+    int32_t *sp = p.sell_ptr, *tp = p.sort_ptr, *perm = p.sort_perm;
     if (sp) {
         const int g = (int)((op->n + 255) / 256);
         hipLaunchKernelGGL(k_sell_width, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sp);
-        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, stream, sp, L.nslices, L.sell_cap);
+        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, stream, sp, p.nslices, p.cap);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&total[0], sp + L.nslices, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(&total[0], sp + p.nslices, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     }
     if (tp) {
-        const int32_t ngroups = L.sort_nslices / sh.sort_ept;
+        const int32_t ngroups = p.sort_nslices / p.sort_ept;
         const int g = (ngroups + 3) / 4;
-        if (sh.sort_ept == 1)
-            hipLaunchKernelGGL(k_sell_sort<1>, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sh.sort_block, ngroups, tp, perm);
-        else if (sh.sort_ept == 2)
-            hipLaunchKernelGGL(k_sell_sort<2>, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sh.sort_block, ngroups, tp, perm);
+        if (p.sort_ept == 1)
+            hipLaunchKernelGGL(k_sell_sort<1>, dim3(g), dim3(256), 0, stream, op->row_ptr, n, p.sort_block, ngroups, tp, perm);
+        else if (p.sort_ept == 2)
+            hipLaunchKernelGGL(k_sell_sort<2>, dim3(g), dim3(256), 0, stream, op->row_ptr, n, p.sort_block, ngroups, tp, perm);
         else
-            hipLaunchKernelGGL(k_sell_sort<4>, dim3(g), dim3(256), 0, stream, op->row_ptr, n, sh.sort_block, ngroups, tp, perm);
-        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, stream, tp, L.sort_nslices, L.sell_cap);
+            hipLaunchKernelGGL(k_sell_sort<4>, dim3(g), dim3(256), 0, stream, op->row_ptr, n, p.sort_block, ngroups, tp, perm);
+        hipLaunchKernelGGL(k_sell_scan, dim3(1), dim3(1024), 0, stream, tp, p.sort_nslices, p.cap);
         HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(&total[1], tp + L.sort_nslices, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipMemcpyAsync(&total[1], tp + p.sort_nslices, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     }
     HIPCHK(hipStreamSynchronize(stream));
     int f = total[0] >= 0 ? 1 : 0;
     if (total[1] >= 0 && (f == 0 || int64_t(total[1]) + total[1] / 32 < int64_t(total[0]))) f = 2;
     if (f == 0) return PCG_OK;
-    int32_t *sc = reinterpret_cast<int32_t *>(ws + L.sell_col);
     auto fill = [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
-        T *sv = reinterpret_cast<T *>(ws + L.sell_val);
+        T *sv = reinterpret_cast<T *>(p.val);
         if (f == 1) {
             const int g = (int)((op->n + 255) / 256);
-            hipLaunchKernelGGL(k_sell_fill<T>, dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sp, sc, sv);
+            hipLaunchKernelGGL(k_sell_fill<T>, dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sp, p.col, sv);
             return;
         }
-        const int64_t slots = int64_t(L.sort_nslices) * 64;
+        const int64_t slots = int64_t(p.sort_nslices) * 64;
         const int g = (int)((slots + 255) / 256);
-        if (sh.sort_ept == 1)
-            hipLaunchKernelGGL((k_sell_fill_sorted<T, 1>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sh.sort_block,
-                               slots, tp, perm, sc, sv);
-        else if (sh.sort_ept == 2)
-            hipLaunchKernelGGL((k_sell_fill_sorted<T, 2>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sh.sort_block,
-                               slots, tp, perm, sc, sv);
+        if (p.sort_ept == 1)
+            hipLaunchKernelGGL((k_sell_fill_sorted<T, 1>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), p.sort_block,
+                               slots, tp, perm, p.col, sv);
+        else if (p.sort_ept == 2)
+            hipLaunchKernelGGL((k_sell_fill_sorted<T, 2>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), p.sort_block,
+                               slots, tp, perm, p.col, sv);
         else
-            hipLaunchKernelGGL((k_sell_fill_sorted<T, 4>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sh.sort_block,
-                               slots, tp, perm, sc, sv);
+            hipLaunchKernelGGL((k_sell_fill_sorted<T, 4>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), p.sort_block,
+                               slots, tp, perm, p.col, sv);
     };
     if (prec == PCG_FP64) fill((double *)nullptr);
     else fill((float *)nullptr);
@@ -725,6 +720,26 @@ pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape &sh, c
     *form = f;
     *entries = total[f - 1];
     return PCG_OK;
+}
+
+// The solver's copies, as its layout reserved them.
+static pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape &sh, const Layout &L, char *ws,
+                             hipStream_t stream, int *form, int64_t *entries)
+{
+    SellPlan p;
+    if (L.sell_col != SIZE_MAX) {
+        p.sell_ptr = L.sell_ptr == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(ws + L.sell_ptr);
+        p.nslices = L.nslices;
+        p.sort_ptr = L.sort_ptr == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(ws + L.sort_ptr);
+        p.sort_perm = L.sort_perm == SIZE_MAX ? nullptr : reinterpret_cast<int32_t *>(ws + L.sort_perm);
+        p.sort_nslices = L.sort_nslices;
+        p.sort_block = sh.sort_block;
+        p.sort_ept = sh.sort_ept;
+        p.cap = L.sell_cap;
+        p.col = reinterpret_cast<int32_t *>(ws + L.sell_col);
+        p.val = ws + L.sell_val;
+    }
+    return sell_build(op, prec, p, stream, form, entries);
 }
 
 pcg_status csr_gershgorin(const pcg_operator *op, int prec, int jac, double *gb, hipStream_t stream, double *lo,
