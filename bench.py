@@ -238,6 +238,10 @@ PASS_PROFILES = {
     "pipe_csr_aniso1024_jacobi_fp64": dict(problem="aniso", N=1024, fp32=False, kernel="k_pipe<double, 2, true"),
     "pipe_csr_aniso1024_jacobi_fp32": dict(problem="aniso", N=1024, fp32=True, kernel="k_pipe<float, 2, true"),
     "batch_rect512_fp32_fullpass": dict(problem="batch", N=512, fp32=True, kernel="k_batch_step<float"),
+    # banded random CSR (rows of 4..40 entries) on the sorted sliced-ELL copy
+    # (the built-in choice there); bytes are the CSR form's, padding excluded
+    "pipe_csr_banded4m_jacobi_fp64": dict(problem="banded", N=4_000_000, fp32=False,
+                                          kernel="k_pipe<double, 2, true, 4, true, false, 2>"),
     # classic CG's two passes (bytes per unknown: A reads r and p, writes p' and s;
     # B reads x, r, p', s and writes x and r)
     "cg_a_3d7_jacobi_fp64_256": dict(problem="poisson3d", N=256, fp32=False, method="cg",
@@ -275,12 +279,17 @@ def pass_workload(name: str, seed: int = 0):
         return (f"3-D Poisson 7-point {cfg['N']}^3 (n={n}), Jacobi, p-CG-sh sigma = 1, "
                 f"{'FP32-stream' if cfg['fp32'] else 'FP64'}",
                 bytes_per_unknown("pipe_shift", True, cfg["fp32"]) * n, p)
-    if cfg["problem"] == "aniso":
-        p = problems.anisotropic_csr(cfg["N"], seed=seed)
-        n, nnz = p.op.n, p.op.nnz
+    if cfg["problem"] in ("aniso", "banded"):
+        if cfg["problem"] == "aniso":
+            p = problems.anisotropic_csr(cfg["N"], seed=seed)
+            what = f"2-D anisotropic diffusion {cfg['N']}^2 CSR"
+        else:
+            p = problems.banded_csr(cfg["N"], seed=1)
+            what = "banded random CSR, rows of 4..40 entries, sorted sliced-ELL copy"
+        n, nnz = p.op.n, int(p.op.row_ptr[-1])
         # streams: x rw every other pass, 7 vectors rw, w r + w' w; CSR values,
         # indices, row_ptr, Jacobi diagonal
-        return (f"2-D anisotropic diffusion {cfg['N']}^2 CSR (n={n}, nnz={nnz}), Jacobi, p-CG-sh sigma = 1, "
+        return (f"{what} (n={n}, nnz={nnz}), Jacobi, p-CG-sh sigma = 1, "
                 f"{'FP32-stream' if cfg['fp32'] else 'FP64'}",
                 n * (8 + es * 16) + nnz * (4 + es) + 4 * (n + 1) + es * n, p)
     ps = problems.batch_rectangles(cfg["N"], seed=seed)

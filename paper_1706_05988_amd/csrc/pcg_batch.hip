@@ -536,6 +536,9 @@ pcg_status BatchEngine::init(char *tables, int max_sys, int64_t max_items, int p
     prec_ = prec;
     stream_ = stream;
     K_ = K > 0 ? K + (K & 1) : 32;  // even: a launch starts at state slot 0
+    // one block per listed system in the transition kernel (its chain of
+    // dependent loads and a block reduction per system is what it costs)
+    trans_grid_ = std::max(256, std::min(max_sys, 2048));
     size_t off = 0;
     auto take = [&](size_t b) {
         char *p = tables + off;

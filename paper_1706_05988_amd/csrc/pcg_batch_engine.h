@@ -70,7 +70,7 @@ private:
     int prec_ = 0;
     int K_ = 8;
     int pass_grid_ = 0;      // persistent blocks of the pass; 0: default_pass_grid()
-    int trans_grid_ = 256;
+    int trans_grid_ = 256;   // blocks of the transition kernel (set by init)
     int chunk_grid_ = 256;
     int spec_ = kSpecAny;
     // above this many items a launch runs split (measured: the fused head
