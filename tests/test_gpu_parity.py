@@ -310,6 +310,27 @@ def test_tiny_grids(torch, method, shape):
     assert abs(g["iterations"] - o["iterations"]) <= 1
 
 
+@pytest.mark.parametrize("n", [1, 2, 7, 65, 257])
+@pytest.mark.parametrize("fp32", [False, True])
+def test_tiny_csr_operators(torch, n, fp32):
+    """Banded random CSR operators of a handful of rows (one ragged tile, a
+    single partial slice; the built-in choice puts them on a sliced-ELL
+    copy): p-CG-sh reaches the dense solution and follows the oracle."""
+    p = problems.banded_csr(n, seed=n)
+    g = gpu_solve(torch, p, "pipe_shift", fp32=fp32, rtol=1e-12 if not fp32 else 1e-6, max_iter=400,
+                  replace_max=8)
+    o = oracle_solve(p, "pipe_shift", fp32=fp32, rtol=1e-12 if not fp32 else 1e-6, max_iter=400)
+    assert g["status"] == "converged", g["status"]
+    assert g["info"]["csr_form_name"] in ("csr", "sell", "sell_sorted")
+    xs = np.linalg.solve(problems.to_scipy(p.op).toarray(), p.b)
+    np.testing.assert_allclose(g["x"], xs, rtol=0, atol=(1e-9 if not fp32 else 1e-4) * np.abs(xs).max())
+    if not fp32:
+        # these converge by 11 orders in ~30 iterations: compare the history
+        # down to 1e-8, below which it is rounding noise relative to ||b||
+        above = np.nonzero(o["res"] < 1e-8)[0]
+        check_history(g, o, upto=int(above[0]) if above.size else 50)
+
+
 def test_zero_iterations_and_exact_start(torch):
     p = problems.poisson2d_manufactured(20)
     g = gpu_solve(torch, p, "pipe_shift", max_iter=0)
