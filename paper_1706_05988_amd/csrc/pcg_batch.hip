@@ -56,6 +56,7 @@ __device__ __forceinline__ PassArgs<T> batch_args(const BatchSys &D, const Batch
     a.sell_col = D.sell_col;
     a.sell_val = (const T *)D.sell_val;
     a.sell_perm = D.sell_perm;
+    a.sell_win = D.sell_win;
     return a;
 }
 
@@ -490,7 +491,7 @@ pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options 
     // the iteration pass of a CSR system reads a sliced-ELL copy where its
     // padding stays within a quarter of nnz: rows in place, or sorted within
     // each wave's rows of a work tile (whichever is smaller)
-    l.sell_ptr = l.sort_ptr = l.sort_perm = l.sell_col = l.sell_val = SIZE_MAX;
+    l.sell_ptr = l.sort_ptr = l.sort_perm = l.sort_win = l.sell_col = l.sell_val = SIZE_MAX;
     l.nslices = l.sort_nslices = 0;
     l.sell_cap = 0;
     if (op->kind == PCG_OP_CSR) {
@@ -506,6 +507,8 @@ pcg_status BatchEngine::system_layout(const pcg_operator *op, const pcg_options 
             off += up256((size_t)(l.sort_nslices + 1) * 4);
             l.sort_perm = off;
             off += up256((size_t)slots * 4);
+            l.sort_win = off;
+            off += up256((size_t)l.nwork * 8);
             l.sell_col = off;
             off += up256((size_t)cap * 4);
             l.sell_val = off;
@@ -621,6 +624,7 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
         p.cap = L.sell_cap;
         p.col = (int32_t *)(region + L.sell_col);
         p.val = region + L.sell_val;
+        p.win = (int2 *)(region + L.sort_win);
         if ((st = sell_build(op, opt->prec, p, stream_, &form, &entries))) return st;
     }
     BatchSys D{};
@@ -661,6 +665,7 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
                              : nullptr;
     D.sell_col = form ? (const int32_t *)(region + L.sell_col) : nullptr;
     D.sell_perm = form == 2 ? (const int32_t *)(region + L.sort_perm) : nullptr;
+    D.sell_win = form == 2 ? (const int2 *)(region + L.sort_win) : nullptr;
     D.sell_val = form ? (const void *)(region + L.sell_val) : nullptr;
     // the counter of written chunk sums starts at zero (the transition that
     // completes it sets it back)

@@ -18,7 +18,7 @@ public:
     struct SysLayout {
         size_t blk, part, chunk, chunks_done, dinv, hist, flag, gersh, bytes;
         // CSR: sliced-ELL copies (SIZE_MAX: none), see SellPlan
-        size_t sell_ptr, sort_ptr, sort_perm, sell_col, sell_val;
+        size_t sell_ptr, sort_ptr, sort_perm, sort_win, sell_col, sell_val;
         int32_t nslices, sort_nslices;
         int64_t sell_cap;
         int32_t nchunks;  // chunks of kChunkParts partials (1: summed whole)

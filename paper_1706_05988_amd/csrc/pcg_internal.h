@@ -48,8 +48,9 @@ struct Layout {
     size_t sell_ptr, sell_col, sell_val;
     int64_t sell_cap;
     int32_t nslices;
-    // its sorted form: slice offsets and per-slot (length << 8) | position
-    size_t sort_ptr, sort_perm;
+    // its sorted form: slice offsets, per-slot (length << 8) | position and
+    // per-tile column windows
+    size_t sort_ptr, sort_perm, sort_win;
     int32_t sort_nslices;
     uint32_t tile_bytes;
     uint32_t slot_off[V_COUNT];  // byte offset of each slot in a tile (kNoSlot: absent)
@@ -58,7 +59,7 @@ struct Layout {
 
 // Type-erased kernel arguments (PassArgs<double> or PassArgs<float>).
 struct PassArgsAny {
-    alignas(16) unsigned char bytes[352];
+    alignas(16) unsigned char bytes[368];
 };
 
 template <typename T>
@@ -111,6 +112,7 @@ struct SellPlan {
     int64_t cap = 0;
     int32_t *col = nullptr;
     void *val = nullptr;  // cap values of the storage type
+    int2 *win = nullptr;  // sorted form: per tile, its column window (see k_sell_window)
 };
 // Build the smaller of the reserved copies that fits cap (synchronous):
 // *form 0 (none fits), 1 (in place; slice offsets at sell_ptr) or 2 (sorted;

@@ -96,6 +96,9 @@ struct PassArgs {
     // sorted form (nullptr: rows in place): per slice slot, (row length << 8)
     // | the row's position among its wave's rows; see sell_sorted_rows
     const int32_t *sell_perm;
+    // sorted form: per tile, the first column its rows gather and the width
+    // of that column window (-1: wider than kSellWindow, gathered directly)
+    const int2 *sell_win;
     int32_t run_through;  // 1: no breakdown stop (PCG_FLAG_RUN_THROUGH_BREAKDOWN)
 };
 
@@ -528,6 +531,34 @@ __device__ __forceinline__ void sell_slice_pair(const PassArgs<T> &a, uint32_t s
     out0 = acc0, out1 = acc1;
 }
 
+// Column window of a tile: the operand values of the columns a tile's rows
+// gather, staged in LDS once per tile when they span at most kSellWindow
+// columns (a banded operator), so that the gathers read LDS.
+constexpr int kSellWindow = 2048;
+
+__device__ __forceinline__ double *sell_window_lds()
+{
+    __shared__ double win[kSellWindow];
+    return win;
+}
+
+// The products of a wave's sorted slices with the operand v (binary64 slices
+// two at a time: measured on banded random operators of 1e6 / 4e6 rows,
+// 94.5 / 382.9 against 99.3 / 402.6 us per pass; the FP32-stream form gained
+// nothing, 75.5 / 251.6 against 73.5 / 253.8).
+template <typename T, int EPT, typename F>
+__device__ __forceinline__ void sell_sorted_products(const PassArgs<T> &a, uint32_t g, uint32_t lane,
+                                                     const int32_t (&len)[EPT], F v, double (&pr)[EPT])
+{
+    if constexpr (sizeof(T) == 8 && EPT % 2 == 0) {
+#pragma unroll
+        for (int j = 0; j < EPT; j += 2) sell_slice_pair(a, g * EPT + j, lane, len[j], len[j + 1], v, pr[j], pr[j + 1]);
+    } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) pr[j] = sell_slice(a, g * EPT + j, lane, len[j], v);
+    }
+}
+
 template <typename T, int EPT, typename F>
 __device__ __forceinline__ void sell_sorted_rows(const PassArgs<T> &a, int tile, double (&ne)[EPT], F v)
 {
@@ -544,15 +575,18 @@ __device__ __forceinline__ void sell_sorted_rows(const PassArgs<T> &a, int tile,
         at[j] = (uint32_t)info & 255;
         len[j] = info >> 8;
     }
-    // binary64 slices go two at a time (measured on banded random operators
-    // of 1e6 / 4e6 rows: 94.5 / 382.9 against 99.3 / 402.6 us per pass; the
-    // FP32-stream form gained nothing, 75.5 / 251.6 against 73.5 / 253.8)
-    if constexpr (sizeof(T) == 8 && EPT % 2 == 0) {
-#pragma unroll
-        for (int j = 0; j < EPT; j += 2) sell_slice_pair(a, g * EPT + j, lane, len[j], len[j + 1], v, pr[j], pr[j + 1]);
+    const int2 wd = a.sell_win ? a.sell_win[tile] : make_int2(0, -1);  // the same in the whole block
+    if (wd.y >= 0) {
+        // the tile's column window: v at columns wd.x .. wd.x + wd.y - 1,
+        // formed once (the same values v gives) and gathered from LDS
+        double *win = sell_window_lds();
+        __syncthreads();  // the previous tile's gathers from the window are done
+        for (int c = threadIdx.x; c < wd.y; c += blockDim.x) win[c] = v((uint32_t)(wd.x + c));
+        __syncthreads();
+        const uint32_t c0 = (uint32_t)wd.x;
+        sell_sorted_products<T, EPT>(a, g, lane, len, [&](uint32_t k) { return win[k - c0]; }, pr);
     } else {
-#pragma unroll
-        for (int j = 0; j < EPT; ++j) pr[j] = sell_slice(a, g * EPT + j, lane, len[j], v);
+        sell_sorted_products<T, EPT>(a, g, lane, len, v, pr);
     }
     double *xw = xch + wave * (EPT * 64);
     // the previous tile's reads of xw are done before it is written again
@@ -1397,8 +1431,8 @@ static __global__ void __launch_bounds__(256) k_sell_sort(const int32_t *row_ptr
 
 // The sorted form, step 3 (after k_sell_scan over the slices): one thread
 // per slot copies its row's entries into the slot's column of its slice,
-// padding with the row's own column (column 0 for a slot past the last row)
-// and a zero value.
+// padding with the row's own column (the last row's for a slot past it) and
+// a zero value.
 template <typename T, int EPT>
 __global__ void __launch_bounds__(256) k_sell_fill_sorted(OpDev<T> A, int32_t block, int64_t slots,
                                                            const int32_t *sell_ptr, const int32_t *perm,
@@ -1413,11 +1447,44 @@ __global__ void __launch_bounds__(256) k_sell_fill_sorted(OpDev<T> A, int32_t bl
     const int64_t r = (g / wpb) * (int64_t)block * EPT + (int64_t)(o >> 6) * block + (g % wpb) * 64 + (o & 63);
     const int32_t p0 = sell_ptr[s], w = (sell_ptr[s + 1] - p0) >> 6;
     const int32_t k0 = len > 0 ? A.row_ptr[r] : 0;  // len > 0 only for r < n
-    const int32_t pad = r < A.n ? (int32_t)r : 0;
+    // a slot past the last row (last tile only) pads with that row, inside
+    // the tile's column window
+    const int32_t pad = r < A.n ? (int32_t)r : A.n - 1;
     for (int32_t k = 0; k < w; ++k) {
         const int64_t idx = p0 + ((int64_t)k << 6) + lane;
         sell_col[idx] = k < len ? A.col[k0 + k] : pad;
         sell_val[idx] = k < len ? A.val[k0 + k] : (T)0;
+    }
+}
+
+// The sorted form, step 4: one block per tile of `rows` rows finds the
+// smallest and largest column its rows gather (their entries and, for the
+// padding, their own indices) and writes (first column, width), or width
+// -1 when the window is wider than kSellWindow.
+static __global__ void __launch_bounds__(256) k_sell_window(const int32_t *row_ptr, const int32_t *col, int32_t n,
+                                                           int32_t rows, int2 *win)
+{
+    __shared__ int32_t lo_s[256], hi_s[256];
+    const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min((int64_t)n, r0 + rows);  // r0 < n: one block per tile
+    int32_t lo = (int32_t)r0, hi = (int32_t)(r1 - 1);
+    const int32_t e0 = row_ptr[r0], e1 = row_ptr[r1];
+    for (int32_t k = e0 + (int32_t)threadIdx.x; k < e1; k += blockDim.x) {
+        lo = min(lo, col[k]);
+        hi = max(hi, col[k]);
+    }
+    lo_s[threadIdx.x] = lo;
+    hi_s[threadIdx.x] = hi;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) {
+            lo_s[threadIdx.x] = min(lo_s[threadIdx.x], lo_s[threadIdx.x + o]);
+            hi_s[threadIdx.x] = max(hi_s[threadIdx.x], hi_s[threadIdx.x + o]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int64_t w = (int64_t)hi_s[0] - lo_s[0] + 1;
+        win[blockIdx.x] = w <= kSellWindow ? make_int2(lo_s[0], (int32_t)w) : make_int2(0, -1);
     }
 }
 

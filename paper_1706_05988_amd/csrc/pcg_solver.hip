@@ -206,15 +206,19 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
     };
     tiles_grid(s.block, s.ept, blocks_per_cu, &s.ntiles, &s.grid);
     // the sorted copy sorts within a wave's rows of a tile, so it takes 4
-    // rows per thread unless the shape is given: four blocks of 128 per CU
-    // (measured on banded random operators of 1e6 and 4e6 rows of 4 to 40
-    // entries: binary64 100.1 / 403.4 us per pass against 98.5 / 406.8 for
-    // two blocks of 256, FP32-stream 73.8 / 253.8 against 74.1 / 263.6)
+    // rows per thread unless the shape is given (measured with the column
+    // windows on banded random operators of 1e6 and 4e6 rows of 4 to 40
+    // entries, us per pass): binary64 four blocks of 128 per CU (73.7 /
+    // 274.0, two of 256: 73.1 / 283.6); FP32-stream blocks of 256, two per
+    // CU up to 2^21 rows (51.9 against 54.7 for three), three beyond (174.8
+    // against 198.3 at 4e6; four blocks of 128: 52.3 / 194.6)
     s.sort_block = s.block, s.sort_ept = s.ept, s.sort_ntiles = s.ntiles, s.sort_grid = s.grid;
     if (!set && op->kind == PCG_OP_CSR) {
-        s.sort_block = o->block_size ? o->block_size : 128;
+        const bool fp64 = o->prec == PCG_FP64;
+        s.sort_block = o->block_size ? o->block_size : fp64 ? 128 : 256;
         s.sort_ept = 4;
-        tiles_grid(s.sort_block, s.sort_ept, 4, &s.sort_ntiles, &s.sort_grid);
+        const int per_cu = fp64 ? 4 : op->n <= (int64_t(1) << 21) ? 2 : 3;
+        tiles_grid(s.sort_block, s.sort_ept, per_cu, &s.sort_ntiles, &s.sort_grid);
     }
     const bool want_xcd = set && (var & PCG_VAR_XCD_MAP) != 0;
     s.xcd_map = (want_xcd && s.grid >= 64 && (s.grid % 8) == 0) ? 1 : 0;
@@ -292,7 +296,7 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
     l.sched = o->method == PCG_PIPE_VAR_SHIFT ? take(size_t(o->sigma_schedule_len) * 8) : SIZE_MAX;
     // the fused pass of p-CG / p-CG-sh reads a CSR operator in sliced-ELL
     // form when its padding stays within a quarter of nnz (decided at set-up)
-    l.sell_ptr = l.sell_col = l.sell_val = l.sort_ptr = l.sort_perm = SIZE_MAX;
+    l.sell_ptr = l.sell_col = l.sell_val = l.sort_ptr = l.sort_perm = l.sort_win = SIZE_MAX;
     l.sell_cap = 0;
     l.nslices = l.sort_nslices = 0;
     if (op->kind == PCG_OP_CSR && (o->method == PCG_PIPE || o->method == PCG_PIPE_SHIFT) && sh.sell) {
@@ -308,6 +312,7 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
                 l.sort_nslices = (int32_t)(slots / 64);
                 l.sort_ptr = take(size_t(l.sort_nslices + 1) * 4);
                 l.sort_perm = take(size_t(slots) * 4);
+                l.sort_win = take(size_t(sh.sort_ntiles) * 8);
             }
             if (l.sell_ptr != SIZE_MAX || l.sort_ptr != SIZE_MAX) {
                 l.sell_col = take(size_t(cap) * 4);
@@ -541,6 +546,7 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
         a.sell_col = sell ? reinterpret_cast<const int32_t *>(ws + L.sell_col) : nullptr;
         a.sell_val = sell ? reinterpret_cast<const T *>(ws + L.sell_val) : nullptr;
         a.sell_perm = sell == 2 ? reinterpret_cast<const int32_t *>(ws + L.sort_perm) : nullptr;
+        a.sell_win = sell == 2 ? reinterpret_cast<const int2 *>(ws + L.sort_win) : nullptr;
         a.run_through = (opt.flags & PCG_FLAG_RUN_THROUGH_BREAKDOWN) ? 1 : 0;
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
@@ -716,6 +722,13 @@ pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipSt
     };
     if (prec == PCG_FP64) fill((double *)nullptr);
     else fill((float *)nullptr);
+    if (f == 2) {
+        // column windows of the tiles, or none: every tile then gathers directly
+        const int rows = p.sort_block * p.sort_ept;
+        const int ntiles = (int)(int64_t(p.sort_nslices) * 64 / rows);
+        if (!p.win) return invalid("sorted sliced-ELL copy without its window table");
+        hipLaunchKernelGGL(k_sell_window, dim3(ntiles), dim3(256), 0, stream, op->row_ptr, op->col_idx, n, rows, p.win);
+    }
     HIPCHK(hipGetLastError());
     *form = f;
     *entries = total[f - 1];
@@ -738,6 +751,7 @@ static pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape
         p.cap = L.sell_cap;
         p.col = reinterpret_cast<int32_t *>(ws + L.sell_col);
         p.val = ws + L.sell_val;
+        p.win = L.sort_win == SIZE_MAX ? nullptr : reinterpret_cast<int2 *>(ws + L.sort_win);
     }
     return sell_build(op, prec, p, stream, form, entries);
 }

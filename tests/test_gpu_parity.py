@@ -829,7 +829,9 @@ def test_csr_sorted_sliced_ell_gives_the_csr_bits(torch, shape, fp32):
     summed alone in CSR storage order, so at one launch shape a p-CG-sh
     solve gives the same bits as on the CSR arrays -- on banded random
     operators (rows of 4 to 40 entries, ragged last tile), the anisotropic
-    operator and a 3-D Laplacian assembled as CSR."""
+    operator and 3-D Laplacians assembled as CSR, with the tiles' operand
+    columns staged in an LDS window (all but the last operator) or gathered
+    directly (planes 1600 columns apart)."""
     from paper_1706_05988_amd import pcg as P
     block, ept = shape
     A = problems.to_scipy(problems.stencil3d(19, 17, 13)).tocsr()
@@ -837,8 +839,15 @@ def test_csr_sorted_sliced_ell_gives_the_csr_bits(torch, shape, fp32):
     op3 = problems.csr_operator(A.indptr, A.indices, A.data)
     xt = np.random.default_rng(9).uniform(-1, 1, op3.n)
     p3 = problems.Problem("lapl3d_csr", op3, A @ xt, np.zeros(op3.n), xt, jacobi=True, sigma=1.0)
+    # a 3-D Laplacian whose planes are 1600 columns apart: its tiles gather
+    # from more columns than fit their LDS window, so they gather directly
+    A4 = problems.to_scipy(problems.stencil3d(40, 40, 21)).tocsr()
+    A4.sort_indices()
+    op4 = problems.csr_operator(A4.indptr, A4.indices, A4.data)
+    xt4 = np.random.default_rng(10).uniform(-1, 1, op4.n)
+    p4 = problems.Problem("lapl3d_wide_csr", op4, A4 @ xt4, np.zeros(op4.n), xt4, jacobi=True, sigma=1.0)
     for p in (problems.banded_csr(5003, seed=3), problems.banded_csr(20011, seed=5),
-              problems.anisotropic_csr(90, seed=4), p3):
+              problems.anisotropic_csr(90, seed=4), p3, p4):
         base = P.PCG_VAR_SET | P.PCG_VAR_NT | (P.PCG_VAR_EPT4 if ept == 4 else 0)
         out = []
         for form in (0, P.PCG_VAR_CSR_SELL_SORTED):
