@@ -221,11 +221,14 @@ def test_tune_workspace_covers_every_candidate():
                            grid_blocks=2048)
     assert P.pcg_workspace_size(csr, sell) > P.pcg_workspace_size(csr, plain)
     assert n.value >= P.pcg_workspace_size(csr, sell)
-    # ... and the sorted copy also its per-slot (length, position) words
+    # ... and the sorted copy also its per-slot (length, position) words and
+    # per-tile column windows
     srt, sell4 = (P.make_options(jacobi=True, fp32=True, variant=P.PCG_VAR_SET | form | P.PCG_VAR_EPT4,
                                  block_size=128, grid_blocks=2048)
                   for form in (P.PCG_VAR_CSR_SELL_SORTED, P.PCG_VAR_CSR_SELL))
-    assert P.pcg_workspace_size(csr, srt) == P.pcg_workspace_size(csr, sell4) + 4 * 4096
+    # 4 bytes per slot, and 8 per tile (8 tiles of 512 rows) for the column
+    # windows, in 256-byte units
+    assert P.pcg_workspace_size(csr, srt) == P.pcg_workspace_size(csr, sell4) + 4 * 4096 + 256
     assert n.value >= P.pcg_workspace_size(csr, srt)
     # the built-in shape reserves both copies' offsets and one set of entries
     assert P.pcg_workspace_size(csr, o32) >= P.pcg_workspace_size(csr, srt)
