@@ -59,7 +59,7 @@ struct Layout {
 
 // Type-erased kernel arguments (PassArgs<double> or PassArgs<float>).
 struct PassArgsAny {
-    alignas(16) unsigned char bytes[368];
+    alignas(16) unsigned char bytes[384];
 };
 
 template <typename T>
@@ -116,8 +116,10 @@ struct SellPlan {
 };
 // Build the smaller of the reserved copies that fits cap (synchronous):
 // *form 0 (none fits), 1 (in place; slice offsets at sell_ptr) or 2 (sorted;
-// at sort_ptr / sort_perm); *entries its entries.
+// at sort_ptr / sort_perm, tile windows at win); *entries its entries;
+// *col_bits 32, or 16 when every tile of a sorted copy has a window (the
+// columns are then 16-bit window offsets in the first half of col).
 pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipStream_t stream, int *form,
-                      int64_t *entries);
+                      int64_t *entries, int *col_bits);
 
 }  // namespace pcg

@@ -99,6 +99,9 @@ struct PassArgs {
     // sorted form: per tile, the first column its rows gather and the width
     // of that column window (-1: wider than kSellWindow, gathered directly)
     const int2 *sell_win;
+    // sorted form with every tile windowed: each entry's column as its offset
+    // in its tile's window, 16 bits (nullptr: 32-bit columns in sell_col)
+    const uint16_t *sell_c16;
     int32_t run_through;  // 1: no breakdown stop (PCG_FLAG_RUN_THROUGH_BREAKDOWN)
 };
 
@@ -433,7 +436,8 @@ struct PipeTile {
 // One row's product from slice s of a sliced-ELL copy: the row sits in
 // lane `lane` of the slice and has len entries (the rest of the slice's
 // width is padding, skipped).
-template <typename T, typename F>
+// C16: the columns are 16-bit window offsets (sell_c16), v takes those.
+template <typename T, typename F, bool C16 = false>
 __device__ __forceinline__ double sell_slice(const PassArgs<T> &a, uint32_t s, uint32_t lane, int32_t len, F v)
 {
     const int32_t p0 = a.sell_ptr[s], w = (a.sell_ptr[s + 1] - p0) >> 6;
@@ -446,7 +450,8 @@ __device__ __forceinline__ double sell_slice(const PassArgs<T> &a, uint32_t s, u
         for (int u = 0; u < kCsrChunk; ++u) {
             const int32_t kk = k + u < w ? k + u : k;
             const int32_t idx = p0 + (kk << 6) + (int32_t)lane;
-            c[u] = a.sell_col[idx];
+            if constexpr (C16) c[u] = a.sell_c16[idx];
+            else c[u] = a.sell_col[idx];
             wv[u] = a.sell_val[idx];
         }
 #pragma unroll
@@ -485,7 +490,7 @@ __device__ __forceinline__ double *sell_exchange_lds()
 // Two slices of one wave at once (s0 the wider, as sorted): their chunks'
 // loads go out together while both have entries left, the second slice's
 // part skipped (a wave-uniform branch) once it has none.
-template <typename T, typename F>
+template <typename T, typename F, bool C16 = false>
 __device__ __forceinline__ void sell_slice_pair(const PassArgs<T> &a, uint32_t s0, uint32_t lane, int32_t len0,
                                                 int32_t len1, F v, double &out0, double &out1)
 {
@@ -501,7 +506,8 @@ __device__ __forceinline__ void sell_slice_pair(const PassArgs<T> &a, uint32_t s
         for (int u = 0; u < kCsrChunk; ++u) {
             const int32_t kk = k + u < w0 ? k + u : k;
             const int32_t idx = p0 + (kk << 6) + (int32_t)lane;
-            c0[u] = a.sell_col[idx];
+            if constexpr (C16) c0[u] = a.sell_c16[idx];
+            else c0[u] = a.sell_col[idx];
             v0[u] = a.sell_val[idx];
         }
         if (two) {
@@ -509,7 +515,8 @@ __device__ __forceinline__ void sell_slice_pair(const PassArgs<T> &a, uint32_t s
             for (int u = 0; u < kCsrChunk; ++u) {
                 const int32_t kk = k + u < w1 ? k + u : k;
                 const int32_t idx = q0 + (kk << 6) + (int32_t)lane;
-                c1[u] = a.sell_col[idx];
+                if constexpr (C16) c1[u] = a.sell_c16[idx];
+                else c1[u] = a.sell_col[idx];
                 v1[u] = a.sell_val[idx];
             }
         }
@@ -546,16 +553,17 @@ __device__ __forceinline__ double *sell_window_lds()
 // two at a time: measured on banded random operators of 1e6 / 4e6 rows,
 // 94.5 / 382.9 against 99.3 / 402.6 us per pass; the FP32-stream form gained
 // nothing, 75.5 / 251.6 against 73.5 / 253.8).
-template <typename T, int EPT, typename F>
+template <typename T, int EPT, bool C16 = false, typename F>
 __device__ __forceinline__ void sell_sorted_products(const PassArgs<T> &a, uint32_t g, uint32_t lane,
                                                      const int32_t (&len)[EPT], F v, double (&pr)[EPT])
 {
     if constexpr (sizeof(T) == 8 && EPT % 2 == 0) {
 #pragma unroll
-        for (int j = 0; j < EPT; j += 2) sell_slice_pair(a, g * EPT + j, lane, len[j], len[j + 1], v, pr[j], pr[j + 1]);
+        for (int j = 0; j < EPT; j += 2)
+            sell_slice_pair<T, F, C16>(a, g * EPT + j, lane, len[j], len[j + 1], v, pr[j], pr[j + 1]);
     } else {
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) pr[j] = sell_slice(a, g * EPT + j, lane, len[j], v);
+        for (int j = 0; j < EPT; ++j) pr[j] = sell_slice<T, F, C16>(a, g * EPT + j, lane, len[j], v);
     }
 }
 
@@ -583,8 +591,13 @@ __device__ __forceinline__ void sell_sorted_rows(const PassArgs<T> &a, int tile,
         __syncthreads();  // the previous tile's gathers from the window are done
         for (int c = threadIdx.x; c < wd.y; c += blockDim.x) win[c] = v((uint32_t)(wd.x + c));
         __syncthreads();
-        const uint32_t c0 = (uint32_t)wd.x;
-        sell_sorted_products<T, EPT>(a, g, lane, len, [&](uint32_t k) { return win[k - c0]; }, pr);
+        if (a.sell_c16) {
+            // every tile windowed: the entries carry their window offsets
+            sell_sorted_products<T, EPT, true>(a, g, lane, len, [&](uint32_t k) { return win[k]; }, pr);
+        } else {
+            const uint32_t c0 = (uint32_t)wd.x;
+            sell_sorted_products<T, EPT>(a, g, lane, len, [&](uint32_t k) { return win[k - c0]; }, pr);
+        }
     } else {
         sell_sorted_products<T, EPT>(a, g, lane, len, v, pr);
     }
@@ -1433,10 +1446,13 @@ static __global__ void __launch_bounds__(256) k_sell_sort(const int32_t *row_ptr
 // per slot copies its row's entries into the slot's column of its slice,
 // padding with the row's own column (the last row's for a slot past it) and
 // a zero value.
+// With c16 (every tile windowed) the columns go out as 16-bit offsets in
+// the slot's tile window instead of into sell_col.
 template <typename T, int EPT>
 __global__ void __launch_bounds__(256) k_sell_fill_sorted(OpDev<T> A, int32_t block, int64_t slots,
                                                            const int32_t *sell_ptr, const int32_t *perm,
-                                                           int32_t *sell_col, T *sell_val)
+                                                           int32_t *sell_col, T *sell_val, const int2 *win,
+                                                           uint16_t *c16)
 {
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= slots) return;
@@ -1450,9 +1466,12 @@ __global__ void __launch_bounds__(256) k_sell_fill_sorted(OpDev<T> A, int32_t bl
     // a slot past the last row (last tile only) pads with that row, inside
     // the tile's column window
     const int32_t pad = r < A.n ? (int32_t)r : A.n - 1;
+    const int32_t base = c16 ? win[(g / wpb)].x : 0;  // the tile's window
     for (int32_t k = 0; k < w; ++k) {
         const int64_t idx = p0 + ((int64_t)k << 6) + lane;
-        sell_col[idx] = k < len ? A.col[k0 + k] : pad;
+        const int32_t c = k < len ? A.col[k0 + k] : pad;
+        if (c16) c16[idx] = (uint16_t)(c - base);
+        else sell_col[idx] = c;
         sell_val[idx] = k < len ? A.val[k0 + k] : (T)0;
     }
 }

@@ -474,6 +474,7 @@ struct pcg_solver_ {
     int sell = 0;            // the fused pass reads the CSR operator's sliced-ELL copy: 1 rows
                              // in place, 2 sorted (0: the CSR arrays)
     int64_t sell_entries = 0;  // entries of that copy, padding included
+    int sell_col_bits = 0;     // its column words: 32, or 16 (window offsets)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     const double *graph_b = nullptr;  // b baked into the captured graph
@@ -547,6 +548,7 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
         a.sell_val = sell ? reinterpret_cast<const T *>(ws + L.sell_val) : nullptr;
         a.sell_perm = sell == 2 ? reinterpret_cast<const int32_t *>(ws + L.sort_perm) : nullptr;
         a.sell_win = sell == 2 ? reinterpret_cast<const int2 *>(ws + L.sort_win) : nullptr;
+        a.sell_c16 = sell == 2 && sell_col_bits == 16 ? reinterpret_cast<const uint16_t *>(ws + L.sell_col) : nullptr;
         a.run_through = (opt.flags & PCG_FLAG_RUN_THROUGH_BREAKDOWN) ? 1 : 0;
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
@@ -668,10 +670,11 @@ pcg_status csr_setup(const pcg_operator *op, int prec, int jac, void *dinv, int 
 // two is kept (the sorted one only when at least 1/32 smaller, since it
 // also routes the products through LDS).
 pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipStream_t stream, int *form,
-                      int64_t *entries)
+                      int64_t *entries, int *col_bits)
 {
     *form = 0;
     *entries = 0;
+    *col_bits = 0;
     if (!p.col || (!p.sell_ptr && !p.sort_ptr)) return PCG_OK;
     const int32_t n = (int32_t)op->n;
     int32_t total[2] = {-1, -1};
@@ -700,6 +703,23 @@ pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipSt
     int f = total[0] >= 0 ? 1 : 0;
     if (total[1] >= 0 && (f == 0 || int64_t(total[1]) + total[1] / 32 < int64_t(total[0]))) f = 2;
     if (f == 0) return PCG_OK;
+    // the sorted copy's tile windows; when every tile has one, the columns
+    // are stored as 16-bit offsets in their tile's window (in the first half
+    // of the column array)
+    uint16_t *c16 = nullptr;
+    if (f == 2) {
+        if (!p.win) return invalid("sorted sliced-ELL copy without its window table");
+        const int rows = p.sort_block * p.sort_ept;
+        const int ntiles = (int)(int64_t(p.sort_nslices) * 64 / rows);
+        hipLaunchKernelGGL(k_sell_window, dim3(ntiles), dim3(256), 0, stream, op->row_ptr, op->col_idx, n, rows, p.win);
+        HIPCHK(hipGetLastError());
+        std::vector<int2> w(ntiles);
+        HIPCHK(hipMemcpyAsync(w.data(), p.win, sizeof(int2) * ntiles, hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        bool all = true;
+        for (const int2 &t : w) all = all && t.y >= 0;
+        if (all) c16 = reinterpret_cast<uint16_t *>(p.col);
+    }
     auto fill = [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         T *sv = reinterpret_cast<T *>(p.val);
@@ -712,32 +732,26 @@ pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipSt
         const int g = (int)((slots + 255) / 256);
         if (p.sort_ept == 1)
             hipLaunchKernelGGL((k_sell_fill_sorted<T, 1>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), p.sort_block,
-                               slots, tp, perm, p.col, sv);
+                               slots, tp, perm, p.col, sv, p.win, c16);
         else if (p.sort_ept == 2)
             hipLaunchKernelGGL((k_sell_fill_sorted<T, 2>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), p.sort_block,
-                               slots, tp, perm, p.col, sv);
+                               slots, tp, perm, p.col, sv, p.win, c16);
         else
             hipLaunchKernelGGL((k_sell_fill_sorted<T, 4>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), p.sort_block,
-                               slots, tp, perm, p.col, sv);
+                               slots, tp, perm, p.col, sv, p.win, c16);
     };
     if (prec == PCG_FP64) fill((double *)nullptr);
     else fill((float *)nullptr);
-    if (f == 2) {
-        // column windows of the tiles, or none: every tile then gathers directly
-        const int rows = p.sort_block * p.sort_ept;
-        const int ntiles = (int)(int64_t(p.sort_nslices) * 64 / rows);
-        if (!p.win) return invalid("sorted sliced-ELL copy without its window table");
-        hipLaunchKernelGGL(k_sell_window, dim3(ntiles), dim3(256), 0, stream, op->row_ptr, op->col_idx, n, rows, p.win);
-    }
     HIPCHK(hipGetLastError());
     *form = f;
     *entries = total[f - 1];
+    *col_bits = c16 ? 16 : 32;
     return PCG_OK;
 }
 
 // The solver's copies, as its layout reserved them.
 static pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape &sh, const Layout &L, char *ws,
-                             hipStream_t stream, int *form, int64_t *entries)
+                             hipStream_t stream, int *form, int64_t *entries, int *col_bits)
 {
     SellPlan p;
     if (L.sell_col != SIZE_MAX) {
@@ -753,7 +767,7 @@ static pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape
         p.val = ws + L.sell_val;
         p.win = L.sort_win == SIZE_MAX ? nullptr : reinterpret_cast<int2 *>(ws + L.sort_win);
     }
-    return sell_build(op, prec, p, stream, form, entries);
+    return sell_build(op, prec, p, stream, form, entries, col_bits);
 }
 
 pcg_status csr_gershgorin(const pcg_operator *op, int prec, int jac, double *gb, hipStream_t stream, double *lo,
@@ -848,9 +862,11 @@ static pcg_status init_solver(pcg_solver_ *s, const pcg_operator *op, const pcg_
             (st = csr_gershgorin(op, opt->prec, jac, reinterpret_cast<double *>(s->ws + L.gersh), s->stream, &gersh[0],
                                  &gersh[1])))
             return st;
-        if ((st = sell_setup(op, opt->prec, sh, L, s->ws, s->stream, &s->sell, &s->sell_entries))) return st;
-        if (s->sell == 2 && (sh.sort_ept != sh.ept || sh.sort_block != sh.block)) {
-            // the sorted copy is laid out for its own shape: the passes take it
+        if ((st = sell_setup(op, opt->prec, sh, L, s->ws, s->stream, &s->sell, &s->sell_entries, &s->sell_col_bits)))
+            return st;
+        if (s->sell == 2 && (sh.sort_ept != sh.ept || sh.sort_block != sh.block || sh.sort_grid != sh.grid)) {
+            // the sorted copy is laid out for its own shape: the passes take
+            // it, and its grid
             s->sh.ept = sh.sort_ept, s->sh.block = sh.sort_block;
             s->sh.ntiles = sh.sort_ntiles, s->sh.grid = sh.sort_grid;
             s->kern = pick(opt->prec, op->kind, opt->pc == PCG_PC_JACOBI, s->sh.ept, s->sh.nt != 0);
@@ -905,6 +921,7 @@ extern "C" pcg_status pcg_solver_info(pcg_solver s, pcg_solver_shape *out)
     out->ntiles = s->sh.ntiles;
     out->iters_per_launch = s->sh.K;
     out->csr_form = s->sell;
+    out->csr_col_bits = s->sell_col_bits;
     out->csr_entries = s->sell_entries;
     return PCG_OK;
 }

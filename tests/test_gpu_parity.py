@@ -310,6 +310,23 @@ def test_tiny_grids(torch, method, shape):
     assert abs(g["iterations"] - o["iterations"]) <= 1
 
 
+@pytest.mark.parametrize("fp32", [False, True])
+def test_builtin_sorted_copy_takes_its_shape(torch, fp32):
+    """A banded operator of 1e6 rows: set-up keeps the sorted copy and the
+    passes run at that copy's built-in shape and grid (binary64 blocks of
+    128, four per CU; FP32-stream blocks of 256, two per CU at this size)."""
+    from paper_1706_05988_amd import pcg as P
+    p = problems.banded_csr(10 ** 6, seed=2)
+    g = gpu_solve(torch, p, "pipe_shift", fp32=fp32, max_iter=3, rtol=1e-30, true_residual_check=False,
+                  hist=False)
+    info = g["info"]
+    assert info["csr_form_name"] == "sell_sorted" and info["csr_col_bits"] == 16
+    block, per_cu = (128, 4) if not fp32 else (256, 2)
+    assert (info["block"], info["ept"]) == (block, 4)
+    assert info["ntiles"] == -(-p.op.n // (block * 4))
+    assert info["grid"] == min(per_cu * 256, info["ntiles"] & ~7)
+
+
 @pytest.mark.parametrize("n", [1, 2, 7, 65, 257])
 @pytest.mark.parametrize("fp32", [False, True])
 def test_tiny_csr_operators(torch, n, fp32):
@@ -830,8 +847,10 @@ def test_csr_sorted_sliced_ell_gives_the_csr_bits(torch, shape, fp32):
     solve gives the same bits as on the CSR arrays -- on banded random
     operators (rows of 4 to 40 entries, ragged last tile), the anisotropic
     operator and 3-D Laplacians assembled as CSR, with the tiles' operand
-    columns staged in an LDS window (all but the last operator) or gathered
-    directly (planes 1600 columns apart)."""
+    columns staged in an LDS window and the columns stored as 16-bit window
+    offsets, or gathered directly (planes 1600 columns apart), or a mix of
+    the two with 32-bit columns (a banded operator with a few long-range
+    couplings)."""
     from paper_1706_05988_amd import pcg as P
     block, ept = shape
     A = problems.to_scipy(problems.stencil3d(19, 17, 13)).tocsr()
@@ -846,8 +865,20 @@ def test_csr_sorted_sliced_ell_gives_the_csr_bits(torch, shape, fp32):
     op4 = problems.csr_operator(A4.indptr, A4.indices, A4.data)
     xt4 = np.random.default_rng(10).uniform(-1, 1, op4.n)
     p4 = problems.Problem("lapl3d_wide_csr", op4, A4 @ xt4, np.zeros(op4.n), xt4, jacobi=True, sigma=1.0)
+    # a banded operator with a few long-range couplings: the tiles holding
+    # them gather directly, the others from their windows (32-bit columns)
+    B5 = problems.to_scipy(problems.banded_csr(20011, seed=6).op).tolil()
+    for i in (300, 9000, 15000):
+        B5[i, i + 4000] = B5[i + 4000, i] = -0.5
+        B5[i, i] += 0.5
+        B5[i + 4000, i + 4000] += 0.5
+    B5 = B5.tocsr()
+    B5.sort_indices()
+    op5 = problems.csr_operator(B5.indptr, B5.indices, B5.data)
+    xt5 = np.random.default_rng(11).uniform(-1, 1, op5.n)
+    p5 = problems.Problem("banded_far_csr", op5, B5 @ xt5, np.zeros(op5.n), xt5, jacobi=True, sigma=1.0)
     for p in (problems.banded_csr(5003, seed=3), problems.banded_csr(20011, seed=5),
-              problems.anisotropic_csr(90, seed=4), p3, p4):
+              problems.anisotropic_csr(90, seed=4), p3, p4, p5):
         base = P.PCG_VAR_SET | P.PCG_VAR_NT | (P.PCG_VAR_EPT4 if ept == 4 else 0)
         out = []
         for form in (0, P.PCG_VAR_CSR_SELL_SORTED):
@@ -873,6 +904,16 @@ def test_csr_sorted_sliced_ell_gives_the_csr_bits(torch, shape, fp32):
             continue
         assert b["info"]["csr_form_name"] == "sell_sorted" and b["info"]["csr_entries"] == want
         assert (b["info"]["block"], b["info"]["ept"]) == (block, ept)
+        # 16-bit window offsets when every tile's columns (its own rows
+        # included) span at most 2048
+        rp, cols = np.asarray(p.op.row_ptr, dtype=np.int64), np.asarray(p.op.col)
+        spans = []
+        for t in range(-(-p.op.n // R)):
+            r0, r1 = t * R, min(p.op.n, (t + 1) * R)
+            c = cols[rp[r0]:rp[r1]]
+            spans.append(max(c.max(initial=r1 - 1), r1 - 1) - min(c.min(initial=r0), r0) + 1)
+        windowed = np.array(spans) <= 2048
+        assert b["info"]["csr_col_bits"] == (16 if windowed.all() else 32), (p.name, windowed.mean())
         assert a["iterations"] == b["iterations"]
         np.testing.assert_array_equal(a["res"], b["res"])
         np.testing.assert_array_equal(a["x"], b["x"])
