@@ -259,7 +259,9 @@ typedef struct {
                                    the rows in place, 2: sorted sliced-ELL copy           */
     int32_t csr_col_bits;       /* the copy's column words: 32, or 16 when every tile of
                                    a sorted copy gathers from an LDS window of at most
-                                   2048 columns (offsets in that window); 0 if no copy    */
+                                   2048 columns (offsets in that window) or every entry
+                                   of an in-place copy lies within 2^15 of its row
+                                   (offsets from the row); 0 if no copy                   */
     int64_t csr_entries;        /* entries of that copy, padding included (0 if none)     */
 } pcg_solver_shape;
 pcg_status pcg_solver_info(pcg_solver solver, pcg_solver_shape *shape);

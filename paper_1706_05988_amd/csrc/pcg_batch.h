@@ -82,7 +82,7 @@ struct BatchSys {
     const int32_t *sell_col;
     const int32_t *sell_perm;
     const int2 *sell_win;   // sorted copy: per work tile, its column window
-    const uint16_t *sell_c16;  // sorted copy, every tile windowed: 16-bit window offsets
+    const uint16_t *sell_c16;  // 16-bit columns (see PassArgs::sell_c16), or nullptr
     const void *sell_val;
     int32_t hist_cap, replace_max, true_check, nchunks;
 };

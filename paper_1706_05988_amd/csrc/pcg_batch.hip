@@ -626,6 +626,7 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
         p.col = (int32_t *)(region + L.sell_col);
         p.val = region + L.sell_val;
         p.win = (int2 *)(region + L.sort_win);
+        p.scratch = (int *)(region + L.flag) + 1;  // after the CSR check's flag
         if ((st = sell_build(op, opt->prec, p, stream_, &form, &entries, &col_bits))) return st;
     }
     BatchSys D{};
@@ -667,7 +668,7 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
     D.sell_col = form ? (const int32_t *)(region + L.sell_col) : nullptr;
     D.sell_perm = form == 2 ? (const int32_t *)(region + L.sort_perm) : nullptr;
     D.sell_win = form == 2 ? (const int2 *)(region + L.sort_win) : nullptr;
-    D.sell_c16 = form == 2 && col_bits == 16 ? (const uint16_t *)(region + L.sell_col) : nullptr;
+    D.sell_c16 = form && col_bits == 16 ? (const uint16_t *)(region + L.sell_col) : nullptr;
     D.sell_val = form ? (const void *)(region + L.sell_val) : nullptr;
     // the counter of written chunk sums starts at zero (the transition that
     // completes it sets it back)

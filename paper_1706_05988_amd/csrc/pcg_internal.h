@@ -113,12 +113,15 @@ struct SellPlan {
     int32_t *col = nullptr;
     void *val = nullptr;  // cap values of the storage type
     int2 *win = nullptr;  // sorted form: per tile, its column window (see k_sell_window)
+    int *scratch = nullptr;  // one device int for the set-up's checks
 };
 // Build the smaller of the reserved copies that fits cap (synchronous):
 // *form 0 (none fits), 1 (in place; slice offsets at sell_ptr) or 2 (sorted;
 // at sort_ptr / sort_perm, tile windows at win); *entries its entries;
 // *col_bits 32, or 16 when every tile of a sorted copy has a window (the
-// columns are then 16-bit window offsets in the first half of col).
+// columns are then 16-bit window offsets in the first half of col) or every
+// entry of an in-place copy lies within 2^15 of its row (16-bit offsets from
+// the row).
 pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipStream_t stream, int *form,
                       int64_t *entries, int *col_bits);
 

@@ -99,8 +99,9 @@ struct PassArgs {
     // sorted form: per tile, the first column its rows gather and the width
     // of that column window (-1: wider than kSellWindow, gathered directly)
     const int2 *sell_win;
-    // sorted form with every tile windowed: each entry's column as its offset
-    // in its tile's window, 16 bits (nullptr: 32-bit columns in sell_col)
+    // 16-bit columns (nullptr: 32-bit columns in sell_col): in the sorted
+    // form with every tile windowed, each entry's offset in its tile's
+    // window; in the in-place form, its column minus its row plus 2^15
     const uint16_t *sell_c16;
     int32_t run_through;  // 1: no breakdown stop (PCG_FLAG_RUN_THROUGH_BREAKDOWN)
 };
@@ -632,7 +633,15 @@ __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, P
     for (int j = 0; j < EPT; ++j) {
         const uint32_t e = ti.e[j];
         we[j] = ld(vp<T>(a, a.off_win, e), 0);
-        if constexpr (OP == OP_CSR && SELL == 1) ne[j] = sell_row(a, e, operand);
+        if constexpr (OP == OP_CSR && SELL == 1) {
+            if (a.sell_c16) {
+                // row-relative 16-bit columns (every entry within 2^15 of its row)
+                auto rel = [&](uint32_t c) { return operand(e + c - 32768u); };
+                ne[j] = sell_slice<T, decltype(rel), true>(a, e >> 6, e & 63, a.A.row_ptr[e + 1] - a.A.row_ptr[e], rel);
+            } else {
+                ne[j] = sell_row(a, e, operand);
+            }
+        }
         else if constexpr (OP != OP_CSR || SELL == 0) ne[j] = apply_row<OP>(a.A, e, operand);
         re[j] = lds<NT>(vp<T>(a, a.off_r, e));
         zo[j] = lds<NT>(vp<T>(a, a.off_z, e));
@@ -1385,9 +1394,12 @@ static __global__ void __launch_bounds__(1024) k_sell_scan(int32_t *sell_ptr, in
 }
 
 // Step 3: each row's entries into its slice column, padding with the row's
-// own column and a zero value.
+// own column and a zero value.  With c16 (every entry within 2^15 of its
+// row) the columns go out as 16-bit column - row + 2^15 instead of into
+// sell_col.
 template <typename T>
-__global__ void __launch_bounds__(256) k_sell_fill(OpDev<T> A, const int32_t *sell_ptr, int32_t *sell_col, T *sell_val)
+__global__ void __launch_bounds__(256) k_sell_fill(OpDev<T> A, const int32_t *sell_ptr, int32_t *sell_col, T *sell_val,
+                                                   uint16_t *c16)
 {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= (uint32_t)A.n) return;
@@ -1396,9 +1408,24 @@ __global__ void __launch_bounds__(256) k_sell_fill(OpDev<T> A, const int32_t *se
     const int32_t k0 = A.row_ptr[r], len = A.row_ptr[r + 1] - k0;
     for (int32_t k = 0; k < w; ++k) {
         const int32_t idx = p0 + (k << 6) + (int32_t)lane;
-        sell_col[idx] = k < len ? A.col[k0 + k] : (int32_t)r;
+        const int32_t c = k < len ? A.col[k0 + k] : (int32_t)r;
+        if (c16) c16[idx] = (uint16_t)(c - (int32_t)r + 32768);
+        else sell_col[idx] = c;
         sell_val[idx] = k < len ? A.val[k0 + k] : (T)0;
     }
+}
+
+// Whether some entry lies 2^15 or more columns from its row (*far = 1; the
+// in-place copy then keeps 32-bit columns).
+static __global__ void __launch_bounds__(256) k_sell_far(const int32_t *row_ptr, const int32_t *col, int32_t n, int *far)
+{
+    int f = 0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x)
+        for (int32_t k = row_ptr[r]; k < row_ptr[r + 1]; ++k) {
+            const int64_t d = (int64_t)col[k] - r;
+            f |= d < -32768 || d > 32767;
+        }
+    if (f) atomicOr(far, 1);
 }
 
 // The sorted form (see sell_sorted_rows), step 1: one wave per group of EPT

@@ -548,7 +548,7 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
         a.sell_val = sell ? reinterpret_cast<const T *>(ws + L.sell_val) : nullptr;
         a.sell_perm = sell == 2 ? reinterpret_cast<const int32_t *>(ws + L.sort_perm) : nullptr;
         a.sell_win = sell == 2 ? reinterpret_cast<const int2 *>(ws + L.sort_win) : nullptr;
-        a.sell_c16 = sell == 2 && sell_col_bits == 16 ? reinterpret_cast<const uint16_t *>(ws + L.sell_col) : nullptr;
+        a.sell_c16 = sell && sell_col_bits == 16 ? reinterpret_cast<const uint16_t *>(ws + L.sell_col) : nullptr;
         a.run_through = (opt.flags & PCG_FLAG_RUN_THROUGH_BREAKDOWN) ? 1 : 0;
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
@@ -707,6 +707,16 @@ pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipSt
     // are stored as 16-bit offsets in their tile's window (in the first half
     // of the column array)
     uint16_t *c16 = nullptr;
+    if (f == 1 && p.scratch) {
+        HIPCHK(hipMemsetAsync(p.scratch, 0, sizeof(int), stream));
+        hipLaunchKernelGGL(k_sell_far, dim3(std::min<int64_t>((op->n + 255) / 256, 4096)), dim3(256), 0, stream,
+                           op->row_ptr, op->col_idx, n, p.scratch);
+        HIPCHK(hipGetLastError());
+        int far = 1;
+        HIPCHK(hipMemcpyAsync(&far, p.scratch, sizeof(int), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (!far) c16 = reinterpret_cast<uint16_t *>(p.col);
+    }
     if (f == 2) {
         if (!p.win) return invalid("sorted sliced-ELL copy without its window table");
         const int rows = p.sort_block * p.sort_ept;
@@ -725,7 +735,7 @@ pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipSt
         T *sv = reinterpret_cast<T *>(p.val);
         if (f == 1) {
             const int g = (int)((op->n + 255) / 256);
-            hipLaunchKernelGGL(k_sell_fill<T>, dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sp, p.col, sv);
+            hipLaunchKernelGGL(k_sell_fill<T>, dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sp, p.col, sv, c16);
             return;
         }
         const int64_t slots = int64_t(p.sort_nslices) * 64;
@@ -766,6 +776,7 @@ static pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape
         p.col = reinterpret_cast<int32_t *>(ws + L.sell_col);
         p.val = ws + L.sell_val;
         p.win = L.sort_win == SIZE_MAX ? nullptr : reinterpret_cast<int2 *>(ws + L.sort_win);
+        p.scratch = reinterpret_cast<int *>(ws + L.flag) + 1;  // after the CSR check's flag
     }
     return sell_build(op, prec, p, stream, form, entries, col_bits);
 }
