@@ -262,6 +262,9 @@ typedef struct {
                                    2048 columns (offsets in that window) or every entry
                                    of an in-place copy lies within 2^15 of its row
                                    (offsets from the row); 0 if no copy                   */
+    int32_t csr_val_bits;       /* the copy's values: 64, or 32 (FP32-stream form, or a
+                                   binary64 operator whose values are all binary32 numbers:
+                                   stored as binary32, exactly); 0 if no copy            */
     int64_t csr_entries;        /* entries of that copy, padding included (0 if none)     */
 } pcg_solver_shape;
 pcg_status pcg_solver_info(pcg_solver solver, pcg_solver_shape *shape);

@@ -83,6 +83,7 @@ struct BatchSys {
     const int32_t *sell_perm;
     const int2 *sell_win;   // sorted copy: per work tile, its column window
     const uint16_t *sell_c16;  // 16-bit columns (see PassArgs::sell_c16), or nullptr
+    const float *sell_v32;     // binary32-stored values of a binary64 system (see PassArgs::sell_v32)
     const void *sell_val;
     int32_t hist_cap, replace_max, true_check, nchunks;
 };

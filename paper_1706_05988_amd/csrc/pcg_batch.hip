@@ -58,6 +58,7 @@ __device__ __forceinline__ PassArgs<T> batch_args(const BatchSys &D, const Batch
     a.sell_perm = D.sell_perm;
     a.sell_win = D.sell_win;
     a.sell_c16 = D.sell_c16;
+    a.sell_v32 = D.sell_v32;
     return a;
 }
 
@@ -611,7 +612,7 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
             (st = csr_gershgorin(op, opt->prec, jac, (double *)(region + L.gersh), stream_, &gersh[0], &gersh[1])))
             return st;
     }
-    int form = 0, col_bits = 0;
+    int form = 0, col_bits = 0, val_bits = 0;
     int64_t entries = 0;
     if (op->kind == PCG_OP_CSR && L.sell_col != SIZE_MAX) {
         SellPlan p;
@@ -627,7 +628,7 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
         p.val = region + L.sell_val;
         p.win = (int2 *)(region + L.sort_win);
         p.scratch = (int *)(region + L.flag) + 1;  // after the CSR check's flag
-        if ((st = sell_build(op, opt->prec, p, stream_, &form, &entries, &col_bits))) return st;
+        if ((st = sell_build(op, opt->prec, p, stream_, &form, &entries, &col_bits, &val_bits))) return st;
     }
     BatchSys D{};
     D.kind = op->kind;
@@ -669,6 +670,7 @@ pcg_status BatchEngine::admit(const pcg_operator *op, const pcg_options *opt, co
     D.sell_perm = form == 2 ? (const int32_t *)(region + L.sort_perm) : nullptr;
     D.sell_win = form == 2 ? (const int2 *)(region + L.sort_win) : nullptr;
     D.sell_c16 = form && col_bits == 16 ? (const uint16_t *)(region + L.sell_col) : nullptr;
+    D.sell_v32 = form && opt->prec == PCG_FP64 && val_bits == 32 ? (const float *)(region + L.sell_val) : nullptr;
     D.sell_val = form ? (const void *)(region + L.sell_val) : nullptr;
     // the counter of written chunk sums starts at zero (the transition that
     // completes it sets it back)

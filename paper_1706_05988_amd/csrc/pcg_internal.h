@@ -121,8 +121,9 @@ struct SellPlan {
 // *col_bits 32, or 16 when every tile of a sorted copy has a window (the
 // columns are then 16-bit window offsets in the first half of col) or every
 // entry of an in-place copy lies within 2^15 of its row (16-bit offsets from
-// the row).
+// the row); *val_bits 32 or 64 (binary64 values that are all binary32
+// numbers are stored as binary32, in the first half of val).
 pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipStream_t stream, int *form,
-                      int64_t *entries, int *col_bits);
+                      int64_t *entries, int *col_bits, int *val_bits);
 
 }  // namespace pcg

@@ -103,6 +103,9 @@ struct PassArgs {
     // form with every tile windowed, each entry's offset in its tile's
     // window; in the in-place form, its column minus its row plus 2^15
     const uint16_t *sell_c16;
+    // binary64 form whose matrix values are all binary32 numbers: the copy's
+    // values stored as binary32 (exactly the same values; nullptr: sell_val)
+    const float *sell_v32;
     int32_t run_through;  // 1: no breakdown stop (PCG_FLAG_RUN_THROUGH_BREAKDOWN)
 };
 
@@ -437,7 +440,37 @@ struct PipeTile {
 // One row's product from slice s of a sliced-ELL copy: the row sits in
 // lane `lane` of the slice and has len entries (the rest of the slice's
 // width is padding, skipped).
-// C16: the columns are 16-bit window offsets (sell_c16), v takes those.
+// The columns and values of entries k .. k + kCsrChunk - 1 of the slice at
+// p0 (width w) in lane `lane`; indices past the width repeat entry k.  C16:
+// 16-bit columns (sell_c16); binary32-stored values widen exactly.
+template <typename T, bool C16>
+__device__ __forceinline__ void sell_load_chunk(const PassArgs<T> &a, int32_t p0, int32_t k, int32_t w, uint32_t lane,
+                                                int32_t (&c)[kCsrChunk], T (&wv)[kCsrChunk])
+{
+    if constexpr (sizeof(T) == 8) {
+        if (a.sell_v32) {
+#pragma unroll
+            for (int u = 0; u < kCsrChunk; ++u) {
+                const int32_t kk = k + u < w ? k + u : k;
+                const int32_t idx = p0 + (kk << 6) + (int32_t)lane;
+                if constexpr (C16) c[u] = a.sell_c16[idx];
+                else c[u] = a.sell_col[idx];
+                wv[u] = (T)a.sell_v32[idx];
+            }
+            return;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < kCsrChunk; ++u) {
+        const int32_t kk = k + u < w ? k + u : k;
+        const int32_t idx = p0 + (kk << 6) + (int32_t)lane;
+        if constexpr (C16) c[u] = a.sell_c16[idx];
+        else c[u] = a.sell_col[idx];
+        wv[u] = a.sell_val[idx];
+    }
+}
+
+// C16: the columns are 16-bit offsets (sell_c16), v takes those.
 template <typename T, typename F, bool C16 = false>
 __device__ __forceinline__ double sell_slice(const PassArgs<T> &a, uint32_t s, uint32_t lane, int32_t len, F v)
 {
@@ -447,14 +480,7 @@ __device__ __forceinline__ double sell_slice(const PassArgs<T> &a, uint32_t s, u
         int32_t c[kCsrChunk];
         T wv[kCsrChunk];
         double g[kCsrChunk];
-#pragma unroll
-        for (int u = 0; u < kCsrChunk; ++u) {
-            const int32_t kk = k + u < w ? k + u : k;
-            const int32_t idx = p0 + (kk << 6) + (int32_t)lane;
-            if constexpr (C16) c[u] = a.sell_c16[idx];
-            else c[u] = a.sell_col[idx];
-            wv[u] = a.sell_val[idx];
-        }
+        sell_load_chunk<T, C16>(a, p0, k, w, lane, c, wv);
 #pragma unroll
         for (int u = 0; u < kCsrChunk; ++u) g[u] = v((uint32_t)c[u]);
 #pragma unroll
@@ -503,24 +529,8 @@ __device__ __forceinline__ void sell_slice_pair(const PassArgs<T> &a, uint32_t s
         int32_t c0[kCsrChunk], c1[kCsrChunk];
         T v0[kCsrChunk], v1[kCsrChunk];
         double g0[kCsrChunk], g1[kCsrChunk];
-#pragma unroll
-        for (int u = 0; u < kCsrChunk; ++u) {
-            const int32_t kk = k + u < w0 ? k + u : k;
-            const int32_t idx = p0 + (kk << 6) + (int32_t)lane;
-            if constexpr (C16) c0[u] = a.sell_c16[idx];
-            else c0[u] = a.sell_col[idx];
-            v0[u] = a.sell_val[idx];
-        }
-        if (two) {
-#pragma unroll
-            for (int u = 0; u < kCsrChunk; ++u) {
-                const int32_t kk = k + u < w1 ? k + u : k;
-                const int32_t idx = q0 + (kk << 6) + (int32_t)lane;
-                if constexpr (C16) c1[u] = a.sell_c16[idx];
-                else c1[u] = a.sell_col[idx];
-                v1[u] = a.sell_val[idx];
-            }
-        }
+        sell_load_chunk<T, C16>(a, p0, k, w0, lane, c0, v0);
+        if (two) sell_load_chunk<T, C16>(a, q0, k, w1, lane, c1, v1);
 #pragma unroll
         for (int u = 0; u < kCsrChunk; ++u) g0[u] = v((uint32_t)c0[u]);
         if (two) {
@@ -1399,7 +1409,7 @@ static __global__ void __launch_bounds__(1024) k_sell_scan(int32_t *sell_ptr, in
 // sell_col.
 template <typename T>
 __global__ void __launch_bounds__(256) k_sell_fill(OpDev<T> A, const int32_t *sell_ptr, int32_t *sell_col, T *sell_val,
-                                                   uint16_t *c16)
+                                                   uint16_t *c16, float *v32)
 {
     const uint32_t r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= (uint32_t)A.n) return;
@@ -1411,7 +1421,9 @@ __global__ void __launch_bounds__(256) k_sell_fill(OpDev<T> A, const int32_t *se
         const int32_t c = k < len ? A.col[k0 + k] : (int32_t)r;
         if (c16) c16[idx] = (uint16_t)(c - (int32_t)r + 32768);
         else sell_col[idx] = c;
-        sell_val[idx] = k < len ? A.val[k0 + k] : (T)0;
+        const T v = k < len ? A.val[k0 + k] : (T)0;
+        if (v32) v32[idx] = (float)v;  // exact: checked at set-up
+        else sell_val[idx] = v;
     }
 }
 
@@ -1479,7 +1491,7 @@ template <typename T, int EPT>
 __global__ void __launch_bounds__(256) k_sell_fill_sorted(OpDev<T> A, int32_t block, int64_t slots,
                                                            const int32_t *sell_ptr, const int32_t *perm,
                                                            int32_t *sell_col, T *sell_val, const int2 *win,
-                                                           uint16_t *c16)
+                                                           uint16_t *c16, float *v32)
 {
     const int64_t P = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (P >= slots) return;
@@ -1499,8 +1511,23 @@ __global__ void __launch_bounds__(256) k_sell_fill_sorted(OpDev<T> A, int32_t bl
         const int32_t c = k < len ? A.col[k0 + k] : pad;
         if (c16) c16[idx] = (uint16_t)(c - base);
         else sell_col[idx] = c;
-        sell_val[idx] = k < len ? A.val[k0 + k] : (T)0;
+        const T v = k < len ? A.val[k0 + k] : (T)0;
+        if (v32) v32[idx] = (float)v;  // exact: checked at set-up
+        else sell_val[idx] = v;
     }
+}
+
+// Whether some matrix value is not a binary32 number (*inexact = 1; the
+// binary64 form's copy then keeps binary64 values).
+template <typename T>
+__global__ void __launch_bounds__(256) k_vals_binary32(const T *val, int64_t nnz, int *inexact)
+{
+    int f = 0;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * blockDim.x) {
+        const double v = (double)val[k];
+        f |= !((double)(float)v == v);
+    }
+    if (f) atomicOr(inexact, 1);
 }
 
 // The sorted form, step 4: one block per tile of `rows` rows finds the

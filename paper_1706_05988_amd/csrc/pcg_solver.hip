@@ -474,7 +474,8 @@ struct pcg_solver_ {
     int sell = 0;            // the fused pass reads the CSR operator's sliced-ELL copy: 1 rows
                              // in place, 2 sorted (0: the CSR arrays)
     int64_t sell_entries = 0;  // entries of that copy, padding included
-    int sell_col_bits = 0;     // its column words: 32, or 16 (window offsets)
+    int sell_col_bits = 0;     // its column words: 32, or 16 (window or row offsets)
+    int sell_val_bits = 0;     // its values: 64, or 32 (binary64 values that are binary32 numbers)
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     const double *graph_b = nullptr;  // b baked into the captured graph
@@ -549,6 +550,8 @@ PassArgsAny pcg_solver_::args(int par, const double *b, double *x_user, int i0, 
         a.sell_perm = sell == 2 ? reinterpret_cast<const int32_t *>(ws + L.sort_perm) : nullptr;
         a.sell_win = sell == 2 ? reinterpret_cast<const int2 *>(ws + L.sort_win) : nullptr;
         a.sell_c16 = sell && sell_col_bits == 16 ? reinterpret_cast<const uint16_t *>(ws + L.sell_col) : nullptr;
+        a.sell_v32 = sell && opt.prec == PCG_FP64 && sell_val_bits == 32
+                         ? reinterpret_cast<const float *>(ws + L.sell_val) : nullptr;
         a.run_through = (opt.flags & PCG_FLAG_RUN_THROUGH_BREAKDOWN) ? 1 : 0;
     };
     if (opt.prec == PCG_FP64) fill((double *)nullptr);
@@ -670,11 +673,12 @@ pcg_status csr_setup(const pcg_operator *op, int prec, int jac, void *dinv, int 
 // two is kept (the sorted one only when at least 1/32 smaller, since it
 // also routes the products through LDS).
 pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipStream_t stream, int *form,
-                      int64_t *entries, int *col_bits)
+                      int64_t *entries, int *col_bits, int *val_bits)
 {
     *form = 0;
     *entries = 0;
     *col_bits = 0;
+    *val_bits = 0;
     if (!p.col || (!p.sell_ptr && !p.sort_ptr)) return PCG_OK;
     const int32_t n = (int32_t)op->n;
     int32_t total[2] = {-1, -1};
@@ -730,25 +734,38 @@ pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipSt
         for (const int2 &t : w) all = all && t.y >= 0;
         if (all) c16 = reinterpret_cast<uint16_t *>(p.col);
     }
+    // binary64 values that are all binary32 numbers are stored as binary32
+    // (the same values; half the bytes), in the first half of the value array
+    float *v32 = nullptr;
+    if (prec == PCG_FP64 && p.scratch) {
+        HIPCHK(hipMemsetAsync(p.scratch, 0, sizeof(int), stream));
+        hipLaunchKernelGGL(k_vals_binary32<double>, dim3((int)std::min<int64_t>((op->nnz + 255) / 256, 4096)), dim3(256),
+                           0, stream, reinterpret_cast<const double *>(op->vals), op->nnz, p.scratch);
+        HIPCHK(hipGetLastError());
+        int inexact = 1;
+        HIPCHK(hipMemcpyAsync(&inexact, p.scratch, sizeof(int), hipMemcpyDeviceToHost, stream));
+        HIPCHK(hipStreamSynchronize(stream));
+        if (!inexact) v32 = reinterpret_cast<float *>(p.val);
+    }
     auto fill = [&](auto *tag) {
         using T = std::remove_pointer_t<decltype(tag)>;
         T *sv = reinterpret_cast<T *>(p.val);
         if (f == 1) {
             const int g = (int)((op->n + 255) / 256);
-            hipLaunchKernelGGL(k_sell_fill<T>, dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sp, p.col, sv, c16);
+            hipLaunchKernelGGL(k_sell_fill<T>, dim3(g), dim3(256), 0, stream, make_opdev<T>(op), sp, p.col, sv, c16, v32);
             return;
         }
         const int64_t slots = int64_t(p.sort_nslices) * 64;
         const int g = (int)((slots + 255) / 256);
         if (p.sort_ept == 1)
             hipLaunchKernelGGL((k_sell_fill_sorted<T, 1>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), p.sort_block,
-                               slots, tp, perm, p.col, sv, p.win, c16);
+                               slots, tp, perm, p.col, sv, p.win, c16, v32);
         else if (p.sort_ept == 2)
             hipLaunchKernelGGL((k_sell_fill_sorted<T, 2>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), p.sort_block,
-                               slots, tp, perm, p.col, sv, p.win, c16);
+                               slots, tp, perm, p.col, sv, p.win, c16, v32);
         else
             hipLaunchKernelGGL((k_sell_fill_sorted<T, 4>), dim3(g), dim3(256), 0, stream, make_opdev<T>(op), p.sort_block,
-                               slots, tp, perm, p.col, sv, p.win, c16);
+                               slots, tp, perm, p.col, sv, p.win, c16, v32);
     };
     if (prec == PCG_FP64) fill((double *)nullptr);
     else fill((float *)nullptr);
@@ -756,12 +773,13 @@ pcg_status sell_build(const pcg_operator *op, int prec, const SellPlan &p, hipSt
     *form = f;
     *entries = total[f - 1];
     *col_bits = c16 ? 16 : 32;
+    *val_bits = prec == PCG_FP64 && !v32 ? 64 : 32;
     return PCG_OK;
 }
 
 // The solver's copies, as its layout reserved them.
 static pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape &sh, const Layout &L, char *ws,
-                             hipStream_t stream, int *form, int64_t *entries, int *col_bits)
+                             hipStream_t stream, int *form, int64_t *entries, int *col_bits, int *val_bits)
 {
     SellPlan p;
     if (L.sell_col != SIZE_MAX) {
@@ -778,7 +796,7 @@ static pcg_status sell_setup(const pcg_operator *op, int prec, const LaunchShape
         p.win = L.sort_win == SIZE_MAX ? nullptr : reinterpret_cast<int2 *>(ws + L.sort_win);
         p.scratch = reinterpret_cast<int *>(ws + L.flag) + 1;  // after the CSR check's flag
     }
-    return sell_build(op, prec, p, stream, form, entries, col_bits);
+    return sell_build(op, prec, p, stream, form, entries, col_bits, val_bits);
 }
 
 pcg_status csr_gershgorin(const pcg_operator *op, int prec, int jac, double *gb, hipStream_t stream, double *lo,
@@ -873,7 +891,8 @@ static pcg_status init_solver(pcg_solver_ *s, const pcg_operator *op, const pcg_
             (st = csr_gershgorin(op, opt->prec, jac, reinterpret_cast<double *>(s->ws + L.gersh), s->stream, &gersh[0],
                                  &gersh[1])))
             return st;
-        if ((st = sell_setup(op, opt->prec, sh, L, s->ws, s->stream, &s->sell, &s->sell_entries, &s->sell_col_bits)))
+        if ((st = sell_setup(op, opt->prec, sh, L, s->ws, s->stream, &s->sell, &s->sell_entries, &s->sell_col_bits,
+                             &s->sell_val_bits)))
             return st;
         if (s->sell == 2 && (sh.sort_ept != sh.ept || sh.sort_block != sh.block || sh.sort_grid != sh.grid)) {
             // the sorted copy is laid out for its own shape: the passes take
@@ -933,6 +952,7 @@ extern "C" pcg_status pcg_solver_info(pcg_solver s, pcg_solver_shape *out)
     out->iters_per_launch = s->sh.K;
     out->csr_form = s->sell;
     out->csr_col_bits = s->sell_col_bits;
+    out->csr_val_bits = s->sell_val_bits;
     out->csr_entries = s->sell_entries;
     return PCG_OK;
 }

@@ -65,7 +65,7 @@ class pcg_result(C.Structure):
 class pcg_solver_shape(C.Structure):
     _fields_ = [("block", C.c_int32), ("ept", C.c_int32), ("grid", C.c_int32), ("ntiles", C.c_int32),
                 ("iters_per_launch", C.c_int32), ("csr_form", C.c_int32), ("csr_col_bits", C.c_int32),
-                ("csr_entries", C.c_int64)]
+                ("csr_val_bits", C.c_int32), ("csr_entries", C.c_int64)]
 
 
 class pcg_server_stats(C.Structure):

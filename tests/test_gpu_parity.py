@@ -818,26 +818,28 @@ def test_csr_sliced_ell_operand_gives_the_csr_bits(torch, method, fp32):
     anisotropic operator (rows of 3 to 5 entries, a ragged last slice) and
     on a 3-D 7-point Laplacian assembled as CSR (rows of 4 to 7 entries,
     Jacobi from its diagonal, a last slice of 4 rows), both with 16-bit
-    row-relative columns, and on a 2-D Laplacian with a few couplings
-    40000 columns away (32-bit columns)."""
+    row-relative columns and binary32-stored values, and on a 2-D Laplacian
+    scaled by 1/3 with a few couplings 40000 columns away (32-bit columns,
+    binary64 values)."""
     from paper_1706_05988_amd import pcg as P
     A = problems.to_scipy(problems.stencil3d(20, 17, 13)).tocsr()
     A.sort_indices()
     op3 = problems.csr_operator(A.indptr, A.indices, A.data)
     xt = np.random.default_rng(8).uniform(-1, 1, op3.n)
     p3 = problems.Problem("lapl3d_csr", op3, A @ xt, np.zeros(op3.n), xt, jacobi=True, sigma=1.0)
-    # a 2-D Laplacian with a few couplings 40000 columns away: 32-bit columns
+    # a 2-D Laplacian scaled by 1/3, with a few couplings 40000 columns away:
+    # 32-bit columns and (binary64) 64-bit values
     A6 = problems.to_scipy(problems.stencil2d(300, 300)).tolil()
     for i in (10, 20000, 45000):
         A6[i, i + 40000] = A6[i + 40000, i] = -0.5
         A6[i, i] += 0.5
         A6[i + 40000, i + 40000] += 0.5
-    A6 = A6.tocsr()
+    A6 = (A6.tocsr() / 3.0).tocsr()  # values that are not binary32 numbers
     A6.sort_indices()
     op6 = problems.csr_operator(A6.indptr, A6.indices, A6.data)
     xt6 = np.random.default_rng(12).uniform(-1, 1, op6.n)
     p6 = problems.Problem("lapl2d_far_csr", op6, A6 @ xt6, np.zeros(op6.n), xt6, jacobi=True, sigma=1.0)
-    for p, bits in ((problems.anisotropic_csr(90, seed=4), 16), (p3, 16), (p6, 32)):
+    for p, bits, vbits in ((problems.anisotropic_csr(90, seed=4), 16, 32), (p3, 16, 32), (p6, 32, 64)):
         base = P.PCG_VAR_SET | P.PCG_VAR_NT | P.PCG_VAR_EPT1
         out = []
         for sell in (0, P.PCG_VAR_CSR_SELL):
@@ -847,8 +849,10 @@ def test_csr_sliced_ell_operand_gives_the_csr_bits(torch, method, fp32):
             out.append(g)
         a, b = out
         # the copy stores columns as 16-bit offsets from the row when every
-        # entry lies within 2^15 of it
+        # entry lies within 2^15 of it, and binary64 values as binary32 when
+        # they all are binary32 numbers
         assert b["info"]["csr_form_name"] == "sell" and b["info"]["csr_col_bits"] == bits, p.name
+        assert b["info"]["csr_val_bits"] == (32 if fp32 else vbits), p.name
         assert a["iterations"] == b["iterations"]
         np.testing.assert_array_equal(a["res"], b["res"])
         np.testing.assert_array_equal(a["x"], b["x"])
@@ -930,6 +934,7 @@ def test_csr_sorted_sliced_ell_gives_the_csr_bits(torch, shape, fp32):
             spans.append(max(c.max(initial=r1 - 1), r1 - 1) - min(c.min(initial=r0), r0) + 1)
         windowed = np.array(spans) <= 2048
         assert b["info"]["csr_col_bits"] == (16 if windowed.all() else 32), (p.name, windowed.mean())
+        assert b["info"]["csr_val_bits"] == 32  # binary32 numbers in either form
         assert a["iterations"] == b["iterations"]
         np.testing.assert_array_equal(a["res"], b["res"])
         np.testing.assert_array_equal(a["x"], b["x"])
