@@ -181,10 +181,12 @@ typedef struct {
 #define PCG_VAR_CG_ZMARCH 0x40  /* PCG_CG, 3-D stencil: pass A marches along z through
                                    LDS also where the built-in rule would not (grids
                                    with fewer work items than CUs)                      */
-#define PCG_VAR_CSR_SELL 0x80   /* CSR, PCG_PIPE / PCG_PIPE_SHIFT: the fused pass reads a
-                                   sliced-ELL copy of the operator (64-row slices, built
-                                   at pcg_create when its padding stays within a quarter
-                                   of nnz; the same sums in the same order)             */
+#define PCG_VAR_CSR_SELL 0x80   /* CSR, PCG_PIPE / PCG_PIPE_SHIFT / PCG_PIPE_VAR_SHIFT:
+                                   the passes (fused iteration, set-up, explicit
+                                   residual) read a sliced-ELL copy of the operator
+                                   (64-row slices, built at pcg_create when its padding
+                                   stays within a quarter of nnz; the same sums in the
+                                   same order)                                          */
 #define PCG_VAR_CSR_SELL_SORTED 0x100 /* as PCG_VAR_CSR_SELL, with the rows sorted by
                                    length (longest first) within each wave's rows of a
                                    tile (SELL-C-sigma, C = 64) so that rows of mixed

@@ -63,8 +63,8 @@ __device__ __forceinline__ PassArgs<T> batch_args(const BatchSys &D, const Batch
 }
 
 // One tile of one system in its current phase; NF partials into acc.
-template <typename T, int OP, bool JAC>
-__device__ __forceinline__ void batch_tile(const PassArgs<T> &a, const BatchState &S, int tile, double (&acc)[3])
+template <typename T, int OP, bool JAC, int SELL>
+__device__ __forceinline__ void batch_tile_form(const PassArgs<T> &a, const BatchState &S, int tile, double (&acc)[3])
 {
     constexpr int E = kBatchEPT;
     switch (S.phase) {
@@ -72,11 +72,11 @@ __device__ __forceinline__ void batch_tile(const PassArgs<T> &a, const BatchStat
     case PH_COPYOUT: tile_copy_x<T, E>(a, tile); break;
     case PH_INIT0: {
         double b1[1] = {0.0};
-        tile_init0<T, OP, JAC, JAC, E, true>(a, tile, b1);
+        tile_init0<T, OP, JAC, JAC, E, true, SELL>(a, tile, b1);
         acc[0] = b1[0];
         break;
     }
-    case PH_INIT1: tile_init1<T, OP, JAC, E, true>(a, tile, acc); break;
+    case PH_INIT1: tile_init1<T, OP, JAC, E, true, SELL>(a, tile, acc); break;
     case PH_ITER: {
         PipeScalars sc;
         sc.alpha = S.alpha;
@@ -85,34 +85,32 @@ __device__ __forceinline__ void batch_tile(const PassArgs<T> &a, const BatchStat
         sc.dsig = 0.0;
         sc.alpha_prev = S.alpha_prev;
         // x every other iteration (the same two updates in the same order)
-        const bool skip = lag_mode(S.iter, S.i_start) == X_SKIP;
-        if constexpr (OP == OP_CSR) {
-            // the CSR operand: sorted sliced-ELL copy, in-place copy, or rows
-            if (a.sell_perm) {
-                if (skip) tile_pipe<T, OP, JAC, E, true, false, X_SKIP, 2>(a, tile, sc, acc);
-                else tile_pipe<T, OP, JAC, E, true, false, X_CATCHUP, 2>(a, tile, sc, acc);
-                break;
-            }
-            if (a.sell_ptr) {
-                if (skip) tile_pipe<T, OP, JAC, E, true, false, X_SKIP, 1>(a, tile, sc, acc);
-                else tile_pipe<T, OP, JAC, E, true, false, X_CATCHUP, 1>(a, tile, sc, acc);
-                break;
-            }
-        }
-        if (skip) tile_pipe<T, OP, JAC, E, true, false, X_SKIP>(a, tile, sc, acc);
-        else tile_pipe<T, OP, JAC, E, true, false, X_CATCHUP>(a, tile, sc, acc);
+        if (lag_mode(S.iter, S.i_start) == X_SKIP) tile_pipe<T, OP, JAC, E, true, false, X_SKIP, SELL>(a, tile, sc, acc);
+        else tile_pipe<T, OP, JAC, E, true, false, X_CATCHUP, SELL>(a, tile, sc, acc);
         break;
     }
     case PH_XFIX: tile_x_fixup<T, JAC, E>(a, tile, S.alpha); break;
     case PH_RESID: {
         double r2[2] = {0.0, 0.0};
-        tile_resid<T, OP, E>(a, tile, r2);
+        tile_resid<T, OP, E, SELL>(a, tile, r2);
         acc[0] = r2[0];
         acc[1] = r2[1];
         break;
     }
     default: break;
     }
+}
+
+// The CSR operand of a system: its sorted sliced-ELL copy, in-place copy, or
+// rows; the same form in every phase.
+template <typename T, int OP, bool JAC>
+__device__ __forceinline__ void batch_tile(const PassArgs<T> &a, const BatchState &S, int tile, double (&acc)[3])
+{
+    if constexpr (OP == OP_CSR) {
+        if (a.sell_perm) return batch_tile_form<T, OP, JAC, 2>(a, S, tile, acc);
+        if (a.sell_ptr) return batch_tile_form<T, OP, JAC, 1>(a, S, tile, acc);
+    }
+    batch_tile_form<T, OP, JAC, 0>(a, S, tile, acc);
 }
 
 template <typename T, int OP>

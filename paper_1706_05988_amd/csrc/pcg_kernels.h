@@ -307,21 +307,25 @@ __global__ void __launch_bounds__(kMaxBlock) k_copy_x(PassArgs<T> a)
     for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_copy_x<T, EPT>(a, tile);
 }
 
+// (A v) at a tile's rows in the form SELL names (defined with the sliced-ELL
+// copies below).
+template <typename T, int OP, int EPT, int SELL, typename F>
+__device__ __forceinline__ void tile_apply(const PassArgs<T> &a, int tile, const TileIdx<EPT> &ti, double (&out)[EPT],
+                                           F v);
+
 // ----------------------------------------------------------------- init 0
 
 // r_0 := b - A x_0 (stored), and for the pipelined methods with a
 // preconditioner u_0 := M^-1 r_0 (stored).  Clears the slots in a.clear (so
 // the first iteration's beta = 0 terms are exact zeros).  Partials of (b, b).
-template <typename T, int OP, bool JAC, bool STORE_U, int EPT, bool NT>
+template <typename T, int OP, bool JAC, bool STORE_U, int EPT, bool NT, int SELL = 0>
 __device__ __forceinline__ void tile_init0(const PassArgs<T> &a, int tile, double (&acc)[1])
 {
     const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
     double be[EPT], ax[EPT];
+    tile_apply<T, OP, EPT, SELL>(a, tile, ti, ax, [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        be[j] = lds<NT>(a.b + ti.e[j]);
-        ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
-    }
+    for (int j = 0; j < EPT; ++j) be[j] = lds<NT>(a.b + ti.e[j]);
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         if (!ti.live[j]) continue;
@@ -339,13 +343,14 @@ __device__ __forceinline__ void tile_init0(const PassArgs<T> &a, int tile, doubl
     }
 }
 
-template <typename T, int OP, bool JAC, bool STORE_U, int EPT, bool NT>
+template <typename T, int OP, bool JAC, bool STORE_U, int EPT, bool NT, int SELL = 0>
 __global__ void __launch_bounds__(kMaxBlock) k_init0(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     double acc[1] = {0.0};
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_init0<T, OP, JAC, STORE_U, EPT, NT>(a, tile, acc);
+    for (int tile = tr.first; tile < tr.end; tile += tr.step)
+        tile_init0<T, OP, JAC, STORE_U, EPT, NT, SELL>(a, tile, acc);
     block_sum<1>(acc, lds_red);
     store_partial<1>(a.part_out, acc);
 }
@@ -354,15 +359,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_init0(PassArgs<T> a)
 
 // w_0 := A u_0 - sigma r_0 into w_out; partials of gamma_0 = (r, u),
 // delta_0 = (w + sigma r, u), rho_0.
-template <typename T, int OP, bool JAC, int EPT, bool NT>
+template <typename T, int OP, bool JAC, int EPT, bool NT, int SELL = 0>
 __device__ __forceinline__ void tile_init1(const PassArgs<T> &a, int tile, double (&acc)[3])
 {
     const uint32_t off_u = JAC ? a.off_u : a.off_r;
     const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
     double au[EPT], re[EPT], ue[EPT];
+    tile_apply<T, OP, EPT, SELL>(a, tile, ti, au, [&](uint32_t k) { return ld(vp<T>(a, off_u, k), 0); });
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
-        au[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return ld(vp<T>(a, off_u, k), 0); });
         re[j] = lds<NT>(vp<T>(a, a.off_r, ti.e[j]));
         ue[j] = JAC ? ld(vp<T>(a, off_u, ti.e[j]), 0) : re[j];
     }
@@ -379,7 +384,7 @@ __device__ __forceinline__ void tile_init1(const PassArgs<T> &a, int tile, doubl
 
 // head: ||b||^2 from the init-0 partials; then tile_init1 over the grid.
 // Block 0 writes the state for iteration i0.
-template <typename T, int OP, bool JAC, int EPT, bool NT>
+template <typename T, int OP, bool JAC, int EPT, bool NT, int SELL = 0>
 __global__ void __launch_bounds__(kMaxBlock) k_init1(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
@@ -396,7 +401,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_init1(PassArgs<T> a)
     }
     double acc[3] = {0.0, 0.0, 0.0};
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_init1<T, OP, JAC, EPT, NT>(a, tile, acc);
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_init1<T, OP, JAC, EPT, NT, SELL>(a, tile, acc);
     block_sum<3>(acc, lds_red);
     store_partial<3>(a.part_out, acc);
 }
@@ -626,6 +631,37 @@ __device__ __forceinline__ void sell_sorted_rows(const PassArgs<T> &a, int tile,
     for (int j = 0; j < EPT; ++j) ne[j] = xw[j * 64 + lane];
 }
 
+// One row of the in-place copy, through its 16-bit row-relative columns when
+// the copy has them (every entry within 2^15 of its row).
+template <typename T, typename F>
+__device__ __forceinline__ double sell_plain_row(const PassArgs<T> &a, uint32_t e, F v)
+{
+    if (a.sell_c16) {
+        auto rel = [&](uint32_t c) { return v(e + c - 32768u); };
+        return sell_slice<T, decltype(rel), true>(a, e >> 6, e & 63, a.A.row_ptr[e + 1] - a.A.row_ptr[e], rel);
+    }
+    return sell_row(a, e, v);
+}
+
+// (A v) at a tile's rows: from the sorted copy (SELL 2), the in-place copy
+// (SELL 1) or the operator itself (SELL 0, and every operator that is not CSR).  All three
+// give the bits of apply_row.  SELL 2 synchronises the block when the tile
+// has a column window, so every thread of the block calls it for the tile.
+template <typename T, int OP, int EPT, int SELL, typename F>
+__device__ __forceinline__ void tile_apply(const PassArgs<T> &a, int tile, const TileIdx<EPT> &ti, double (&out)[EPT],
+                                           F v)
+{
+    if constexpr (OP == OP_CSR && SELL == 2) {
+        sell_sorted_rows<T, EPT>(a, tile, out, v);
+    } else {
+#pragma unroll
+        for (int j = 0; j < EPT; ++j) {
+            if constexpr (OP == OP_CSR && SELL == 1) out[j] = sell_plain_row(a, ti.e[j], v);
+            else out[j] = apply_row<OP>(a.A, ti.e[j], v);
+        }
+    }
+}
+
 template <typename T, int OP, bool JAC, int EPT, bool NT, int XM = X_EACH, int SELL = 0>
 __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, PipeTile<EPT> &d)
 {
@@ -643,15 +679,7 @@ __device__ __forceinline__ void tile_pipe_load(const PassArgs<T> &a, int tile, P
     for (int j = 0; j < EPT; ++j) {
         const uint32_t e = ti.e[j];
         we[j] = ld(vp<T>(a, a.off_win, e), 0);
-        if constexpr (OP == OP_CSR && SELL == 1) {
-            if (a.sell_c16) {
-                // row-relative 16-bit columns (every entry within 2^15 of its row)
-                auto rel = [&](uint32_t c) { return operand(e + c - 32768u); };
-                ne[j] = sell_slice<T, decltype(rel), true>(a, e >> 6, e & 63, a.A.row_ptr[e + 1] - a.A.row_ptr[e], rel);
-            } else {
-                ne[j] = sell_row(a, e, operand);
-            }
-        }
+        if constexpr (OP == OP_CSR && SELL == 1) ne[j] = sell_plain_row(a, e, operand);
         else if constexpr (OP != OP_CSR || SELL == 0) ne[j] = apply_row<OP>(a.A, e, operand);
         re[j] = lds<NT>(vp<T>(a, a.off_r, e));
         zo[j] = lds<NT>(vp<T>(a, a.off_z, e));
@@ -1305,19 +1333,17 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_b(PassArgs<T> a)
 
 // partials of ||b - A x||^2 and ||b||^2 in binary64 (A in its storage
 // precision); x is the internal copy, or the caller's when x_plain is set.
-template <typename T, int OP, int EPT>
+template <typename T, int OP, int EPT, int SELL = 0>
 __device__ __forceinline__ void tile_resid(const PassArgs<T> &a, int tile, double (&acc)[2])
 {
     const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
     double be[EPT], ax[EPT];
+    if (a.x_plain)
+        tile_apply<T, OP, EPT, SELL>(a, tile, ti, ax, [&](uint32_t k) { return a.x_user[k]; });
+    else
+        tile_apply<T, OP, EPT, SELL>(a, tile, ti, ax, [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        be[j] = a.b[ti.e[j]];
-        if (a.x_plain)
-            ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return a.x_user[k]; });
-        else
-            ax[j] = apply_row<OP>(a.A, ti.e[j], [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
-    }
+    for (int j = 0; j < EPT; ++j) be[j] = a.b[ti.e[j]];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         if (!ti.live[j]) continue;
@@ -1327,13 +1353,13 @@ __device__ __forceinline__ void tile_resid(const PassArgs<T> &a, int tile, doubl
     }
 }
 
-template <typename T, int OP, int EPT>
+template <typename T, int OP, int EPT, int SELL = 0>
 __global__ void __launch_bounds__(kMaxBlock) k_resid(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
     double acc[2] = {0.0, 0.0};
     const TileRange tr = tile_range(a.ntiles, a.xcd_map);
-    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_resid<T, OP, EPT>(a, tile, acc);
+    for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_resid<T, OP, EPT, SELL>(a, tile, acc);
     block_sum<2>(acc, lds_red);
     store_partial<2>(a.part_out, acc);
 }

@@ -294,12 +294,14 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
     l.hist = take(size_t(o->history_cap) * PCG_HISTORY_FIELDS * 8);
     l.dinv = (op->kind == PCG_OP_CSR && jac) ? take(n * es) : SIZE_MAX;
     l.sched = o->method == PCG_PIPE_VAR_SHIFT ? take(size_t(o->sigma_schedule_len) * 8) : SIZE_MAX;
-    // the fused pass of p-CG / p-CG-sh reads a CSR operator in sliced-ELL
-    // form when its padding stays within a quarter of nnz (decided at set-up)
+    // the passes of p-CG / p-CG-sh (and of Alg. 4) read a CSR operator in
+    // sliced-ELL form when its padding stays within a quarter of nnz
+    // (decided at set-up): the fused pass, the set-up passes and the
+    // explicit residual
     l.sell_ptr = l.sell_col = l.sell_val = l.sort_ptr = l.sort_perm = l.sort_win = SIZE_MAX;
     l.sell_cap = 0;
     l.nslices = l.sort_nslices = 0;
-    if (op->kind == PCG_OP_CSR && (o->method == PCG_PIPE || o->method == PCG_PIPE_SHIFT) && sh.sell) {
+    if (op->kind == PCG_OP_CSR && sell_method(o->method) && sh.sell) {
         const int64_t cap = op->nnz + op->nnz / 4 + 4096;
         const int64_t slots = int64_t(sh.sort_ntiles) * sh.sort_block * sh.sort_ept;
         if (cap < (int64_t(1) << 31) - 64) {
@@ -370,28 +372,48 @@ struct KernelSet {
     static PassArgs<T> &A(PassArgsAny &a) { return *reinterpret_cast<PassArgs<T> *>(a.bytes); }
     static void copy_x(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_copy_x<T, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void init0_pipe(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_init0<T, OP, JAC, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void init0_cg(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_init0<T, OP, JAC, false, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void init1(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_init1<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
-    static void pipe(PassArgsAny a, int g, int b, hipStream_t s)
+    // Launches `launch` with the CSR operand form of the pass as a constant:
+    // 2 the sorted sliced-ELL copy, 1 the in-place copy, 0 the rows (and
+    // every operator that is not CSR).
+    template <typename L>
+    static void by_form(PassArgsAny &a, L launch)
     {
         if constexpr (OP == OP_CSR) {
-            if (A(a).sell_perm) {
-                hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, false, 2>), dim3(g), dim3(b), 0, s, A(a));
-                return;
-            }
-            if (A(a).sell_ptr) {
-                hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, false, 1>), dim3(g), dim3(b), 0, s, A(a));
-                return;
-            }
+            if (A(a).sell_perm) return launch(std::integral_constant<int, 2>{});
+            if (A(a).sell_ptr) return launch(std::integral_constant<int, 1>{});
         }
-        hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a));
+        launch(std::integral_constant<int, 0>{});
+    }
+    static void init0_pipe(PassArgsAny a, int g, int b, hipStream_t s)
+    {
+        by_form(a, [&](auto f) {
+            hipLaunchKernelGGL((k_init0<T, OP, JAC, JAC, EPT, NT, decltype(f)::value>), dim3(g), dim3(b), 0, s, A(a));
+        });
+    }
+    static void init0_cg(PassArgsAny a, int g, int b, hipStream_t s)
+    {
+        by_form(a, [&](auto f) {
+            hipLaunchKernelGGL((k_init0<T, OP, JAC, false, EPT, NT, decltype(f)::value>), dim3(g), dim3(b), 0, s, A(a));
+        });
+    }
+    static void init1(PassArgsAny a, int g, int b, hipStream_t s)
+    {
+        by_form(a, [&](auto f) {
+            hipLaunchKernelGGL((k_init1<T, OP, JAC, EPT, NT, decltype(f)::value>), dim3(g), dim3(b), 0, s, A(a));
+        });
+    }
+    static void pipe(PassArgsAny a, int g, int b, hipStream_t s)
+    {
+        by_form(a, [&](auto f) {
+            hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, false, decltype(f)::value>), dim3(g), dim3(b), 0, s, A(a));
+        });
     }
     static void pipe_var(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, true>), dim3(g), dim3(b), 0, s, A(a)); }
+    {
+        by_form(a, [&](auto f) {
+            hipLaunchKernelGGL((k_pipe<T, OP, JAC, EPT, NT, true, decltype(f)::value>), dim3(g), dim3(b), 0, s, A(a));
+        });
+    }
     static void pipe_rr(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_pipe_rr<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void cg_init1(PassArgsAny a, int g, int b, hipStream_t s)
@@ -411,7 +433,11 @@ struct KernelSet {
     static void cg_b(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_cg_b<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void resid(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_resid<T, OP, EPT>), dim3(g), dim3(b), 0, s, A(a)); }
+    {
+        by_form(a, [&](auto f) {
+            hipLaunchKernelGGL((k_resid<T, OP, EPT, decltype(f)::value>), dim3(g), dim3(b), 0, s, A(a));
+        });
+    }
     static void x_fixup(PassArgsAny a, double alpha, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_x_fixup<T, JAC, EPT>), dim3(g), dim3(b), 0, s, A(a), alpha); }
     static Kernels table()

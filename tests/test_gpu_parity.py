@@ -938,3 +938,58 @@ def test_csr_sorted_sliced_ell_gives_the_csr_bits(torch, shape, fp32):
         assert a["iterations"] == b["iterations"]
         np.testing.assert_array_equal(a["res"], b["res"])
         np.testing.assert_array_equal(a["x"], b["x"])
+
+
+@pytest.mark.parametrize("fp32", [False, True])
+@pytest.mark.parametrize("form", ["sell", "sell_sorted"])
+def test_csr_copies_serve_every_pass(torch, form, fp32):
+    """The set-up passes (r_0 = b - A x_0, w_0 = A u_0), the explicit
+    residual and the fused pass of p-CG with a shift schedule (Alg. 4) read
+    the sliced-ELL copy too, each row summed in CSR order: a p-CG-sh solve
+    with the explicit-residual check at convergence (a restart from x when it
+    misses the tolerance), an Alg. 4 solve and the explicit residual of a
+    caller's x give the same bits as on the CSR arrays, from a nonzero x_0."""
+    from paper_1706_05988_amd import pcg as P
+    flag, ept_flag, shape = ((P.PCG_VAR_CSR_SELL, P.PCG_VAR_EPT1, (256, 1)) if form == "sell"
+                             else (P.PCG_VAR_CSR_SELL_SORTED, P.PCG_VAR_EPT4, (256, 4)))
+    runs = [("pipe_shift", dict(sigma=1.0, true_residual_check=True, rtol=1e-9, max_iter=400)),
+            ("pipe_var", dict(sigma=1.0, sigma_schedule=[1.0, 0.5, 1.0], rtol=1e-30, max_iter=120,
+                              true_residual_check=False))]
+    # the in-place copy needs rows of even length (padding within a quarter);
+    # the sorted copy takes the banded random rows of 4 to 40 entries
+    A = problems.to_scipy(problems.stencil3d(20, 17, 13)).tocsr()
+    A.sort_indices()
+    op3 = problems.csr_operator(A.indptr, A.indices, A.data)
+    xt = np.random.default_rng(8).uniform(-1, 1, op3.n)
+    p3 = problems.Problem("lapl3d_csr", op3, A @ xt, np.zeros(op3.n), xt, jacobi=True, sigma=1.0)
+    first = p3 if form == "sell" else problems.banded_csr(20011, seed=5)
+    for p in (first, problems.anisotropic_csr(90, seed=4)):
+        x0 = np.random.default_rng(13).uniform(-1, 1, p.op.n)
+        xu = torch.from_numpy(np.random.default_rng(14).uniform(-1, 1, p.op.n)).cuda()
+        b = torch.from_numpy(p.b).cuda()
+        for method, kw in runs:
+            out = []
+            for var in (0, flag):
+                mi = kw["max_iter"]
+                opt = P.make_options(method=method, jacobi=True, fp32=fp32, history_cap=mi + 2,
+                                     variant=P.PCG_VAR_SET | P.PCG_VAR_NT | ept_flag | var,
+                                     block_size=shape[0], grid_blocks=48, **kw)
+                s = P.Solver(p.op, opt)
+                x = torch.from_numpy(x0).clone().cuda()
+                r = s.solve(b, x)
+                r["x"] = x.cpu().numpy()
+                r["info"] = s.info()
+                r["user_res"] = s.true_residual(b, xu)
+                torch.cuda.synchronize()
+                s.close()
+                out.append(r)
+            a, c = out
+            print(f"[csr-copies] {p.name} {method} {form} fp32={fp32}: {a['status']} {a['iterations']} it, "
+                  f"{a['replacements']} restarts", flush=True)
+            assert a["info"]["csr_form_name"] == "csr" and c["info"]["csr_form_name"] == form, (p.name, method)
+            assert (c["info"]["block"], c["info"]["ept"]) == shape
+            assert a["iterations"] == c["iterations"] and a["status"] == c["status"]
+            assert a["replacements"] == c["replacements"]
+            np.testing.assert_array_equal(a["res"], c["res"])
+            np.testing.assert_array_equal(a["x"], c["x"])
+            assert a["rel_res_true"] == c["rel_res_true"] and a["user_res"] == c["user_res"]
