@@ -33,9 +33,10 @@ struct LaunchShape {
     // fits): bit 0 rows in place, bit 1 rows sorted by length within each
     // wave's rows; with both, set-up keeps the smaller copy.  The sorted copy
     // is laid out for the shape sort_*, which replaces the shape above when
-    // that copy is the one kept.
+    // that copy is the one kept.  sort_grid_v32 is the sorted copy's grid
+    // when it stores binary64 values as binary32 (known after set-up).
     int sell;
-    int sort_block, sort_ept, sort_ntiles, sort_grid;
+    int sort_block, sort_ept, sort_ntiles, sort_grid, sort_grid_v32;
 };
 
 // byte offsets into the caller's workspace (SIZE_MAX: absent)

@@ -207,18 +207,24 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
     tiles_grid(s.block, s.ept, blocks_per_cu, &s.ntiles, &s.grid);
     // the sorted copy sorts within a wave's rows of a tile, so it takes 4
     // rows per thread unless the shape is given (measured with the column
-    // windows on banded random operators of 1e6 and 4e6 rows of 4 to 40
-    // entries, us per pass): binary64 four blocks of 128 per CU (73.7 /
-    // 274.0, two of 256: 73.1 / 283.6); FP32-stream blocks of 256, two per
-    // CU up to 2^21 rows (51.9 against 54.7 for three), three beyond (174.8
-    // against 198.3 at 4e6; four blocks of 128: 52.3 / 194.6)
+    // windows and 16-bit window offsets on banded random operators of 1e6
+    // and 4e6 rows of 4 to 40 entries, us per pass): binary64 four blocks of
+    // 128 per CU (binary64 values: 67.7 / 249.7, two of 256: 67.3 / 261.1,
+    // six of 128: 75.6 / 285.1), and six beyond 2^21 rows when the values
+    // are stored as binary32 (61.0 / 218.9 for four, 65.4 / 197.8 for six);
+    // FP32-stream blocks of 256, two per CU up to 2^21 rows (48.5 against
+    // 49.8 for three), three beyond (154.3 against 185.4 at 4e6; four blocks
+    // of 128: 48.8 / 182.9)
     s.sort_block = s.block, s.sort_ept = s.ept, s.sort_ntiles = s.ntiles, s.sort_grid = s.grid;
+    s.sort_grid_v32 = s.grid;
     if (!set && op->kind == PCG_OP_CSR) {
-        const bool fp64 = o->prec == PCG_FP64;
+        const bool fp64 = o->prec == PCG_FP64, large = op->n > (int64_t(1) << 21);
         s.sort_block = o->block_size ? o->block_size : fp64 ? 128 : 256;
         s.sort_ept = 4;
-        const int per_cu = fp64 ? 4 : op->n <= (int64_t(1) << 21) ? 2 : 3;
+        const int per_cu = fp64 ? 4 : large ? 3 : 2;
         tiles_grid(s.sort_block, s.sort_ept, per_cu, &s.sort_ntiles, &s.sort_grid);
+        s.sort_grid_v32 = s.sort_grid;
+        if (fp64 && large) tiles_grid(s.sort_block, s.sort_ept, 6, &s.sort_ntiles, &s.sort_grid_v32);
     }
     const bool want_xcd = set && (var & PCG_VAR_XCD_MAP) != 0;
     s.xcd_map = (want_xcd && s.grid >= 64 && (s.grid % 8) == 0) ? 1 : 0;
@@ -284,9 +290,9 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
     };
     Layout l{};
     l.state = take(2 * sizeof(DevState) + 128);
-    // partials for the larger of the two grids (a sorted sliced-ELL copy
-    // brings its own shape)
-    const size_t parts = size_t(std::max(sh.grid, sh.sort_grid)) * kFields * 8;
+    // partials for the largest grid the passes may take (a sorted
+    // sliced-ELL copy brings its own shape)
+    const size_t parts = size_t(std::max({sh.grid, sh.sort_grid, sh.sort_grid_v32})) * kFields * 8;
     l.part[0] = take(parts);
     l.part[1] = take(parts);
     l.gersh = take(size_t(kGershBlocks) * 2 * 8);
@@ -920,11 +926,12 @@ static pcg_status init_solver(pcg_solver_ *s, const pcg_operator *op, const pcg_
         if ((st = sell_setup(op, opt->prec, sh, L, s->ws, s->stream, &s->sell, &s->sell_entries, &s->sell_col_bits,
                              &s->sell_val_bits)))
             return st;
-        if (s->sell == 2 && (sh.sort_ept != sh.ept || sh.sort_block != sh.block || sh.sort_grid != sh.grid)) {
-            // the sorted copy is laid out for its own shape: the passes take
-            // it, and its grid
+        // the sorted copy is laid out for its own shape: the passes take it,
+        // and its grid
+        const int sort_grid = opt->prec == PCG_FP64 && s->sell_val_bits == 32 ? sh.sort_grid_v32 : sh.sort_grid;
+        if (s->sell == 2 && (sh.sort_ept != sh.ept || sh.sort_block != sh.block || sort_grid != sh.grid)) {
             s->sh.ept = sh.sort_ept, s->sh.block = sh.sort_block;
-            s->sh.ntiles = sh.sort_ntiles, s->sh.grid = sh.sort_grid;
+            s->sh.ntiles = sh.sort_ntiles, s->sh.grid = sort_grid;
             s->kern = pick(opt->prec, op->kind, opt->pc == PCG_PC_JACOBI, s->sh.ept, s->sh.nt != 0);
         }
     }
