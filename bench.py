@@ -816,13 +816,17 @@ def report_csr_shapes(P, torch, sizes=(1024, 2048), passes: int = 200) -> dict:
     return out
 
 
-def report_csr_banded(P, torch, sizes=(10 ** 6, 4 * 10 ** 6), passes: int = 200) -> dict:
+SORTED_SHAPES = ((128, 2), (128, 4), (128, 6), (128, 8), (256, 2), (256, 3), (256, 4))
+
+
+def report_csr_banded(P, torch, sizes=(10 ** 6, 4 * 10 ** 6), passes: int = 200,
+                      sorted_shapes=SORTED_SHAPES) -> dict:
     """The fused CSR pass on banded random operators (rows of 4 to 40
     entries, the serving mix's CSR half), Jacobi, p-CG-sh sigma = 1, both
     storage forms: the built-in choice, CSR rows at their best shape, and
-    the sorted sliced-ELL copy at 4 rows per thread x 128 / 256 threads x 2,
-    4 or 6 / 2, 3 blocks per CU; microseconds per pass over `passes` passes
-    (HIP events) with the form, shape and copy size the solver reports."""
+    the sorted sliced-ELL copy at 4 rows per thread x (threads, blocks per
+    CU) of `sorted_shapes`; microseconds per pass over `passes` passes (HIP
+    events) with the form, shape and copy size the solver reports."""
     import problems
     out = {"workload": f"banded random CSR (rows 4..40 entries), Jacobi, p-CG-sh sigma = 1, {passes} passes",
            "runs": []}
@@ -839,7 +843,7 @@ def report_csr_banded(P, torch, sizes=(10 ** 6, 4 * 10 ** 6), passes: int = 200)
                                                       block_size=256, grid_blocks=1024)))
             shapes.append(("csr ept2 b256 x2/CU", dict(variant=P.PCG_VAR_SET | P.PCG_VAR_NT, block_size=256,
                                                       grid_blocks=512)))
-            for block, per_cu in ((128, 2), (128, 4), (128, 6), (256, 2), (256, 3)):
+            for block, per_cu in sorted_shapes:
                 shapes.append((f"sorted ept4 b{block} x{per_cu}/CU",
                                dict(variant=P.PCG_VAR_SET | P.PCG_VAR_NT | P.PCG_VAR_EPT4 | P.PCG_VAR_CSR_SELL_SORTED,
                                     block_size=block, grid_blocks=per_cu * 256)))

@@ -207,18 +207,19 @@ LaunchShape choose_shape(const pcg_operator *op, const pcg_options *o)
     tiles_grid(s.block, s.ept, blocks_per_cu, &s.ntiles, &s.grid);
     // the sorted copy sorts within a wave's rows of a tile, so it takes 4
     // rows per thread unless the shape is given (measured with the column
-    // windows and 16-bit window offsets on banded random operators of 1e6
-    // and 4e6 rows of 4 to 40 entries, us per pass): binary64 four blocks of
-    // 128 per CU (binary64 values: 67.7 / 249.7, two of 256: 67.3 / 261.1,
-    // six of 128: 75.6 / 285.1), and six beyond 2^21 rows when the values
-    // are stored as binary32 (61.0 / 218.9 for four, 65.4 / 197.8 for six);
-    // FP32-stream blocks of 256, two per CU up to 2^21 rows (48.5 against
-    // 49.8 for three), three beyond (154.3 against 185.4 at 4e6; four blocks
-    // of 128: 48.8 / 182.9)
+    // windows and 16-bit window offsets on banded random operators of 1e6,
+    // 2e6, 4e6 and 1e7 rows of 4 to 40 entries, us per pass): binary64 four
+    // blocks of 128 per CU (binary64 values at 1e6 / 4e6: 67.7 / 249.7, two
+    // of 256: 67.3 / 261.1, six of 128: 75.6 / 285.1), and six beyond 1.5e6
+    // rows when the values are stored as binary32 (four: 61.0 / 105.6 /
+    // 218.9 / 512.0, six: 65.4 / 97.3 / 197.8 / 475.6, eight: 117.6 at 2e6);
+    // FP32-stream blocks of 256, two per CU up to 1.5e6 rows (48.5 against
+    // 49.8 for three at 1e6), three beyond (72.4 / 154.3 / 369.5 against
+    // 83.0 / 185.4 / 437.0 for two, 89.3 at 2e6 for four)
     s.sort_block = s.block, s.sort_ept = s.ept, s.sort_ntiles = s.ntiles, s.sort_grid = s.grid;
     s.sort_grid_v32 = s.grid;
     if (!set && op->kind == PCG_OP_CSR) {
-        const bool fp64 = o->prec == PCG_FP64, large = op->n > (int64_t(1) << 21);
+        const bool fp64 = o->prec == PCG_FP64, large = op->n > 1500000;
         s.sort_block = o->block_size ? o->block_size : fp64 ? 128 : 256;
         s.sort_ept = 4;
         const int per_cu = fp64 ? 4 : large ? 3 : 2;

@@ -311,16 +311,16 @@ def test_tiny_grids(torch, method, shape):
 
 
 @pytest.mark.parametrize("fp32", [False, True])
-@pytest.mark.parametrize("n", [10 ** 6, 4 * 10 ** 6])
+@pytest.mark.parametrize("n", [10 ** 6, 2 * 10 ** 6])
 def test_builtin_sorted_copy_takes_its_shape(torch, n, fp32):
-    """Banded operators of 1e6 and 4e6 rows: set-up keeps the sorted copy and
+    """Banded operators of 1e6 and 2e6 rows: set-up keeps the sorted copy and
     the passes run at that copy's built-in shape and grid: binary64 blocks of
-    128, four per CU, six beyond 2^21 rows when the values are stored as
+    128, four per CU, six beyond 1.5e6 rows when the values are stored as
     binary32 (four with binary64 values); FP32-stream blocks of 256, two per
-    CU up to 2^21 rows, three beyond."""
+    CU up to 1.5e6 rows, three beyond."""
     p = problems.banded_csr(n, seed=2)
     cases = [(p, 32)]
-    if not fp32 and n > 2 ** 21:
+    if not fp32 and n > 1500000:
         # the same pattern with values that are not binary32 numbers
         op = problems.csr_operator(p.op.row_ptr, p.op.col, p.op.val / 3.0)
         cases.append((problems.Problem("banded_thirds", op, p.b / 3.0, p.x0, p.x_true, jacobi=True, sigma=1.0), 64))
@@ -331,9 +331,9 @@ def test_builtin_sorted_copy_takes_its_shape(torch, n, fp32):
         assert info["csr_form_name"] == "sell_sorted" and info["csr_col_bits"] == 16
         assert info["csr_val_bits"] == (32 if fp32 else vbits)
         if fp32:
-            block, per_cu = 256, (2 if n <= 2 ** 21 else 3)
+            block, per_cu = 256, (2 if n <= 1500000 else 3)
         else:
-            block, per_cu = 128, (6 if n > 2 ** 21 and vbits == 32 else 4)
+            block, per_cu = 128, (6 if n > 1500000 and vbits == 32 else 4)
         assert (info["block"], info["ept"]) == (block, 4)
         assert info["ntiles"] == -(-q.op.n // (block * 4))
         assert info["grid"] == min(per_cu * 256, info["ntiles"] & ~7), (q.name, info)
