@@ -181,12 +181,12 @@ typedef struct {
 #define PCG_VAR_CG_ZMARCH 0x40  /* PCG_CG, 3-D stencil: pass A marches along z through
                                    LDS also where the built-in rule would not (grids
                                    with fewer work items than CUs)                      */
-#define PCG_VAR_CSR_SELL 0x80   /* CSR, PCG_PIPE / PCG_PIPE_SHIFT / PCG_PIPE_VAR_SHIFT:
-                                   the passes (fused iteration, set-up, explicit
-                                   residual) read a sliced-ELL copy of the operator
-                                   (64-row slices, built at pcg_create when its padding
-                                   stays within a quarter of nnz; the same sums in the
-                                   same order)                                          */
+#define PCG_VAR_CSR_SELL 0x80   /* CSR: the passes of every method (iteration, set-up,
+                                   explicit residual; not the |A||x| rounding scale of
+                                   PCG_PIPE_RR's gap check) read a sliced-ELL copy of
+                                   the operator (64-row slices, built at pcg_create
+                                   when its padding stays within a quarter of nnz; the
+                                   same sums in the same order)                         */
 #define PCG_VAR_CSR_SELL_SORTED 0x100 /* as PCG_VAR_CSR_SELL, with the rows sorted by
                                    length (longest first) within each wave's rows of a
                                    tile (SELL-C-sigma, C = 64) so that rows of mixed
@@ -307,8 +307,8 @@ pcg_status pcg_solve_static(const pcg_operator *op, const pcg_options *opt, cons
  * bandwidth, and how many unknowns each thread handles (1, 2 or 4), the
  * block size (128 or 256) and the number of resident blocks per CU (1, 2 or
  * 4; 8 for 128-thread blocks) decide how many independent loads are in
- * flight; for a CSR operator of PCG_PIPE / PCG_PIPE_SHIFT each shape is
- * also tried on the sliced-ELL copies (PCG_VAR_CSR_SELL, and with 2 or 4
+ * flight; for a CSR operator each shape is also tried on the sliced-ELL
+ * copies (PCG_VAR_CSR_SELL, and with 2 or 4
  * unknowns per thread PCG_VAR_CSR_SELL_SORTED).  The best choice
  * depends on the operator, the method, the preconditioner and the storage
  * form.  pcg_tune measures every candidate (and the library's built-in

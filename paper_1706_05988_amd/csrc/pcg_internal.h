@@ -99,13 +99,6 @@ double default_sigma(const pcg_operator *op, const pcg_options *opt, const doubl
 pcg_status csr_gershgorin(const pcg_operator *op, int prec, int jac, double *scratch_dev, hipStream_t stream,
                           double *lo, double *hi);
 
-// The methods whose passes read a sliced-ELL copy of a CSR operator: the
-// pipelined ones with one fused pass per iteration (Algs. 2 to 4).
-inline bool sell_method(int method)
-{
-    return method == PCG_PIPE || method == PCG_PIPE_SHIFT || method == PCG_PIPE_VAR_SHIFT;
-}
-
 // Where the sliced-ELL copies of a CSR operator go (device memory; nullptr /
 // 0 for a form not reserved): the in-place form's nslices + 1 slice offsets,
 // the sorted form's sort_nslices + 1 offsets and per-slot words (laid out for

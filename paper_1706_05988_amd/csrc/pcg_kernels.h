@@ -859,19 +859,16 @@ __device__ __forceinline__ void tile_gap(const PassArgs<T> &a, int tile, double 
 
 // Replacement, first pass: r := b - A x, u := M^-1 r, s := A p, q := M^-1 s
 // (p = p_{i-1}; the method runs without shift).
-template <typename T, int OP, bool JAC, int EPT>
+template <typename T, int OP, bool JAC, int EPT, int SELL = 0>
 __device__ __forceinline__ void tile_rr1(const PassArgs<T> &a, int tile)
 {
     const uint32_t off_p = JAC ? a.off_p : a.off_t;
     const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
     double be[EPT], ax[EPT], ap[EPT];
+    tile_apply<T, OP, EPT, SELL>(a, tile, ti, ax, [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
+    tile_apply<T, OP, EPT, SELL>(a, tile, ti, ap, [&](uint32_t k) { return ld(vp<T>(a, off_p, k), 0); });
 #pragma unroll
-    for (int j = 0; j < EPT; ++j) {
-        const uint32_t e = ti.e[j];
-        be[j] = a.b[e];
-        ax[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
-        ap[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return ld(vp<T>(a, off_p, k), 0); });
-    }
+    for (int j = 0; j < EPT; ++j) be[j] = a.b[ti.e[j]];
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         if (!ti.live[j]) continue;
@@ -889,18 +886,18 @@ __device__ __forceinline__ void tile_rr1(const PassArgs<T> &a, int tile)
 
 // Replacement, second pass: w := A u, z := A q (neighbours written by the
 // first pass); partials of gamma_i, delta_i, rho_i from the reset vectors.
-template <typename T, int OP, bool JAC, int EPT>
+template <typename T, int OP, bool JAC, int EPT, int SELL = 0>
 __device__ __forceinline__ void tile_rr2(const PassArgs<T> &a, uint32_t off_wout, int tile, double (&acc)[3])
 {
     const uint32_t off_u = JAC ? a.off_u : a.off_r;
     const uint32_t off_q = JAC ? a.off_q : a.off_s;
     const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
     double au[EPT], aq[EPT], re[EPT], ue[EPT];
+    tile_apply<T, OP, EPT, SELL>(a, tile, ti, au, [&](uint32_t k) { return ld(vp<T>(a, off_u, k), 0); });
+    tile_apply<T, OP, EPT, SELL>(a, tile, ti, aq, [&](uint32_t k) { return ld(vp<T>(a, off_q, k), 0); });
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const uint32_t e = ti.e[j];
-        au[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return ld(vp<T>(a, off_u, k), 0); });
-        aq[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return ld(vp<T>(a, off_q, k), 0); });
         re[j] = ld(vp<T>(a, a.off_r, e), 0);
         ue[j] = JAC ? ld(vp<T>(a, off_u, e), 0) : re[j];
     }
@@ -926,8 +923,9 @@ __device__ __forceinline__ void tile_rr2(const PassArgs<T> &a, uint32_t off_wout
 //   CHECK phase (after a gap pass): if ||f|| > tau ||r|| and ||f|| > floor,
 //     the pass does replacement step 1, else it iterates;
 //   RR2 phase: replacement step 2, whose partials restart iteration i.
-// Passes that leave w alone flip `wflip`, so w_i is always found.
-template <typename T, int OP, bool JAC, int EPT, bool NT>
+// Passes that leave w alone flip `wflip`, so w_i is always found.  A CSR
+// operator is read in the form SELL names, except by the gap pass (|A| |x|).
+template <typename T, int OP, bool JAC, int EPT, bool NT, int SELL = 0>
 __global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
 {
     enum { ROLE_ITER, ROLE_GAP, ROLE_RR1, ROLE_RR2, ROLE_STOP };
@@ -1025,13 +1023,15 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
         sc.beta = beta;
         sc.sigma = 0.0;
         sc.dsig = 0.0;
-        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_pipe<T, OP, JAC, EPT, NT>(w, tile, sc, acc);
+        for (int tile = tr.first; tile < tr.end; tile += tr.step)
+            tile_pipe<T, OP, JAC, EPT, NT, false, X_EACH, SELL>(w, tile, sc, acc);
     } else if (role == ROLE_GAP) {
         for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_gap<T, OP, EPT>(a, tile, acc);
     } else if (role == ROLE_RR1) {
-        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_rr1<T, OP, JAC, EPT>(a, tile);
+        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_rr1<T, OP, JAC, EPT, SELL>(a, tile);
     } else {
-        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_rr2<T, OP, JAC, EPT>(a, w.off_wout, tile, acc);
+        for (int tile = tr.first; tile < tr.end; tile += tr.step)
+            tile_rr2<T, OP, JAC, EPT, SELL>(a, w.off_wout, tile, acc);
     }
     block_sum<3>(acc, lds_red);
     store_partial<3>(a.part_out, acc);
@@ -1130,8 +1130,9 @@ __device__ __forceinline__ double cg_pnew(const PassArgs<T> &a, uint32_t k, doub
     return cg_pnew_of<T, JAC, OP>(a, k, ld(vp<T>(a, a.off_r, k), 0), ld(vp<T>(a, a.off_win, k), 0), beta);
 }
 
-// Pass A of CG iteration i.  w_in = p_{i-1}, w_out = p_i.
-template <typename T, int OP, bool JAC, int EPT, bool NT>
+// Pass A of CG iteration i.  w_in = p_{i-1}, w_out = p_i; a CSR operator
+// from the form SELL names (tile_apply).
+template <typename T, int OP, bool JAC, int EPT, bool NT, int SELL = 0>
 __global__ void __launch_bounds__(kMaxBlock) k_cg_a(PassArgs<T> a)
 {
     __shared__ double lds_red[kMaxWaves * kFields];
@@ -1146,11 +1147,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_cg_a(PassArgs<T> a)
     for (int tile = tr.first; tile < tr.end; tile += tr.step) {
         const TileIdx<EPT> ti = tile_idx<EPT>(tile, n);
         double pe[EPT], se[EPT];
+        tile_apply<T, OP, EPT, SELL>(a, tile, ti, se, pnew);
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) {
-            pe[j] = pnew(ti.e[j]);
-            se[j] = apply_row<OP>(a.A, ti.e[j], pnew);
-        }
+        for (int j = 0; j < EPT; ++j) pe[j] = pnew(ti.e[j]);
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
             if (!ti.live[j]) continue;

@@ -301,14 +301,12 @@ size_t layout(const pcg_operator *op, const pcg_options *o, const LaunchShape &s
     l.hist = take(size_t(o->history_cap) * PCG_HISTORY_FIELDS * 8);
     l.dinv = (op->kind == PCG_OP_CSR && jac) ? take(n * es) : SIZE_MAX;
     l.sched = o->method == PCG_PIPE_VAR_SHIFT ? take(size_t(o->sigma_schedule_len) * 8) : SIZE_MAX;
-    // the passes of p-CG / p-CG-sh (and of Alg. 4) read a CSR operator in
-    // sliced-ELL form when its padding stays within a quarter of nnz
-    // (decided at set-up): the fused pass, the set-up passes and the
-    // explicit residual
+    // the passes read a CSR operator in sliced-ELL form when its padding
+    // stays within a quarter of nnz (decided at set-up)
     l.sell_ptr = l.sell_col = l.sell_val = l.sort_ptr = l.sort_perm = l.sort_win = SIZE_MAX;
     l.sell_cap = 0;
     l.nslices = l.sort_nslices = 0;
-    if (op->kind == PCG_OP_CSR && sell_method(o->method) && sh.sell) {
+    if (op->kind == PCG_OP_CSR && sh.sell) {
         const int64_t cap = op->nnz + op->nnz / 4 + 4096;
         const int64_t slots = int64_t(sh.sort_ntiles) * sh.sort_block * sh.sort_ept;
         if (cap < (int64_t(1) << 31) - 64) {
@@ -422,7 +420,11 @@ struct KernelSet {
         });
     }
     static void pipe_rr(PassArgsAny a, int g, int b, hipStream_t s)
-    { hipLaunchKernelGGL((k_pipe_rr<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
+    {
+        by_form(a, [&](auto f) {
+            hipLaunchKernelGGL((k_pipe_rr<T, OP, JAC, EPT, NT, decltype(f)::value>), dim3(g), dim3(b), 0, s, A(a));
+        });
+    }
     static void cg_init1(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_cg_init1<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }
     static void cg_a(PassArgsAny a, int g, int b, hipStream_t s)
@@ -435,7 +437,9 @@ struct KernelSet {
                 return;
             }
         }
-        hipLaunchKernelGGL((k_cg_a<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a));
+        by_form(a, [&](auto f) {
+            hipLaunchKernelGGL((k_cg_a<T, OP, JAC, EPT, NT, decltype(f)::value>), dim3(g), dim3(b), 0, s, A(a));
+        });
     }
     static void cg_b(PassArgsAny a, int g, int b, hipStream_t s)
     { hipLaunchKernelGGL((k_cg_b<T, OP, JAC, EPT, NT>), dim3(g), dim3(b), 0, s, A(a)); }

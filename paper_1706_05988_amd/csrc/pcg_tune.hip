@@ -16,7 +16,6 @@
 #include <vector>
 
 #include "pcg.h"
-#include "pcg_internal.h"
 
 namespace pcg {
 pcg_status invalid(const char *why);  // records the message for pcg_last_error
@@ -44,7 +43,7 @@ std::vector<Shape> candidates(const pcg_operator *op, const pcg_options *o)
     std::vector<Shape> c;
     c.push_back({0, 0, 0});
     const int ept_bits[3] = {PCG_VAR_EPT1, 0, PCG_VAR_EPT4};
-    const bool sell = op->kind == PCG_OP_CSR && pcg::sell_method(o->method);
+    const bool sell = op->kind == PCG_OP_CSR;
     for (int sb : {0, PCG_VAR_CSR_SELL, PCG_VAR_CSR_SELL_SORTED}) {
         if (sb && !sell) continue;
         for (int eb : ept_bits) {

@@ -956,17 +956,22 @@ def test_csr_sorted_sliced_ell_gives_the_csr_bits(torch, shape, fp32):
 @pytest.mark.parametrize("form", ["sell", "sell_sorted"])
 def test_csr_copies_serve_every_pass(torch, form, fp32):
     """The set-up passes (r_0 = b - A x_0, w_0 = A u_0), the explicit
-    residual and the fused pass of p-CG with a shift schedule (Alg. 4) read
-    the sliced-ELL copy too, each row summed in CSR order: a p-CG-sh solve
-    with the explicit-residual check at convergence (a restart from x when it
-    misses the tolerance), an Alg. 4 solve and the explicit residual of a
-    caller's x give the same bits as on the CSR arrays, from a nonzero x_0."""
+    residual and the passes of every method read the sliced-ELL copy too,
+    each row summed in CSR order: a p-CG-sh solve with the explicit-residual
+    check at convergence (a restart from x when it misses the tolerance), an
+    Alg. 4 solve, a CG solve, a p-CG-rr solve with residual replacements
+    and the explicit residual of a caller's x give the same bits as on the
+    CSR arrays, from a nonzero x_0."""
     from paper_1706_05988_amd import pcg as P
     flag, ept_flag, shape = ((P.PCG_VAR_CSR_SELL, P.PCG_VAR_EPT1, (256, 1)) if form == "sell"
                              else (P.PCG_VAR_CSR_SELL_SORTED, P.PCG_VAR_EPT4, (256, 4)))
     runs = [("pipe_shift", dict(sigma=1.0, true_residual_check=True, rtol=1e-9, max_iter=400)),
             ("pipe_var", dict(sigma=1.0, sigma_schedule=[1.0, 0.5, 1.0], rtol=1e-30, max_iter=120,
-                              true_residual_check=False))]
+                              true_residual_check=False)),
+            ("cg", dict(sigma=0.0, rtol=1e-30, max_iter=120, true_residual_check=False)),
+            # thresholds that let every gap check (each 8 iterations) replace
+            ("pipe_rr", dict(sigma=0.0, rtol=1e-30, max_iter=120, true_residual_check=False, rr_period=8,
+                             rr_tau=1e-300, rr_floor=1e-300))]
     # the in-place copy needs rows of even length (padding within a quarter);
     # the sorted copy takes the banded random rows of 4 to 40 entries
     A = problems.to_scipy(problems.stencil3d(20, 17, 13)).tocsr()
@@ -1005,3 +1010,5 @@ def test_csr_copies_serve_every_pass(torch, form, fp32):
             np.testing.assert_array_equal(a["res"], c["res"])
             np.testing.assert_array_equal(a["x"], c["x"])
             assert a["rel_res_true"] == c["rel_res_true"] and a["user_res"] == c["user_res"]
+            if method == "pipe_rr":
+                assert a["replacements"] > 0
