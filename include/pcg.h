@@ -182,11 +182,11 @@ typedef struct {
                                    LDS also where the built-in rule would not (grids
                                    with fewer work items than CUs)                      */
 #define PCG_VAR_CSR_SELL 0x80   /* CSR: the passes of every method (iteration, set-up,
-                                   explicit residual; not the |A||x| rounding scale of
-                                   PCG_PIPE_RR's gap check) read a sliced-ELL copy of
-                                   the operator (64-row slices, built at pcg_create
-                                   when its padding stays within a quarter of nnz; the
-                                   same sums in the same order)                         */
+                                   explicit residual, PCG_PIPE_RR's gap check and
+                                   replacement) read a sliced-ELL copy of the operator
+                                   (64-row slices, built at pcg_create when its padding
+                                   stays within a quarter of nnz; the same sums in the
+                                   same order)                                          */
 #define PCG_VAR_CSR_SELL_SORTED 0x100 /* as PCG_VAR_CSR_SELL, with the rows sorted by
                                    length (longest first) within each wave's rows of a
                                    tile (SELL-C-sigma, C = 64) so that rows of mixed

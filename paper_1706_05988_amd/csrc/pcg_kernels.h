@@ -307,9 +307,9 @@ __global__ void __launch_bounds__(kMaxBlock) k_copy_x(PassArgs<T> a)
     for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_copy_x<T, EPT>(a, tile);
 }
 
-// (A v) at a tile's rows in the form SELL names (defined with the sliced-ELL
-// copies below).
-template <typename T, int OP, int EPT, int SELL, typename F>
+// (A v) at a tile's rows in the form SELL names, (|A| v) with ABS (defined
+// with the sliced-ELL copies below).
+template <typename T, int OP, int EPT, int SELL, bool ABS = false, typename F>
 __device__ __forceinline__ void tile_apply(const PassArgs<T> &a, int tile, const TileIdx<EPT> &ti, double (&out)[EPT],
                                            F v);
 
@@ -442,9 +442,7 @@ struct PipeTile {
 // for one load instead of two.  Entries are summed in the row's CSR storage
 // order and padding is skipped by the row's length, so (A v)_e has the bits
 // of apply_row.
-// One row's product from slice s of a sliced-ELL copy: the row sits in
-// lane `lane` of the slice and has len entries (the rest of the slice's
-// width is padding, skipped).
+//
 // The columns and values of entries k .. k + kCsrChunk - 1 of the slice at
 // p0 (width w) in lane `lane`; indices past the width repeat entry k.  C16:
 // 16-bit columns (sell_c16); binary32-stored values widen exactly.
@@ -475,8 +473,11 @@ __device__ __forceinline__ void sell_load_chunk(const PassArgs<T> &a, int32_t p0
     }
 }
 
-// C16: the columns are 16-bit offsets (sell_c16), v takes those.
-template <typename T, typename F, bool C16 = false>
+// One row's product from slice s of a sliced-ELL copy: the row sits in
+// lane `lane` of the slice and has len entries (the rest of the slice's
+// width is padding, skipped).  C16: the columns are 16-bit offsets
+// (sell_c16), v takes those.  ABS: |a_ij| in place of a_ij (as apply_row).
+template <typename T, typename F, bool C16 = false, bool ABS = false>
 __device__ __forceinline__ double sell_slice(const PassArgs<T> &a, uint32_t s, uint32_t lane, int32_t len, F v)
 {
     const int32_t p0 = a.sell_ptr[s], w = (a.sell_ptr[s + 1] - p0) >> 6;
@@ -490,15 +491,15 @@ __device__ __forceinline__ double sell_slice(const PassArgs<T> &a, uint32_t s, u
         for (int u = 0; u < kCsrChunk; ++u) g[u] = v((uint32_t)c[u]);
 #pragma unroll
         for (int u = 0; u < kCsrChunk; ++u)
-            if (k + u < len) acc += (double)wv[u] * g[u];
+            if (k + u < len) acc += (ABS ? fabs((double)wv[u]) : (double)wv[u]) * g[u];
     }
     return acc;
 }
 
-template <typename T, typename F>
+template <typename T, typename F, bool ABS = false>
 __device__ __forceinline__ double sell_row(const PassArgs<T> &a, uint32_t e, F v)
 {
-    return sell_slice(a, e >> 6, e & 63, a.A.row_ptr[e + 1] - a.A.row_ptr[e], v);
+    return sell_slice<T, F, false, ABS>(a, e >> 6, e & 63, a.A.row_ptr[e + 1] - a.A.row_ptr[e], v);
 }
 
 // The sorted sliced-ELL form (SELL-C-sigma of Kreutzer et al., SIAM J. Sci.
@@ -522,7 +523,7 @@ __device__ __forceinline__ double *sell_exchange_lds()
 // Two slices of one wave at once (s0 the wider, as sorted): their chunks'
 // loads go out together while both have entries left, the second slice's
 // part skipped (a wave-uniform branch) once it has none.
-template <typename T, typename F, bool C16 = false>
+template <typename T, typename F, bool C16 = false, bool ABS = false>
 __device__ __forceinline__ void sell_slice_pair(const PassArgs<T> &a, uint32_t s0, uint32_t lane, int32_t len0,
                                                 int32_t len1, F v, double &out0, double &out1)
 {
@@ -544,11 +545,11 @@ __device__ __forceinline__ void sell_slice_pair(const PassArgs<T> &a, uint32_t s
         }
 #pragma unroll
         for (int u = 0; u < kCsrChunk; ++u)
-            if (k + u < len0) acc0 += (double)v0[u] * g0[u];
+            if (k + u < len0) acc0 += (ABS ? fabs((double)v0[u]) : (double)v0[u]) * g0[u];
         if (two) {
 #pragma unroll
             for (int u = 0; u < kCsrChunk; ++u)
-                if (k + u < len1) acc1 += (double)v1[u] * g1[u];
+                if (k + u < len1) acc1 += (ABS ? fabs((double)v1[u]) : (double)v1[u]) * g1[u];
         }
     }
     out0 = acc0, out1 = acc1;
@@ -569,21 +570,21 @@ __device__ __forceinline__ double *sell_window_lds()
 // two at a time: measured on banded random operators of 1e6 / 4e6 rows,
 // 94.5 / 382.9 against 99.3 / 402.6 us per pass; the FP32-stream form gained
 // nothing, 75.5 / 251.6 against 73.5 / 253.8).
-template <typename T, int EPT, bool C16 = false, typename F>
+template <typename T, int EPT, bool C16 = false, bool ABS = false, typename F>
 __device__ __forceinline__ void sell_sorted_products(const PassArgs<T> &a, uint32_t g, uint32_t lane,
                                                      const int32_t (&len)[EPT], F v, double (&pr)[EPT])
 {
     if constexpr (sizeof(T) == 8 && EPT % 2 == 0) {
 #pragma unroll
         for (int j = 0; j < EPT; j += 2)
-            sell_slice_pair<T, F, C16>(a, g * EPT + j, lane, len[j], len[j + 1], v, pr[j], pr[j + 1]);
+            sell_slice_pair<T, F, C16, ABS>(a, g * EPT + j, lane, len[j], len[j + 1], v, pr[j], pr[j + 1]);
     } else {
 #pragma unroll
-        for (int j = 0; j < EPT; ++j) pr[j] = sell_slice<T, F, C16>(a, g * EPT + j, lane, len[j], v);
+        for (int j = 0; j < EPT; ++j) pr[j] = sell_slice<T, F, C16, ABS>(a, g * EPT + j, lane, len[j], v);
     }
 }
 
-template <typename T, int EPT, typename F>
+template <typename T, int EPT, bool ABS = false, typename F>
 __device__ __forceinline__ void sell_sorted_rows(const PassArgs<T> &a, int tile, double (&ne)[EPT], F v)
 {
     static_assert(EPT * 64 <= 256, "a row's position in its wave's rows is kept in 8 bits");
@@ -609,13 +610,13 @@ __device__ __forceinline__ void sell_sorted_rows(const PassArgs<T> &a, int tile,
         __syncthreads();
         if (a.sell_c16) {
             // every tile windowed: the entries carry their window offsets
-            sell_sorted_products<T, EPT, true>(a, g, lane, len, [&](uint32_t k) { return win[k]; }, pr);
+            sell_sorted_products<T, EPT, true, ABS>(a, g, lane, len, [&](uint32_t k) { return win[k]; }, pr);
         } else {
             const uint32_t c0 = (uint32_t)wd.x;
-            sell_sorted_products<T, EPT>(a, g, lane, len, [&](uint32_t k) { return win[k - c0]; }, pr);
+            sell_sorted_products<T, EPT, false, ABS>(a, g, lane, len, [&](uint32_t k) { return win[k - c0]; }, pr);
         }
     } else {
-        sell_sorted_products<T, EPT>(a, g, lane, len, v, pr);
+        sell_sorted_products<T, EPT, false, ABS>(a, g, lane, len, v, pr);
     }
     double *xw = xch + wave * (EPT * 64);
     // the previous tile's reads of xw are done before it is written again
@@ -633,31 +634,32 @@ __device__ __forceinline__ void sell_sorted_rows(const PassArgs<T> &a, int tile,
 
 // One row of the in-place copy, through its 16-bit row-relative columns when
 // the copy has them (every entry within 2^15 of its row).
-template <typename T, typename F>
+template <bool ABS = false, typename T, typename F>
 __device__ __forceinline__ double sell_plain_row(const PassArgs<T> &a, uint32_t e, F v)
 {
     if (a.sell_c16) {
         auto rel = [&](uint32_t c) { return v(e + c - 32768u); };
-        return sell_slice<T, decltype(rel), true>(a, e >> 6, e & 63, a.A.row_ptr[e + 1] - a.A.row_ptr[e], rel);
+        return sell_slice<T, decltype(rel), true, ABS>(a, e >> 6, e & 63, a.A.row_ptr[e + 1] - a.A.row_ptr[e], rel);
     }
-    return sell_row(a, e, v);
+    return sell_row<T, F, ABS>(a, e, v);
 }
 
-// (A v) at a tile's rows: from the sorted copy (SELL 2), the in-place copy
-// (SELL 1) or the operator itself (SELL 0, and every operator that is not CSR).  All three
-// give the bits of apply_row.  SELL 2 synchronises the block when the tile
-// has a column window, so every thread of the block calls it for the tile.
-template <typename T, int OP, int EPT, int SELL, typename F>
+// (A v) at a tile's rows (ABS: (|A| v)): from the sorted copy (SELL 2), the
+// in-place copy (SELL 1) or the operator itself (SELL 0, and every operator
+// that is not CSR).  All three give the bits of apply_row.  SELL 2
+// synchronises the block when the tile has a column window, so every
+// thread of the block calls it for the tile.
+template <typename T, int OP, int EPT, int SELL, bool ABS, typename F>
 __device__ __forceinline__ void tile_apply(const PassArgs<T> &a, int tile, const TileIdx<EPT> &ti, double (&out)[EPT],
                                            F v)
 {
     if constexpr (OP == OP_CSR && SELL == 2) {
-        sell_sorted_rows<T, EPT>(a, tile, out, v);
+        sell_sorted_rows<T, EPT, ABS>(a, tile, out, v);
     } else {
 #pragma unroll
         for (int j = 0; j < EPT; ++j) {
-            if constexpr (OP == OP_CSR && SELL == 1) out[j] = sell_plain_row(a, ti.e[j], v);
-            else out[j] = apply_row<OP>(a.A, ti.e[j], v);
+            if constexpr (OP == OP_CSR && SELL == 1) out[j] = sell_plain_row<ABS>(a, ti.e[j], v);
+            else out[j] = apply_row<OP, ABS>(a.A, ti.e[j], v);
         }
     }
 }
@@ -834,17 +836,17 @@ __global__ void __launch_bounds__(kMaxBlock) k_x_fixup(PassArgs<T> a, double alp
 
 // Gap check: partials of ||(b - A x) - r||^2 and || |A||x| + |b| ||^2 (the
 // rounding scale of the explicit residual), x the internal binary64 copy.
-template <typename T, int OP, int EPT>
+template <typename T, int OP, int EPT, int SELL = 0>
 __device__ __forceinline__ void tile_gap(const PassArgs<T> &a, int tile, double (&acc)[3])
 {
     const TileIdx<EPT> ti = tile_idx<EPT>(tile, (uint32_t)a.A.n);
     double be[EPT], ax[EPT], aax[EPT], re[EPT];
+    tile_apply<T, OP, EPT, SELL>(a, tile, ti, ax, [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
+    tile_apply<T, OP, EPT, SELL, true>(a, tile, ti, aax, [&](uint32_t k) { return fabs(*vp<double>(a, a.off_x, k)); });
 #pragma unroll
     for (int j = 0; j < EPT; ++j) {
         const uint32_t e = ti.e[j];
         be[j] = a.b[e];
-        ax[j] = apply_row<OP>(a.A, e, [&](uint32_t k) { return *vp<double>(a, a.off_x, k); });
-        aax[j] = apply_row<OP, true>(a.A, e, [&](uint32_t k) { return fabs(*vp<double>(a, a.off_x, k)); });
         re[j] = ld(vp<T>(a, a.off_r, e), 0);
     }
 #pragma unroll
@@ -924,7 +926,7 @@ __device__ __forceinline__ void tile_rr2(const PassArgs<T> &a, uint32_t off_wout
 //     the pass does replacement step 1, else it iterates;
 //   RR2 phase: replacement step 2, whose partials restart iteration i.
 // Passes that leave w alone flip `wflip`, so w_i is always found.  A CSR
-// operator is read in the form SELL names, except by the gap pass (|A| |x|).
+// operator is read in the form SELL names.
 template <typename T, int OP, bool JAC, int EPT, bool NT, int SELL = 0>
 __global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
 {
@@ -1026,7 +1028,7 @@ __global__ void __launch_bounds__(kMaxBlock) k_pipe_rr(PassArgs<T> a)
         for (int tile = tr.first; tile < tr.end; tile += tr.step)
             tile_pipe<T, OP, JAC, EPT, NT, false, X_EACH, SELL>(w, tile, sc, acc);
     } else if (role == ROLE_GAP) {
-        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_gap<T, OP, EPT>(a, tile, acc);
+        for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_gap<T, OP, EPT, SELL>(a, tile, acc);
     } else if (role == ROLE_RR1) {
         for (int tile = tr.first; tile < tr.end; tile += tr.step) tile_rr1<T, OP, JAC, EPT, SELL>(a, tile);
     } else {
